@@ -1,0 +1,192 @@
+/*
+ * moss.h -- C ABI of the MI355X (gfx950) microscopic traffic simulator.
+ *
+ * The library advances a road network full of vehicles in fixed time steps.
+ * Each step follows the two-phase iteration of the paper's GPU simulator
+ * (Sec. III-A): a prepare phase that orders every lane's vehicles by
+ * position and keeps a read-only copy of their motion state, then an update
+ * phase in which every vehicle, reading only that copy, finds its leader,
+ * evaluates IDM car-following and a randomised MOBIL lane change, and moves
+ * by Newton's equations of motion.  Inputs are a road network and travel
+ * demand, outputs the per-vehicle state and road-level measures (Sec. III-A,
+ * last paragraphs).
+ *
+ * Conventions
+ * -----------
+ * - All functions return MOSS_OK (0) or a negative MOSS_E* code; the text of
+ *   the last error of the calling thread is returned by moss_last_error().
+ * - Input structs hold HOST pointers; moss_create copies everything it needs,
+ *   so the caller may free them when it returns.
+ * - Device memory is owned by the caller: moss_create receives a workspace of
+ *   at least moss_query_workspace() bytes (e.g. a uint8 torch tensor) that must
+ *   stay allocated, and untouched, until moss_destroy.
+ * - All device work is enqueued on the HIP stream given to moss_create
+ *   (hipStream_t passed as void*, NULL = the null stream).  moss_step is
+ *   asynchronous; the read functions synchronise that stream.
+ * - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Units: metres, seconds, m/s, m/s^2; time in integer steps of dt seconds.
+ */
+#ifndef MOSS_H
+#define MOSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOSS_OK 0
+#define MOSS_EINVAL (-1)   /* malformed input or argument */
+#define MOSS_ENOMEM (-2)   /* workspace or output buffer too small */
+#define MOSS_EDEVICE (-3)  /* a HIP call failed */
+#define MOSS_ESTATE (-4)   /* the device flagged an invalid state (see moss_read_counters) */
+
+/* Flags for moss_params.flags */
+#define MOSS_FLAG_DEBUG 1u /* record per-vehicle decisions of each step (moss_read_debug) */
+
+/* Road network.  Roads are directed; road r has road_nlanes[r] lanes numbered
+ * road_lane0[r] .. road_lane0[r]+road_nlanes[r]-1 (lane index k inside the
+ * road = lane - road_lane0[r]); lanes must be numbered road by road without
+ * gaps.  All lanes of a road have the road's length.  lane_scen (optional)
+ * labels each lane with a scenario id in [0, n_scen) when several independent
+ * scenarios are simulated as one disjoint network; counters are kept per
+ * scenario. */
+typedef struct {
+    int32_t n_nodes, n_roads, n_lanes, n_scen;
+    const int32_t *road_from;    /* [n_roads] upstream node */
+    const int32_t *road_to;      /* [n_roads] downstream node */
+    const int32_t *road_nlanes;  /* [n_roads] 1..255 */
+    const int32_t *road_lane0;   /* [n_roads] */
+    const float *road_length;    /* [n_roads] m, > 0 */
+    const float *lane_vlim;      /* [n_lanes] speed limit, m/s, > 0 */
+    const int32_t *lane_scen;    /* [n_lanes] or NULL (all 0) */
+} moss_network;
+
+/* Fixed-time signal plans.  Node j with node_cycle[j] > 0 shows phase
+ * ((t + node_offset[j]) mod node_cycle[j]) div node_phase[j] at step t.
+ * A road r ending at a signalised node may enter the junction only while
+ * that phase equals road_group[r]; road_group[r] = -1 means always green. */
+typedef struct {
+    const int32_t *node_cycle;   /* [n_nodes] steps, 0 = unsignalised */
+    const int32_t *node_phase;   /* [n_nodes] steps per phase, > 0 if signalised */
+    const int32_t *node_offset;  /* [n_nodes] steps, >= 0 */
+    const int8_t *road_group;    /* [n_roads] */
+} moss_signals;
+
+/* Travel demand.  Vehicle i follows route_roads[route_off[i] ..
+ * route_off[i+1]-1], a chain of at least one road where each road starts at
+ * the node the previous one ends.  Vehicle ids must be unique and differ from
+ * 0xFFFFFFFF.  A vehicle with placed[i] = 0 (or placed = NULL) enters its first
+ * road at s = 0 at or after step depart[i]: it queues on lane id mod nlanes of
+ * that road.  A vehicle with placed[i] = 1 starts on lane[i] at front-bumper
+ * position s[i] with speed v[i], previous acceleration a[i] and route index
+ * cursor[i]; placed vehicles of a lane must keep at least one vehicle length
+ * between consecutive fronts. */
+typedef struct {
+    int32_t n;
+    const uint32_t *id;          /* [n] */
+    const int32_t *depart;       /* [n] step of departure (trip time counts from it) */
+    const float *v0;             /* [n] desired speed, m/s, > 0 */
+    const int64_t *route_off;    /* [n+1] */
+    const int32_t *route_roads;  /* [route_off[n]] */
+    const uint8_t *placed;       /* [n] or NULL */
+    const int32_t *lane;         /* [n] used where placed */
+    const int32_t *cursor;       /* [n] */
+    const float *s, *v, *a;      /* [n] */
+} moss_vehicles;
+
+/* Model parameters (IDM: a_max, b, s0, T with exponent 4; MOBIL: politeness,
+ * a_thr, b_safe; lane changes that pass are executed with probability p_lc
+ * using Philox4x32-10 keyed by seed and counted by (step, vehicle id)). */
+typedef struct {
+    float dt;          /* s */
+    float a_max, b, s0, T;
+    float length;      /* vehicle length, m */
+    float b_max;       /* braking limit, m/s^2 */
+    float b_safe;      /* MOBIL safe braking of the new follower, m/s^2 */
+    float politeness, a_thr, p_lc;
+    float d_look;      /* m, lookahead range beyond the lane end */
+    int32_t h_look;    /* roads scanned ahead, >= 0 */
+    int32_t t0;        /* index of the first step, >= 0 */
+    uint64_t seed;
+    uint32_t flags;    /* MOSS_FLAG_* */
+} moss_params;
+
+typedef struct moss_sim moss_sim;
+
+/* Per-vehicle state rows in lane order (lane ascending, then position).
+ * Any pointer may be NULL to skip the field.  device = 1: pointers are device
+ * memory of the simulator's GPU, 0: host memory.  capacity = rows available;
+ * n receives the number of active vehicles (MOSS_ENOMEM if above capacity,
+ * nothing written), t the index of the next step. */
+typedef struct {
+    int32_t capacity;
+    int32_t device;
+    uint32_t *id;
+    int32_t *lane;
+    float *s, *v, *a;
+    int32_t *cursor;             /* index into the vehicle's route */
+    int32_t n;                   /* out */
+    int64_t t;                   /* out */
+} moss_state_out;
+
+/* Counter indices of moss_read_counters (per scenario). */
+enum {
+    MOSS_CNT_INSERTED = 0,   /* vehicles that entered the network */
+    MOSS_CNT_INSERT_FAIL,    /* due queue heads that found no gap */
+    MOSS_CNT_ARRIVED,        /* vehicles that completed their route */
+    MOSS_CNT_TRIP_TIME,      /* sum over arrivals of (arrival step - depart) */
+    MOSS_CNT_CLAMPS,         /* overlap corrections */
+    MOSS_CNT_LANE_CHANGES,
+    MOSS_CNT_VEH_STEPS,      /* sum over steps of active vehicles after the step */
+    MOSS_N_COUNTERS
+};
+
+/* Device bytes needed for these inputs (host-only work). */
+int moss_query_workspace(const moss_network *net, const moss_signals *sig,
+                         const moss_vehicles *veh, const moss_params *prm, size_t *bytes);
+
+/* Validates and copies the inputs into the workspace and returns a handle.
+ * Errors: MOSS_EINVAL (inconsistent network, route that is not a chain,
+ * overlapping placed vehicles, non-finite or non-positive parameters),
+ * MOSS_ENOMEM (ws_bytes too small), MOSS_EDEVICE. */
+int moss_create(const moss_network *net, const moss_signals *sig, const moss_vehicles *veh,
+                const moss_params *prm, void *d_ws, size_t ws_bytes, void *hip_stream,
+                moss_sim **out);
+
+/* Enqueues n >= 0 steps.  Asynchronous.  MOSS_ESTATE if an earlier read
+ * found the device error word set. */
+int moss_step(moss_sim *h, int32_t n);
+
+/* Synchronises the stream and copies the requested state rows. */
+int moss_read_state(moss_sim *h, moss_state_out *out);
+
+/* Synchronises and copies host arrays counters[n_scen][MOSS_N_COUNTERS] and
+ * sum_v[n_scen] (sum over steps and active vehicles of speed) and the device
+ * error word (0 = healthy; bit 0 lane capacity exceeded, bit 1 non-finite
+ * state).  Any pointer may be NULL. */
+int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *error_word);
+
+/* With MOSS_FLAG_DEBUG: per-vehicle decisions of the most recent step, in the
+ * row order of the state that step started from (host pointers, capacity
+ * rows, NULL to skip): vehicle id, leader id (0xFFFFFFFF = none), flags
+ * (bits 0-1: 0 no lane-change evaluation, 1 evaluated and kept, 2 changed;
+ * bit 2 red-light obstacle applied; bit 3 leader found beyond the lane end;
+ * bit 4 arrived), MOBIL margin (incentive minus threshold), target-lane
+ * leader and follower ids.  *n receives the row count. */
+int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leader,
+                    int32_t *flags, float *margin, uint32_t *t_leader, uint32_t *t_follower,
+                    int32_t *n);
+
+/* Frees host-side resources of the handle (the workspace stays the caller's). */
+int moss_destroy(moss_sim *h);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *moss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

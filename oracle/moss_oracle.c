@@ -1,0 +1,712 @@
+/*
+ * CPU oracle for the per-step microscopic vehicle update.
+ *
+ * TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the simulator library.
+ *
+ * The paper (Sec. III-A) fixes the skeleton of one simulation step:
+ *   prepare  - build a per-lane spatial index of the vehicles and take a
+ *              read-only copy of their motion state;
+ *   update   - every vehicle reads its leader through the index, computes
+ *              its acceleration from IDM [Treiber et al. 2000], decides on
+ *              a lane change with a randomised MOBIL rule [Kesting et al.
+ *              2007], and moves by Newton's equations of motion.
+ * It also fixes the 1 s step, the inputs (road network plus demand) and the
+ * outputs (per-vehicle position and speed, road averages).  Everything else is
+ * a reading of this project, marked [reading] below; the HIP library follows
+ * the same readings.
+ *
+ * Arithmetic is FP32, each expression evaluated in the written order; the
+ * file is compiled without FP contraction or fast-math so that every rounding
+ * is a plain IEEE single-precision operation.
+ *
+ * The implementation is deliberately plain: the whole state is rebuilt every
+ * step, neighbour searches are linear scans, joiners are ordered with qsort.
+ */
+#include "moss_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+static char g_err[256];
+static void set_err(const char *m) { snprintf(g_err, sizeof g_err, "%s", m); }
+const char *orc_error(void) { return g_err; }
+
+/* ---------------------------------------------------------------- RNG --- */
+
+/* Philox4x32-10 as published by Salmon, Moraes, Dror, Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two 32x32->64 bit
+ * multiplications with a Weyl-sequence key schedule. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ---------------------------------------------------------------- IDM --- */
+
+static float fmin32(float x, float y) { return x < y ? x : y; }
+static float fmax32(float x, float y) { return x > y ? x : y; }
+
+/* IDM acceleration (Treiber, Hennecke, Helbing 2000) with exponent 4:
+ *   a_max * (1 - (v/v0)^4 - (s*(v, dv) / gap)^2),
+ *   s* = s0 + max(0, v*T + v*dv / (2*sqrt(a_max*b))).
+ * Without a leader only the free-road term remains.  A non-positive gap
+ * returns the braking limit [reading: guards the division]. */
+float orc_idm(float v, float v0e, int has_leader, float v_lead, float gap, float a_max,
+              float two_sqrt_ab, float s0, float T, float b_max)
+{
+    float r = v / v0e;
+    float r2 = r * r;
+    float r4 = r2 * r2;
+    float free_term = 1.0f - r4;
+    if (!has_leader)
+        return a_max * free_term;
+    if (gap <= 0.0f)
+        return -b_max;
+    float dv = v - v_lead;
+    float t1 = v * T;
+    float t2 = (v * dv) / two_sqrt_ab;
+    float tt = t1 + t2;
+    float ss = s0 + (tt > 0.0f ? tt : 0.0f);
+    float q = ss / gap;
+    return a_max * (free_term - q * q);
+}
+
+/* -------------------------------------------------------------- model --- */
+
+typedef struct {
+    float dt, a_max, b, s0, T, len, b_max, b_safe, p, a_thr, p_lc, d_look;
+    float two_sqrt_ab;     /* fl32(2*sqrt(a_max*b)), formed in double */
+    int32_t h_look;
+    uint32_t key0, key1;
+} params_t;
+
+enum { ST_STAY = 0, ST_JOIN = 1, ST_ARRIVE = 2 };
+
+typedef struct {
+    float s, v, a;
+    int32_t lane, cur;
+    int32_t veh;       /* vehicle table index */
+    int32_t status;
+    int32_t src_lane;  /* lane at step start (-1 for an insertion) */
+} prop_t;
+
+struct orc_sim {
+    params_t P;
+    int32_t n_nodes, n_roads, n_lanes, n_scen, n_veh;
+    int32_t *road_from, *road_to, *road_nlanes, *road_lane0;
+    float *road_length, *lane_vlim;
+    int32_t *lane_scen, *lane_road, *lane_k;
+    int32_t *node_cycle, *node_phase, *node_offset;
+    int8_t *road_group;
+    uint32_t *vid;
+    int32_t *depart;
+    float *v0;
+    int64_t *route_off;
+    int32_t *route_len;
+    int32_t *routes;
+    /* active state, lane order */
+    int32_t n_act;
+    int32_t *ls;       /* lane segment starts, n_lanes+1 */
+    int32_t *sl;       /* lane of each slot */
+    int32_t *vi;
+    float *s, *v, *a;
+    int32_t *cur;
+    /* departure queues per origin lane */
+    int32_t *q_start, *q_end, *q_head, *q_list;
+    int64_t t;
+    int64_t *cnt;      /* [n_scen][ORC_N_COUNTERS] */
+    double *sumv;
+    /* decisions of the last step, indexed by slot at step start */
+    int32_t dbg_n;
+    uint32_t *d_id, *d_leader, *d_tl, *d_tf;
+    int32_t *d_flags;
+    float *d_margin;
+};
+
+/* copies an input array; size 0 or NULL source yields a zero-filled block */
+static void *dup_arr(const void *src, size_t n, size_t elt)
+{
+    size_t bytes = n * elt;
+    void *p = malloc(bytes ? bytes : 1);
+    if (!p)
+        return NULL;
+    if (src && bytes)
+        memcpy(p, src, bytes);
+    else
+        memset(p, 0, bytes ? bytes : 1);
+    return p;
+}
+
+static void free_sim(orc_sim *m)
+{
+    if (!m)
+        return;
+    void *ptrs[] = {m->road_from, m->road_to, m->road_nlanes, m->road_lane0, m->road_length,
+                    m->lane_vlim, m->lane_scen, m->lane_road, m->lane_k, m->node_cycle,
+                    m->node_phase, m->node_offset, m->road_group, m->vid, m->depart, m->v0,
+                    m->route_off, m->route_len, m->routes, m->ls, m->sl, m->vi, m->s, m->v,
+                    m->a, m->cur, m->q_start, m->q_end, m->q_head, m->q_list, m->cnt, m->sumv,
+                    m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin};
+    for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i)
+        free(ptrs[i]);
+    free(m);
+}
+
+void orc_destroy(orc_sim *m) { free_sim(m); }
+
+/* ------------------------------------------------------------ create --- */
+
+typedef struct { int32_t lane; float s; uint32_t id; int32_t veh; } place_t;
+
+static int cmp_place(const void *x, const void *y)
+{
+    const place_t *p = x, *q = y;
+    if (p->lane != q->lane) return p->lane < q->lane ? -1 : 1;
+    if (p->s != q->s) return p->s < q->s ? -1 : 1;
+    return p->id < q->id ? -1 : (p->id > q->id);
+}
+
+typedef struct { int32_t lane, depart; uint32_t id; int32_t veh; } pend_t;
+
+static int cmp_pend(const void *x, const void *y)
+{
+    const pend_t *p = x, *q = y;
+    if (p->lane != q->lane) return p->lane < q->lane ? -1 : 1;
+    if (p->depart != q->depart) return p->depart < q->depart ? -1 : 1;
+    return p->id < q->id ? -1 : (p->id > q->id);
+}
+
+orc_sim *orc_create(const orc_input *in)
+{
+    orc_sim *m = calloc(1, sizeof *m);
+    if (!m) { set_err("out of memory"); return NULL; }
+    m->n_nodes = in->n_nodes; m->n_roads = in->n_roads; m->n_lanes = in->n_lanes;
+    m->n_scen = in->n_scen > 0 ? in->n_scen : 1; m->n_veh = in->n_veh;
+    int32_t R = m->n_roads, Lc = m->n_lanes, N = m->n_veh;
+
+    m->road_from = dup_arr(in->road_from, R, 4);
+    m->road_to = dup_arr(in->road_to, R, 4);
+    m->road_nlanes = dup_arr(in->road_nlanes, R, 4);
+    m->road_lane0 = dup_arr(in->road_lane0, R, 4);
+    m->road_length = dup_arr(in->road_length, R, 4);
+    m->lane_vlim = dup_arr(in->lane_vlim, Lc, 4);
+    m->lane_scen = dup_arr(in->lane_scen, Lc, 4);
+    m->node_cycle = dup_arr(in->node_cycle, m->n_nodes, 4);
+    m->node_phase = dup_arr(in->node_phase, m->n_nodes, 4);
+    m->node_offset = dup_arr(in->node_offset, m->n_nodes, 4);
+    m->road_group = dup_arr(in->road_group, R, 1);
+    m->vid = dup_arr(in->veh_id, N, 4);
+    m->depart = dup_arr(in->depart, N, 4);
+    m->v0 = dup_arr(in->v0, N, 4);
+    m->route_off = dup_arr(in->route_off, (size_t)N + 1, 8);
+    m->route_len = malloc(sizeof(int32_t) * (N ? N : 1));
+    int64_t n_route = N ? in->route_off[N] : 0;
+    m->routes = dup_arr(in->route_roads, (size_t)n_route, 4);
+    m->lane_road = malloc(sizeof(int32_t) * (Lc ? Lc : 1));
+    m->lane_k = malloc(sizeof(int32_t) * (Lc ? Lc : 1));
+    for (int32_t r = 0; r < R; ++r)
+        for (int32_t k = 0; k < m->road_nlanes[r]; ++k) {
+            m->lane_road[m->road_lane0[r] + k] = r;
+            m->lane_k[m->road_lane0[r] + k] = k;
+        }
+    for (int32_t i = 0; i < N; ++i)
+        m->route_len[i] = (int32_t)(m->route_off[i + 1] - m->route_off[i]);
+
+    params_t *P = &m->P;
+    P->dt = in->dt; P->a_max = in->a_max; P->b = in->b; P->s0 = in->s0; P->T = in->T;
+    P->len = in->length; P->b_max = in->b_max; P->b_safe = in->b_safe; P->p = in->politeness;
+    P->a_thr = in->a_thr; P->p_lc = in->p_lc; P->d_look = in->d_look; P->h_look = in->h_look;
+    P->two_sqrt_ab = (float)(2.0 * sqrt((double)in->a_max * (double)in->b));
+    P->key0 = (uint32_t)(in->seed & 0xFFFFFFFFu);
+    P->key1 = (uint32_t)(in->seed >> 32);
+    m->t = in->t0;
+
+    /* pre-placed vehicles: ordered by (lane, s, id) */
+    int32_t n_pl = 0;
+    for (int32_t i = 0; i < N; ++i)
+        if (in->placed && in->placed[i]) ++n_pl;
+    place_t *pl = malloc(sizeof(place_t) * (n_pl ? n_pl : 1));
+    int32_t j = 0;
+    for (int32_t i = 0; i < N; ++i)
+        if (in->placed && in->placed[i]) {
+            pl[j].lane = in->lane[i]; pl[j].s = in->s[i]; pl[j].id = m->vid[i]; pl[j].veh = i; ++j;
+        }
+    qsort(pl, n_pl, sizeof(place_t), cmp_place);
+    size_t cap = (size_t)N + (size_t)Lc + 1;
+    m->ls = calloc((size_t)Lc + 1, 4);
+    m->sl = malloc(4 * cap); m->vi = malloc(4 * cap); m->cur = malloc(4 * cap);
+    m->s = malloc(4 * cap); m->v = malloc(4 * cap); m->a = malloc(4 * cap);
+    m->d_id = malloc(4 * cap); m->d_leader = malloc(4 * cap); m->d_tl = malloc(4 * cap);
+    m->d_tf = malloc(4 * cap); m->d_flags = malloc(4 * cap); m->d_margin = malloc(4 * cap);
+    for (int32_t k = 0; k < n_pl; ++k) {
+        int32_t i = pl[k].veh;
+        m->sl[k] = pl[k].lane; m->vi[k] = i; m->s[k] = in->s[i]; m->v[k] = in->v[i];
+        m->a[k] = in->a[i]; m->cur[k] = in->cursor[i];
+        m->ls[pl[k].lane + 1]++;
+        if (pl[k].lane < 0 || pl[k].lane >= Lc || m->cur[k] < 0 || m->cur[k] >= m->route_len[i]
+            || m->routes[m->route_off[i] + m->cur[k]] != m->lane_road[pl[k].lane]) {
+            set_err("pre-placed vehicle is not on the road its route cursor names");
+            free(pl); free_sim(m); return NULL;
+        }
+        if (k > 0 && pl[k - 1].lane == pl[k].lane && !(m->s[k - 1] <= m->s[k] - P->len)) {
+            set_err("pre-placed vehicles overlap");
+            free(pl); free_sim(m); return NULL;
+        }
+    }
+    for (int32_t l = 0; l < Lc; ++l)
+        m->ls[l + 1] += m->ls[l];
+    m->n_act = n_pl;
+    free(pl);
+
+    /* pending vehicles queue on the origin lane of their first road, lane
+     * index id mod (lanes of that road) [reading], in (depart, id) order */
+    int32_t n_pe = N - n_pl;
+    pend_t *pe = malloc(sizeof(pend_t) * (n_pe ? n_pe : 1));
+    j = 0;
+    for (int32_t i = 0; i < N; ++i)
+        if (!(in->placed && in->placed[i])) {
+            int32_t r0 = m->routes[m->route_off[i]];
+            pe[j].lane = m->road_lane0[r0] + (int32_t)(m->vid[i] % (uint32_t)m->road_nlanes[r0]);
+            pe[j].depart = m->depart[i]; pe[j].id = m->vid[i]; pe[j].veh = i; ++j;
+        }
+    qsort(pe, n_pe, sizeof(pend_t), cmp_pend);
+    m->q_start = calloc((size_t)Lc + 1, 4);
+    m->q_end = calloc((size_t)Lc + 1, 4);
+    m->q_head = calloc((size_t)Lc + 1, 4);
+    m->q_list = malloc(4 * (size_t)(n_pe ? n_pe : 1));
+    for (int32_t k = 0; k < n_pe; ++k) {
+        m->q_list[k] = pe[k].veh;
+        m->q_end[pe[k].lane]++;
+    }
+    int32_t acc = 0;
+    for (int32_t l = 0; l < Lc; ++l) {
+        m->q_start[l] = acc; m->q_head[l] = acc; acc += m->q_end[l]; m->q_end[l] = acc;
+    }
+    free(pe);
+    m->cnt = calloc((size_t)m->n_scen * ORC_N_COUNTERS, 8);
+    m->sumv = calloc((size_t)m->n_scen, 8);
+    return m;
+}
+
+/* ------------------------------------------------------------ helpers --- */
+
+static float road_len(const orc_sim *m, int32_t lane) { return m->road_length[m->lane_road[lane]]; }
+
+/* Signal reading [reading]: a node with cycle C, phase length P and offset O
+ * shows phase ((t + O) mod C) div P; an in-road of group g may enter the
+ * junction only while that phase equals g.  Group -1, unsignalised nodes and
+ * the last road of a route are always green. */
+static int red_for(const orc_sim *m, int32_t road, int64_t t)
+{
+    int32_t g = m->road_group[road];
+    int32_t node = m->road_to[road];
+    if (g < 0 || m->node_cycle[node] <= 0)
+        return 0;
+    int64_t c = m->node_cycle[node];
+    int64_t ph = ((t + m->node_offset[node]) % c) / m->node_phase[node];
+    return ph != g;
+}
+
+typedef struct { int has; float v, gap; uint32_t id; } leader_t;
+
+/* Leader beyond the end of the vehicle's lane [reading]: follow the route for
+ * at most h_look roads and while the distance already covered is within
+ * d_look; on each next road take lane min(k, lanes-1) (k carried along) and
+ * use its last vehicle (lowest position) as leader.  A vehicle never leads
+ * itself (a ring road with one vehicle). */
+static leader_t lookahead(const orc_sim *m, int32_t lane, float s, int32_t veh, int32_t cur)
+{
+    leader_t L = {0, 0.0f, 0.0f, ORC_NONE};
+    float dist = road_len(m, lane) - s;
+    int32_t kk = m->lane_k[lane];
+    int32_t c = cur;
+    for (int32_t h = 0; h < m->P.h_look; ++h) {
+        if (c + 1 >= m->route_len[veh])
+            break;
+        if (dist > m->P.d_look)
+            break;
+        c += 1;
+        int32_t rd = m->routes[m->route_off[veh] + c];
+        if (kk > m->road_nlanes[rd] - 1)
+            kk = m->road_nlanes[rd] - 1;
+        int32_t y = m->road_lane0[rd] + kk;
+        if (m->ls[y] < m->ls[y + 1]) {
+            int32_t tail = m->ls[y];
+            if (m->vi[tail] != veh) {
+                L.has = 1;
+                L.v = m->v[tail];
+                L.gap = (dist + m->s[tail]) - m->P.len;
+                L.id = m->vid[m->vi[tail]];
+            }
+            return L;
+        }
+        dist = dist + m->road_length[rd];
+    }
+    return L;
+}
+
+static float idm_p(const params_t *P, float v, float v0e, int has, float vl, float gap)
+{
+    return orc_idm(v, v0e, has, vl, gap, P->a_max, P->two_sqrt_ab, P->s0, P->T, P->b_max);
+}
+
+/* --------------------------------------------------------- update phase --- */
+
+/* One vehicle of the snapshot: everything read here belongs to the state at
+ * the start of the step; the result goes to the proposal only. */
+static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
+{
+    const params_t *P = &m->P;
+    const int64_t t = m->t;
+    int32_t l = m->sl[i];
+    int32_t r = m->lane_road[l];
+    int32_t k = m->lane_k[l];
+    int32_t nl = m->road_nlanes[r];
+    float L = m->road_length[r];
+    int32_t veh = m->vi[i];
+    uint32_t id = m->vid[veh];
+    float s = m->s[i], v = m->v[i];
+    float v0 = m->v0[veh];
+    int32_t c = m->cur[i];
+    int has_next = c + 1 < m->route_len[veh];
+    int32_t lo = m->ls[l], hi = m->ls[l + 1];
+
+    m->d_id[i] = id; m->d_leader[i] = ORC_NONE; m->d_tl[i] = ORC_NONE; m->d_tf[i] = ORC_NONE;
+    m->d_flags[i] = 0; m->d_margin[i] = 0.0f;
+
+    /* red light obstacle at the stop line, applied only if the vehicle can
+     * still stop with the braking limit [reading] */
+    int red = 0;
+    if (has_next && red_for(m, r, t)) {
+        float stop_dist = (v * v) / (2.0f * P->b_max);
+        if (L - s >= stop_dist)
+            red = 1;
+    }
+
+    /* in-lane neighbours through the ordering */
+    int32_t Lc = (i + 1 < hi) ? i + 1 : -1;
+    int32_t o = (i - 1 >= lo) ? i - 1 : -1;
+
+    /* --- randomised MOBIL (Kesting, Treiber, Helbing 2007) ---
+     * [reading] one side per step: even steps look at lane k-1, odd steps at
+     * k+1; only vehicles at s >= 0; neighbours within the same road only,
+     * accelerations from IDM without signal or lookahead. */
+    int change = 0;
+    int32_t lt = -1, Lt = -1, nb = -1;
+    if (s >= 0.0f) {
+        int32_t kt = (t % 2 == 0) ? k - 1 : k + 1;
+        if (kt >= 0 && kt < nl) {
+            lt = m->road_lane0[r] + kt;
+            /* brute force over the target lane: leader = lowest s_j >= s,
+             * follower = highest s_j < s */
+            for (int32_t j = m->ls[lt]; j < m->ls[lt + 1]; ++j) {
+                if (m->s[j] >= s) {
+                    if (Lt < 0 || m->s[j] < m->s[Lt]) Lt = j;
+                } else {
+                    if (nb < 0 || m->s[j] > m->s[nb]) nb = j;
+                }
+            }
+            float vlim_c = m->lane_vlim[l], vlim_t = m->lane_vlim[lt];
+            float v0e_c = fmin32(v0, vlim_c), v0e_t = fmin32(v0, vlim_t);
+            float a_c = Lc >= 0 ? idm_p(P, v, v0e_c, 1, m->v[Lc], (m->s[Lc] - P->len) - s)
+                                : idm_p(P, v, v0e_c, 0, 0.0f, 0.0f);
+            float at_c = Lt >= 0 ? idm_p(P, v, v0e_t, 1, m->v[Lt], (m->s[Lt] - P->len) - s)
+                                 : idm_p(P, v, v0e_t, 0, 0.0f, 0.0f);
+            float d_o = 0.0f, d_n = 0.0f;
+            int safe = 1;
+            if (o >= 0) {
+                float vo = m->v[o], so = m->s[o];
+                float v0e_o = fmin32(m->v0[m->vi[o]], vlim_c);
+                float a_o = idm_p(P, vo, v0e_o, 1, v, (s - P->len) - so);
+                float at_o = Lc >= 0 ? idm_p(P, vo, v0e_o, 1, m->v[Lc], (m->s[Lc] - P->len) - so)
+                                     : idm_p(P, vo, v0e_o, 0, 0.0f, 0.0f);
+                d_o = at_o - a_o;
+            }
+            if (nb >= 0) {
+                float vn = m->v[nb], sn = m->s[nb];
+                float v0e_n = fmin32(m->v0[m->vi[nb]], vlim_t);
+                float a_n = Lt >= 0 ? idm_p(P, vn, v0e_n, 1, m->v[Lt], (m->s[Lt] - P->len) - sn)
+                                    : idm_p(P, vn, v0e_n, 0, 0.0f, 0.0f);
+                float at_n = idm_p(P, vn, v0e_n, 1, v, (s - P->len) - sn);
+                d_n = at_n - a_n;
+                float gap_b = (s - P->len) - sn;
+                if (!(gap_b > 0.0f)) safe = 0;
+                if (!(at_n >= -P->b_safe)) safe = 0;
+            }
+            if (Lt >= 0) {
+                float gap_f = (m->s[Lt] - P->len) - s;
+                if (!(gap_f > 0.0f)) safe = 0;
+            }
+            float inc = (at_c - a_c) + P->p * (d_n + d_o);
+            uint32_t ctr[4] = {(uint32_t)t, id, 0u, 0u}, key[2] = {P->key0, P->key1}, rnd[4];
+            orc_philox4x32_10(ctr, key, rnd);
+            float u = (float)(rnd[0] >> 8) * (1.0f / 16777216.0f);
+            change = safe && inc > P->a_thr && u < P->p_lc;
+            m->d_margin[i] = inc - P->a_thr;
+            m->d_flags[i] |= change ? 2 : 1;
+            m->d_tl[i] = Lt >= 0 ? m->vid[m->vi[Lt]] : ORC_NONE;
+            m->d_tf[i] = nb >= 0 ? m->vid[m->vi[nb]] : ORC_NONE;
+        }
+    }
+
+    /* --- car-following in the final lane --- */
+    int32_t lf = change ? lt : l;
+    leader_t ld = {0, 0.0f, 0.0f, ORC_NONE};
+    int32_t lead_slot = change ? Lt : Lc;
+    if (lead_slot >= 0) {
+        ld.has = 1; ld.v = m->v[lead_slot]; ld.gap = (m->s[lead_slot] - P->len) - s;
+        ld.id = m->vid[m->vi[lead_slot]];
+    } else {
+        ld = lookahead(m, lf, s, veh, c);
+        if (ld.has) m->d_flags[i] |= 8;
+    }
+    m->d_leader[i] = ld.id;
+    float v0e = fmin32(v0, m->lane_vlim[lf]);
+    float acc = idm_p(P, v, v0e, ld.has, ld.v, ld.gap);
+    if (red) {
+        float acc_red = idm_p(P, v, v0e, 1, 0.0f, L - s);
+        acc = fmin32(acc, acc_red);
+        m->d_flags[i] |= 4;
+    }
+    float a = fmax32(-P->b_max, acc);
+
+    /* --- Newton's equations over one step, stopping at v = 0 --- */
+    float vn = v + a * P->dt;
+    float dx;
+    if (vn < 0.0f) {
+        dx = -((v * v) / (2.0f * a));
+        vn = 0.0f;
+    } else {
+        dx = v * P->dt + (0.5f * a) * (P->dt * P->dt);
+    }
+    float sp = s + dx;
+
+    /* --- transfer along the route; arrival at the end of the last road --- */
+    int32_t x = lf, c2 = c, kk = m->lane_k[lf];
+    while (sp >= road_len(m, x) && c2 + 1 < m->route_len[veh]) {
+        sp = sp - road_len(m, x);
+        c2 += 1;
+        int32_t rd = m->routes[m->route_off[veh] + c2];
+        if (kk > m->road_nlanes[rd] - 1)
+            kk = m->road_nlanes[rd] - 1;
+        x = m->road_lane0[rd] + kk;
+    }
+    int arrived = sp >= road_len(m, x);
+    out->s = sp; out->v = vn; out->a = a; out->lane = x; out->cur = c2; out->veh = veh;
+    out->src_lane = l;
+    out->status = arrived ? ST_ARRIVE : ((x == l && c2 == c) ? ST_STAY : ST_JOIN);
+    if (arrived) m->d_flags[i] |= 16;
+    if (change) m->cnt[(size_t)m->lane_scen[l] * ORC_N_COUNTERS + ORC_LANE_CHANGES]++;
+}
+
+/* ------------------------------------------------------- prepare phase --- */
+
+static const orc_sim *g_sort_sim;
+static int cmp_joiner(const void *x, const void *y)
+{
+    const prop_t *p = x, *q = y;
+    if (p->lane != q->lane) return p->lane < q->lane ? -1 : 1;
+    if (p->s != q->s) return p->s < q->s ? -1 : 1;
+    uint32_t a = g_sort_sim->vid[p->veh], b = g_sort_sim->vid[q->veh];
+    return a < b ? -1 : (a > b);
+}
+
+/* key order (s, id) used by the merge */
+static int key_less(const orc_sim *m, const prop_t *p, const prop_t *q)
+{
+    if (p->s != q->s) return p->s < q->s;
+    return m->vid[p->veh] < m->vid[q->veh];
+}
+
+static void one_step(orc_sim *m)
+{
+    const params_t *P = &m->P;
+    const int64_t t = m->t;
+    int32_t Lc = m->n_lanes;
+    int32_t n = m->n_act;
+
+    /* --- insertion [reading]: the head of each origin-lane queue may enter
+     * when due, at most one per lane and step, if the lane is empty or the
+     * gap behind its last vehicle is at least s0 + v*T for the entry speed
+     * v = min(v0, speed limit, speed of that vehicle).  It joins the lane at
+     * s = 0 at the end of the step. --- */
+    prop_t *ins = malloc(sizeof(prop_t) * ((size_t)Lc + 1));
+    int32_t n_ins = 0;
+    for (int32_t l = 0; l < Lc; ++l) {
+        if (m->q_head[l] >= m->q_end[l])
+            continue;
+        int32_t veh = m->q_list[m->q_head[l]];
+        if (m->depart[veh] > t)
+            continue;
+        float v0e = fmin32(m->v0[veh], m->lane_vlim[l]);
+        int ok;
+        float vins;
+        if (m->ls[l] == m->ls[l + 1]) {
+            ok = 1; vins = v0e;
+        } else {
+            int32_t tail = m->ls[l];
+            vins = fmin32(v0e, m->v[tail]);
+            ok = (m->s[tail] - P->len) >= (P->s0 + vins * P->T);
+        }
+        size_t sc = (size_t)m->lane_scen[l] * ORC_N_COUNTERS;
+        if (ok) {
+            prop_t *q = &ins[n_ins++];
+            q->s = 0.0f; q->v = vins; q->a = 0.0f; q->lane = l; q->cur = 0; q->veh = veh;
+            q->status = ST_JOIN; q->src_lane = -1;
+            m->q_head[l]++;
+            m->cnt[sc + ORC_INSERTED]++;
+        } else {
+            m->cnt[sc + ORC_INSERT_FAIL]++;
+        }
+    }
+
+    /* --- update phase: every vehicle reads the snapshot --- */
+    prop_t *pr = malloc(sizeof(prop_t) * ((size_t)n + 1));
+    for (int32_t i = 0; i < n; ++i)
+        update_vehicle(m, i, &pr[i]);
+    m->dbg_n = n;
+
+    /* --- arrivals --- */
+    for (int32_t i = 0; i < n; ++i)
+        if (pr[i].status == ST_ARRIVE) {
+            size_t sc = (size_t)m->lane_scen[pr[i].src_lane] * ORC_N_COUNTERS;
+            m->cnt[sc + ORC_ARRIVED]++;
+            m->cnt[sc + ORC_TRIP_TIME] += (t + 1) - m->depart[pr[i].veh];
+        }
+
+    /* --- joiners (lane changers, road transfers, insertions) by (lane, s, id) --- */
+    int32_t n_join = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (pr[i].status == ST_JOIN) ++n_join;
+    prop_t *jn = malloc(sizeof(prop_t) * ((size_t)n_join + n_ins + 1));
+    int32_t nj = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (pr[i].status == ST_JOIN) jn[nj++] = pr[i];
+    for (int32_t q = 0; q < n_ins; ++q)
+        jn[nj++] = ins[q];
+    g_sort_sim = m;
+    qsort(jn, nj, sizeof(prop_t), cmp_joiner);
+
+    /* --- per lane: stayers keep their order, joiners are merged in by
+     * (s, id), then overlaps are removed from the head of the lane backwards
+     * [reading: the paper does not model collisions] --- */
+    size_t cap = (size_t)m->n_veh + (size_t)Lc + 1;
+    int32_t *ls2 = calloc((size_t)Lc + 1, 4);
+    int32_t *sl2 = malloc(4 * cap), *vi2 = malloc(4 * cap), *cur2 = malloc(4 * cap);
+    float *s2 = malloc(4 * cap), *v2 = malloc(4 * cap), *a2 = malloc(4 * cap);
+    prop_t *lanebuf = malloc(sizeof(prop_t) * ((size_t)n + nj + 1));
+    int32_t w = 0, jp = 0;
+    for (int32_t l = 0; l < Lc; ++l) {
+        ls2[l] = w;
+        int32_t nb = 0;
+        int32_t ip = m->ls[l];
+        int32_t jend = jp;
+        while (jend < nj && jn[jend].lane == l) ++jend;
+        for (;;) {
+            while (ip < m->ls[l + 1] && pr[ip].status != ST_STAY) ++ip;
+            int has_s = ip < m->ls[l + 1];
+            int has_j = jp < jend;
+            if (!has_s && !has_j) break;
+            if (has_s && (!has_j || key_less(m, &pr[ip], &jn[jp])))
+                lanebuf[nb++] = pr[ip++];
+            else
+                lanebuf[nb++] = jn[jp++];
+        }
+        for (int32_t f = nb - 2; f >= 0; --f) {
+            float lim = lanebuf[f + 1].s - P->len;
+            if (lanebuf[f].s > lim) {
+                lanebuf[f].s = lim;
+                lanebuf[f].v = fmin32(lanebuf[f].v, lanebuf[f + 1].v);
+                m->cnt[(size_t)m->lane_scen[l] * ORC_N_COUNTERS + ORC_CLAMPS]++;
+            }
+        }
+        for (int32_t q = 0; q < nb; ++q) {
+            sl2[w] = l; vi2[w] = lanebuf[q].veh; cur2[w] = lanebuf[q].cur;
+            s2[w] = lanebuf[q].s; v2[w] = lanebuf[q].v; a2[w] = lanebuf[q].a;
+            ++w;
+        }
+    }
+    ls2[Lc] = w;
+    free(m->ls); free(m->sl); free(m->vi); free(m->cur); free(m->s); free(m->v); free(m->a);
+    m->ls = ls2; m->sl = sl2; m->vi = vi2; m->cur = cur2; m->s = s2; m->v = v2; m->a = a2;
+    m->n_act = w;
+    m->t = t + 1;
+
+    /* --- observables on the new state --- */
+    for (int32_t q = 0; q < w; ++q) {
+        size_t sc = (size_t)m->lane_scen[m->sl[q]];
+        m->cnt[sc * ORC_N_COUNTERS + ORC_VEH_STEPS]++;
+        m->sumv[sc] += (double)m->v[q];
+    }
+    free(lanebuf); free(jn); free(pr); free(ins);
+}
+
+int orc_step(orc_sim *m, int32_t n)
+{
+    for (int32_t k = 0; k < n; ++k)
+        one_step(m);
+    return 0;
+}
+
+int32_t orc_n_active(const orc_sim *m) { return m->n_act; }
+int64_t orc_time(const orc_sim *m) { return m->t; }
+
+int32_t orc_pending(const orc_sim *m)
+{
+    int32_t p = 0;
+    for (int32_t l = 0; l < m->n_lanes; ++l) p += m->q_end[l] - m->q_head[l];
+    return p;
+}
+
+void orc_read(const orc_sim *m, uint32_t *id, int32_t *lane, float *s, float *v, float *a,
+              int32_t *cursor)
+{
+    for (int32_t q = 0; q < m->n_act; ++q) {
+        if (id) id[q] = m->vid[m->vi[q]];
+        if (lane) lane[q] = m->sl[q];
+        if (s) s[q] = m->s[q];
+        if (v) v[q] = m->v[q];
+        if (a) a[q] = m->a[q];
+        if (cursor) cursor[q] = m->cur[q];
+    }
+}
+
+int32_t orc_read_debug(const orc_sim *m, uint32_t *id, uint32_t *leader, int32_t *flags,
+                       float *margin, uint32_t *t_leader, uint32_t *t_follower)
+{
+    for (int32_t q = 0; q < m->dbg_n; ++q) {
+        if (id) id[q] = m->d_id[q];
+        if (leader) leader[q] = m->d_leader[q];
+        if (flags) flags[q] = m->d_flags[q];
+        if (margin) margin[q] = m->d_margin[q];
+        if (t_leader) t_leader[q] = m->d_tl[q];
+        if (t_follower) t_follower[q] = m->d_tf[q];
+    }
+    return m->dbg_n;
+}
+
+void orc_counters(const orc_sim *m, int64_t *cnt, double *sum_v)
+{
+    memcpy(cnt, m->cnt, sizeof(int64_t) * (size_t)m->n_scen * ORC_N_COUNTERS);
+    memcpy(sum_v, m->sumv, sizeof(double) * (size_t)m->n_scen);
+}

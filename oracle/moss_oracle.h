@@ -1,0 +1,92 @@
+/*
+ * CPU oracle for the per-step microscopic vehicle update (test infrastructure).
+ *
+ * This is the slow, plain reference that the HIP simulator is checked
+ * against.  It is only used by the test-suite, the smoke check and the CPU
+ * baseline of the benchmark; the product path never calls it.  It shares no
+ * code, header or table with the HIP library: the only thing the two have in
+ * common is the seeded scenario generator that produces their inputs.
+ *
+ * What it computes follows the paper's simulator description (Sec. III-A):
+ * each step has a prepare phase (per-lane spatial ordering plus a read-only
+ * copy of the motion state) and an update phase in which every vehicle senses
+ * its leader through that ordering, applies IDM car-following and a
+ * randomised MOBIL lane-change rule, and advances by Newton's equations of
+ * motion.  Points the paper leaves open (insertion, junctions, signals,
+ * randomisation, collisions) follow the readings written next to each rule
+ * in moss_oracle.c.
+ */
+#ifndef MOSS_ORACLE_H
+#define MOSS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    /* network */
+    int32_t n_nodes, n_roads, n_lanes, n_scen;
+    const int32_t *road_from, *road_to, *road_nlanes, *road_lane0;
+    const float *road_length, *lane_vlim;
+    const int32_t *lane_scen;          /* may be NULL: one scenario */
+    /* signals */
+    const int32_t *node_cycle, *node_phase, *node_offset;
+    const int8_t *road_group;
+    /* vehicles */
+    int32_t n_veh;
+    const uint32_t *veh_id;
+    const int32_t *depart;
+    const float *v0;
+    const int64_t *route_off;
+    const int32_t *route_roads;
+    const uint8_t *placed;             /* may be NULL: nobody pre-placed */
+    const int32_t *lane, *cursor;
+    const float *s, *v, *a;
+    /* parameters */
+    float dt, a_max, b, s0, T, length, b_max, b_safe, politeness, a_thr, p_lc, d_look;
+    int32_t h_look;
+    int32_t t0;
+    uint64_t seed;
+} orc_input;
+
+typedef struct orc_sim orc_sim;
+
+/* counters per scenario, in this order */
+enum { ORC_INSERTED = 0, ORC_INSERT_FAIL, ORC_ARRIVED, ORC_TRIP_TIME, ORC_CLAMPS,
+       ORC_LANE_CHANGES, ORC_VEH_STEPS, ORC_N_COUNTERS };
+
+#define ORC_NONE 0xFFFFFFFFu
+
+orc_sim *orc_create(const orc_input *in);
+const char *orc_error(void);
+void orc_destroy(orc_sim *m);
+int orc_step(orc_sim *m, int32_t n);
+int32_t orc_n_active(const orc_sim *m);
+int64_t orc_time(const orc_sim *m);
+/* State in lane order (lane ascending, then position ascending). */
+void orc_read(const orc_sim *m, uint32_t *id, int32_t *lane, float *s, float *v, float *a,
+              int32_t *cursor);
+/* Per-vehicle decisions of the last step, in the order of the state the step
+ * started from: vehicle id, leader id (ORC_NONE if none), flags (bits 0-1:
+ * 0 no lane-change evaluation, 1 evaluated and kept, 2 changed; bit 2 red
+ * light obstacle applied; bit 3 leader found by lookahead; bit 4 arrived),
+ * MOBIL margin (incentive minus threshold, 0 when not evaluated), target-lane
+ * leader and follower ids. */
+int32_t orc_read_debug(const orc_sim *m, uint32_t *id, uint32_t *leader, int32_t *flags,
+                       float *margin, uint32_t *t_leader, uint32_t *t_follower);
+/* counters: int64 [n_scen][ORC_N_COUNTERS], sum of speeds [n_scen] */
+void orc_counters(const orc_sim *m, int64_t *cnt, double *sum_v);
+int32_t orc_pending(const orc_sim *m);
+
+/* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* IDM acceleration in FP32 (has_leader = 0: free road). */
+float orc_idm(float v, float v0e, int has_leader, float v_lead, float gap, float a_max,
+              float two_sqrt_ab, float s0, float T, float b_max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
