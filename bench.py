@@ -1,0 +1,162 @@
+"""Benchmark: vehicle-steps per second of the per-step microscopic update on
+one MI355X, with the roofline of the dominant kernel and the CPU oracle's
+throughput on the host as a baseline.
+
+Workload (default): the city-scale synthetic network (200 x 200 jittered
+lattice, ~40k nodes, ~120k lanes, log-normal road lengths with median 150 m)
+with 2,000,000 vehicles pre-placed on long random-walk routes, IDM + MOBIL,
+dt = 1 s, FP32 state.  Inputs are generated on the host, copied to the GPU
+once, and are resident in HBM when the timed region starts.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "vehicle-steps/sec at 2M vehicles + HBM GB/s vs peak; MLP vs IDM on same GPU"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per vehicle and launch of the two per-vehicle kernels
+# (the minimum each must move; lane tables and neighbour reads are on-chip
+# reuse): k_update reads 7 state fields (lane, s, v, id, route ptr, next road,
+# v0 = 28 B) and writes an 8-field proposal (32 B); k_merge_lane reads the
+# proposal (32 B) and writes the 8-field state (32 B).
+ALGO_BYTES = {"k_update": 28 + 32, "k_merge_lane": 32 + 32}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for f in ("moss_kernels.hip", "moss_internal.h"):
+        with open(os.path.join(ROOT, "paper_2405_12520_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """Measured HBM bytes per launch from the committed counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != kernel_sources_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(sc, steps):
+    from oracle import OracleSim
+    say(f"[bench] cpu oracle: {steps} steps of the same workload")
+    o = OracleSim(sc)
+    c0 = o.counters()[0][:, 6].sum()
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    vs = o.counters()[0][:, 6].sum() - c0
+    return dict(value=float(vs / dt), unit="vehicle-steps/s", cores=1, kind="oracle",
+                sample=f"{steps} steps of the {sc.n_veh}-vehicle city snapshot, single thread "
+                       f"({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--vehicles", type=int, default=2_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + timed steps only (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "partition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2405_12520_amd import scenarios as S
+    from paper_2405_12520_amd.moss import Simulator
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    say(f"[bench] generating city snapshot with {args.vehicles} vehicles")
+    t0 = time.time()
+    sc = S.city_snapshot(args.vehicles)
+    say(f"[bench] generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    sim = Simulator(sc)
+    stream = sim.stream
+    say("[bench] created; warmup")
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    c0, _, _ = sim.counters()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    c1, _, err = sim.counters()
+    if err:
+        print(f"device error word {err}", file=sys.stderr)
+        sys.exit(3)
+    veh_steps = int(c1[:, 6].sum() - c0[:, 6].sum())
+    value = veh_steps / (ms / 1e3)
+    say(f"[bench] {args.steps} steps in {ms:.2f} ms -> {value:.4g} vehicle-steps/s")
+    if args.profile_only:
+        return
+
+    # per-kernel durations with HIP events on the simulator's stream
+    kms = sim.step_timed(args.steps)
+    n_act = sim.n_active
+    per_launch = {k: v / args.steps for k, v in kms.items()}
+    dom = max(ALGO_BYTES, key=lambda k: per_launch[k])
+    algo = ALGO_BYTES[dom] * n_act
+    achieved = algo / (per_launch[dom] / 1e3) / 1e9
+    traffic = load_traffic(dom)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic / per_launch[dom] / 1e6, 1),
+                    kernel=dom, kernel_ms=round(per_launch[dom], 5),
+                    algo_bytes_per_launch=int(algo),
+                    kernel_ms_all={k: round(v, 5) for k, v in per_launch.items()})
+    say(f"[bench] per-kernel ms: {roofline['kernel_ms_all']}")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_steps)
+    out = dict(metric=METRIC, value=round(value, 1), unit="vehicle-steps/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=round(ms / args.steps, 5),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload="city-scale synthetic network, 2M vehicles pre-placed, "
+                                    "IDM car-following + randomised MOBIL, dt = 1 s",
+                           vehicles=int(sc.n_veh), lanes=int(sc.n_lanes), roads=int(sc.n_roads),
+                           nodes=int(sc.n_nodes), active_vehicles=int(n_act)),
+               roofline=roofline, cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

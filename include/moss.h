@@ -180,6 +180,17 @@ int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leade
                     int32_t *flags, float *margin, uint32_t *t_leader, uint32_t *t_follower,
                     int32_t *n);
 
+/* Runs n steps like moss_step but synchronises after each one and adds the
+ * duration of each of its kernels, measured with HIP events on the
+ * simulator's stream, to kernel_ms[k] (milliseconds; array of capacity
+ * entries, zeroed first).  *n_kernels receives the number of kernels per
+ * step; moss_kernel_name(k) names kernel k (NULL if out of range).  Meant
+ * for measurement: the per-step synchronisation makes it slower than
+ * moss_step. */
+int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
+                    int32_t *n_kernels);
+const char *moss_kernel_name(int32_t i);
+
 /* Frees host-side resources of the handle (the workspace stays the caller's). */
 int moss_destroy(moss_sim *h);
 

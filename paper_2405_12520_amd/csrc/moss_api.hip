@@ -1,0 +1,732 @@
+// Host runtime and C ABI of libmoss: input validation, device layout,
+// step launches and state read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/moss.h"
+#include "moss_internal.h"
+
+using namespace moss;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(MOSS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets of every device array inside the caller's workspace.
+struct Layout {
+    int32_t cap, n_lanes, n_roads, n_scen, n_qlanes, n_pend, n_veh, nblk;
+    int64_t n_route;
+    bool debug;
+    size_t total;
+    size_t S[8], Pr[8], ls[2], tails, scount, jcount, joff, blk, jrank, jlist, jidx, scal, lanes,
+        roads, sigs, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
+        vt_rstart, cnt, sumv, dbg[6], cursor;
+
+    void plan()
+    {
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off += align_up(bytes ? bytes : 1);
+            return o;
+        };
+        const size_t c = (size_t)std::max(cap, 1);
+        for (auto &x : S) x = take(4 * c);
+        for (auto &x : Pr) x = take(4 * c);
+        for (auto &x : ls) x = take(4 * ((size_t)n_lanes + 1));
+        tails = take(sizeof(Tail) * (size_t)n_lanes);
+        scount = take(4 * (size_t)n_lanes);
+        jcount = take(4 * (size_t)n_lanes);
+        joff = take(4 * ((size_t)n_lanes + 1));
+        blk = take(8 * (size_t)nblk);
+        jrank = take(4 * c);
+        jlist = take(4 * c);
+        jidx = take(4 * c);
+        scal = take(64);
+        lanes = take(sizeof(LaneInfo) * (size_t)n_lanes);
+        roads = take(sizeof(RoadInfo) * (size_t)n_roads);
+        sigs = take(sizeof(SigInfo) * (size_t)n_roads);
+        route = take(4 * ((size_t)n_route + (size_t)n_veh + 1));
+        qlanes = take(4 * (size_t)n_qlanes);
+        q_head = take(4 * (size_t)n_lanes);
+        q_end = take(4 * (size_t)n_lanes);
+        q_id = take(4 * (size_t)n_pend);
+        q_dep = take(4 * (size_t)n_pend);
+        q_v0 = take(4 * (size_t)n_pend);
+        q_ptr = take(4 * (size_t)n_pend);
+        q_next = take(4 * (size_t)n_pend);
+        vt_id = take(4 * (size_t)n_veh);
+        vt_dep = take(4 * (size_t)n_veh);
+        vt_rstart = take(4 * (size_t)n_veh);
+        cnt = take(8 * (size_t)n_scen * C_N);
+        sumv = take(8 * (size_t)n_scen);
+        for (auto &x : dbg) x = take(debug ? 4 * c : 4);
+        cursor = take(4 * c);
+        total = off;
+    }
+};
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
+bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
+
+int validate(const moss_network *net, const moss_signals *sig, const moss_vehicles *veh,
+             const moss_params *prm)
+{
+    if (!net || !sig || !veh || !prm)
+        return fail(MOSS_EINVAL, "null input struct");
+    if (net->n_nodes <= 0 || net->n_roads <= 0 || net->n_lanes <= 0 || veh->n < 0)
+        return fail(MOSS_EINVAL, "empty network or negative vehicle count");
+    if (!net->road_from || !net->road_to || !net->road_nlanes || !net->road_lane0 ||
+        !net->road_length || !net->lane_vlim)
+        return fail(MOSS_EINVAL, "missing network array");
+    if (!sig->node_cycle || !sig->node_phase || !sig->node_offset || !sig->road_group)
+        return fail(MOSS_EINVAL, "missing signal array");
+    if (veh->n > 0 && (!veh->id || !veh->depart || !veh->v0 || !veh->route_off ||
+                       !veh->route_roads))
+        return fail(MOSS_EINVAL, "missing vehicle array");
+    const int32_t n_scen = net->n_scen > 0 ? net->n_scen : 1;
+    int64_t lanes = 0;
+    for (int32_t r = 0; r < net->n_roads; ++r) {
+        int32_t a = net->road_from[r], b = net->road_to[r];
+        if (a < 0 || a >= net->n_nodes || b < 0 || b >= net->n_nodes)
+            return fail(MOSS_EINVAL, "road %d: node out of range", r);
+        if (net->road_nlanes[r] < 1 || net->road_nlanes[r] > 255)
+            return fail(MOSS_EINVAL, "road %d: lane count %d not in 1..255", r,
+                        net->road_nlanes[r]);
+        if (net->road_lane0[r] != lanes)
+            return fail(MOSS_EINVAL, "road %d: lanes not numbered road by road", r);
+        if (!finite_pos(net->road_length[r]))
+            return fail(MOSS_EINVAL, "road %d: length must be finite and > 0", r);
+        lanes += net->road_nlanes[r];
+        int8_t g = sig->road_group[r];
+        if (g < -1)
+            return fail(MOSS_EINVAL, "road %d: signal group < -1", r);
+    }
+    if (lanes != net->n_lanes)
+        return fail(MOSS_EINVAL, "lane count %lld != n_lanes %d", (long long)lanes, net->n_lanes);
+    for (int32_t l = 0; l < net->n_lanes; ++l) {
+        if (!finite_pos(net->lane_vlim[l]))
+            return fail(MOSS_EINVAL, "lane %d: speed limit must be finite and > 0", l);
+        if (net->lane_scen && (net->lane_scen[l] < 0 || net->lane_scen[l] >= n_scen))
+            return fail(MOSS_EINVAL, "lane %d: scenario out of range", l);
+    }
+    for (int32_t j = 0; j < net->n_nodes; ++j) {
+        if (sig->node_cycle[j] < 0)
+            return fail(MOSS_EINVAL, "node %d: negative cycle", j);
+        if (sig->node_cycle[j] > 0 && (sig->node_phase[j] <= 0 || sig->node_offset[j] < 0))
+            return fail(MOSS_EINVAL, "node %d: phase must be > 0 and offset >= 0", j);
+    }
+    const moss_params &p = *prm;
+    const float pos[] = {p.dt, p.a_max, p.b, p.length, p.b_max};
+    for (float x : pos)
+        if (!finite_pos(x))
+            return fail(MOSS_EINVAL, "dt, a_max, b, length and b_max must be finite and > 0");
+    const float nonneg[] = {p.s0, p.T, p.b_safe, p.politeness, p.d_look};
+    for (float x : nonneg)
+        if (!finite_nonneg(x))
+            return fail(MOSS_EINVAL, "s0, T, b_safe, politeness and d_look must be finite, >= 0");
+    if (!std::isfinite(p.a_thr) || !std::isfinite(p.p_lc) || p.p_lc < 0.0f || p.p_lc > 1.0f)
+        return fail(MOSS_EINVAL, "a_thr must be finite and p_lc in [0, 1]");
+    if (p.h_look < 0 || p.t0 < 0)
+        return fail(MOSS_EINVAL, "h_look and t0 must be >= 0");
+    // vehicles
+    std::vector<uint32_t> ids(veh->id, veh->id + veh->n);
+    std::sort(ids.begin(), ids.end());
+    for (int32_t i = 0; i < veh->n; ++i) {
+        if (ids[i] == kNone)
+            return fail(MOSS_EINVAL, "vehicle id 0xFFFFFFFF is reserved");
+        if (i > 0 && ids[i] == ids[i - 1])
+            return fail(MOSS_EINVAL, "duplicate vehicle id %u", ids[i]);
+    }
+    if (veh->n > 0 && veh->route_off[0] != 0)
+        return fail(MOSS_EINVAL, "route_off[0] must be 0");
+    for (int32_t i = 0; i < veh->n; ++i) {
+        if (!finite_pos(veh->v0[i]))
+            return fail(MOSS_EINVAL, "vehicle %d: v0 must be finite and > 0", i);
+        int64_t a = veh->route_off[i], b = veh->route_off[i + 1];
+        if (b <= a)
+            return fail(MOSS_EINVAL, "vehicle %d: empty route", i);
+        for (int64_t k = a; k < b; ++k) {
+            int32_t r = veh->route_roads[k];
+            if (r < 0 || r >= net->n_roads)
+                return fail(MOSS_EINVAL, "vehicle %d: road out of range", i);
+            if (k > a && net->road_to[veh->route_roads[k - 1]] != net->road_from[r])
+                return fail(MOSS_EINVAL, "vehicle %d: route is not a chain of roads", i);
+        }
+        if (veh->placed && veh->placed[i]) {
+            if (!veh->lane || !veh->cursor || !veh->s || !veh->v || !veh->a)
+                return fail(MOSS_EINVAL, "missing placement arrays");
+            int32_t l = veh->lane[i], c = veh->cursor[i];
+            if (l < 0 || l >= net->n_lanes || c < 0 || c >= b - a)
+                return fail(MOSS_EINVAL, "vehicle %d: lane or cursor out of range", i);
+            int32_t r = veh->route_roads[a + c];
+            if (l < net->road_lane0[r] || l >= net->road_lane0[r] + net->road_nlanes[r])
+                return fail(MOSS_EINVAL, "vehicle %d: lane is not on route road %d", i, r);
+            if (!std::isfinite(veh->s[i]) || !(veh->s[i] < net->road_length[r]) ||
+                !finite_nonneg(veh->v[i]) || !std::isfinite(veh->a[i]))
+                return fail(MOSS_EINVAL, "vehicle %d: bad position, speed or acceleration", i);
+        }
+    }
+    return MOSS_OK;
+}
+
+}  // namespace
+
+struct moss_sim {
+    Layout lay;
+    Dev dev;
+    hipStream_t stream;
+    int device;
+    int parity;           // which lane_start buffer holds the current state
+    int64_t t;            // host copy of the next step index
+    int32_t n_scen;
+    uint32_t err_seen;
+    char *ws;
+};
+
+static void fill_dev(moss_sim *h)
+{
+    const Layout &L = h->lay;
+    char *w = h->ws;
+    Dev &d = h->dev;
+    auto F = [&](size_t o) { return (float *)(w + o); };
+    auto U = [&](size_t o) { return (uint32_t *)(w + o); };
+    auto I = [&](size_t o) { return (int32_t *)(w + o); };
+    SoA *sets[2] = {&d.S, &d.Pr};
+    const size_t *offs[2] = {L.S, L.Pr};
+    for (int k = 0; k < 2; ++k) {
+        SoA &x = *sets[k];
+        x.s = F(offs[k][0]);
+        x.v = F(offs[k][1]);
+        x.a = F(offs[k][2]);
+        x.id = U(offs[k][3]);
+        x.lane = U(offs[k][4]);
+        x.ptr = U(offs[k][5]);
+        x.next = I(offs[k][6]);
+        x.v0 = F(offs[k][7]);
+    }
+    d.n_lanes = L.n_lanes;
+    d.n_scen = L.n_scen;
+    d.cap = L.cap;
+    d.n_qlanes = L.n_qlanes;
+    d.lanes = (const LaneInfo *)(w + L.lanes);
+    d.roads = (const RoadInfo *)(w + L.roads);
+    d.sigs = (const SigInfo *)(w + L.sigs);
+    d.route = I(L.route);
+    d.tails = (Tail *)(w + L.tails);
+    d.scount = I(L.scount);
+    d.jcount = I(L.jcount);
+    d.joff = I(L.joff);
+    d.blk = I(L.blk);
+    d.jrank = U(L.jrank);
+    d.jlist = U(L.jlist);
+    d.jidx = U(L.jidx);
+    int32_t *sc = I(L.scal);
+    d.n_cur = sc + 0;
+    d.n_next = sc + 1;
+    d.n_dbg = sc + 2;
+    d.n_ins = (uint32_t *)(sc + 3);
+    d.n_join = (uint32_t *)(sc + 4);
+    d.err = (uint32_t *)(sc + 5);
+    d.t = (int64_t *)(sc + 8);
+    d.qlanes = I(L.qlanes);
+    d.q_head = I(L.q_head);
+    d.q_end = I(L.q_end);
+    d.q_id = U(L.q_id);
+    d.q_dep = I(L.q_dep);
+    d.q_v0 = F(L.q_v0);
+    d.q_ptr = U(L.q_ptr);
+    d.q_next = I(L.q_next);
+    d.n_veh = L.n_veh;
+    d.vt_id = U(L.vt_id);
+    d.vt_dep = I(L.vt_dep);
+    d.vt_rstart = U(L.vt_rstart);
+    d.cnt = (unsigned long long *)(w + L.cnt);
+    d.sumv = (double *)(w + L.sumv);
+    d.d_id = U(L.dbg[0]);
+    d.d_leader = U(L.dbg[1]);
+    d.d_flags = I(L.dbg[2]);
+    d.d_margin = F(L.dbg[3]);
+    d.d_tl = U(L.dbg[4]);
+    d.d_tf = U(L.dbg[5]);
+}
+
+static Dev step_dev(const moss_sim *h, int parity)
+{
+    Dev d = h->dev;
+    d.ls_old = (const int32_t *)(h->ws + h->lay.ls[parity]);
+    d.ls_new = (int32_t *)(h->ws + h->lay.ls[1 - parity]);
+    return d;
+}
+
+static void plan_layout(const moss_network *net, const moss_vehicles *veh, const moss_params *prm,
+                        Layout *L)
+{
+    L->n_lanes = net->n_lanes;
+    L->n_roads = net->n_roads;
+    L->n_scen = net->n_scen > 0 ? net->n_scen : 1;
+    L->n_veh = veh->n;
+    L->cap = veh->n;
+    L->n_route = veh->n > 0 ? veh->route_off[veh->n] : 0;
+    int32_t n_pl = 0;
+    std::vector<char> is_q(net->n_lanes, 0);
+    for (int32_t i = 0; i < veh->n; ++i) {
+        if (veh->placed && veh->placed[i]) {
+            ++n_pl;
+        } else {
+            int32_t r0 = veh->route_roads[veh->route_off[i]];
+            is_q[net->road_lane0[r0] + (int32_t)(veh->id[i] % (uint32_t)net->road_nlanes[r0])] = 1;
+        }
+    }
+    L->n_pend = veh->n - n_pl;
+    L->n_qlanes = (int32_t)std::count(is_q.begin(), is_q.end(), 1);
+    L->nblk = (net->n_lanes + 2047) / 2048;
+    L->debug = (prm->flags & MOSS_FLAG_DEBUG) != 0;
+    L->plan();
+}
+
+extern "C" {
+
+const char *moss_last_error(void) { return g_err.c_str(); }
+
+int moss_query_workspace(const moss_network *net, const moss_signals *sig,
+                         const moss_vehicles *veh, const moss_params *prm, size_t *bytes)
+{
+    g_err.clear();
+    if (!bytes)
+        return fail(MOSS_EINVAL, "bytes is null");
+    int rc = validate(net, sig, veh, prm);
+    if (rc)
+        return rc;
+    Layout L;
+    plan_layout(net, veh, prm, &L);
+    *bytes = L.total;
+    return MOSS_OK;
+}
+
+int moss_create(const moss_network *net, const moss_signals *sig, const moss_vehicles *veh,
+                const moss_params *prm, void *d_ws, size_t ws_bytes, void *hip_stream,
+                moss_sim **out)
+{
+    g_err.clear();
+    if (!out)
+        return fail(MOSS_EINVAL, "out is null");
+    *out = nullptr;
+    int rc = validate(net, sig, veh, prm);
+    if (rc)
+        return rc;
+    if (!d_ws)
+        return fail(MOSS_EINVAL, "workspace is null");
+    Layout L;
+    plan_layout(net, veh, prm, &L);
+    if (ws_bytes < L.total)
+        return fail(MOSS_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    if (((uintptr_t)d_ws & 255) != 0)
+        return fail(MOSS_EINVAL, "workspace must be 256-byte aligned");
+
+    hipPointerAttribute_t attr;
+    HIP_TRY(hipPointerGetAttributes(&attr, d_ws));
+    if (attr.type != hipMemoryTypeDevice)
+        return fail(MOSS_EINVAL, "workspace is not device memory");
+    HIP_TRY(hipSetDevice(attr.device));
+
+    const int32_t NL = net->n_lanes, NR = net->n_roads, N = veh->n;
+    const moss_params &p = *prm;
+
+    // --- static tables
+    std::vector<LaneInfo> lanes(NL);
+    std::vector<RoadInfo> roads(NR);
+    std::vector<SigInfo> sigs(NR);
+    for (int32_t r = 0; r < NR; ++r) {
+        roads[r] = {net->road_lane0[r], net->road_nlanes[r], net->road_length[r], 0};
+        int32_t j = net->road_to[r];
+        int8_t g = sig->road_group[r];
+        bool signalised = g >= 0 && sig->node_cycle[j] > 0;
+        sigs[r] = {signalised ? sig->node_cycle[j] : 1, signalised ? sig->node_phase[j] : 1,
+                   signalised ? sig->node_offset[j] : 0, (int32_t)g};
+        for (int32_t k = 0; k < net->road_nlanes[r]; ++k) {
+            int32_t l = net->road_lane0[r] + k;
+            LaneInfo &li = lanes[l];
+            li.L = net->road_length[r];
+            li.vlim = net->lane_vlim[l];
+            li.road = r;
+            li.lane0 = net->road_lane0[r];
+            li.k = k;
+            li.nlanes = net->road_nlanes[r];
+            li.scen = net->lane_scen ? net->lane_scen[l] : 0;
+            li.sig = signalised ? r : -1;
+        }
+    }
+
+    // --- routes, each followed by -1
+    std::vector<int32_t> route((size_t)L.n_route + N + 1);
+    std::vector<uint32_t> rstart(N);
+    {
+        size_t w = 0;
+        for (int32_t i = 0; i < N; ++i) {
+            rstart[i] = (uint32_t)w;
+            for (int64_t k = veh->route_off[i]; k < veh->route_off[i + 1]; ++k)
+                route[w++] = veh->route_roads[k];
+            route[w++] = -1;
+        }
+        route[w] = -1;
+    }
+
+    // --- placed vehicles in lane order
+    std::vector<int32_t> placed;
+    std::vector<int32_t> pend;
+    for (int32_t i = 0; i < N; ++i)
+        ((veh->placed && veh->placed[i]) ? placed : pend).push_back(i);
+    std::sort(placed.begin(), placed.end(), [&](int32_t x, int32_t y) {
+        if (veh->lane[x] != veh->lane[y]) return veh->lane[x] < veh->lane[y];
+        if (veh->s[x] != veh->s[y]) return veh->s[x] < veh->s[y];
+        return veh->id[x] < veh->id[y];
+    });
+    const int32_t NP = (int32_t)placed.size();
+    std::vector<float> hs(NP), hv(NP), ha(NP), hv0(NP);
+    std::vector<uint32_t> hid(NP), hlane(NP), hptr(NP);
+    std::vector<int32_t> hnext(NP), ls(NL + 1, 0);
+    for (int32_t k = 0; k < NP; ++k) {
+        int32_t i = placed[k];
+        hs[k] = veh->s[i];
+        hv[k] = veh->v[i];
+        ha[k] = veh->a[i];
+        hv0[k] = veh->v0[i];
+        hid[k] = veh->id[i];
+        hlane[k] = (uint32_t)veh->lane[i];
+        hptr[k] = rstart[i] + (uint32_t)veh->cursor[i];
+        hnext[k] = route[hptr[k] + 1];
+        ls[veh->lane[i] + 1]++;
+        if (k > 0 && hlane[k - 1] == hlane[k] && !(hs[k - 1] <= hs[k] - p.length))
+            return fail(MOSS_EINVAL, "placed vehicles %u and %u overlap", hid[k - 1], hid[k]);
+    }
+    for (int32_t l = 0; l < NL; ++l)
+        ls[l + 1] += ls[l];
+
+    // --- departure queues: origin lane, then (depart, id)
+    auto origin = [&](int32_t i) {
+        int32_t r0 = veh->route_roads[veh->route_off[i]];
+        return net->road_lane0[r0] + (int32_t)(veh->id[i] % (uint32_t)net->road_nlanes[r0]);
+    };
+    std::vector<int32_t> olane(N, -1);
+    for (int32_t i : pend)
+        olane[i] = origin(i);
+    std::sort(pend.begin(), pend.end(), [&](int32_t x, int32_t y) {
+        if (olane[x] != olane[y]) return olane[x] < olane[y];
+        if (veh->depart[x] != veh->depart[y]) return veh->depart[x] < veh->depart[y];
+        return veh->id[x] < veh->id[y];
+    });
+    const int32_t NQ = (int32_t)pend.size();
+    std::vector<uint32_t> qid(NQ), qptr(NQ);
+    std::vector<int32_t> qdep(NQ), qnext(NQ), qhead(NL, 0), qend(NL, 0), qlanes;
+    std::vector<float> qv0(NQ);
+    for (int32_t k = 0; k < NQ; ++k) {
+        int32_t i = pend[k];
+        qid[k] = veh->id[i];
+        qdep[k] = veh->depart[i];
+        qv0[k] = veh->v0[i];
+        qptr[k] = rstart[i];
+        qnext[k] = route[rstart[i] + 1];
+        qend[olane[i]]++;
+    }
+    {
+        int32_t acc = 0;
+        for (int32_t l = 0; l < NL; ++l) {
+            qhead[l] = acc;
+            acc += qend[l];
+            qend[l] = acc;
+            if (qend[l] > qhead[l])
+                qlanes.push_back(l);
+        }
+    }
+
+    // --- vehicle table by id
+    std::vector<int32_t> byid(N);
+    std::iota(byid.begin(), byid.end(), 0);
+    std::sort(byid.begin(), byid.end(), [&](int32_t x, int32_t y) { return veh->id[x] < veh->id[y]; });
+    std::vector<uint32_t> vtid(N), vtr(N);
+    std::vector<int32_t> vtdep(N);
+    for (int32_t k = 0; k < N; ++k) {
+        vtid[k] = veh->id[byid[k]];
+        vtdep[k] = veh->depart[byid[k]];
+        vtr[k] = rstart[byid[k]];
+    }
+
+    moss_sim *h = new moss_sim();
+    h->lay = L;
+    h->ws = (char *)d_ws;
+    h->stream = (hipStream_t)hip_stream;
+    h->device = attr.device;
+    h->parity = 0;
+    h->t = p.t0;
+    h->n_scen = L.n_scen;
+    h->err_seen = 0;
+    fill_dev(h);
+    Params &P = h->dev.P;
+    P.dt = p.dt;
+    P.a_max = p.a_max;
+    P.s0 = p.s0;
+    P.T = p.T;
+    P.len = p.length;
+    P.b_max = p.b_max;
+    P.b_safe = p.b_safe;
+    P.pol = p.politeness;
+    P.a_thr = p.a_thr;
+    P.p_lc = p.p_lc;
+    P.d_look = p.d_look;
+    P.two_sqrt_ab = (float)(2.0 * std::sqrt((double)p.a_max * (double)p.b));
+    P.h_look = p.h_look;
+    P.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
+    P.key1 = (uint32_t)(p.seed >> 32);
+    P.debug = L.debug ? 1u : 0u;
+
+    hipStream_t st = h->stream;
+    char *w = h->ws;
+    auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    int32_t scal[16] = {0};
+    scal[0] = NP;
+    int64_t t0 = p.t0;
+    std::memcpy(&scal[8], &t0, 8);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(hipMemsetAsync(w, 0, L.total, st));
+    chk(up(L.S[0], hs.data(), 4 * (size_t)NP));
+    chk(up(L.S[1], hv.data(), 4 * (size_t)NP));
+    chk(up(L.S[2], ha.data(), 4 * (size_t)NP));
+    chk(up(L.S[3], hid.data(), 4 * (size_t)NP));
+    chk(up(L.S[4], hlane.data(), 4 * (size_t)NP));
+    chk(up(L.S[5], hptr.data(), 4 * (size_t)NP));
+    chk(up(L.S[6], hnext.data(), 4 * (size_t)NP));
+    chk(up(L.S[7], hv0.data(), 4 * (size_t)NP));
+    chk(up(L.ls[0], ls.data(), 4 * (size_t)(NL + 1)));
+    chk(up(L.scal, scal, sizeof scal));
+    chk(up(L.lanes, lanes.data(), sizeof(LaneInfo) * NL));
+    chk(up(L.roads, roads.data(), sizeof(RoadInfo) * NR));
+    chk(up(L.sigs, sigs.data(), sizeof(SigInfo) * NR));
+    chk(up(L.route, route.data(), 4 * route.size()));
+    chk(up(L.qlanes, qlanes.data(), 4 * qlanes.size()));
+    chk(up(L.q_head, qhead.data(), 4 * (size_t)NL));
+    chk(up(L.q_end, qend.data(), 4 * (size_t)NL));
+    chk(up(L.q_id, qid.data(), 4 * (size_t)NQ));
+    chk(up(L.q_dep, qdep.data(), 4 * (size_t)NQ));
+    chk(up(L.q_v0, qv0.data(), 4 * (size_t)NQ));
+    chk(up(L.q_ptr, qptr.data(), 4 * (size_t)NQ));
+    chk(up(L.q_next, qnext.data(), 4 * (size_t)NQ));
+    chk(up(L.vt_id, vtid.data(), 4 * (size_t)N));
+    chk(up(L.vt_dep, vtdep.data(), 4 * (size_t)N));
+    chk(up(L.vt_rstart, vtr.data(), 4 * (size_t)N));
+    if (e == hipSuccess)
+        e = launch_tails(step_dev(h, 0), st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(MOSS_EDEVICE, "device setup failed: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return MOSS_OK;
+}
+
+int moss_step(moss_sim *h, int32_t n)
+{
+    g_err.clear();
+    if (!h)
+        return fail(MOSS_EINVAL, "null handle");
+    if (n < 0)
+        return fail(MOSS_EINVAL, "negative step count");
+    if (h->err_seen)
+        return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
+    if (h->t + n >= (int64_t)1 << 31)
+        return fail(MOSS_EINVAL, "step index would exceed 2^31");
+    HIP_TRY(hipSetDevice(h->device));
+    for (int32_t k = 0; k < n; ++k) {
+        HIP_TRY(launch_step(step_dev(h, h->parity), h->stream));
+        h->parity ^= 1;
+        h->t += 1;
+    }
+    return MOSS_OK;
+}
+
+int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
+                    int32_t *n_kernels)
+{
+    g_err.clear();
+    if (!h || !kernel_ms || !n_kernels)
+        return fail(MOSS_EINVAL, "null argument");
+    const int K = step_kernel_count();
+    *n_kernels = K;
+    if (capacity < K)
+        return fail(MOSS_ENOMEM, "%d kernels, capacity %d", K, capacity);
+    if (n < 0)
+        return fail(MOSS_EINVAL, "negative step count");
+    if (h->err_seen)
+        return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
+    if (h->t + n >= (int64_t)1 << 31)
+        return fail(MOSS_EINVAL, "step index would exceed 2^31");
+    HIP_TRY(hipSetDevice(h->device));
+    std::vector<hipEvent_t> ev(K + 1);
+    for (auto &e : ev)
+        HIP_TRY(hipEventCreate(&e));
+    for (int k = 0; k < K; ++k)
+        kernel_ms[k] = 0.0;
+    int rc = MOSS_OK;
+    for (int32_t s = 0; s < n && rc == MOSS_OK; ++s) {
+        hipError_t e = launch_step(step_dev(h, h->parity), h->stream, ev.data());
+        if (e == hipSuccess)
+            e = hipEventSynchronize(ev[K]);
+        if (e != hipSuccess) {
+            rc = fail(MOSS_EDEVICE, "timed step failed: %s", hipGetErrorString(e));
+            break;
+        }
+        h->parity ^= 1;
+        h->t += 1;
+        for (int k = 0; k < K; ++k) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            kernel_ms[k] += ms;
+        }
+    }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    return rc;
+}
+
+const char *moss_kernel_name(int32_t i) { return step_kernel_name(i); }
+
+static int sync_and_check(moss_sim *h)
+{
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, h->dev.err, 4, hipMemcpyDeviceToHost));
+    h->err_seen |= err;
+    return MOSS_OK;
+}
+
+int moss_read_state(moss_sim *h, moss_state_out *out)
+{
+    g_err.clear();
+    if (!h || !out)
+        return fail(MOSS_EINVAL, "null argument");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    int32_t n = 0;
+    HIP_TRY(hipMemcpy(&n, h->dev.n_cur, 4, hipMemcpyDeviceToHost));
+    out->n = n;
+    out->t = h->t;
+    if (n > out->capacity)
+        return fail(MOSS_ENOMEM, "%d active vehicles, capacity %d", n, out->capacity);
+    const hipMemcpyKind kind = out->device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t b = 4 * (size_t)n;
+    const SoA &S = h->dev.S;
+    if (n > 0) {
+        if (out->id) HIP_TRY(hipMemcpy(out->id, S.id, b, kind));
+        if (out->lane) HIP_TRY(hipMemcpy(out->lane, S.lane, b, kind));
+        if (out->s) HIP_TRY(hipMemcpy(out->s, S.s, b, kind));
+        if (out->v) HIP_TRY(hipMemcpy(out->v, S.v, b, kind));
+        if (out->a) HIP_TRY(hipMemcpy(out->a, S.a, b, kind));
+        if (out->cursor) {
+            int32_t *tmp = (int32_t *)(h->ws + h->lay.cursor);
+            HIP_TRY(launch_cursor(h->dev, S.id, S.ptr, tmp, n, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            HIP_TRY(hipMemcpy(out->cursor, tmp, b, kind));
+        }
+    }
+    if (h->err_seen)
+        return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
+    return MOSS_OK;
+}
+
+int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *error_word)
+{
+    g_err.clear();
+    if (!h)
+        return fail(MOSS_EINVAL, "null handle");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    if (counters)
+        HIP_TRY(hipMemcpy(counters, h->dev.cnt, 8 * (size_t)h->n_scen * C_N,
+                          hipMemcpyDeviceToHost));
+    if (sum_v)
+        HIP_TRY(hipMemcpy(sum_v, h->dev.sumv, 8 * (size_t)h->n_scen, hipMemcpyDeviceToHost));
+    if (error_word)
+        *error_word = h->err_seen;
+    return MOSS_OK;
+}
+
+int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leader,
+                    int32_t *flags, float *margin, uint32_t *t_leader, uint32_t *t_follower,
+                    int32_t *n)
+{
+    g_err.clear();
+    if (!h || !n)
+        return fail(MOSS_EINVAL, "null argument");
+    if (!h->lay.debug)
+        return fail(MOSS_EINVAL, "created without MOSS_FLAG_DEBUG");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    int32_t m = 0;
+    HIP_TRY(hipMemcpy(&m, h->dev.n_dbg, 4, hipMemcpyDeviceToHost));
+    *n = m;
+    if (m > capacity)
+        return fail(MOSS_ENOMEM, "%d rows, capacity %d", m, capacity);
+    const size_t b = 4 * (size_t)m;
+    if (m > 0) {
+        if (id) HIP_TRY(hipMemcpy(id, h->dev.d_id, b, hipMemcpyDeviceToHost));
+        if (leader) HIP_TRY(hipMemcpy(leader, h->dev.d_leader, b, hipMemcpyDeviceToHost));
+        if (flags) HIP_TRY(hipMemcpy(flags, h->dev.d_flags, b, hipMemcpyDeviceToHost));
+        if (margin) HIP_TRY(hipMemcpy(margin, h->dev.d_margin, b, hipMemcpyDeviceToHost));
+        if (t_leader) HIP_TRY(hipMemcpy(t_leader, h->dev.d_tl, b, hipMemcpyDeviceToHost));
+        if (t_follower) HIP_TRY(hipMemcpy(t_follower, h->dev.d_tf, b, hipMemcpyDeviceToHost));
+    }
+    return MOSS_OK;
+}
+
+int moss_destroy(moss_sim *h)
+{
+    g_err.clear();
+    if (!h)
+        return fail(MOSS_EINVAL, "null handle");
+    if (h->device >= 0) {
+        (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize(h->stream);
+    }
+    delete h;
+    return MOSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal layout shared by the host runtime and the kernels of libmoss.
+//
+// Vehicle state is a structure of arrays kept in lane order: lane 0's
+// vehicles by ascending front position, then lane 1's, ...; lane_start[l]
+// gives the first row of lane l.  This is the per-lane spatial index of the
+// paper's prepare phase (Sec. III-A), stored as a compact sorted array
+// instead of linked lists so that the update phase reads it with coalesced
+// loads and finds in-lane neighbours at row +-1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace moss {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;      // "no vehicle" id
+constexpr uint32_t kJoinBit = 0x80000000u;   // proposal lane: vehicle joins another lane
+constexpr uint32_t kArrived = 0xFFFFFFFFu;   // proposal lane: vehicle left the network
+
+// Per-lane constants, 32 bytes, read with one broadcast load per lane.
+struct LaneInfo {
+    float L;            // road length
+    float vlim;         // speed limit
+    int32_t road;
+    int32_t lane0;      // first lane of the road
+    int32_t k;          // index in the road
+    int32_t nlanes;
+    int32_t scen;       // scenario of the lane
+    int32_t sig;        // signal of the downstream junction: -1 none, else index into SigInfo
+};
+
+// Per-road constants used when following a route.
+struct RoadInfo {
+    int32_t lane0;
+    int32_t nlanes;
+    float L;
+    int32_t pad;
+};
+
+// Fixed-time plan seen by one in-road: cycle, phase length, offset, group.
+struct SigInfo {
+    int32_t cycle, phase, offset, group;
+};
+
+// Last vehicle (lowest position) of each lane; id == kNone when empty.
+struct Tail {
+    float s, v;
+    uint32_t id;
+    int32_t pad;
+};
+
+// Hot per-vehicle state, structure of arrays (32 bytes per vehicle).
+struct SoA {
+    float *s, *v, *a;
+    uint32_t *id;
+    uint32_t *lane;     // in proposals: target lane | kJoinBit, or kArrived
+    uint32_t *ptr;      // absolute index of the current road in the route array
+    int32_t *next;      // next road of the route, -1 on the last road
+    float *v0;
+};
+
+struct Params {
+    float dt, a_max, s0, T, len, b_max, b_safe, pol, a_thr, p_lc, d_look;
+    float two_sqrt_ab;  // fl32(2 sqrt(a_max b)) formed in double on the host
+    int32_t h_look;
+    uint32_t key0, key1;
+    uint32_t debug;
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+    Params P;
+    int32_t n_lanes, n_scen, cap, n_qlanes;
+    const LaneInfo *lanes;
+    const RoadInfo *roads;
+    const SigInfo *sigs;
+    const int32_t *route;         // routes, each followed by -1
+    SoA S;                        // state at the start of a step
+    SoA Pr;                       // proposals, indexed by row at step start (+ insertions)
+    const int32_t *ls_old;        // lane_start of the state being read
+    int32_t *ls_new;              // lane_start being built
+    Tail *tails;
+    int32_t *scount, *jcount;     // stayers / joiners per lane (zeroed by the scan)
+    int32_t *joff;                // exclusive scan of jcount
+    int32_t *blk;                 // scan block sums
+    uint32_t *jrank, *jlist, *jidx;
+    int32_t *n_cur, *n_next, *n_dbg;
+    uint32_t *n_ins, *n_join;
+    int64_t *t;
+    // departure queues
+    const int32_t *qlanes;
+    int32_t *q_head;
+    const int32_t *q_end;
+    const uint32_t *q_id;
+    const int32_t *q_dep;
+    const float *q_v0;
+    const uint32_t *q_ptr;
+    const int32_t *q_next;
+    // vehicle table sorted by id (arrival bookkeeping, cursor output)
+    int32_t n_veh;
+    const uint32_t *vt_id;
+    const int32_t *vt_dep;
+    const uint32_t *vt_rstart;
+    // observables
+    unsigned long long *cnt;      // [n_scen][7]
+    double *sumv;                 // [n_scen]
+    uint32_t *err;
+    // debug per row at step start
+    uint32_t *d_id, *d_leader, *d_tl, *d_tf;
+    int32_t *d_flags;
+    float *d_margin;
+};
+
+enum { C_INSERTED = 0, C_INSERT_FAIL, C_ARRIVED, C_TRIP_TIME, C_CLAMPS, C_LANE_CHANGES,
+       C_VEH_STEPS, C_N };
+
+// Kernel launchers (moss_kernels.hip).
+hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);
+int step_kernel_count();
+const char *step_kernel_name(int i);
+hipError_t launch_tails(const Dev &d, hipStream_t st);
+hipError_t launch_cursor(const Dev &d, const uint32_t *ids, const uint32_t *ptrs, int32_t *out,
+                         int32_t n, hipStream_t st);
+
+}  // namespace moss

@@ -1,0 +1,280 @@
+"""Python binding of libmoss (ctypes): argument marshalling only.
+
+Every simulation step runs in the HIP kernels of ``libmoss.so``; this module
+builds the C structs of ``include/moss.h`` from numpy arrays, allocates the
+device workspace as a torch tensor and passes torch's current HIP stream.
+It raises if the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libmoss.so")
+
+MOSS_OK, MOSS_EINVAL, MOSS_ENOMEM, MOSS_EDEVICE, MOSS_ESTATE = 0, -1, -2, -3, -4
+MOSS_FLAG_DEBUG = 1
+COUNTER_NAMES = ("inserted", "insert_fail", "arrived", "trip_time", "clamps", "lane_changes",
+                 "veh_steps")
+NONE = 0xFFFFFFFF
+
+vp = C.c_void_p
+
+
+class moss_network(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_roads", C.c_int32), ("n_lanes", C.c_int32),
+                ("n_scen", C.c_int32), ("road_from", vp), ("road_to", vp), ("road_nlanes", vp),
+                ("road_lane0", vp), ("road_length", vp), ("lane_vlim", vp), ("lane_scen", vp)]
+
+
+class moss_signals(C.Structure):
+    _fields_ = [("node_cycle", vp), ("node_phase", vp), ("node_offset", vp), ("road_group", vp)]
+
+
+class moss_vehicles(C.Structure):
+    _fields_ = [("n", C.c_int32), ("id", vp), ("depart", vp), ("v0", vp), ("route_off", vp),
+                ("route_roads", vp), ("placed", vp), ("lane", vp), ("cursor", vp), ("s", vp),
+                ("v", vp), ("a", vp)]
+
+
+class moss_params(C.Structure):
+    _fields_ = [("dt", C.c_float), ("a_max", C.c_float), ("b", C.c_float), ("s0", C.c_float),
+                ("T", C.c_float), ("length", C.c_float), ("b_max", C.c_float),
+                ("b_safe", C.c_float), ("politeness", C.c_float), ("a_thr", C.c_float),
+                ("p_lc", C.c_float), ("d_look", C.c_float), ("h_look", C.c_int32),
+                ("t0", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32)]
+
+
+class moss_state_out(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("device", C.c_int32), ("id", vp), ("lane", vp),
+                ("s", vp), ("v", vp), ("a", vp), ("cursor", vp), ("n", C.c_int32),
+                ("t", C.c_int64)]
+
+
+EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state",
+           "moss_read_counters", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
+           "moss_destroy", "moss_last_error")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libmoss.so; raises FileNotFoundError if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with paper_2405_12520_amd.build")
+    L = C.CDLL(path)
+    L.moss_query_workspace.argtypes = [C.POINTER(moss_network), C.POINTER(moss_signals),
+                                       C.POINTER(moss_vehicles), C.POINTER(moss_params),
+                                       C.POINTER(C.c_size_t)]
+    L.moss_create.argtypes = [C.POINTER(moss_network), C.POINTER(moss_signals),
+                              C.POINTER(moss_vehicles), C.POINTER(moss_params), vp, C.c_size_t,
+                              vp, C.POINTER(vp)]
+    L.moss_step.argtypes = [vp, C.c_int32]
+    L.moss_read_state.argtypes = [vp, C.POINTER(moss_state_out)]
+    L.moss_read_counters.argtypes = [vp, vp, vp, C.POINTER(C.c_uint32)]
+    L.moss_read_debug.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp,
+                                  C.POINTER(C.c_int32)]
+    L.moss_step_timed.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
+    L.moss_kernel_name.argtypes = [C.c_int32]
+    L.moss_destroy.argtypes = [vp]
+    for f in EXPORTS:
+        getattr(L, f).restype = C.c_char_p if f in ("moss_last_error", "moss_kernel_name") \
+            else C.c_int
+    _lib = L
+    return L
+
+
+class MossError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmoss error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != MOSS_OK:
+        raise MossError(rc, load().moss_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(vp)
+
+
+def marshal(sc, debug: bool = False):
+    """C structs (and the numpy arrays they point to) for a Scenario."""
+    keep = []
+
+    def arr(x, dt):
+        a = np.ascontiguousarray(x, dtype=dt)
+        keep.append(a)
+        return _ptr(a)
+
+    net = moss_network(sc.n_nodes, sc.n_roads, sc.n_lanes, sc.n_scen,
+                       arr(sc.road_from, np.int32), arr(sc.road_to, np.int32),
+                       arr(sc.road_nlanes, np.int32), arr(sc.road_lane0, np.int32),
+                       arr(sc.road_length, np.float32), arr(sc.lane_vlim, np.float32),
+                       arr(sc.lane_scen, np.int32))
+    sig = moss_signals(arr(sc.node_cycle, np.int32), arr(sc.node_phase, np.int32),
+                       arr(sc.node_offset, np.int32), arr(sc.road_group, np.int8))
+    veh = moss_vehicles(sc.n_veh, arr(sc.veh_id, np.uint32), arr(sc.depart, np.int32),
+                        arr(sc.v0, np.float32), arr(sc.route_off, np.int64),
+                        arr(sc.route_roads, np.int32), arr(sc.placed, np.uint8),
+                        arr(sc.lane, np.int32), arr(sc.cursor, np.int32), arr(sc.s, np.float32),
+                        arr(sc.v, np.float32), arr(sc.a, np.float32))
+    p = sc.params
+    prm = moss_params(p["dt"], p["a_max"], p["b"], p["s0"], p["T"], p["length"], p["b_max"],
+                      p["b_safe"], p["politeness"], p["a_thr"], p["p_lc"], p["d_look"],
+                      int(p["h_look"]), int(p["t0"]), int(p["seed"]),
+                      MOSS_FLAG_DEBUG if debug else 0)
+    return net, sig, veh, prm, keep
+
+
+def moss_query_workspace(net, sig, veh, prm) -> int:
+    n = C.c_size_t(0)
+    _check(load().moss_query_workspace(C.byref(net), C.byref(sig), C.byref(veh), C.byref(prm),
+                                       C.byref(n)))
+    return int(n.value)
+
+
+def moss_create(net, sig, veh, prm, ws_ptr: int, ws_bytes: int, stream: int) -> int:
+    h = vp()
+    _check(load().moss_create(C.byref(net), C.byref(sig), C.byref(veh), C.byref(prm),
+                              vp(ws_ptr), ws_bytes, vp(stream), C.byref(h)))
+    return h.value
+
+
+def moss_step(h: int, n: int):
+    _check(load().moss_step(vp(h), int(n)))
+
+
+def moss_read_state(h: int, out: moss_state_out):
+    _check(load().moss_read_state(vp(h), C.byref(out)))
+    return out
+
+
+def moss_read_counters(h: int, n_scen: int):
+    cnt = np.zeros((n_scen, len(COUNTER_NAMES)), np.int64)
+    sv = np.zeros(n_scen, np.float64)
+    err = C.c_uint32(0)
+    _check(load().moss_read_counters(vp(h), _ptr(cnt), _ptr(sv), C.byref(err)))
+    return cnt, sv, int(err.value)
+
+
+def moss_read_debug(h: int, capacity: int):
+    d = dict(id=np.empty(capacity, np.uint32), leader=np.empty(capacity, np.uint32),
+             flags=np.empty(capacity, np.int32), margin=np.empty(capacity, np.float32),
+             t_leader=np.empty(capacity, np.uint32), t_follower=np.empty(capacity, np.uint32))
+    n = C.c_int32(0)
+    _check(load().moss_read_debug(vp(h), capacity, _ptr(d["id"]), _ptr(d["leader"]),
+                                  _ptr(d["flags"]), _ptr(d["margin"]), _ptr(d["t_leader"]),
+                                  _ptr(d["t_follower"]), C.byref(n)))
+    return {k: v[:n.value].copy() for k, v in d.items()}
+
+
+def moss_step_timed(h: int, n: int):
+    """Runs n steps; returns {kernel name: total milliseconds over the n steps}."""
+    ms = np.zeros(32, np.float64)
+    k = C.c_int32(0)
+    _check(load().moss_step_timed(vp(h), int(n), _ptr(ms), 32, C.byref(k)))
+    return {load().moss_kernel_name(i).decode(): float(ms[i]) for i in range(k.value)}
+
+
+def moss_destroy(h: int):
+    _check(load().moss_destroy(vp(h)))
+
+
+def moss_last_error() -> str:
+    return load().moss_last_error().decode()
+
+
+class Simulator:
+    """A simulation of one Scenario on the current torch device and stream."""
+
+    def __init__(self, sc, *, debug: bool = False, device: Optional[int] = None, stream=None):
+        import torch
+        load()
+        self.sc = sc
+        self.n_scen = sc.n_scen
+        self.cap = max(sc.n_veh, 1)
+        net, sig, veh, prm, keep = marshal(sc, debug)
+        nbytes = moss_query_workspace(net, sig, veh, prm)
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.h = moss_create(net, sig, veh, prm, aligned, nbytes, self.stream.cuda_stream)
+        self.debug_enabled = debug
+        del keep
+
+    def step(self, n: int = 1):
+        moss_step(self.h, n)
+
+    def state(self, cursor: bool = True) -> Dict[str, np.ndarray]:
+        c = self.cap
+        out = dict(id=np.empty(c, np.uint32), lane=np.empty(c, np.int32),
+                   s=np.empty(c, np.float32), v=np.empty(c, np.float32),
+                   a=np.empty(c, np.float32), cursor=np.empty(c, np.int32))
+        so = moss_state_out(c, 0, _ptr(out["id"]), _ptr(out["lane"]), _ptr(out["s"]),
+                            _ptr(out["v"]), _ptr(out["a"]),
+                            _ptr(out["cursor"]) if cursor else None, 0, 0)
+        moss_read_state(self.h, so)
+        self.t = int(so.t)
+        n = int(so.n)
+        res = {k: v[:n].copy() for k, v in out.items()}
+        if not cursor:
+            res.pop("cursor")
+        return res
+
+    def state_device(self):
+        """State rows as torch tensors on the simulator's device (device copy)."""
+        import torch
+        c = self.cap
+        dev = self.ws.device
+        out = dict(id=torch.empty(c, dtype=torch.int32, device=dev),
+                   lane=torch.empty(c, dtype=torch.int32, device=dev),
+                   s=torch.empty(c, dtype=torch.float32, device=dev),
+                   v=torch.empty(c, dtype=torch.float32, device=dev),
+                   a=torch.empty(c, dtype=torch.float32, device=dev))
+        so = moss_state_out(c, 1, vp(out["id"].data_ptr()), vp(out["lane"].data_ptr()),
+                            vp(out["s"].data_ptr()), vp(out["v"].data_ptr()),
+                            vp(out["a"].data_ptr()), None, 0, 0)
+        moss_read_state(self.h, so)
+        n = int(so.n)
+        return {k: v[:n] for k, v in out.items()}
+
+    @property
+    def n_active(self) -> int:
+        so = moss_state_out(0, 0, None, None, None, None, None, None, 0, 0)
+        try:
+            moss_read_state(self.h, so)
+        except MossError as e:
+            if e.code != MOSS_ENOMEM:
+                raise
+        return int(so.n)
+
+    def counters(self):
+        return moss_read_counters(self.h, self.n_scen)
+
+    def step_timed(self, n: int):
+        return moss_step_timed(self.h, n)
+
+    def debug(self):
+        return moss_read_debug(self.h, self.cap)
+
+    def close(self):
+        if getattr(self, "h", None):
+            moss_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
