@@ -46,8 +46,8 @@ struct Layout {
     int64_t n_route;
     bool debug;
     size_t total;
-    size_t S[8], Pr[8], ls[2], tails, scount, jcount, joff, blk, jrank, jlist, jidx, scal, lanes,
-        roads, sigs, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
+    size_t S[8], Pr[8], ls[2], tails, leave, jcount, joff, blk, jrank, jlist, jidx, scal, lanes,
+        roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor;
 
     void plan()
@@ -63,7 +63,7 @@ struct Layout {
         for (auto &x : Pr) x = take(4 * c);
         for (auto &x : ls) x = take(4 * ((size_t)n_lanes + 1));
         tails = take(sizeof(Tail) * (size_t)n_lanes);
-        scount = take(4 * (size_t)n_lanes);
+        leave = take(4 * (size_t)n_lanes);
         jcount = take(4 * (size_t)n_lanes);
         joff = take(4 * ((size_t)n_lanes + 1));
         blk = take(8 * (size_t)nblk);
@@ -73,7 +73,6 @@ struct Layout {
         scal = take(64);
         lanes = take(sizeof(LaneInfo) * (size_t)n_lanes);
         roads = take(sizeof(RoadInfo) * (size_t)n_roads);
-        sigs = take(sizeof(SigInfo) * (size_t)n_roads);
         route = take(4 * ((size_t)n_route + (size_t)n_veh + 1));
         qlanes = take(4 * (size_t)n_qlanes);
         q_head = take(4 * (size_t)n_lanes);
@@ -143,6 +142,8 @@ int validate(const moss_network *net, const moss_signals *sig, const moss_vehicl
             return fail(MOSS_EINVAL, "node %d: negative cycle", j);
         if (sig->node_cycle[j] > 0 && (sig->node_phase[j] <= 0 || sig->node_offset[j] < 0))
             return fail(MOSS_EINVAL, "node %d: phase must be > 0 and offset >= 0", j);
+        if (sig->node_cycle[j] > 65535 || sig->node_phase[j] > 65535)
+            return fail(MOSS_EINVAL, "node %d: cycle and phase must be < 65536 steps", j);
     }
     const moss_params &p = *prm;
     const float pos[] = {p.dt, p.a_max, p.b, p.length, p.b_max};
@@ -210,7 +211,51 @@ struct moss_sim {
     int32_t n_scen;
     uint32_t err_seen;
     char *ws;
+    // captured step loops: kGraphSteps steps starting at lane-start parity p
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool graphs_ok = true;
 };
+
+static Dev step_dev(const moss_sim *h, int parity);
+
+// Steps per captured graph (even, so a replay returns to the same parity).
+static constexpr int32_t kGraphSteps = 16;
+
+static void drop_graphs(moss_sim *h)
+{
+    for (auto &g : h->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Captures kGraphSteps steps on the simulator's stream into an executable
+// graph.  The kernels read the step index and vehicle counts from device
+// memory, so one graph serves every replay.
+static hipError_t capture_graph(moss_sim *h, int parity, hipGraphExec_t *out)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return e;
+    int p = parity;
+    hipError_t le = hipSuccess;
+    for (int32_t k = 0; k < kGraphSteps && le == hipSuccess; ++k) {
+        le = launch_step(step_dev(h, p), h->stream);
+        p ^= 1;
+    }
+    e = hipStreamEndCapture(h->stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess)
+        return e;
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
 
 static void fill_dev(moss_sim *h)
 {
@@ -239,10 +284,9 @@ static void fill_dev(moss_sim *h)
     d.n_qlanes = L.n_qlanes;
     d.lanes = (const LaneInfo *)(w + L.lanes);
     d.roads = (const RoadInfo *)(w + L.roads);
-    d.sigs = (const SigInfo *)(w + L.sigs);
     d.route = I(L.route);
     d.tails = (Tail *)(w + L.tails);
-    d.scount = I(L.scount);
+    d.leave = I(L.leave);
     d.jcount = I(L.jcount);
     d.joff = I(L.joff);
     d.blk = I(L.blk);
@@ -364,25 +408,26 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     // --- static tables
     std::vector<LaneInfo> lanes(NL);
     std::vector<RoadInfo> roads(NR);
-    std::vector<SigInfo> sigs(NR);
     for (int32_t r = 0; r < NR; ++r) {
         roads[r] = {net->road_lane0[r], net->road_nlanes[r], net->road_length[r], 0};
         int32_t j = net->road_to[r];
         int8_t g = sig->road_group[r];
         bool signalised = g >= 0 && sig->node_cycle[j] > 0;
-        sigs[r] = {signalised ? sig->node_cycle[j] : 1, signalised ? sig->node_phase[j] : 1,
-                   signalised ? sig->node_offset[j] : 0, (int32_t)g};
         for (int32_t k = 0; k < net->road_nlanes[r]; ++k) {
             int32_t l = net->road_lane0[r] + k;
             LaneInfo &li = lanes[l];
+            std::memset(&li, 0, sizeof li);
             li.L = net->road_length[r];
             li.vlim = net->lane_vlim[l];
-            li.road = r;
             li.lane0 = net->road_lane0[r];
-            li.k = k;
-            li.nlanes = net->road_nlanes[r];
             li.scen = net->lane_scen ? net->lane_scen[l] : 0;
-            li.sig = signalised ? r : -1;
+            li.k = (uint8_t)k;
+            li.nlanes = (uint8_t)net->road_nlanes[r];
+            li.group = signalised ? g : (int8_t)-1;
+            li.cycle = (uint16_t)(signalised ? sig->node_cycle[j] : 1);
+            li.phase = (uint16_t)(signalised ? sig->node_phase[j] : 1);
+            li.offset = (uint16_t)(signalised ? sig->node_offset[j] % sig->node_cycle[j] : 0);
+            li.road = r;
         }
     }
 
@@ -533,7 +578,6 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     chk(up(L.scal, scal, sizeof scal));
     chk(up(L.lanes, lanes.data(), sizeof(LaneInfo) * NL));
     chk(up(L.roads, roads.data(), sizeof(RoadInfo) * NR));
-    chk(up(L.sigs, sigs.data(), sizeof(SigInfo) * NR));
     chk(up(L.route, route.data(), 4 * route.size()));
     chk(up(L.qlanes, qlanes.data(), 4 * qlanes.size()));
     chk(up(L.q_head, qhead.data(), 4 * (size_t)NL));
@@ -570,7 +614,21 @@ int moss_step(moss_sim *h, int32_t n)
     if (h->t + n >= (int64_t)1 << 31)
         return fail(MOSS_EINVAL, "step index would exceed 2^31");
     HIP_TRY(hipSetDevice(h->device));
-    for (int32_t k = 0; k < n; ++k) {
+    int32_t left = n;
+    // whole graphs first (not on the legacy null stream, which cannot capture)
+    while (left >= kGraphSteps && h->graphs_ok && h->stream != nullptr) {
+        hipGraphExec_t &g = h->graph[h->parity];
+        if (!g && capture_graph(h, h->parity, &g) != hipSuccess) {
+            (void)hipGetLastError();
+            g = nullptr;
+            h->graphs_ok = false;
+            break;
+        }
+        HIP_TRY(hipGraphLaunch(g, h->stream));
+        left -= kGraphSteps;
+        h->t += kGraphSteps;
+    }
+    for (; left > 0; --left) {
         HIP_TRY(launch_step(step_dev(h, h->parity), h->stream));
         h->parity ^= 1;
         h->t += 1;
@@ -724,6 +782,7 @@ int moss_destroy(moss_sim *h)
     if (h->device >= 0) {
         (void)hipSetDevice(h->device);
         (void)hipStreamSynchronize(h->stream);
+        drop_graphs(h);
     }
     delete h;
     return MOSS_OK;

@@ -17,16 +17,20 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;      // "no vehicle" id
 constexpr uint32_t kJoinBit = 0x80000000u;   // proposal lane: vehicle joins another lane
 constexpr uint32_t kArrived = 0xFFFFFFFFu;   // proposal lane: vehicle left the network
 
-// Per-lane constants, 32 bytes, read with one broadcast load per lane.
+// Per-lane constants, 32 bytes, read with one broadcast load per lane.  The
+// fixed-time plan of the downstream junction is folded in (group < 0: the
+// lane's road never waits for a signal).
 struct LaneInfo {
     float L;            // road length
     float vlim;         // speed limit
-    int32_t road;
     int32_t lane0;      // first lane of the road
-    int32_t k;          // index in the road
-    int32_t nlanes;
     int32_t scen;       // scenario of the lane
-    int32_t sig;        // signal of the downstream junction: -1 none, else index into SigInfo
+    uint8_t k;          // index in the road
+    uint8_t nlanes;
+    int8_t group;       // signal group of the road at its downstream node, -1 none
+    uint8_t pad0;
+    uint16_t cycle, phase, offset, pad1;   // plan of the downstream node (offset < cycle)
+    int32_t road;
 };
 
 // Per-road constants used when following a route.
@@ -35,11 +39,6 @@ struct RoadInfo {
     int32_t nlanes;
     float L;
     int32_t pad;
-};
-
-// Fixed-time plan seen by one in-road: cycle, phase length, offset, group.
-struct SigInfo {
-    int32_t cycle, phase, offset, group;
 };
 
 // Last vehicle (lowest position) of each lane; id == kNone when empty.
@@ -73,14 +72,13 @@ struct Dev {
     int32_t n_lanes, n_scen, cap, n_qlanes;
     const LaneInfo *lanes;
     const RoadInfo *roads;
-    const SigInfo *sigs;
     const int32_t *route;         // routes, each followed by -1
     SoA S;                        // state at the start of a step
     SoA Pr;                       // proposals, indexed by row at step start (+ insertions)
     const int32_t *ls_old;        // lane_start of the state being read
     int32_t *ls_new;              // lane_start being built
     Tail *tails;
-    int32_t *scount, *jcount;     // stayers / joiners per lane (zeroed by the scan)
+    int32_t *leave, *jcount;      // vehicles leaving / joining each lane (zeroed by the scan)
     int32_t *joff;                // exclusive scan of jcount
     int32_t *blk;                 // scan block sums
     uint32_t *jrank, *jlist, *jidx;

@@ -170,191 +170,315 @@ __global__ void k_insert(Dev d)
 
 // ----------------------------------------------------------------- update --
 
-__global__ void __launch_bounds__(256) k_update(Dev d)
+constexpr int kUT = 256;               // rows per update block
+constexpr int kUH = 96;                // rows staged before and after them
+constexpr int kUW = kUT + 2 * kUH;
+
+__device__ __forceinline__ int lds_lower_bound_u32(const uint32_t *a, int lo, int hi, uint32_t x)
 {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int hi, float x)
+{
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] >= x)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Wave-aggregated slot allocation: every lane with pred gets a distinct
+// index from *ctr; one atomic per wave.
+__device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool pred)
+{
+    const unsigned long long m = __ballot(pred);
+    if (m == 0)
+        return 0;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader)
+        base = atomicAdd(ctr, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    return base + (uint32_t)__popcll(m & lt);
+}
+
+// Wave-aggregated counter increment (counters of one scenario per wave are
+// the common case; other waves fall back to one atomic per lane).
+__device__ __forceinline__ void wave_count(unsigned long long *c, bool pred, int scen,
+                                           int scen0, bool uniform)
+{
+    if (uniform) {
+        const unsigned long long m = __ballot(pred);
+        if (m && __lane_id() == __ffsll((long long)m) - 1)
+            atomicAdd(c + (size_t)scen0 * C_N, (unsigned long long)__popcll(m));
+    } else if (pred) {
+        atomicAdd(c + (size_t)scen * C_N, 1ull);
+    }
+}
+
+// Update phase for kUT rows per block.  The block stages the rows around its
+// own (s, v, v0, id, lane of rows [base-kUH, base+kUT+kUH)) in LDS; in-lane
+// neighbours are the adjacent rows and the target lane of a lane change is
+// found by binary search in that window, falling back to global memory when
+// the lane does not fit in it.
+__global__ void __launch_bounds__(kUT) k_update(Dev d)
+{
+    __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
+    __shared__ uint32_t w_id[kUW], w_ln[kUW];
+
     const int n = *d.n_cur;
     const int64_t t = *d.t;
     const Params &P = d.P;
     const uint32_t tt = (uint32_t)t;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t l = d.S.lane[i];
+    const int tid = threadIdx.x;
+
+    for (int base = blockIdx.x * kUT; base < n; base += gridDim.x * kUT) {
+        const int ws = max(base - kUH, 0), we = min(base + kUT + kUH, n);
+        const int i = base + tid;
+        const bool act = i < n;
+        uint32_t ptr = 0;
+        int32_t nxt = -1;
+        if (act) {
+            ptr = d.S.ptr[i];
+            nxt = d.S.next[i];
+        }
+        __syncthreads();
+        for (int r = ws + tid; r < we; r += kUT) {
+            w_s[r - ws] = d.S.s[r];
+            w_v[r - ws] = d.S.v[r];
+            w_v0[r - ws] = d.S.v0[r];
+            w_id[r - ws] = d.S.id[r];
+            w_ln[r - ws] = d.S.lane[r];
+        }
+        __syncthreads();
+
+        const int x_i = i - ws;
+        const uint32_t l = act ? w_ln[x_i] : 0u;
         const LaneInfo li = d.lanes[l];
-        const float s = d.S.s[i], v = d.S.v[i];
-        const uint32_t id = d.S.id[i], ptr = d.S.ptr[i];
-        const int32_t nxt = d.S.next[i];
-        const float v0 = d.S.v0[i];
-        const int lo = d.ls_old[l], hi = d.ls_old[l + 1];
-        const float L = li.L;
-        int32_t flags = 0;
-        float margin = 0.0f;
-        uint32_t tl_id = kNone, tf_id = kNone;
-
-        // red light at the stop line, applied if the vehicle can still stop
-        bool red = false;
-        if (nxt >= 0 && li.sig >= 0) {
-            SigInfo g = d.sigs[li.sig];
-            uint32_t ph = ((tt + (uint32_t)g.offset) % (uint32_t)g.cycle) / (uint32_t)g.phase;
-            if ((int)ph != g.group) {
-                float stop_dist = (v * v) / (2.0f * P.b_max);
-                if (L - s >= stop_dist)
-                    red = true;
-            }
-        }
-
-        const int Lc = (i + 1 < hi) ? i + 1 : -1;
-        const int o = (i - 1 >= lo) ? i - 1 : -1;
-
-        // randomised MOBIL on one side per step (even: k-1, odd: k+1)
-        bool change = false;
-        int lt = -1, Lt = -1, nb = -1;
-        if (s >= 0.0f) {
-            int kt = ((t & 1) == 0) ? li.k - 1 : li.k + 1;
-            if (kt >= 0 && kt < li.nlanes) {
-                lt = li.lane0 + kt;
-                const int a0 = d.ls_old[lt], a1 = d.ls_old[lt + 1];
-                int lo2 = a0, hi2 = a1;
-                while (lo2 < hi2) {
-                    int mid = (lo2 + hi2) >> 1;
-                    if (d.S.s[mid] >= s)
-                        hi2 = mid;
-                    else
-                        lo2 = mid + 1;
-                }
-                Lt = lo2 < a1 ? lo2 : -1;
-                nb = lo2 - 1 >= a0 ? lo2 - 1 : -1;
-                const float vlim_c = li.vlim, vlim_t = d.lanes[lt].vlim;
-                const float v0e_c = fmin32(v0, vlim_c), v0e_t = fmin32(v0, vlim_t);
-                float sLc = 0.0f, vLc = 0.0f, sLt = 0.0f, vLt = 0.0f;
-                if (Lc >= 0) { sLc = d.S.s[Lc]; vLc = d.S.v[Lc]; }
-                if (Lt >= 0) { sLt = d.S.s[Lt]; vLt = d.S.v[Lt]; }
-                float a_c = Lc >= 0 ? idm(P, v, v0e_c, true, vLc, (sLc - P.len) - s)
-                                    : idm(P, v, v0e_c, false, 0.0f, 0.0f);
-                float at_c = Lt >= 0 ? idm(P, v, v0e_t, true, vLt, (sLt - P.len) - s)
-                                     : idm(P, v, v0e_t, false, 0.0f, 0.0f);
-                float d_o = 0.0f, d_n = 0.0f;
-                bool safe = true;
-                if (o >= 0) {
-                    const float vo = d.S.v[o], so = d.S.s[o];
-                    const float v0e_o = fmin32(d.S.v0[o], vlim_c);
-                    float a_o = idm(P, vo, v0e_o, true, v, (s - P.len) - so);
-                    float at_o = Lc >= 0 ? idm(P, vo, v0e_o, true, vLc, (sLc - P.len) - so)
-                                         : idm(P, vo, v0e_o, false, 0.0f, 0.0f);
-                    d_o = at_o - a_o;
-                }
-                if (nb >= 0) {
-                    const float vn = d.S.v[nb], sn = d.S.s[nb];
-                    const float v0e_n = fmin32(d.S.v0[nb], vlim_t);
-                    float a_n = Lt >= 0 ? idm(P, vn, v0e_n, true, vLt, (sLt - P.len) - sn)
-                                        : idm(P, vn, v0e_n, false, 0.0f, 0.0f);
-                    float at_n = idm(P, vn, v0e_n, true, v, (s - P.len) - sn);
-                    d_n = at_n - a_n;
-                    float gap_b = (s - P.len) - sn;
-                    if (!(gap_b > 0.0f)) safe = false;
-                    if (!(at_n >= -P.b_safe)) safe = false;
-                }
-                if (Lt >= 0) {
-                    float gap_f = (sLt - P.len) - s;
-                    if (!(gap_f > 0.0f)) safe = false;
-                }
-                float inc = (at_c - a_c) + P.pol * (d_n + d_o);
-                uint32_t x0 = philox_x0(tt, id, 0u, 0u, P.key0, P.key1);
-                float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
-                change = safe && inc > P.a_thr && u < P.p_lc;
-                margin = inc - P.a_thr;
-                flags |= change ? 2 : 1;
-                if (Lt >= 0) tl_id = d.S.id[Lt];
-                if (nb >= 0) tf_id = d.S.id[nb];
-            }
-        }
-
-        // car-following in the final lane
-        const int lf = change ? lt : (int)l;
-        const LaneInfo lif = change ? d.lanes[lf] : li;
-        const int lead = change ? Lt : Lc;
-        Lead ld;
-        if (lead >= 0) {
-            ld.has = true;
-            ld.v = d.S.v[lead];
-            ld.gap = (d.S.s[lead] - P.len) - s;
-            ld.id = d.S.id[lead];
-        } else {
-            ld = lookahead(d, lif, s, id, ptr, nxt);
-            if (ld.has) flags |= 8;
-        }
-        const float v0e = fmin32(v0, lif.vlim);
-        float acc = idm(P, v, v0e, ld.has, ld.v, ld.gap);
-        if (red) {
-            float acc_red = idm(P, v, v0e, true, 0.0f, L - s);
-            acc = fmin32(acc, acc_red);
-            flags |= 4;
-        }
-        const float a = fmax32(-P.b_max, acc);
-
-        // Newton's equations over one step, stopping at v = 0
-        float vn = v + a * P.dt;
-        float dx;
-        if (vn < 0.0f) {
-            dx = -((v * v) / (2.0f * a));
-            vn = 0.0f;
-        } else {
-            dx = v * P.dt + (0.5f * a) * (P.dt * P.dt);
-        }
-        float sp = s + dx;
-
-        // transfer along the route, arrival at the end of the last road
-        int x = lf;
+        const int scen0 = __shfl(li.scen, 0);
+        const bool uni_scen = __all(!act || li.scen == scen0);
+        bool arrived = false, change = false, joins = false;
+        int x = 0;
         uint32_t p = ptr;
+        float sp = 0.0f, vn = 0.0f, a = 0.0f;
         int32_t nr = nxt;
-        int kk = lif.k;
-        float Lx = lif.L;
-        while (sp >= Lx && nr >= 0) {
-            sp = sp - Lx;
-            p += 1;
-            RoadInfo rd = d.roads[nr];
-            if (kk > rd.nlanes - 1)
-                kk = rd.nlanes - 1;
-            x = rd.lane0 + kk;
-            Lx = rd.L;
-            nr = d.route[p + 1];
-        }
-        const bool arrived = sp >= Lx;
-        if (!(isfinite(sp) && isfinite(vn)))
-            atomicOr(d.err, 2u);
+        uint32_t id = 0;
+        float v0 = 0.0f;
 
-        unsigned long long *c = d.cnt + (size_t)li.scen * C_N;
-        uint32_t plane;
-        if (arrived) {
-            plane = kArrived;
-            flags |= 16;
-            int vi = find_vehicle(d, id);
-            atomicAdd(c + C_ARRIVED, 1ull);
-            atomicAdd(c + C_TRIP_TIME, (unsigned long long)((t + 1) - (int64_t)d.vt_dep[vi]));
-        } else if (x == (int)l && p == ptr) {
-            plane = l;
-            atomicAdd(d.scount + l, 1);
-        } else {
-            plane = (uint32_t)x | kJoinBit;
-            d.jrank[i] = (uint32_t)atomicAdd(d.jcount + x, 1);
-            d.jlist[atomicAdd(d.n_join, 1u)] = (uint32_t)i;
+        if (act) {
+            const float s = w_s[x_i], v = w_v[x_i];
+            id = w_id[x_i];
+            v0 = w_v0[x_i];
+            const float L = li.L;
+            int32_t flags = 0;
+            float margin = 0.0f;
+            uint32_t tl_id = kNone, tf_id = kNone;
+
+            // red light at the stop line, applied if the vehicle can still stop
+            bool red = false;
+            if (nxt >= 0 && li.group >= 0) {
+                uint32_t ph = ((tt + (uint32_t)li.offset) % (uint32_t)li.cycle) / (uint32_t)li.phase;
+                if ((int)ph != (int)li.group) {
+                    float stop_dist = (v * v) / (2.0f * P.b_max);
+                    if (L - s >= stop_dist)
+                        red = true;
+                }
+            }
+
+            // in-lane neighbours are the adjacent rows
+            const bool hasLc = (i + 1 < n) && w_ln[x_i + 1] == l;
+            const bool hasO = (i >= 1) && w_ln[x_i - 1] == l;
+            float sLc = 0.0f, vLc = 0.0f;
+            if (hasLc) {
+                sLc = w_s[x_i + 1];
+                vLc = w_v[x_i + 1];
+            }
+
+            // randomised MOBIL on one side per step (even: k-1, odd: k+1)
+            int lt = -1;
+            bool hasLt = false, hasN = false;
+            float sLt = 0.0f, vLt = 0.0f;
+            uint32_t idLt = kNone;
+            if (s >= 0.0f) {
+                int kt = ((t & 1) == 0) ? (int)li.k - 1 : (int)li.k + 1;
+                if (kt >= 0 && kt < (int)li.nlanes) {
+                    lt = li.lane0 + kt;
+                    float sN = 0.0f, vN = 0.0f, v0N = 0.0f;
+                    uint32_t idN = kNone;
+                    int a0 = lds_lower_bound_u32(w_ln, 0, we - ws, (uint32_t)lt);
+                    int a1 = lds_lower_bound_u32(w_ln, a0, we - ws, (uint32_t)lt + 1u);
+                    const bool inside = (a0 > 0 || ws == 0) && (a1 < we - ws || we == n);
+                    if (inside) {
+                        const int j = lds_lower_bound_f32(w_s, a0, a1, s);
+                        if (j < a1) {
+                            hasLt = true; sLt = w_s[j]; vLt = w_v[j]; idLt = w_id[j];
+                        }
+                        if (j - 1 >= a0) {
+                            hasN = true; sN = w_s[j - 1]; vN = w_v[j - 1]; v0N = w_v0[j - 1];
+                            idN = w_id[j - 1];
+                        }
+                    } else {
+                        const int g0 = d.ls_old[lt], g1 = d.ls_old[lt + 1];
+                        int lo2 = g0, hi2 = g1;
+                        while (lo2 < hi2) {
+                            int mid = (lo2 + hi2) >> 1;
+                            if (d.S.s[mid] >= s)
+                                hi2 = mid;
+                            else
+                                lo2 = mid + 1;
+                        }
+                        if (lo2 < g1) {
+                            hasLt = true; sLt = d.S.s[lo2]; vLt = d.S.v[lo2]; idLt = d.S.id[lo2];
+                        }
+                        if (lo2 - 1 >= g0) {
+                            hasN = true; sN = d.S.s[lo2 - 1]; vN = d.S.v[lo2 - 1];
+                            v0N = d.S.v0[lo2 - 1]; idN = d.S.id[lo2 - 1];
+                        }
+                    }
+                    const float vlim_c = li.vlim, vlim_t = d.lanes[lt].vlim;
+                    const float v0e_c = fmin32(v0, vlim_c), v0e_t = fmin32(v0, vlim_t);
+                    float a_c = hasLc ? idm(P, v, v0e_c, true, vLc, (sLc - P.len) - s)
+                                      : idm(P, v, v0e_c, false, 0.0f, 0.0f);
+                    float at_c = hasLt ? idm(P, v, v0e_t, true, vLt, (sLt - P.len) - s)
+                                       : idm(P, v, v0e_t, false, 0.0f, 0.0f);
+                    float d_o = 0.0f, d_n = 0.0f;
+                    bool safe = true;
+                    if (hasO) {
+                        const float vo = w_v[x_i - 1], so = w_s[x_i - 1];
+                        const float v0e_o = fmin32(w_v0[x_i - 1], vlim_c);
+                        float a_o = idm(P, vo, v0e_o, true, v, (s - P.len) - so);
+                        float at_o = hasLc ? idm(P, vo, v0e_o, true, vLc, (sLc - P.len) - so)
+                                           : idm(P, vo, v0e_o, false, 0.0f, 0.0f);
+                        d_o = at_o - a_o;
+                    }
+                    if (hasN) {
+                        const float v0e_n = fmin32(v0N, vlim_t);
+                        float a_n = hasLt ? idm(P, vN, v0e_n, true, vLt, (sLt - P.len) - sN)
+                                          : idm(P, vN, v0e_n, false, 0.0f, 0.0f);
+                        float at_n = idm(P, vN, v0e_n, true, v, (s - P.len) - sN);
+                        d_n = at_n - a_n;
+                        float gap_b = (s - P.len) - sN;
+                        if (!(gap_b > 0.0f)) safe = false;
+                        if (!(at_n >= -P.b_safe)) safe = false;
+                    }
+                    if (hasLt) {
+                        float gap_f = (sLt - P.len) - s;
+                        if (!(gap_f > 0.0f)) safe = false;
+                    }
+                    float inc = (at_c - a_c) + P.pol * (d_n + d_o);
+                    uint32_t x0 = philox_x0(tt, id, 0u, 0u, P.key0, P.key1);
+                    float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
+                    change = safe && inc > P.a_thr && u < P.p_lc;
+                    margin = inc - P.a_thr;
+                    flags |= change ? 2 : 1;
+                    tl_id = idLt;
+                    tf_id = idN;
+                }
+            }
+
+            // car-following in the final lane
+            const int lf = change ? lt : (int)l;
+            const LaneInfo lif = change ? d.lanes[lf] : li;
+            Lead ld;
+            if (change ? hasLt : hasLc) {
+                ld.has = true;
+                ld.v = change ? vLt : vLc;
+                ld.gap = ((change ? sLt : sLc) - P.len) - s;
+                ld.id = change ? idLt : w_id[x_i + 1];
+            } else {
+                ld = lookahead(d, lif, s, id, ptr, nxt);
+                if (ld.has) flags |= 8;
+            }
+            const float v0e = fmin32(v0, lif.vlim);
+            float acc = idm(P, v, v0e, ld.has, ld.v, ld.gap);
+            if (red) {
+                float acc_red = idm(P, v, v0e, true, 0.0f, L - s);
+                acc = fmin32(acc, acc_red);
+                flags |= 4;
+            }
+            a = fmax32(-P.b_max, acc);
+
+            // Newton's equations over one step, stopping at v = 0
+            vn = v + a * P.dt;
+            float dx;
+            if (vn < 0.0f) {
+                dx = -((v * v) / (2.0f * a));
+                vn = 0.0f;
+            } else {
+                dx = v * P.dt + (0.5f * a) * (P.dt * P.dt);
+            }
+            sp = s + dx;
+
+            // transfer along the route, arrival at the end of the last road
+            x = lf;
+            int kk = lif.k;
+            float Lx = lif.L;
+            while (sp >= Lx && nr >= 0) {
+                sp = sp - Lx;
+                p += 1;
+                RoadInfo rd = d.roads[nr];
+                if (kk > rd.nlanes - 1)
+                    kk = rd.nlanes - 1;
+                x = rd.lane0 + kk;
+                Lx = rd.L;
+                nr = d.route[p + 1];
+            }
+            arrived = sp >= Lx;
+            joins = !arrived && !(x == (int)l && p == ptr);
+            if (!(isfinite(sp) && isfinite(vn)))
+                atomicOr(d.err, 2u);
+            if (arrived)
+                flags |= 16;
+            if (P.debug) {
+                d.d_id[i] = id;
+                d.d_leader[i] = ld.id;
+                d.d_flags[i] = flags;
+                d.d_margin[i] = margin;
+                d.d_tl[i] = tl_id;
+                d.d_tf[i] = tf_id;
+            }
         }
-        if (change)
-            atomicAdd(c + C_LANE_CHANGES, 1ull);
-        d.Pr.s[i] = sp;
-        d.Pr.v[i] = vn;
-        d.Pr.a[i] = a;
-        d.Pr.id[i] = id;
-        d.Pr.lane[i] = plane;
-        d.Pr.ptr[i] = p;
-        d.Pr.next[i] = nr;
-        d.Pr.v0[i] = v0;
-        if (P.debug) {
-            d.d_id[i] = id;
-            d.d_leader[i] = ld.id;
-            d.d_flags[i] = flags;
-            d.d_margin[i] = margin;
-            d.d_tl[i] = tl_id;
-            d.d_tf[i] = tf_id;
+
+        // bookkeeping: joiner slots, per-lane leave/join counts, counters
+        const uint32_t jslot = wave_alloc(d.n_join, joins);
+        if (act) {
+            uint32_t plane = (uint32_t)l;
+            if (arrived) {
+                plane = kArrived;
+                atomicAdd(d.leave + l, 1);
+                const int vi = find_vehicle(d, id);
+                atomicAdd(d.cnt + (size_t)li.scen * C_N + C_TRIP_TIME,
+                          (unsigned long long)((t + 1) - (int64_t)d.vt_dep[vi]));
+            } else if (joins) {
+                plane = (uint32_t)x | kJoinBit;
+                atomicAdd(d.leave + l, 1);
+                d.jrank[i] = (uint32_t)atomicAdd(d.jcount + x, 1);
+                d.jlist[jslot] = (uint32_t)i;
+            }
+            d.Pr.s[i] = sp;
+            d.Pr.v[i] = vn;
+            d.Pr.a[i] = a;
+            d.Pr.id[i] = id;
+            d.Pr.lane[i] = plane;
+            d.Pr.ptr[i] = p;
+            d.Pr.next[i] = nr;
+            d.Pr.v0[i] = v0;
         }
+        wave_count(d.cnt + C_ARRIVED, arrived, li.scen, scen0, uni_scen);
+        wave_count(d.cnt + C_LANE_CHANGES, change, li.scen, scen0, uni_scen);
     }
 }
 
@@ -396,7 +520,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Dev d)
         int l = base + q;
         if (l < d.n_lanes) {
             int j = d.jcount[l];
-            tot += d.scount[l] + j;
+            tot += (d.ls_old[l + 1] - d.ls_old[l]) - d.leave[l] + j;
             tj += j;
         }
     }
@@ -433,7 +557,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
         jc[q] = 0;
         if (l < d.n_lanes) {
             jc[q] = d.jcount[l];
-            cnt[q] = d.scount[l] + jc[q];
+            cnt[q] = (d.ls_old[l + 1] - d.ls_old[l]) - d.leave[l] + jc[q];
         }
         tot += cnt[q];
         tj += jc[q];
@@ -446,7 +570,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
         if (l < d.n_lanes) {
             d.ls_new[l] = run;
             d.joff[l] = runj;
-            d.scount[l] = 0;
+            d.leave[l] = 0;
             d.jcount[l] = 0;
         }
         run += cnt[q];
@@ -481,115 +605,314 @@ __device__ __forceinline__ bool key_less(const Dev &d, uint32_t a, uint32_t b)
     return d.Pr.id[a] < d.Pr.id[b];
 }
 
-// One thread per lane: stayers keep their order, joiners are sorted by
-// (s, id) and merged in, then overlaps are removed from the lane head
-// backwards (a follower is put one vehicle length behind its leader and
-// takes the leader's speed if faster).
-__global__ void __launch_bounds__(256) k_merge_lane(Dev d)
+__device__ __forceinline__ void write_row(const Dev &d, int w, uint32_t src, uint32_t lane, float s,
+                                          float v)
 {
-    __shared__ double s_sum[256];
-    __shared__ unsigned long long s_cnt[256], s_clamp[256];
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    double vsum = 0.0;
-    unsigned long long count = 0, clamps = 0;
-    if (l < d.n_lanes) {
-        const int o0 = d.ls_old[l], o1 = d.ls_old[l + 1];
-        const int j0 = d.joff[l], j1 = d.joff[l + 1];
-        const int w0 = d.ls_new[l], w1 = d.ls_new[l + 1];
-        for (int a = j0 + 1; a < j1; ++a) {
-            uint32_t xk = d.jidx[a];
-            int b = a - 1;
-            while (b >= j0 && key_less(d, xk, d.jidx[b])) {
-                d.jidx[b + 1] = d.jidx[b];
-                --b;
-            }
-            d.jidx[b + 1] = xk;
+    d.S.s[w] = s;
+    d.S.v[w] = v;
+    d.S.a[w] = d.Pr.a[src];
+    d.S.id[w] = d.Pr.id[src];
+    d.S.lane[w] = lane;
+    d.S.ptr[w] = d.Pr.ptr[src];
+    d.S.next[w] = d.Pr.next[src];
+    d.S.v0[w] = d.Pr.v0[src];
+}
+
+__device__ __forceinline__ void write_tail(const Dev &d, int l, bool any, float s, float v,
+                                           uint32_t id)
+{
+    Tail tl;
+    tl.pad = 0;
+    tl.s = any ? s : 0.0f;
+    tl.v = any ? v : 0.0f;
+    tl.id = any ? id : kNone;
+    d.tails[l] = tl;
+}
+
+// Merge of one lane straight from global memory (used for chunks too large
+// for the LDS tile): stayers keep their order, joiners are sorted by (s, id)
+// and merged in, then overlaps are removed from the lane head backwards.
+__device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned long long &clamps)
+{
+    vsum = 0.0;
+    clamps = 0;
+    const int o0 = d.ls_old[l], o1 = d.ls_old[l + 1];
+    const int j0 = d.joff[l], j1 = d.joff[l + 1];
+    const int w0 = d.ls_new[l], w1 = d.ls_new[l + 1];
+    for (int a = j0 + 1; a < j1; ++a) {
+        uint32_t xk = d.jidx[a];
+        int b = a - 1;
+        while (b >= j0 && key_less(d, xk, d.jidx[b])) {
+            d.jidx[b + 1] = d.jidx[b];
+            --b;
         }
-        int ip = o0, jp = j0, w = w0;
-        for (;;) {
-            while (ip < o1 && d.Pr.lane[ip] != (uint32_t)l)
-                ++ip;
-            const bool hs = ip < o1, hj = jp < j1;
-            if (!hs && !hj)
-                break;
-            if (w >= w1) {          // counts disagree with the scan: never write past the lane
-                atomicOr(d.err, 1u);
-                break;
-            }
-            uint32_t src;
-            if (hs && (!hj || key_less(d, (uint32_t)ip, d.jidx[jp])))
-                src = (uint32_t)ip++;
-            else
-                src = d.jidx[jp++];
-            d.S.s[w] = d.Pr.s[src];
-            d.S.v[w] = d.Pr.v[src];
-            d.S.a[w] = d.Pr.a[src];
-            d.S.id[w] = d.Pr.id[src];
-            d.S.lane[w] = (uint32_t)l;
-            d.S.ptr[w] = d.Pr.ptr[src];
-            d.S.next[w] = d.Pr.next[src];
-            d.S.v0[w] = d.Pr.v0[src];
-            ++w;
-        }
-        if (w != w1)
-            atomicOr(d.err, 1u);
-        for (int f = w1 - 2; f >= w0; --f) {
-            float lim = d.S.s[f + 1] - d.P.len;
-            if (d.S.s[f] > lim) {
-                d.S.s[f] = lim;
-                d.S.v[f] = fmin32(d.S.v[f], d.S.v[f + 1]);
-                ++clamps;
-            }
-        }
-        Tail tl;
-        tl.pad = 0;
-        if (w1 > w0) {
-            tl.s = d.S.s[w0];
-            tl.v = d.S.v[w0];
-            tl.id = d.S.id[w0];
-        } else {
-            tl.s = 0.0f;
-            tl.v = 0.0f;
-            tl.id = kNone;
-        }
-        d.tails[l] = tl;
-        for (int f = w0; f < w1; ++f)
-            vsum += (double)d.S.v[f];
-        count = (unsigned long long)(w1 - w0);
+        d.jidx[b + 1] = xk;
     }
-    // reduce per block when all its lanes belong to one scenario
-    const int lfirst = blockIdx.x * blockDim.x;
-    const int llast = min(lfirst + (int)blockDim.x, d.n_lanes) - 1;
-    const int sc0 = d.lanes[lfirst].scen;
-    if (sc0 == d.lanes[llast].scen) {
-        s_sum[threadIdx.x] = vsum;
-        s_cnt[threadIdx.x] = count;
-        s_clamp[threadIdx.x] = clamps;
+    int ip = o0, jp = j0, w = w0;
+    for (;;) {
+        while (ip < o1 && (d.Pr.lane[ip] & kJoinBit))
+            ++ip;
+        const bool hs = ip < o1, hj = jp < j1;
+        if (!hs && !hj)
+            break;
+        if (w >= w1) {          // counts disagree with the scan: never write past the lane
+            atomicOr(d.err, 1u);
+            break;
+        }
+        uint32_t src;
+        if (hs && (!hj || key_less(d, (uint32_t)ip, d.jidx[jp])))
+            src = (uint32_t)ip++;
+        else
+            src = d.jidx[jp++];
+        write_row(d, w, src, (uint32_t)l, d.Pr.s[src], d.Pr.v[src]);
+        ++w;
+    }
+    if (w != w1)
+        atomicOr(d.err, 1u);
+    for (int f = w1 - 2; f >= w0; --f) {
+        float lim = d.S.s[f + 1] - d.P.len;
+        if (d.S.s[f] > lim) {
+            d.S.s[f] = lim;
+            d.S.v[f] = fmin32(d.S.v[f], d.S.v[f + 1]);
+            ++clamps;
+        }
+    }
+    write_tail(d, l, w1 > w0, d.S.s[w0], d.S.v[w0], d.S.id[w0]);
+    for (int f = w0; f < w1; ++f)
+        vsum += (double)d.S.v[f];
+}
+
+constexpr int kMT = 256;          // threads per merge block
+constexpr int kMC = 2048;         // new rows per chunk
+constexpr int kOldCap = 3072;     // old rows staged per chunk
+constexpr int kNewCap = 3072;     // new rows staged per chunk
+constexpr int kJCap = 1024;       // joiners staged per chunk
+constexpr uint32_t kTagJ = 0x80000000u;
+constexpr uint32_t kSkip = 0xFFFFFFFFu;
+
+// Adds one lane's observables to the block totals, or straight to its
+// scenario's counters when the chunk spans several scenarios.
+__device__ __forceinline__ void lane_obs(const Dev &d, bool one_scen, int l, int count, double lsum,
+                                         unsigned long long lclamps, double &vsum,
+                                         unsigned long long &cnt, unsigned long long &clamps)
+{
+    if (one_scen) {
+        vsum += lsum;
+        cnt += (unsigned long long)count;
+        clamps += lclamps;
+        return;
+    }
+    unsigned long long *c = d.cnt + (size_t)d.lanes[l].scen * C_N;
+    if (count) {
+        atomicAdd(c + C_VEH_STEPS, (unsigned long long)count);
+        atomicAdd(d.sumv + d.lanes[l].scen, lsum);
+    }
+    if (lclamps)
+        atomicAdd(c + C_CLAMPS, lclamps);
+}
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int x)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Next state, one chunk of kMC new rows per block.  A block owns the lanes
+// whose first new row falls in its chunk; their old rows and joiners are
+// staged in LDS, one thread per lane merges and clamps in LDS, and the block
+// writes the new rows with coalesced stores.  Chunks that do not fit the LDS
+// tile take merge_lane_global.
+__global__ void __launch_bounds__(kMT) k_merge(Dev d)
+{
+    __shared__ float o_s[kOldCap], o_v[kOldCap];
+    __shared__ uint32_t o_pl[kOldCap];
+    __shared__ float j_s[kJCap], j_v[kJCap];
+    __shared__ uint32_t j_src[kJCap];
+    __shared__ uint32_t w_src[kNewCap];
+    __shared__ int sh_i[8];
+    __shared__ double red_d[kMT];
+    __shared__ unsigned long long red_c[kMT], red_k[kMT];
+
+    const int tid = threadIdx.x;
+    const int n_next = *d.n_next;
+    const int w = blockIdx.x;
+    if (w > n_next / kMC)
+        return;
+    if (tid == 0) {
+        int la = lower_bound_i32(d.ls_new, d.n_lanes, w * kMC);
+        int lb = lower_bound_i32(d.ls_new, d.n_lanes, (w + 1) * kMC);
+        sh_i[0] = la;
+        sh_i[1] = lb;
+        sh_i[2] = d.ls_new[la];
+        sh_i[3] = d.ls_new[lb];
+        sh_i[4] = d.ls_old[la];
+        sh_i[5] = d.ls_old[lb];
+        sh_i[6] = d.joff[la];
+        sh_i[7] = d.joff[lb];
+    }
+    __syncthreads();
+    const int la = sh_i[0], lb = sh_i[1];
+    const int n0 = sh_i[2], n1 = sh_i[3], o0 = sh_i[4], o1 = sh_i[5], j0 = sh_i[6], j1 = sh_i[7];
+    const float len = d.P.len;
+    const bool one_scen = (lb <= la) || d.lanes[la].scen == d.lanes[lb - 1].scen;
+    double vsum = 0.0;
+    unsigned long long clamps = 0, count = 0;
+
+    if (n1 - n0 > kNewCap || o1 - o0 > kOldCap || j1 - j0 > kJCap) {
+        for (int l = la + tid; l < lb; l += kMT) {
+            double ls;
+            unsigned long long lc;
+            merge_lane_global(d, l, ls, lc);
+            lane_obs(d, one_scen, l, d.ls_new[l + 1] - d.ls_new[l], ls, lc, vsum, count, clamps);
+        }
+    } else {
+        for (int r = o0 + tid; r < o1; r += kMT) {
+            o_s[r - o0] = d.Pr.s[r];
+            o_v[r - o0] = d.Pr.v[r];
+            o_pl[r - o0] = d.Pr.lane[r];
+        }
+        for (int e = j0 + tid; e < j1; e += kMT) {
+            uint32_t src = d.jidx[e];
+            j_src[e - j0] = src;
+            j_s[e - j0] = d.Pr.s[src];
+            j_v[e - j0] = d.Pr.v[src];
+        }
         __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
-            if (threadIdx.x < off) {
-                s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
-                s_cnt[threadIdx.x] += s_cnt[threadIdx.x + off];
-                s_clamp[threadIdx.x] += s_clamp[threadIdx.x + off];
+        for (int l = la + tid; l < lb; l += kMT) {
+            const int lo = d.ls_old[l] - o0, hi = d.ls_old[l + 1] - o0;
+            const int jl = d.joff[l] - j0, jh = d.joff[l + 1] - j0;
+            const int wl = d.ls_new[l] - n0, wh = d.ls_new[l + 1] - n0;
+            // joiners of the lane by (s, id)
+            for (int a = jl + 1; a < jh; ++a) {
+                const float xs = j_s[a], xv = j_v[a];
+                const uint32_t xsrc = j_src[a];
+                int b = a - 1;
+                while (b >= jl) {
+                    const float bs = j_s[b];
+                    bool gt = bs > xs || (bs == xs && d.Pr.id[j_src[b]] > d.Pr.id[xsrc]);
+                    if (!gt)
+                        break;
+                    j_s[b + 1] = bs;
+                    j_v[b + 1] = j_v[b];
+                    j_src[b + 1] = j_src[b];
+                    --b;
+                }
+                j_s[b + 1] = xs;
+                j_v[b + 1] = xv;
+                j_src[b + 1] = xsrc;
+            }
+            // merge: the smaller (s, id) key of the two heads goes first
+            int ip = lo, jp = jl, q = wl;
+            for (;;) {
+                while (ip < hi && (o_pl[ip] & kJoinBit))
+                    ++ip;
+                const bool hs = ip < hi, hj = jp < jh;
+                if (!hs && !hj)
+                    break;
+                if (q >= wh) {
+                    atomicOr(d.err, 1u);
+                    break;
+                }
+                bool take_s = hs;
+                if (hs && hj) {
+                    const float a_s = o_s[ip], b_s = j_s[jp];
+                    take_s = a_s < b_s ||
+                             (a_s == b_s && d.Pr.id[(uint32_t)(o0 + ip)] < d.Pr.id[j_src[jp]]);
+                }
+                if (take_s)
+                    w_src[q++] = (uint32_t)ip++;
+                else
+                    w_src[q++] = kTagJ | (uint32_t)jp++;
+            }
+            if (q != wh) {
+                atomicOr(d.err, 1u);
+                for (; q < wh; ++q)      // rows without a source are not written
+                    w_src[q] = kSkip;
+            }
+            // overlap removal from the lane head backwards, in place
+            double lsum = 0.0;
+            unsigned long long lc = 0;
+            if (wh > wl && w_src[wh - 1] != kSkip) {
+                uint32_t xl = w_src[wh - 1];
+                float sl = (xl & kTagJ) ? j_s[xl & ~kTagJ] : o_s[xl];
+                float vl = (xl & kTagJ) ? j_v[xl & ~kTagJ] : o_v[xl];
+                lsum = (double)vl;
+                int f = wh - 2;
+                for (; f >= wl; --f) {
+                    const uint32_t xf = w_src[f];
+                    if (xf == kSkip)
+                        break;
+                    const bool jf = (xf & kTagJ) != 0;
+                    const uint32_t kf = xf & ~kTagJ;
+                    float sf = jf ? j_s[kf] : o_s[kf];
+                    float vf = jf ? j_v[kf] : o_v[kf];
+                    const float lim = sl - len;
+                    if (sf > lim) {
+                        sf = lim;
+                        vf = fmin32(vf, vl);
+                        if (jf) { j_s[kf] = sf; j_v[kf] = vf; }
+                        else { o_s[kf] = sf; o_v[kf] = vf; }
+                        ++lc;
+                    }
+                    sl = sf;
+                    vl = vf;
+                    lsum += (double)vf;
+                }
+                xl = w_src[f + 1];
+                const uint32_t src = (xl & kTagJ) ? j_src[xl & ~kTagJ] : (uint32_t)(o0 + xl);
+                write_tail(d, l, true, sl, vl, d.Pr.id[src]);
+            } else {
+                write_tail(d, l, false, 0.0f, 0.0f, kNone);
+            }
+            lane_obs(d, one_scen, l, wh - wl, lsum, lc, vsum, count, clamps);
+        }
+        __syncthreads();
+        // coalesced write-out of the chunk's new rows
+        for (int k = n0 + tid; k < n1; k += kMT) {
+            const uint32_t x = w_src[k - n0];
+            if (x == kSkip)
+                continue;
+            if (x & kTagJ) {
+                const uint32_t e = x & ~kTagJ;
+                const uint32_t src = j_src[e];
+                write_row(d, k, src, d.Pr.lane[src] & ~kJoinBit, j_s[e], j_v[e]);
+            } else {
+                write_row(d, k, (uint32_t)o0 + x, o_pl[x], o_s[x], o_v[x]);
+            }
+        }
+    }
+
+    if (one_scen) {
+        red_d[tid] = vsum;
+        red_c[tid] = count;
+        red_k[tid] = clamps;
+        __syncthreads();
+        for (int off = kMT / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                red_d[tid] += red_d[tid + off];
+                red_c[tid] += red_c[tid + off];
+                red_k[tid] += red_k[tid + off];
             }
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            unsigned long long *c = d.cnt + (size_t)sc0 * C_N;
-            if (s_cnt[0]) atomicAdd(c + C_VEH_STEPS, s_cnt[0]);
-            if (s_clamp[0]) atomicAdd(c + C_CLAMPS, s_clamp[0]);
-            if (s_cnt[0]) atomicAdd(d.sumv + sc0, s_sum[0]);
+        if (tid == 0 && lb > la) {
+            const int sc = d.lanes[la].scen;
+            unsigned long long *c = d.cnt + (size_t)sc * C_N;
+            if (red_c[0]) atomicAdd(c + C_VEH_STEPS, red_c[0]);
+            if (red_k[0]) atomicAdd(c + C_CLAMPS, red_k[0]);
+            if (red_c[0]) atomicAdd(d.sumv + sc, red_d[0]);
         }
-    } else if (l < d.n_lanes) {
-        const int sc = d.lanes[l].scen;
-        unsigned long long *c = d.cnt + (size_t)sc * C_N;
-        if (count) atomicAdd(c + C_VEH_STEPS, count);
-        if (clamps) atomicAdd(c + C_CLAMPS, clamps);
-        if (count) atomicAdd(d.sumv + sc, vsum);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (w == 0 && tid == 0) {
         *d.n_dbg = *d.n_cur;
-        *d.n_cur = *d.n_next;
+        *d.n_cur = n_next;
         *d.n_ins = 0u;
         *d.n_join = 0u;
         *d.t = *d.t + 1;
@@ -634,7 +957,7 @@ static inline unsigned blocks_for(long long n, int per)
 }
 
 static const char *const kStepKernels[] = {"k_insert", "k_update", "k_scan_reduce",
-                                            "k_scan_apply", "k_jscatter", "k_merge_lane"};
+                                            "k_scan_apply", "k_jscatter", "k_merge"};
 
 int step_kernel_count() { return (int)(sizeof kStepKernels / sizeof kStepKernels[0]); }
 const char *step_kernel_name(int i)
@@ -666,7 +989,7 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     if (gj > 4096) gj = 4096;
     hipLaunchKernelGGL(k_jscatter, dim3(gj), dim3(256), 0, st, d);
     mark(5);
-    hipLaunchKernelGGL(k_merge_lane, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)(d.cap / kMC + 1)), dim3(kMT), 0, st, d);
     mark(6);
     return hipGetLastError();
 }

@@ -208,7 +208,9 @@ class Simulator:
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
         aligned = (base + 255) & ~255
-        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        # a stream of its own (default priority): the legacy null stream cannot
+        # capture the step graphs
+        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
         self.h = moss_create(net, sig, veh, prm, aligned, nbytes, self.stream.cuda_stream)
         self.debug_enabled = debug
         del keep

@@ -178,3 +178,21 @@ def test_city_snapshot_full_size(sim_cls):
     co, svo = o.counters()
     assert err == 0 and np.array_equal(cg, co)
     g.close()
+
+
+def test_graph_replay_matches_direct_steps(sim_cls):
+    """Steps enqueued through the captured step graphs (16 at a time) give
+    the same bits as steps launched one by one, replay after replay."""
+    sc = S.grid(10, 6000, horizon=600)
+    _say("graph vs direct")
+    a = sim_cls(sc)
+    b = sim_cls(sc)
+    for _ in range(6):
+        a.step(32)
+        for _ in range(32):
+            b.step(1)
+        sa, sb = a.state(), b.state()
+        for f in sa:
+            assert np.array_equal(sa[f], sb[f]), f
+    a.close()
+    b.close()
