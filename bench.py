@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="also copy a device buffer of this size once (calibrates the HBM "
+                         "byte counters of a profiler run against a known transfer)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -98,6 +101,14 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        say(f"[bench] copy probe: {args.copy_probe} bytes read and written")
+        del src, dst
     say(f"[bench] generating city snapshot with {args.vehicles} vehicles")
     t0 = time.time()
     sc = S.city_snapshot(args.vehicles)

@@ -46,7 +46,7 @@ struct Layout {
     int64_t n_route;
     bool debug;
     size_t total;
-    size_t S[8], Pr[8], ls[2], tails, leave, jcount, joff, blk, jrank, jlist, jidx, scal, lanes,
+    size_t S[8], Pr[8], ls[2], tails, chunk_lane, leave, jcount, joff, blk, jrank, jlist, jidx, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor;
 
@@ -64,6 +64,7 @@ struct Layout {
         for (auto &x : ls) x = take(4 * ((size_t)n_lanes + 1));
         tails = take(sizeof(Tail) * (size_t)n_lanes);
         leave = take(4 * (size_t)n_lanes);
+        chunk_lane = take(4 * ((size_t)c / kMergeRows + 3));
         jcount = take(4 * (size_t)n_lanes);
         joff = take(4 * ((size_t)n_lanes + 1));
         blk = take(8 * (size_t)nblk);
@@ -287,6 +288,7 @@ static void fill_dev(moss_sim *h)
     d.route = I(L.route);
     d.tails = (Tail *)(w + L.tails);
     d.leave = I(L.leave);
+    d.chunk_lane = I(L.chunk_lane);
     d.jcount = I(L.jcount);
     d.joff = I(L.joff);
     d.blk = I(L.blk);

@@ -81,6 +81,7 @@ struct Dev {
     int32_t *leave, *jcount;      // vehicles leaving / joining each lane (zeroed by the scan)
     int32_t *joff;                // exclusive scan of jcount
     int32_t *blk;                 // scan block sums
+    int32_t *chunk_lane;          // [cap / kMergeRows + 3]
     uint32_t *jrank, *jlist, *jidx;
     int32_t *n_cur, *n_next, *n_dbg;
     uint32_t *n_ins, *n_join;
@@ -108,6 +109,10 @@ struct Dev {
     int32_t *d_flags;
     float *d_margin;
 };
+
+// New rows per merge block; chunk_lane[w] is the first lane whose first new
+// row is >= w * kMergeRows (written by the lane-count scan).
+constexpr int kMergeRows = 2048;
 
 enum { C_INSERTED = 0, C_INSERT_FAIL, C_ARRIVED, C_TRIP_TIME, C_CLAMPS, C_LANE_CHANGES,
        C_VEH_STEPS, C_N };

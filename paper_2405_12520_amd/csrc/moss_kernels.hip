@@ -572,14 +572,21 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
             d.joff[l] = runj;
             d.leave[l] = 0;
             d.jcount[l] = 0;
+            // chunks whose first row lies in (start, end] of lane l begin at lane l+1
+            for (int w = run / kMergeRows + 1; w * kMergeRows <= run + cnt[q]; ++w)
+                d.chunk_lane[w] = l + 1;
         }
         run += cnt[q];
         runj += jc[q];
     }
+    if (b == 0 && threadIdx.x == 0)
+        d.chunk_lane[0] = 0;
     if (b == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
         d.ls_new[d.n_lanes] = run;
         d.joff[d.n_lanes] = runj;
         *d.n_next = run;
+        for (int w = run / kMergeRows + 1; w <= d.cap / kMergeRows + 1; ++w)
+            d.chunk_lane[w] = d.n_lanes;
     }
 }
 
@@ -683,7 +690,7 @@ __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned lo
 }
 
 constexpr int kMT = 256;          // threads per merge block
-constexpr int kMC = 2048;         // new rows per chunk
+constexpr int kMC = kMergeRows;   // new rows per chunk
 constexpr int kOldCap = 3072;     // old rows staged per chunk
 constexpr int kNewCap = 3072;     // new rows staged per chunk
 constexpr int kJCap = 1024;       // joiners staged per chunk
@@ -746,8 +753,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     if (w > n_next / kMC)
         return;
     if (tid == 0) {
-        int la = lower_bound_i32(d.ls_new, d.n_lanes, w * kMC);
-        int lb = lower_bound_i32(d.ls_new, d.n_lanes, (w + 1) * kMC);
+        const int la = d.chunk_lane[w], lb = d.chunk_lane[w + 1];
         sh_i[0] = la;
         sh_i[1] = lb;
         sh_i[2] = d.ls_new[la];
