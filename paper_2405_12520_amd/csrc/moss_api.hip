@@ -46,7 +46,7 @@ struct Layout {
     int64_t n_route;
     bool debug;
     size_t total;
-    size_t S[8], Pr[8], ls[2], tails, chunk_lane, leave, jcount, joff, blk, jrank, jlist, jidx, scal, lanes,
+    size_t S[8], Pr[8], ls[2], tails, chunk_lane, leave, jcount, joff, blk, jrank, jlist, jlane, jidx, jslane, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor;
 
@@ -70,11 +70,13 @@ struct Layout {
         blk = take(8 * (size_t)nblk);
         jrank = take(4 * c);
         jlist = take(4 * c);
+        jlane = take(4 * c);
         jidx = take(4 * c);
+        jslane = take(4 * c);
         scal = take(64);
         lanes = take(sizeof(LaneInfo) * (size_t)n_lanes);
         roads = take(sizeof(RoadInfo) * (size_t)n_roads);
-        route = take(4 * ((size_t)n_route + (size_t)n_veh + 1));
+        route = take(4 * ((size_t)n_route + 2 * (size_t)n_veh + 1));
         qlanes = take(4 * (size_t)n_qlanes);
         q_head = take(4 * (size_t)n_lanes);
         q_end = take(4 * (size_t)n_lanes);
@@ -294,7 +296,9 @@ static void fill_dev(moss_sim *h)
     d.blk = I(L.blk);
     d.jrank = U(L.jrank);
     d.jlist = U(L.jlist);
+    d.jlane = U(L.jlane);
     d.jidx = U(L.jidx);
+    d.jslane = U(L.jslane);
     int32_t *sc = I(L.scal);
     d.n_cur = sc + 0;
     d.n_next = sc + 1;
@@ -433,8 +437,8 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
         }
     }
 
-    // --- routes, each followed by -1
-    std::vector<int32_t> route((size_t)L.n_route + N + 1);
+    // --- routes, each followed by -1 and the vehicle's departure step
+    std::vector<int32_t> route((size_t)L.n_route + 2 * (size_t)N + 1);
     std::vector<uint32_t> rstart(N);
     {
         size_t w = 0;
@@ -443,6 +447,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
             for (int64_t k = veh->route_off[i]; k < veh->route_off[i + 1]; ++k)
                 route[w++] = veh->route_roads[k];
             route[w++] = -1;
+            route[w++] = veh->depart[i];
         }
         route[w] = -1;
     }

@@ -14,8 +14,7 @@
 namespace moss {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;      // "no vehicle" id
-constexpr uint32_t kJoinBit = 0x80000000u;   // proposal lane: vehicle joins another lane
-constexpr uint32_t kArrived = 0xFFFFFFFFu;   // proposal lane: vehicle left the network
+constexpr uint32_t kJoinBit = 0x80000000u;   // proposal lane: vehicle leaves its lane
 
 // Per-lane constants, 32 bytes, read with one broadcast load per lane.  The
 // fixed-time plan of the downstream junction is folded in (group < 0: the
@@ -52,7 +51,7 @@ struct Tail {
 struct SoA {
     float *s, *v, *a;
     uint32_t *id;
-    uint32_t *lane;     // in proposals: target lane | kJoinBit, or kArrived
+    uint32_t *lane;     // in proposals: lane at step start, | kJoinBit if the vehicle leaves it
     uint32_t *ptr;      // absolute index of the current road in the route array
     int32_t *next;      // next road of the route, -1 on the last road
     float *v0;
@@ -82,7 +81,10 @@ struct Dev {
     int32_t *joff;                // exclusive scan of jcount
     int32_t *blk;                 // scan block sums
     int32_t *chunk_lane;          // [cap / kMergeRows + 3]
-    uint32_t *jrank, *jlist, *jidx;
+    // joiners (lane changers, road transfers, insertions): slot e of this
+    // step holds source row jlist[e], target lane jlane[e] and rank jrank[e]
+    // among the lane's joiners; jidx/jslane list them grouped by lane
+    uint32_t *jrank, *jlist, *jlane, *jidx, *jslane;
     int32_t *n_cur, *n_next, *n_dbg;
     uint32_t *n_ins, *n_join;
     int64_t *t;
@@ -112,7 +114,7 @@ struct Dev {
 
 // New rows per merge block; chunk_lane[w] is the first lane whose first new
 // row is >= w * kMergeRows (written by the lane-count scan).
-constexpr int kMergeRows = 2048;
+constexpr int kMergeRows = 1024;
 
 enum { C_INSERTED = 0, C_INSERT_FAIL, C_ARRIVED, C_TRIP_TIME, C_CLAMPS, C_LANE_CHANGES,
        C_VEH_STEPS, C_N };

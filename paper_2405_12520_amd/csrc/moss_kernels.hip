@@ -71,20 +71,23 @@ struct Lead {
 // Leader beyond the lane end: follow the route for at most h_look roads while
 // the distance covered is within d_look; on each road take lane min(k, n-1)
 // and use its last vehicle (lane tail).  A vehicle never leads itself.
+// rd0 is the record of the next road nxt (already loaded by the caller).
 __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id, uint32_t ptr,
-                          int32_t nxt)
+                          int32_t nxt, RoadInfo rd0)
 {
     Lead r = {false, 0.0f, 0.0f, kNone};
     float dist = li.L - s;
     int kk = li.k;
     uint32_t p = ptr;
     int32_t nr = nxt;
+    RoadInfo rd = rd0;
     for (int h = 0; h < d.P.h_look; ++h) {
         if (nr < 0)
             break;
         if (dist > d.P.d_look)
             break;
-        RoadInfo rd = d.roads[nr];
+        if (h > 0)
+            rd = d.roads[nr];
         if (kk > rd.nlanes - 1)
             kk = rd.nlanes - 1;
         Tail tl = d.tails[rd.lane0 + kk];
@@ -104,17 +107,35 @@ __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id
     return r;
 }
 
-__device__ __forceinline__ int find_vehicle(const Dev &d, uint32_t id)
+// Wave-aggregated slot allocation: every lane with pred gets a distinct
+// index from *ctr; one atomic per wave.
+__device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool pred)
 {
-    int lo = 0, hi = d.n_veh;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (d.vt_id[mid] < id)
-            lo = mid + 1;
-        else
-            hi = mid;
+    const unsigned long long m = __ballot(pred);
+    if (m == 0)
+        return 0;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader)
+        base = atomicAdd(ctr, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    return base + (uint32_t)__popcll(m & lt);
+}
+
+// Wave-aggregated counter increment for waves whose vehicles are all in one
+// scenario (the common case); other waves use one atomic per lane.
+__device__ __forceinline__ void wave_count(unsigned long long *c, bool pred, int scen,
+                                           int scen0, bool uniform)
+{
+    if (uniform) {
+        const unsigned long long m = __ballot(pred);
+        if (m && __lane_id() == __ffsll((long long)m) - 1)
+            atomicAdd(c + (size_t)scen0 * C_N, (unsigned long long)__popcll(m));
+    } else if (pred) {
+        atomicAdd(c + (size_t)scen * C_N, 1ull);
     }
-    return lo;
 }
 
 // ----------------------------------------------------------------- insert --
@@ -153,7 +174,7 @@ __global__ void k_insert(Dev d)
         atomicAdd(c + C_INSERT_FAIL, 1ull);
         return;
     }
-    uint32_t slot = (uint32_t)(*d.n_cur) + atomicAdd(d.n_ins, 1u);
+    const uint32_t slot = (uint32_t)(*d.n_cur) + atomicAdd(d.n_ins, 1u);
     d.Pr.s[slot] = 0.0f;
     d.Pr.v[slot] = vins;
     d.Pr.a[slot] = 0.0f;
@@ -162,8 +183,10 @@ __global__ void k_insert(Dev d)
     d.Pr.ptr[slot] = d.q_ptr[h];
     d.Pr.next[slot] = d.q_next[h];
     d.Pr.v0[slot] = d.q_v0[h];
-    d.jrank[slot] = (uint32_t)atomicAdd(d.jcount + l, 1);
-    d.jlist[atomicAdd(d.n_join, 1u)] = slot;
+    const uint32_t e = atomicAdd(d.n_join, 1u);
+    d.jlist[e] = slot;
+    d.jlane[e] = (uint32_t)l;
+    d.jrank[e] = (uint32_t)atomicAdd(d.jcount + l, 1);
     d.q_head[l] = h + 1;
     atomicAdd(c + C_INSERTED, 1ull);
 }
@@ -198,42 +221,12 @@ __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int h
     return lo;
 }
 
-// Wave-aggregated slot allocation: every lane with pred gets a distinct
-// index from *ctr; one atomic per wave.
-__device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool pred)
-{
-    const unsigned long long m = __ballot(pred);
-    if (m == 0)
-        return 0;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader)
-        base = atomicAdd(ctr, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    return base + (uint32_t)__popcll(m & lt);
-}
-
-// Wave-aggregated counter increment (counters of one scenario per wave are
-// the common case; other waves fall back to one atomic per lane).
-__device__ __forceinline__ void wave_count(unsigned long long *c, bool pred, int scen,
-                                           int scen0, bool uniform)
-{
-    if (uniform) {
-        const unsigned long long m = __ballot(pred);
-        if (m && __lane_id() == __ffsll((long long)m) - 1)
-            atomicAdd(c + (size_t)scen0 * C_N, (unsigned long long)__popcll(m));
-    } else if (pred) {
-        atomicAdd(c + (size_t)scen * C_N, 1ull);
-    }
-}
-
 // Update phase for kUT rows per block.  The block stages the rows around its
 // own (s, v, v0, id, lane of rows [base-kUH, base+kUT+kUH)) in LDS; in-lane
 // neighbours are the adjacent rows and the target lane of a lane change is
 // found by binary search in that window, falling back to global memory when
-// the lane does not fit in it.
+// the lane does not fit in it.  Records needed later (the side lane, the next
+// road of lane heads) are loaded up front so that their latencies overlap.
 __global__ void __launch_bounds__(kUT) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
@@ -244,6 +237,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
     const Params &P = d.P;
     const uint32_t tt = (uint32_t)t;
     const int tid = threadIdx.x;
+    const int side = ((t & 1) == 0) ? -1 : 1;     // MOBIL looks at lane k-1 on even steps
 
     for (int base = blockIdx.x * kUT; base < n; base += gridDim.x * kUT) {
         const int ws = max(base - kUH, 0), we = min(base + kUT + kUH, n);
@@ -267,7 +261,18 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
 
         const int x_i = i - ws;
         const uint32_t l = act ? w_ln[x_i] : 0u;
+        const bool hasLc = act && (i + 1 < n) && w_ln[x_i + 1] == l;
+        // independent loads of the second round
         const LaneInfo li = d.lanes[l];
+        const int ls_side = (int)l + side;
+        const float vlim_side = (act && ls_side >= 0 && ls_side < d.n_lanes)
+                                    ? d.lanes[ls_side].vlim : 0.0f;
+        RoadInfo rd_next = {0, 1, 0.0f, 0};
+        bool rd_ok = false;       // rd_next holds roads[nxt]
+        if (act && !hasLc && nxt >= 0) {
+            rd_next = d.roads[nxt];
+            rd_ok = true;
+        }
         const int scen0 = __shfl(li.scen, 0);
         const bool uni_scen = __all(!act || li.scen == scen0);
         bool arrived = false, change = false, joins = false;
@@ -299,7 +304,6 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             }
 
             // in-lane neighbours are the adjacent rows
-            const bool hasLc = (i + 1 < n) && w_ln[x_i + 1] == l;
             const bool hasO = (i >= 1) && w_ln[x_i - 1] == l;
             float sLc = 0.0f, vLc = 0.0f;
             if (hasLc) {
@@ -313,9 +317,9 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             float sLt = 0.0f, vLt = 0.0f;
             uint32_t idLt = kNone;
             if (s >= 0.0f) {
-                int kt = ((t & 1) == 0) ? (int)li.k - 1 : (int)li.k + 1;
+                const int kt = (int)li.k + side;
                 if (kt >= 0 && kt < (int)li.nlanes) {
-                    lt = li.lane0 + kt;
+                    lt = ls_side;
                     float sN = 0.0f, vN = 0.0f, v0N = 0.0f;
                     uint32_t idN = kNone;
                     int a0 = lds_lower_bound_u32(w_ln, 0, we - ws, (uint32_t)lt);
@@ -348,7 +352,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                             v0N = d.S.v0[lo2 - 1]; idN = d.S.id[lo2 - 1];
                         }
                     }
-                    const float vlim_c = li.vlim, vlim_t = d.lanes[lt].vlim;
+                    const float vlim_c = li.vlim, vlim_t = vlim_side;
                     const float v0e_c = fmin32(v0, vlim_c), v0e_t = fmin32(v0, vlim_t);
                     float a_c = hasLc ? idm(P, v, v0e_c, true, vLc, (sLc - P.len) - s)
                                       : idm(P, v, v0e_c, false, 0.0f, 0.0f);
@@ -391,7 +395,11 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
 
             // car-following in the final lane
             const int lf = change ? lt : (int)l;
-            const LaneInfo lif = change ? d.lanes[lf] : li;
+            LaneInfo lif = li;
+            if (change) {
+                lif.vlim = vlim_side;
+                lif.k = (uint8_t)((int)li.k + side);
+            }
             Lead ld;
             if (change ? hasLt : hasLc) {
                 ld.has = true;
@@ -399,7 +407,11 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 ld.gap = ((change ? sLt : sLc) - P.len) - s;
                 ld.id = change ? idLt : w_id[x_i + 1];
             } else {
-                ld = lookahead(d, lif, s, id, ptr, nxt);
+                if (!rd_ok && nxt >= 0) {
+                    rd_next = d.roads[nxt];
+                    rd_ok = true;
+                }
+                ld = lookahead(d, lif, s, id, ptr, nxt, rd_next);
                 if (ld.has) flags |= 8;
             }
             const float v0e = fmin32(v0, lif.vlim);
@@ -426,10 +438,12 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             x = lf;
             int kk = lif.k;
             float Lx = lif.L;
+            bool first = true;
             while (sp >= Lx && nr >= 0) {
                 sp = sp - Lx;
                 p += 1;
-                RoadInfo rd = d.roads[nr];
+                const RoadInfo rd = (first && rd_ok) ? rd_next : d.roads[nr];
+                first = false;
                 if (kk > rd.nlanes - 1)
                     kk = rd.nlanes - 1;
                 x = rd.lane0 + kk;
@@ -455,24 +469,24 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
         // bookkeeping: joiner slots, per-lane leave/join counts, counters
         const uint32_t jslot = wave_alloc(d.n_join, joins);
         if (act) {
-            uint32_t plane = (uint32_t)l;
+            if (arrived || joins)
+                atomicAdd(d.leave + l, 1);
             if (arrived) {
-                plane = kArrived;
-                atomicAdd(d.leave + l, 1);
-                const int vi = find_vehicle(d, id);
+                // the route array stores the departure step after the -1 that
+                // ends the route
+                const int32_t dep = d.route[p + 2];
                 atomicAdd(d.cnt + (size_t)li.scen * C_N + C_TRIP_TIME,
-                          (unsigned long long)((t + 1) - (int64_t)d.vt_dep[vi]));
+                          (unsigned long long)((t + 1) - (int64_t)dep));
             } else if (joins) {
-                plane = (uint32_t)x | kJoinBit;
-                atomicAdd(d.leave + l, 1);
-                d.jrank[i] = (uint32_t)atomicAdd(d.jcount + x, 1);
                 d.jlist[jslot] = (uint32_t)i;
+                d.jlane[jslot] = (uint32_t)x;
+                d.jrank[jslot] = (uint32_t)atomicAdd(d.jcount + x, 1);
             }
             d.Pr.s[i] = sp;
             d.Pr.v[i] = vn;
             d.Pr.a[i] = a;
             d.Pr.id[i] = id;
-            d.Pr.lane[i] = plane;
+            d.Pr.lane[i] = l | ((arrived || joins) ? kJoinBit : 0u);
             d.Pr.ptr[i] = p;
             d.Pr.next[i] = nr;
             d.Pr.v0[i] = v0;
@@ -511,6 +525,13 @@ __device__ void block_scan2(int &x, int &y, int *sh)
     __syncthreads();
 }
 
+// new lane size = old size - vehicles leaving + vehicles joining
+__device__ __forceinline__ int new_count(const Dev &d, int l, int &j)
+{
+    j = d.jcount[l];
+    return (d.ls_old[l + 1] - d.ls_old[l]) - d.leave[l] + j;
+}
+
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Dev d)
 {
     __shared__ int sh[2 * kScanThreads];
@@ -519,8 +540,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Dev d)
     for (int q = 0; q < kScanPer; ++q) {
         int l = base + q;
         if (l < d.n_lanes) {
-            int j = d.jcount[l];
-            tot += (d.ls_old[l + 1] - d.ls_old[l]) - d.leave[l] + j;
+            int j;
+            tot += new_count(d, l, j);
             tj += j;
         }
     }
@@ -555,10 +576,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
         int l = base + q;
         cnt[q] = 0;
         jc[q] = 0;
-        if (l < d.n_lanes) {
-            jc[q] = d.jcount[l];
-            cnt[q] = (d.ls_old[l + 1] - d.ls_old[l]) - d.leave[l] + jc[q];
-        }
+        if (l < d.n_lanes)
+            cnt[q] = new_count(d, l, jc[q]);
         tot += cnt[q];
         tj += jc[q];
     }
@@ -595,14 +614,25 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
 __global__ void k_jscatter(Dev d)
 {
     const int n = (int)*d.n_join;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        uint32_t p = d.jlist[i];
-        uint32_t x = d.Pr.lane[p] & ~kJoinBit;
-        d.jidx[d.joff[x] + d.jrank[p]] = p;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const uint32_t x = d.jlane[e];
+        const int pos = d.joff[x] + (int)d.jrank[e];
+        d.jidx[pos] = d.jlist[e];
+        d.jslane[pos] = x;
     }
 }
 
 // ------------------------------------------------------------------ merge --
+//
+// The next order of lane l is the merge of its stayers (rows of l that stay,
+// in their old order) with its joiners (by (s, id)): walking both lists from
+// the tail, the smaller (s, id) key goes first.  Stayers need not be sorted by
+// their new positions, and the walk is then characterised by prefix maxima:
+// with pm_p the largest stayer key among stayers 0..p, stayer p is preceded by
+// exactly the joiners whose key is below pm_p, and a joiner by exactly the
+// stayers up to the first one with pm above its key.  k_merge evaluates those
+// counts in parallel; overlaps are then removed from the lane head backwards,
+// starting at the highest overlapping pair (rows above it keep their values).
 
 __device__ __forceinline__ bool key_less(const Dev &d, uint32_t a, uint32_t b)
 {
@@ -610,6 +640,15 @@ __device__ __forceinline__ bool key_less(const Dev &d, uint32_t a, uint32_t b)
     if (sa != sb)
         return sa < sb;
     return d.Pr.id[a] < d.Pr.id[b];
+}
+
+// (s, id) as one unsigned key with the order of the float comparison followed
+// by the id; -0 is first made +0 because the two compare equal.
+__device__ __forceinline__ uint64_t okey(float s, uint32_t id)
+{
+    uint32_t b = __float_as_uint(s + 0.0f);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((uint64_t)b << 32) | id;
 }
 
 __device__ __forceinline__ void write_row(const Dev &d, int w, uint32_t src, uint32_t lane, float s,
@@ -636,9 +675,8 @@ __device__ __forceinline__ void write_tail(const Dev &d, int l, bool any, float 
     d.tails[l] = tl;
 }
 
-// Merge of one lane straight from global memory (used for chunks too large
-// for the LDS tile): stayers keep their order, joiners are sorted by (s, id)
-// and merged in, then overlaps are removed from the lane head backwards.
+// Merge of one lane straight from global memory, walking both lists (used for
+// chunks too large for the LDS tile).
 __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned long long &clamps)
 {
     vsum = 0.0;
@@ -689,65 +727,73 @@ __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned lo
         vsum += (double)d.S.v[f];
 }
 
-constexpr int kMT = 256;          // threads per merge block
+constexpr int kMT = 256;          // threads per merge block (4 waves)
 constexpr int kMC = kMergeRows;   // new rows per chunk
-constexpr int kOldCap = 3072;     // old rows staged per chunk
-constexpr int kNewCap = 3072;     // new rows staged per chunk
-constexpr int kJCap = 1024;       // joiners staged per chunk
+constexpr int kOldCap = 1536;     // old rows staged per chunk
+constexpr int kNewCap = 1536;     // new rows staged per chunk
+constexpr int kJCap = 512;        // joiners staged per chunk
 constexpr uint32_t kTagJ = 0x80000000u;
-constexpr uint32_t kSkip = 0xFFFFFFFFu;
+constexpr uint32_t kNoSrc = 0xFFFFFFFFu;
 
-// Adds one lane's observables to the block totals, or straight to its
-// scenario's counters when the chunk spans several scenarios.
-__device__ __forceinline__ void lane_obs(const Dev &d, bool one_scen, int l, int count, double lsum,
-                                         unsigned long long lclamps, double &vsum,
-                                         unsigned long long &cnt, unsigned long long &clamps)
+// Segmented scan over one wave of old rows: inclusive prefix maximum of the
+// stayer keys and exclusive count of stayers, restarting at lane heads and
+// continuing from the carry when the wave's first rows continue a lane.
+__device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, uint64_t key,
+                                              uint64_t &c_pm, uint32_t &c_p, uint64_t &pm_out,
+                                              uint32_t &p_out)
 {
-    if (one_scen) {
-        vsum += lsum;
-        cnt += (unsigned long long)count;
-        clamps += lclamps;
-        return;
+    const int lane = __lane_id();
+    const unsigned long long hm = __ballot(valid && head);
+    const unsigned long long sm = __ballot(valid && st);
+    const unsigned long long upto = (lane == 63) ? hm : (hm & ((2ull << lane) - 1ull));
+    const int h = upto ? 63 - __clzll(upto) : -1;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const unsigned long long seg = (h < 0) ? below : (below & ~((1ull << h) - 1ull));
+    uint32_t p = (uint32_t)__popcll(sm & seg);
+    uint64_t v = (valid && st) ? key : 0ull;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t lo = __shfl_up((uint32_t)v, off), hi = __shfl_up((uint32_t)(v >> 32), off);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        if (lane >= off && lane - off >= h && o > v)
+            v = o;
     }
-    unsigned long long *c = d.cnt + (size_t)d.lanes[l].scen * C_N;
-    if (count) {
-        atomicAdd(c + C_VEH_STEPS, (unsigned long long)count);
-        atomicAdd(d.sumv + d.lanes[l].scen, lsum);
+    if (h < 0) {
+        p += c_p;
+        if (c_pm > v)
+            v = c_pm;
     }
-    if (lclamps)
-        atomicAdd(c + C_CLAMPS, lclamps);
-}
-
-__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int x)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < x)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
+    pm_out = v;
+    p_out = p;
+    // carry for the next wave of rows: the state after row 63
+    const uint64_t last_v = ((uint64_t)__shfl((uint32_t)(v >> 32), 63) << 32) |
+                            __shfl((uint32_t)v, 63);
+    const uint32_t last_p = __shfl(p, 63) + (uint32_t)((sm >> 63) & 1ull);
+    c_pm = last_v;
+    c_p = last_p;
 }
 
 // Next state, one chunk of kMC new rows per block.  A block owns the lanes
 // whose first new row falls in its chunk; their old rows and joiners are
-// staged in LDS, one thread per lane merges and clamps in LDS, and the block
-// writes the new rows with coalesced stores.  Chunks that do not fit the LDS
-// tile take merge_lane_global.
+// staged in LDS, positions are computed in parallel (see above), overlaps are
+// removed per lane, and the new rows are written with coalesced stores.
+// Chunks that do not fit the LDS tile take merge_lane_global.
 __global__ void __launch_bounds__(kMT) k_merge(Dev d)
 {
     __shared__ float o_s[kOldCap], o_v[kOldCap];
-    __shared__ uint32_t o_pl[kOldCap];
+    __shared__ uint32_t o_ln[kOldCap], o_id[kOldCap], o_p[kOldCap];
+    __shared__ uint32_t o_pmh[kOldCap], o_pml[kOldCap];
     __shared__ float j_s[kJCap], j_v[kJCap];
-    __shared__ uint32_t j_src[kJCap];
-    __shared__ uint32_t w_src[kNewCap];
+    __shared__ uint32_t j_src[kJCap], j_id[kJCap], j_ln[kJCap], j_kh[kJCap], j_kl[kJCap];
+    __shared__ uint32_t w_src[kNewCap], w_ln[kNewCap];
+    __shared__ int w_top[kNewCap];
     __shared__ int sh_i[8];
+    __shared__ int wave_start[5];
     __shared__ double red_d[kMT];
-    __shared__ unsigned long long red_c[kMT], red_k[kMT];
+    __shared__ unsigned long long red_k[kMT];
 
     const int tid = threadIdx.x;
+    const int lane = __lane_id();
+    const int wv = tid >> 6;
     const int n_next = *d.n_next;
     const int w = blockIdx.x;
     if (w > n_next / kMC)
@@ -766,144 +812,243 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     __syncthreads();
     const int la = sh_i[0], lb = sh_i[1];
     const int n0 = sh_i[2], n1 = sh_i[3], o0 = sh_i[4], o1 = sh_i[5], j0 = sh_i[6], j1 = sh_i[7];
+    const int no = o1 - o0, nw = n1 - n0, nj = j1 - j0;
     const float len = d.P.len;
     const bool one_scen = (lb <= la) || d.lanes[la].scen == d.lanes[lb - 1].scen;
     double vsum = 0.0;
-    unsigned long long clamps = 0, count = 0;
+    unsigned long long clamps = 0;
 
-    if (n1 - n0 > kNewCap || o1 - o0 > kOldCap || j1 - j0 > kJCap) {
+    if (nw > kNewCap || no > kOldCap || nj > kJCap) {
         for (int l = la + tid; l < lb; l += kMT) {
             double ls;
             unsigned long long lc;
             merge_lane_global(d, l, ls, lc);
-            lane_obs(d, one_scen, l, d.ls_new[l + 1] - d.ls_new[l], ls, lc, vsum, count, clamps);
+            const int cnt = d.ls_new[l + 1] - d.ls_new[l];
+            if (one_scen) {
+                vsum += ls;
+                clamps += lc;
+            } else {
+                unsigned long long *c = d.cnt + (size_t)d.lanes[l].scen * C_N;
+                if (cnt) {
+                    atomicAdd(c + C_VEH_STEPS, (unsigned long long)cnt);
+                    atomicAdd(d.sumv + d.lanes[l].scen, ls);
+                }
+                if (lc) atomicAdd(c + C_CLAMPS, lc);
+            }
         }
     } else {
-        for (int r = o0 + tid; r < o1; r += kMT) {
-            o_s[r - o0] = d.Pr.s[r];
-            o_v[r - o0] = d.Pr.v[r];
-            o_pl[r - o0] = d.Pr.lane[r];
+        // ---- stage old rows and joiners
+        for (int r = tid; r < no; r += kMT) {
+            o_s[r] = d.Pr.s[o0 + r];
+            o_v[r] = d.Pr.v[o0 + r];
+            o_ln[r] = d.Pr.lane[o0 + r];
+            o_id[r] = d.Pr.id[o0 + r];
         }
-        for (int e = j0 + tid; e < j1; e += kMT) {
-            uint32_t src = d.jidx[e];
-            j_src[e - j0] = src;
-            j_s[e - j0] = d.Pr.s[src];
-            j_v[e - j0] = d.Pr.v[src];
+        for (int e = tid; e < nj; e += kMT) {
+            const uint32_t src = d.jidx[j0 + e];
+            j_src[e] = src;
+            j_s[e] = d.Pr.s[src];
+            j_v[e] = d.Pr.v[src];
+            j_id[e] = d.Pr.id[src];
+            j_ln[e] = d.jslane[j0 + e];
+        }
+        for (int k = tid; k < nw; k += kMT) {
+            w_src[k] = kNoSrc;
+            w_top[k] = -1;
         }
         __syncthreads();
-        for (int l = la + tid; l < lb; l += kMT) {
-            const int lo = d.ls_old[l] - o0, hi = d.ls_old[l + 1] - o0;
+        // ---- split the old rows among the 4 waves at lane boundaries
+        if (lane == 0) {
+            int r = (no * wv) / 4;
+            if (wv == 0) {
+                r = 0;
+            } else {
+                while (r < no && r > 0 && (o_ln[r] & ~kJoinBit) == (o_ln[r - 1] & ~kJoinBit))
+                    ++r;
+            }
+            wave_start[wv] = r;
+            if (wv == 3)
+                wave_start[4] = no;
+        }
+        __syncthreads();
+        // ---- stayer ranks and prefix maxima, one wave per row range
+        {
+            const int ra = wave_start[wv], rb = max(wave_start[wv + 1], ra);
+            uint64_t c_pm = 0;
+            uint32_t c_p = 0;
+            for (int r0 = ra; r0 < rb; r0 += 64) {
+                const int r = r0 + lane;
+                const bool valid = r < rb;
+                uint32_t ln = 0;
+                bool head = false, st = false;
+                uint64_t key = 0;
+                if (valid) {
+                    ln = o_ln[r];
+                    st = (ln & kJoinBit) == 0;
+                    head = (r == ra) || ((o_ln[r - 1] & ~kJoinBit) != (ln & ~kJoinBit));
+                    key = okey(o_s[r], o_id[r]);
+                }
+                uint64_t pm;
+                uint32_t p;
+                wave_seg_scan(valid, head, st, key, c_pm, c_p, pm, p);
+                if (valid) {
+                    o_p[r] = p;
+                    o_pmh[r] = (uint32_t)(pm >> 32);
+                    o_pml[r] = (uint32_t)pm;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- joiners: rank among the lane's joiners, stayers before them
+        for (int e = tid; e < nj; e += kMT) {
+            const uint32_t l = j_ln[e];
+            const uint64_t key = okey(j_s[e], j_id[e]);
             const int jl = d.joff[l] - j0, jh = d.joff[l + 1] - j0;
-            const int wl = d.ls_new[l] - n0, wh = d.ls_new[l + 1] - n0;
-            // joiners of the lane by (s, id)
-            for (int a = jl + 1; a < jh; ++a) {
-                const float xs = j_s[a], xv = j_v[a];
-                const uint32_t xsrc = j_src[a];
-                int b = a - 1;
-                while (b >= jl) {
-                    const float bs = j_s[b];
-                    bool gt = bs > xs || (bs == xs && d.Pr.id[j_src[b]] > d.Pr.id[xsrc]);
-                    if (!gt)
-                        break;
-                    j_s[b + 1] = bs;
-                    j_v[b + 1] = j_v[b];
-                    j_src[b + 1] = j_src[b];
-                    --b;
-                }
-                j_s[b + 1] = xs;
-                j_v[b + 1] = xv;
-                j_src[b + 1] = xsrc;
-            }
-            // merge: the smaller (s, id) key of the two heads goes first
-            int ip = lo, jp = jl, q = wl;
-            for (;;) {
-                while (ip < hi && (o_pl[ip] & kJoinBit))
-                    ++ip;
-                const bool hs = ip < hi, hj = jp < jh;
-                if (!hs && !hj)
-                    break;
-                if (q >= wh) {
-                    atomicOr(d.err, 1u);
-                    break;
-                }
-                bool take_s = hs;
-                if (hs && hj) {
-                    const float a_s = o_s[ip], b_s = j_s[jp];
-                    take_s = a_s < b_s ||
-                             (a_s == b_s && d.Pr.id[(uint32_t)(o0 + ip)] < d.Pr.id[j_src[jp]]);
-                }
-                if (take_s)
-                    w_src[q++] = (uint32_t)ip++;
+            int q = 0;
+            for (int e2 = jl; e2 < jh; ++e2)
+                q += okey(j_s[e2], j_id[e2]) < key;
+            const int lo = d.ls_old[l] - o0, hi = d.ls_old[l + 1] - o0;
+            int a = lo, b = hi;       // first old row of l with prefix max > key
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                const uint64_t pm = ((uint64_t)o_pmh[mid] << 32) | o_pml[mid];
+                if (pm > key)
+                    b = mid;
                 else
-                    w_src[q++] = kTagJ | (uint32_t)jp++;
+                    a = mid + 1;
             }
-            if (q != wh) {
+            const int wl = d.ls_new[l] - n0;
+            const int stay_total = (d.ls_new[l + 1] - d.ls_new[l]) - (jh - jl);
+            const int f = (a < hi) ? (int)o_p[a] : stay_total;
+            const int pos = wl + f + q;
+            if (pos >= 0 && pos < nw) {
+                w_src[pos] = kTagJ | (uint32_t)e;
+                w_ln[pos] = l;
+            } else {
                 atomicOr(d.err, 1u);
-                for (; q < wh; ++q)      // rows without a source are not written
-                    w_src[q] = kSkip;
             }
-            // overlap removal from the lane head backwards, in place
-            double lsum = 0.0;
-            unsigned long long lc = 0;
-            if (wh > wl && w_src[wh - 1] != kSkip) {
-                uint32_t xl = w_src[wh - 1];
-                float sl = (xl & kTagJ) ? j_s[xl & ~kTagJ] : o_s[xl];
-                float vl = (xl & kTagJ) ? j_v[xl & ~kTagJ] : o_v[xl];
-                lsum = (double)vl;
-                int f = wh - 2;
-                for (; f >= wl; --f) {
-                    const uint32_t xf = w_src[f];
-                    if (xf == kSkip)
-                        break;
-                    const bool jf = (xf & kTagJ) != 0;
-                    const uint32_t kf = xf & ~kTagJ;
-                    float sf = jf ? j_s[kf] : o_s[kf];
-                    float vf = jf ? j_v[kf] : o_v[kf];
-                    const float lim = sl - len;
-                    if (sf > lim) {
-                        sf = lim;
-                        vf = fmin32(vf, vl);
-                        if (jf) { j_s[kf] = sf; j_v[kf] = vf; }
-                        else { o_s[kf] = sf; o_v[kf] = vf; }
-                        ++lc;
-                    }
-                    sl = sf;
-                    vl = vf;
-                    lsum += (double)vf;
+            j_kh[jl + q] = (uint32_t)(key >> 32);
+            j_kl[jl + q] = (uint32_t)key;
+        }
+        __syncthreads();
+        // ---- stayers: joiners with a smaller key than their prefix maximum
+        for (int r = tid; r < no; r += kMT) {
+            const uint32_t ln = o_ln[r];
+            if (ln & kJoinBit)
+                continue;
+            const uint64_t pm = ((uint64_t)o_pmh[r] << 32) | o_pml[r];
+            const int jl = d.joff[ln] - j0, jh = d.joff[ln + 1] - j0;
+            int a = jl, b = jh;       // joiners of the lane with key < pm (sorted keys)
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                const uint64_t k = ((uint64_t)j_kh[mid] << 32) | j_kl[mid];
+                if (k < pm)
+                    a = mid + 1;
+                else
+                    b = mid;
+            }
+            const int pos = (d.ls_new[ln] - n0) + (int)o_p[r] + (a - jl);
+            if (pos >= 0 && pos < nw) {
+                w_src[pos] = (uint32_t)r;
+                w_ln[pos] = ln;
+            } else {
+                atomicOr(d.err, 1u);
+            }
+        }
+        __syncthreads();
+        // ---- overlaps: highest offending pair of each lane
+        for (int k = tid; k < nw; k += kMT) {
+            const uint32_t x = w_src[k];
+            if (x == kNoSrc) {
+                atomicOr(d.err, 1u);
+                continue;
+            }
+            if (k + 1 < nw && w_src[k + 1] != kNoSrc && w_ln[k + 1] == w_ln[k]) {
+                const uint32_t y = w_src[k + 1];
+                const float sk = (x & kTagJ) ? j_s[x & ~kTagJ] : o_s[x];
+                const float sn = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
+                if (sk > sn - len)
+                    atomicMax(&w_top[d.ls_new[w_ln[k]] - n0], k);
+            }
+        }
+        __syncthreads();
+        // ---- sequential removal from there down to the lane tail
+        for (int k = tid; k < nw; k += kMT) {
+            const int top = w_top[k];
+            if (top < 0)
+                continue;     // set only at a lane's first row
+            const uint32_t y = w_src[top + 1];
+            float sl = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
+            float vl = (y & kTagJ) ? j_v[y & ~kTagJ] : o_v[y];
+            for (int f = top; f >= k; --f) {
+                const uint32_t xf = w_src[f];
+                const bool jf = (xf & kTagJ) != 0;
+                const uint32_t kf = xf & ~kTagJ;
+                float sf = jf ? j_s[kf] : o_s[kf];
+                float vf = jf ? j_v[kf] : o_v[kf];
+                const float lim = sl - len;
+                if (sf > lim) {
+                    sf = lim;
+                    vf = fmin32(vf, vl);
+                    if (jf) { j_s[kf] = sf; j_v[kf] = vf; }
+                    else { o_s[kf] = sf; o_v[kf] = vf; }
+                    ++clamps;
+                    if (!one_scen)
+                        atomicAdd(d.cnt + (size_t)d.lanes[w_ln[k]].scen * C_N + C_CLAMPS, 1ull);
                 }
-                xl = w_src[f + 1];
-                const uint32_t src = (xl & kTagJ) ? j_src[xl & ~kTagJ] : (uint32_t)(o0 + xl);
-                write_tail(d, l, true, sl, vl, d.Pr.id[src]);
+                sl = sf;
+                vl = vf;
+            }
+        }
+        __syncthreads();
+        // ---- lane tails (empty lanes too)
+        for (int l = la + tid; l < lb; l += kMT) {
+            const int wl = d.ls_new[l] - n0, wh = d.ls_new[l + 1] - n0;
+            if (wh > wl && w_src[wl] != kNoSrc) {
+                const uint32_t x = w_src[wl];
+                if (x & kTagJ)
+                    write_tail(d, l, true, j_s[x & ~kTagJ], j_v[x & ~kTagJ], j_id[x & ~kTagJ]);
+                else
+                    write_tail(d, l, true, o_s[x], o_v[x], o_id[x]);
             } else {
                 write_tail(d, l, false, 0.0f, 0.0f, kNone);
             }
-            lane_obs(d, one_scen, l, wh - wl, lsum, lc, vsum, count, clamps);
         }
-        __syncthreads();
-        // coalesced write-out of the chunk's new rows
-        for (int k = n0 + tid; k < n1; k += kMT) {
-            const uint32_t x = w_src[k - n0];
-            if (x == kSkip)
+        // ---- coalesced write-out of the chunk's new rows
+        for (int k = tid; k < nw; k += kMT) {
+            const uint32_t x = w_src[k];
+            if (x == kNoSrc)
                 continue;
+            float s, v;
+            uint32_t src;
             if (x & kTagJ) {
                 const uint32_t e = x & ~kTagJ;
-                const uint32_t src = j_src[e];
-                write_row(d, k, src, d.Pr.lane[src] & ~kJoinBit, j_s[e], j_v[e]);
+                src = j_src[e];
+                s = j_s[e];
+                v = j_v[e];
             } else {
-                write_row(d, k, (uint32_t)o0 + x, o_pl[x], o_s[x], o_v[x]);
+                src = (uint32_t)o0 + x;
+                s = o_s[x];
+                v = o_v[x];
+            }
+            write_row(d, n0 + k, src, w_ln[k], s, v);
+            if (one_scen) {
+                vsum += (double)v;
+            } else {
+                const int sc = d.lanes[w_ln[k]].scen;
+                atomicAdd(d.cnt + (size_t)sc * C_N + C_VEH_STEPS, 1ull);
+                atomicAdd(d.sumv + sc, (double)v);
             }
         }
     }
 
     if (one_scen) {
         red_d[tid] = vsum;
-        red_c[tid] = count;
         red_k[tid] = clamps;
         __syncthreads();
         for (int off = kMT / 2; off > 0; off >>= 1) {
             if (tid < off) {
                 red_d[tid] += red_d[tid + off];
-                red_c[tid] += red_c[tid + off];
                 red_k[tid] += red_k[tid + off];
             }
             __syncthreads();
@@ -911,9 +1056,9 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         if (tid == 0 && lb > la) {
             const int sc = d.lanes[la].scen;
             unsigned long long *c = d.cnt + (size_t)sc * C_N;
-            if (red_c[0]) atomicAdd(c + C_VEH_STEPS, red_c[0]);
+            if (nw) atomicAdd(c + C_VEH_STEPS, (unsigned long long)nw);
             if (red_k[0]) atomicAdd(c + C_CLAMPS, red_k[0]);
-            if (red_c[0]) atomicAdd(d.sumv + sc, red_d[0]);
+            if (nw) atomicAdd(d.sumv + sc, red_d[0]);
         }
     }
     if (w == 0 && tid == 0) {
@@ -933,18 +1078,22 @@ __global__ void k_tails(Dev d)
     if (l >= d.n_lanes)
         return;
     const int w0 = d.ls_old[l], w1 = d.ls_old[l + 1];
-    Tail tl;
-    tl.pad = 0;
-    if (w1 > w0) {
-        tl.s = d.S.s[w0];
-        tl.v = d.S.v[w0];
-        tl.id = d.S.id[w0];
-    } else {
-        tl.s = 0.0f;
-        tl.v = 0.0f;
-        tl.id = kNone;
+    const bool any = w1 > w0;
+    write_tail(d, l, any, any ? d.S.s[w0] : 0.0f, any ? d.S.v[w0] : 0.0f,
+               any ? d.S.id[w0] : kNone);
+}
+
+__device__ __forceinline__ int find_vehicle(const Dev &d, uint32_t id)
+{
+    int lo = 0, hi = d.n_veh;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (d.vt_id[mid] < id)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    d.tails[l] = tl;
+    return lo;
 }
 
 __global__ void k_cursor(Dev d, const uint32_t *ids, const uint32_t *ptrs, int32_t *out, int32_t n)
@@ -982,16 +1131,16 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     if (d.n_qlanes > 0)
         hipLaunchKernelGGL(k_insert, dim3(blocks_for(d.n_qlanes, 256)), dim3(256), 0, st, d);
     mark(1);
-    unsigned gu = blocks_for(d.cap, 256);
+    unsigned gu = blocks_for(d.cap, kUT);
     if (gu > 16384) gu = 16384;
-    hipLaunchKernelGGL(k_update, dim3(gu), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_update, dim3(gu), dim3(kUT), 0, st, d);
     mark(2);
     const unsigned gs = blocks_for(d.n_lanes, kScanLanes);
     hipLaunchKernelGGL(k_scan_reduce, dim3(gs), dim3(kScanThreads), 0, st, d);
     mark(3);
     hipLaunchKernelGGL(k_scan_apply, dim3(gs), dim3(kScanThreads), 0, st, d);
     mark(4);
-    unsigned gj = blocks_for((long long)d.cap + d.n_lanes, 256);
+    unsigned gj = blocks_for((long long)d.cap, 256);
     if (gj > 4096) gj = 4096;
     hipLaunchKernelGGL(k_jscatter, dim3(gj), dim3(256), 0, st, d);
     mark(5);
