@@ -46,7 +46,7 @@ struct Layout {
     int64_t n_route;
     bool debug;
     size_t total;
-    size_t S[8], Pr[8], ls[2], tails, chunk_lane, leave, jcount, joff, blk, jrank, jlist, jlane, jidx, jslane, scal, lanes,
+    size_t S[8], Pr[8], ls[2], tails, chunk_lane, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor;
 
@@ -68,11 +68,16 @@ struct Layout {
         jcount = take(4 * (size_t)n_lanes);
         joff = take(4 * ((size_t)n_lanes + 1));
         blk = take(8 * (size_t)nblk);
-        jrank = take(4 * c);
-        jlist = take(4 * c);
-        jlane = take(4 * c);
+        const size_t tiles = (c + kUpdateRows - 1) / kUpdateRows;
+        jlist = take(4 * tiles * kUpdateRows);
+        jlane = take(4 * tiles * kUpdateRows);
+        jcnt = take(4 * tiles);
         jidx = take(4 * c);
         jslane = take(4 * c);
+        jins_list = take(4 * (size_t)n_lanes);
+        jins_lane = take(4 * (size_t)n_lanes);
+        jcur = take(4 * (size_t)n_lanes);
+        lane_red = take((size_t)n_lanes);
         scal = take(64);
         lanes = take(sizeof(LaneInfo) * (size_t)n_lanes);
         roads = take(sizeof(RoadInfo) * (size_t)n_roads);
@@ -294,11 +299,15 @@ static void fill_dev(moss_sim *h)
     d.jcount = I(L.jcount);
     d.joff = I(L.joff);
     d.blk = I(L.blk);
-    d.jrank = U(L.jrank);
     d.jlist = U(L.jlist);
     d.jlane = U(L.jlane);
     d.jidx = U(L.jidx);
     d.jslane = U(L.jslane);
+    d.jins_list = U(L.jins_list);
+    d.jins_lane = U(L.jins_lane);
+    d.jcnt = I(L.jcnt);
+    d.jcur = I(L.jcur);
+    d.lane_red = (uint8_t *)(w + L.lane_red);
     int32_t *sc = I(L.scal);
     d.n_cur = sc + 0;
     d.n_next = sc + 1;
@@ -434,6 +443,17 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
             li.phase = (uint16_t)(signalised ? sig->node_phase[j] : 1);
             li.offset = (uint16_t)(signalised ? sig->node_offset[j] % sig->node_cycle[j] : 0);
             li.road = r;
+        }
+    }
+
+    // --- red lights at the first step: phase ((t + offset) mod cycle) div
+    // phase_len differs from the road's group
+    std::vector<uint8_t> red0(NL, 0);
+    for (int32_t l = 0; l < NL; ++l) {
+        const LaneInfo &li = lanes[l];
+        if (li.group >= 0) {
+            uint32_t ph = (((uint32_t)p.t0 + li.offset) % li.cycle) / li.phase;
+            red0[l] = (int)ph != (int)li.group;
         }
     }
 
@@ -584,6 +604,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     chk(up(L.ls[0], ls.data(), 4 * (size_t)(NL + 1)));
     chk(up(L.scal, scal, sizeof scal));
     chk(up(L.lanes, lanes.data(), sizeof(LaneInfo) * NL));
+    chk(up(L.lane_red, red0.data(), (size_t)NL));
     chk(up(L.roads, roads.data(), sizeof(RoadInfo) * NR));
     chk(up(L.route, route.data(), 4 * route.size()));
     chk(up(L.qlanes, qlanes.data(), 4 * qlanes.size()));

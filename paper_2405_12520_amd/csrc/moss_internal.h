@@ -81,10 +81,14 @@ struct Dev {
     int32_t *joff;                // exclusive scan of jcount
     int32_t *blk;                 // scan block sums
     int32_t *chunk_lane;          // [cap / kMergeRows + 3]
-    // joiners (lane changers, road transfers, insertions): slot e of this
-    // step holds source row jlist[e], target lane jlane[e] and rank jrank[e]
-    // among the lane's joiners; jidx/jslane list them grouped by lane
-    uint32_t *jrank, *jlist, *jlane, *jidx, *jslane;
+    // joiners (lane changers, road transfers, insertions).  Update tile b
+    // (rows [b*kUpdateRows, (b+1)*kUpdateRows)) lists its jcnt[b] joiners in
+    // jlist/jlane[b*kUpdateRows ...]; insertions go to jins_list/jins_lane;
+    // k_jscatter groups all of them by target lane into jidx/jslane using the
+    // per-lane cursors jcur (initialised to joff by the scan).
+    uint32_t *jlist, *jlane, *jidx, *jslane, *jins_list, *jins_lane;
+    int32_t *jcnt, *jcur;
+    uint8_t *lane_red;            // red light for the lane's road at the current step
     int32_t *n_cur, *n_next, *n_dbg;
     uint32_t *n_ins, *n_join;
     int64_t *t;
@@ -114,7 +118,9 @@ struct Dev {
 
 // New rows per merge block; chunk_lane[w] is the first lane whose first new
 // row is >= w * kMergeRows (written by the lane-count scan).
-constexpr int kMergeRows = 1024;
+constexpr int kMergeRows = 512;
+// Rows per update block (one joiner region per such tile).
+constexpr int kUpdateRows = 256;
 
 enum { C_INSERTED = 0, C_INSERT_FAIL, C_ARRIVED, C_TRIP_TIME, C_CLAMPS, C_LANE_CHANGES,
        C_VEH_STEPS, C_N };

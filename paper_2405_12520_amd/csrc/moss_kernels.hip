@@ -19,18 +19,24 @@ namespace moss {
 __device__ __forceinline__ float fmin32(float x, float y) { return x < y ? x : y; }
 __device__ __forceinline__ float fmax32(float x, float y) { return x > y ? x : y; }
 
-// IDM acceleration (Treiber, Hennecke, Helbing 2000), exponent 4.  Without a
-// leader only the free-road term a(1 - (v/v0)^4) remains; a non-positive gap
-// returns the braking limit.
-__device__ __forceinline__ float idm(const Params &P, float v, float v0e, bool has, float vl,
-                                     float gap)
+// IDM acceleration (Treiber, Hennecke, Helbing 2000), exponent 4:
+//   a_max (1 - (v/v0)^4 - (s*/gap)^2),  s* = s0 + max(0, v T + v dv / (2 sqrt(a b))).
+// idm_free gives the free-road factor 1 - (v/v0)^4, idm_lead the acceleration
+// behind a leader from that factor (a non-positive gap returns the braking
+// limit); without a leader the acceleration is a_max times the factor.  The
+// split lets one factor serve every evaluation with the same (v, v0) -- the
+// same operations on the same operands, so the same bits.
+__device__ __forceinline__ float idm_free(float v, float v0e)
 {
     float r = v / v0e;
     float r2 = r * r;
     float r4 = r2 * r2;
-    float free_term = 1.0f - r4;
-    if (!has)
-        return P.a_max * free_term;
+    return 1.0f - r4;
+}
+
+__device__ __forceinline__ float idm_lead(const Params &P, float free_term, float v, float vl,
+                                          float gap)
+{
     if (gap <= 0.0f)
         return -P.b_max;
     float dv = v - vl;
@@ -40,6 +46,12 @@ __device__ __forceinline__ float idm(const Params &P, float v, float v0e, bool h
     float ss = P.s0 + (tt > 0.0f ? tt : 0.0f);
     float q = ss / gap;
     return P.a_max * (free_term - q * q);
+}
+
+__device__ __forceinline__ float idm_any(const Params &P, float free_term, bool has, float v,
+                                         float vl, float gap)
+{
+    return has ? idm_lead(P, free_term, v, vl, gap) : P.a_max * free_term;
 }
 
 // First output word of Philox4x32-10 (Salmon et al., SC'11).
@@ -183,17 +195,17 @@ __global__ void k_insert(Dev d)
     d.Pr.ptr[slot] = d.q_ptr[h];
     d.Pr.next[slot] = d.q_next[h];
     d.Pr.v0[slot] = d.q_v0[h];
-    const uint32_t e = atomicAdd(d.n_join, 1u);
-    d.jlist[e] = slot;
-    d.jlane[e] = (uint32_t)l;
-    d.jrank[e] = (uint32_t)atomicAdd(d.jcount + l, 1);
+    const uint32_t e = slot - (uint32_t)(*d.n_cur);
+    d.jins_list[e] = slot;
+    d.jins_lane[e] = (uint32_t)l;
+    atomicAdd(d.jcount + l, 1);
     d.q_head[l] = h + 1;
     atomicAdd(c + C_INSERTED, 1ull);
 }
 
 // ----------------------------------------------------------------- update --
 
-constexpr int kUT = 256;               // rows per update block
+constexpr int kUT = kUpdateRows;       // rows per update block
 constexpr int kUH = 96;                // rows staged before and after them
 constexpr int kUW = kUT + 2 * kUH;
 
@@ -227,10 +239,13 @@ __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int h
 // found by binary search in that window, falling back to global memory when
 // the lane does not fit in it.  Records needed later (the side lane, the next
 // road of lane heads) are loaded up front so that their latencies overlap.
+// Joiners are listed in the tile's own region of jlist, so no atomic result
+// is waited for.
 __global__ void __launch_bounds__(kUT) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
     __shared__ uint32_t w_id[kUW], w_ln[kUW];
+    __shared__ uint32_t s_jn;
 
     const int n = *d.n_cur;
     const int64_t t = *d.t;
@@ -250,6 +265,8 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             nxt = d.S.next[i];
         }
         __syncthreads();
+        if (tid == 0)
+            s_jn = 0;
         for (int r = ws + tid; r < we; r += kUT) {
             w_s[r - ws] = d.S.s[r];
             w_v[r - ws] = d.S.v[r];
@@ -264,6 +281,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
         const bool hasLc = act && (i + 1 < n) && w_ln[x_i + 1] == l;
         // independent loads of the second round
         const LaneInfo li = d.lanes[l];
+        const bool red_now = act && d.lane_red[l] != 0;
         const int ls_side = (int)l + side;
         const float vlim_side = (act && ls_side >= 0 && ls_side < d.n_lanes)
                                     ? d.lanes[ls_side].vlim : 0.0f;
@@ -294,13 +312,10 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
 
             // red light at the stop line, applied if the vehicle can still stop
             bool red = false;
-            if (nxt >= 0 && li.group >= 0) {
-                uint32_t ph = ((tt + (uint32_t)li.offset) % (uint32_t)li.cycle) / (uint32_t)li.phase;
-                if ((int)ph != (int)li.group) {
-                    float stop_dist = (v * v) / (2.0f * P.b_max);
-                    if (L - s >= stop_dist)
-                        red = true;
-                }
+            if (nxt >= 0 && red_now) {
+                float stop_dist = (v * v) / (2.0f * P.b_max);
+                if (L - s >= stop_dist)
+                    red = true;
             }
 
             // in-lane neighbours are the adjacent rows
@@ -310,6 +325,10 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 sLc = w_s[x_i + 1];
                 vLc = w_v[x_i + 1];
             }
+            const float v0e_c = fmin32(v0, li.vlim);
+            const float free_c = idm_free(v, v0e_c);
+            float acc_c = 0.0f, acc_t = 0.0f, free_t = 0.0f;   // valid when MOBIL ran
+            bool mobil = false;
 
             // randomised MOBIL on one side per step (even: k-1, odd: k+1)
             int lt = -1;
@@ -319,6 +338,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             if (s >= 0.0f) {
                 const int kt = (int)li.k + side;
                 if (kt >= 0 && kt < (int)li.nlanes) {
+                    mobil = true;
                     lt = ls_side;
                     float sN = 0.0f, vN = 0.0f, v0N = 0.0f;
                     uint32_t idN = kNone;
@@ -353,26 +373,23 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                         }
                     }
                     const float vlim_c = li.vlim, vlim_t = vlim_side;
-                    const float v0e_c = fmin32(v0, vlim_c), v0e_t = fmin32(v0, vlim_t);
-                    float a_c = hasLc ? idm(P, v, v0e_c, true, vLc, (sLc - P.len) - s)
-                                      : idm(P, v, v0e_c, false, 0.0f, 0.0f);
-                    float at_c = hasLt ? idm(P, v, v0e_t, true, vLt, (sLt - P.len) - s)
-                                       : idm(P, v, v0e_t, false, 0.0f, 0.0f);
+                    const float v0e_t = fmin32(v0, vlim_t);
+                    free_t = (v0e_t == v0e_c) ? free_c : idm_free(v, v0e_t);
+                    acc_c = idm_any(P, free_c, hasLc, v, vLc, (sLc - P.len) - s);
+                    acc_t = idm_any(P, free_t, hasLt, v, vLt, (sLt - P.len) - s);
                     float d_o = 0.0f, d_n = 0.0f;
                     bool safe = true;
                     if (hasO) {
                         const float vo = w_v[x_i - 1], so = w_s[x_i - 1];
-                        const float v0e_o = fmin32(w_v0[x_i - 1], vlim_c);
-                        float a_o = idm(P, vo, v0e_o, true, v, (s - P.len) - so);
-                        float at_o = hasLc ? idm(P, vo, v0e_o, true, vLc, (sLc - P.len) - so)
-                                           : idm(P, vo, v0e_o, false, 0.0f, 0.0f);
+                        const float free_o = idm_free(vo, fmin32(w_v0[x_i - 1], vlim_c));
+                        float a_o = idm_lead(P, free_o, vo, v, (s - P.len) - so);
+                        float at_o = idm_any(P, free_o, hasLc, vo, vLc, (sLc - P.len) - so);
                         d_o = at_o - a_o;
                     }
                     if (hasN) {
-                        const float v0e_n = fmin32(v0N, vlim_t);
-                        float a_n = hasLt ? idm(P, vN, v0e_n, true, vLt, (sLt - P.len) - sN)
-                                          : idm(P, vN, v0e_n, false, 0.0f, 0.0f);
-                        float at_n = idm(P, vN, v0e_n, true, v, (s - P.len) - sN);
+                        const float free_n = idm_free(vN, fmin32(v0N, vlim_t));
+                        float a_n = idm_any(P, free_n, hasLt, vN, vLt, (sLt - P.len) - sN);
+                        float at_n = idm_lead(P, free_n, vN, v, (s - P.len) - sN);
                         d_n = at_n - a_n;
                         float gap_b = (s - P.len) - sN;
                         if (!(gap_b > 0.0f)) safe = false;
@@ -382,10 +399,13 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                         float gap_f = (sLt - P.len) - s;
                         if (!(gap_f > 0.0f)) safe = false;
                     }
-                    float inc = (at_c - a_c) + P.pol * (d_n + d_o);
-                    uint32_t x0 = philox_x0(tt, id, 0u, 0u, P.key0, P.key1);
-                    float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
-                    change = safe && inc > P.a_thr && u < P.p_lc;
+                    float inc = (acc_t - acc_c) + P.pol * (d_n + d_o);
+                    const bool cand = safe && inc > P.a_thr;
+                    if (cand) {       // the random draw only matters for candidates
+                        uint32_t x0 = philox_x0(tt, id, 0u, 0u, P.key0, P.key1);
+                        float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
+                        change = u < P.p_lc;
+                    }
                     margin = inc - P.a_thr;
                     flags |= change ? 2 : 1;
                     tl_id = idLt;
@@ -400,24 +420,27 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 lif.vlim = vlim_side;
                 lif.k = (uint8_t)((int)li.k + side);
             }
-            Lead ld;
-            if (change ? hasLt : hasLc) {
-                ld.has = true;
-                ld.v = change ? vLt : vLc;
-                ld.gap = ((change ? sLt : sLc) - P.len) - s;
-                ld.id = change ? idLt : w_id[x_i + 1];
+            const float free_f = change ? free_t : free_c;
+            const bool inlane = change ? hasLt : hasLc;
+            float acc;
+            uint32_t lead_id;
+            if (inlane) {
+                // same operands as MOBIL's own-lane / target-lane evaluation
+                acc = mobil ? (change ? acc_t : acc_c)
+                            : idm_lead(P, free_f, v, vLc, (sLc - P.len) - s);
+                lead_id = change ? idLt : w_id[x_i + 1];
             } else {
                 if (!rd_ok && nxt >= 0) {
                     rd_next = d.roads[nxt];
                     rd_ok = true;
                 }
-                ld = lookahead(d, lif, s, id, ptr, nxt, rd_next);
+                const Lead ld = lookahead(d, lif, s, id, ptr, nxt, rd_next);
                 if (ld.has) flags |= 8;
+                acc = idm_any(P, free_f, ld.has, v, ld.v, ld.gap);
+                lead_id = ld.id;
             }
-            const float v0e = fmin32(v0, lif.vlim);
-            float acc = idm(P, v, v0e, ld.has, ld.v, ld.gap);
             if (red) {
-                float acc_red = idm(P, v, v0e, true, 0.0f, L - s);
+                float acc_red = idm_lead(P, free_f, v, 0.0f, L - s);
                 acc = fmin32(acc, acc_red);
                 flags |= 4;
             }
@@ -458,7 +481,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 flags |= 16;
             if (P.debug) {
                 d.d_id[i] = id;
-                d.d_leader[i] = ld.id;
+                d.d_leader[i] = lead_id;
                 d.d_flags[i] = flags;
                 d.d_margin[i] = margin;
                 d.d_tl[i] = tl_id;
@@ -466,8 +489,16 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             }
         }
 
-        // bookkeeping: joiner slots, per-lane leave/join counts, counters
-        const uint32_t jslot = wave_alloc(d.n_join, joins);
+        // bookkeeping: joiners in the tile's region, per-lane leave/join
+        // counts (no returned values awaited), counters
+        const unsigned long long jm = __ballot(joins);
+        uint32_t jbase = 0;
+        if (jm) {
+            const int leader = __ffsll((long long)jm) - 1;
+            if (__lane_id() == leader)
+                jbase = atomicAdd(&s_jn, (uint32_t)__popcll(jm));
+            jbase = __shfl(jbase, leader);
+        }
         if (act) {
             if (arrived || joins)
                 atomicAdd(d.leave + l, 1);
@@ -478,9 +509,12 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 atomicAdd(d.cnt + (size_t)li.scen * C_N + C_TRIP_TIME,
                           (unsigned long long)((t + 1) - (int64_t)dep));
             } else if (joins) {
-                d.jlist[jslot] = (uint32_t)i;
-                d.jlane[jslot] = (uint32_t)x;
-                d.jrank[jslot] = (uint32_t)atomicAdd(d.jcount + x, 1);
+                const int lane_id = __lane_id();
+                const unsigned long long below = lane_id ? (~0ull >> (64 - lane_id)) : 0ull;
+                const uint32_t slot = (uint32_t)base + jbase + (uint32_t)__popcll(jm & below);
+                d.jlist[slot] = (uint32_t)i;
+                d.jlane[slot] = (uint32_t)x;
+                atomicAdd(d.jcount + x, 1);
             }
             d.Pr.s[i] = sp;
             d.Pr.v[i] = vn;
@@ -493,6 +527,9 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
         }
         wave_count(d.cnt + C_ARRIVED, arrived, li.scen, scen0, uni_scen);
         wave_count(d.cnt + C_LANE_CHANGES, change, li.scen, scen0, uni_scen);
+        __syncthreads();
+        if (tid == 0)
+            d.jcnt[base / kUT] = (int32_t)s_jn;
     }
 }
 
@@ -569,6 +606,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
     }
     __syncthreads();
     const int b0 = base_tot, bj = base_j;
+    const uint32_t tnext = (uint32_t)(*d.t + 1);
     const int base = b * kScanLanes + threadIdx.x * kScanPer;
     int cnt[kScanPer], jc[kScanPer];
     int tot = 0, tj = 0;
@@ -589,8 +627,18 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
         if (l < d.n_lanes) {
             d.ls_new[l] = run;
             d.joff[l] = runj;
+            d.jcur[l] = runj;
             d.leave[l] = 0;
             d.jcount[l] = 0;
+            // red light of the lane's road at the next step
+            const LaneInfo li = d.lanes[l];
+            uint8_t red = 0;
+            if (li.group >= 0) {
+                const uint32_t ph = ((tnext + (uint32_t)li.offset) % (uint32_t)li.cycle) /
+                                    (uint32_t)li.phase;
+                red = (int)ph != (int)li.group;
+            }
+            d.lane_red[l] = red;
             // chunks whose first row lies in (start, end] of lane l begin at lane l+1
             for (int w = run / kMergeRows + 1; w * kMergeRows <= run + cnt[q]; ++w)
                 d.chunk_lane[w] = l + 1;
@@ -611,14 +659,25 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
 
 // ----------------------------------------------------- joiners by lane --
 
-__global__ void k_jscatter(Dev d)
+// One wave per update tile (plus one for the insertions): each joiner takes
+// the next slot of its target lane's bucket.
+__global__ void __launch_bounds__(256) k_jscatter(Dev d)
 {
-    const int n = (int)*d.n_join;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const uint32_t x = d.jlane[e];
-        const int pos = d.joff[x] + (int)d.jrank[e];
-        d.jidx[pos] = d.jlist[e];
-        d.jslane[pos] = x;
+    const int ntiles = (*d.n_cur + kUpdateRows - 1) / kUpdateRows;
+    const int lane = __lane_id();
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile <= ntiles;
+         tile += waves) {
+        const bool ins = tile == ntiles;
+        const int cnt = ins ? (int)*d.n_ins : d.jcnt[tile];
+        const uint32_t *lst = ins ? d.jins_list : d.jlist + (size_t)tile * kUpdateRows;
+        const uint32_t *lan = ins ? d.jins_lane : d.jlane + (size_t)tile * kUpdateRows;
+        for (int k = lane; k < cnt; k += 64) {
+            const uint32_t x = lan[k];
+            const int pos = atomicAdd(d.jcur + x, 1);
+            d.jidx[pos] = lst[k];
+            d.jslane[pos] = x;
+        }
     }
 }
 
@@ -729,9 +788,10 @@ __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned lo
 
 constexpr int kMT = 256;          // threads per merge block (4 waves)
 constexpr int kMC = kMergeRows;   // new rows per chunk
-constexpr int kOldCap = 1536;     // old rows staged per chunk
-constexpr int kNewCap = 1536;     // new rows staged per chunk
-constexpr int kJCap = 512;        // joiners staged per chunk
+constexpr int kOldCap = 3 * kMT;  // old rows staged per chunk (3 per thread)
+constexpr int kNewCap = 3 * kMT;  // new rows staged per chunk
+constexpr int kJCap = kMT;        // joiners staged per chunk (1 per thread)
+constexpr int kLaneCap = 256;     // owned lanes whose starts are cached in LDS
 constexpr uint32_t kTagJ = 0x80000000u;
 constexpr uint32_t kNoSrc = 0xFFFFFFFFu;
 
@@ -774,22 +834,24 @@ __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, ui
 
 // Next state, one chunk of kMC new rows per block.  A block owns the lanes
 // whose first new row falls in its chunk; their old rows and joiners are
-// staged in LDS, positions are computed in parallel (see above), overlaps are
-// removed per lane, and the new rows are written with coalesced stores.
-// Chunks that do not fit the LDS tile take merge_lane_global.
+// staged in LDS (their other fields in registers of the staging thread),
+// positions are computed in parallel (see above), overlaps are removed per
+// lane, and the rows are written out.  Chunks that do not fit the LDS tile
+// take merge_lane_global.
 __global__ void __launch_bounds__(kMT) k_merge(Dev d)
 {
     __shared__ float o_s[kOldCap], o_v[kOldCap];
     __shared__ uint32_t o_ln[kOldCap], o_id[kOldCap], o_p[kOldCap];
     __shared__ uint32_t o_pmh[kOldCap], o_pml[kOldCap];
     __shared__ float j_s[kJCap], j_v[kJCap];
-    __shared__ uint32_t j_src[kJCap], j_id[kJCap], j_ln[kJCap], j_kh[kJCap], j_kl[kJCap];
+    __shared__ uint32_t j_id[kJCap], j_ln[kJCap], j_kh[kJCap], j_kl[kJCap];
     __shared__ uint32_t w_src[kNewCap], w_ln[kNewCap];
     __shared__ int w_top[kNewCap];
+    __shared__ int lt_old[kLaneCap + 1], lt_new[kLaneCap + 1], lt_jo[kLaneCap + 1];
     __shared__ int sh_i[8];
     __shared__ int wave_start[5];
-    __shared__ double red_d[kMT];
-    __shared__ unsigned long long red_k[kMT];
+    __shared__ double red_d[kMT / 64];
+    __shared__ unsigned long long red_k[kMT / 64];
 
     const int tid = threadIdx.x;
     const int lane = __lane_id();
@@ -837,20 +899,50 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             }
         }
     } else {
-        // ---- stage old rows and joiners
-        for (int r = tid; r < no; r += kMT) {
-            o_s[r] = d.Pr.s[o0 + r];
-            o_v[r] = d.Pr.v[o0 + r];
-            o_ln[r] = d.Pr.lane[o0 + r];
-            o_id[r] = d.Pr.id[o0 + r];
+        // ---- owned lanes' old starts, new starts and joiner offsets
+        const bool lt_ok = lb - la <= kLaneCap;
+        if (lt_ok) {
+            for (int q = tid; q <= lb - la; q += kMT) {
+                lt_old[q] = d.ls_old[la + q];
+                lt_new[q] = d.ls_new[la + q];
+                lt_jo[q] = d.joff[la + q];
+            }
         }
-        for (int e = tid; e < nj; e += kMT) {
-            const uint32_t src = d.jidx[j0 + e];
-            j_src[e] = src;
-            j_s[e] = d.Pr.s[src];
-            j_v[e] = d.Pr.v[src];
-            j_id[e] = d.Pr.id[src];
-            j_ln[e] = d.jslane[j0 + e];
+        auto LO = [&](int l) { return lt_ok ? lt_old[l - la] : d.ls_old[l]; };
+        auto LN = [&](int l) { return lt_ok ? lt_new[l - la] : d.ls_new[l]; };
+        auto JO = [&](int l) { return lt_ok ? lt_jo[l - la] : d.joff[l]; };
+
+        // ---- stage old rows (3 per thread) and joiners (1 per thread)
+        float ra[3], rv0[3];
+        uint32_t rptr[3];
+        int32_t rnext[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int r = tid + k * kMT;
+            if (r < no) {
+                o_s[r] = d.Pr.s[o0 + r];
+                o_v[r] = d.Pr.v[o0 + r];
+                o_ln[r] = d.Pr.lane[o0 + r];
+                o_id[r] = d.Pr.id[o0 + r];
+                ra[k] = d.Pr.a[o0 + r];
+                rptr[k] = d.Pr.ptr[o0 + r];
+                rnext[k] = d.Pr.next[o0 + r];
+                rv0[k] = d.Pr.v0[o0 + r];
+            }
+        }
+        float ja = 0.0f, jv0 = 0.0f;
+        uint32_t jptr = 0;
+        int32_t jnext = 0;
+        if (tid < nj) {
+            const uint32_t src = d.jidx[j0 + tid];
+            j_s[tid] = d.Pr.s[src];
+            j_v[tid] = d.Pr.v[src];
+            j_id[tid] = d.Pr.id[src];
+            j_ln[tid] = d.jslane[j0 + tid];
+            ja = d.Pr.a[src];
+            jptr = d.Pr.ptr[src];
+            jnext = d.Pr.next[src];
+            jv0 = d.Pr.v0[src];
         }
         for (int k = tid; k < nw; k += kMT) {
             w_src[k] = kNoSrc;
@@ -873,19 +965,18 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         __syncthreads();
         // ---- stayer ranks and prefix maxima, one wave per row range
         {
-            const int ra = wave_start[wv], rb = max(wave_start[wv + 1], ra);
+            const int ra0 = wave_start[wv], rb0 = max(wave_start[wv + 1], ra0);
             uint64_t c_pm = 0;
             uint32_t c_p = 0;
-            for (int r0 = ra; r0 < rb; r0 += 64) {
+            for (int r0 = ra0; r0 < rb0; r0 += 64) {
                 const int r = r0 + lane;
-                const bool valid = r < rb;
-                uint32_t ln = 0;
+                const bool valid = r < rb0;
                 bool head = false, st = false;
                 uint64_t key = 0;
                 if (valid) {
-                    ln = o_ln[r];
+                    const uint32_t ln = o_ln[r];
                     st = (ln & kJoinBit) == 0;
-                    head = (r == ra) || ((o_ln[r - 1] & ~kJoinBit) != (ln & ~kJoinBit));
+                    head = (r == ra0) || ((o_ln[r - 1] & ~kJoinBit) != (ln & ~kJoinBit));
                     key = okey(o_s[r], o_id[r]);
                 }
                 uint64_t pm;
@@ -900,14 +991,15 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         }
         __syncthreads();
         // ---- joiners: rank among the lane's joiners, stayers before them
-        for (int e = tid; e < nj; e += kMT) {
+        if (tid < nj) {
+            const int e = tid;
             const uint32_t l = j_ln[e];
             const uint64_t key = okey(j_s[e], j_id[e]);
-            const int jl = d.joff[l] - j0, jh = d.joff[l + 1] - j0;
+            const int jl = JO(l) - j0, jh = JO(l + 1) - j0;
             int q = 0;
             for (int e2 = jl; e2 < jh; ++e2)
                 q += okey(j_s[e2], j_id[e2]) < key;
-            const int lo = d.ls_old[l] - o0, hi = d.ls_old[l + 1] - o0;
+            const int lo = LO(l) - o0, hi = LO(l + 1) - o0;
             int a = lo, b = hi;       // first old row of l with prefix max > key
             while (a < b) {
                 const int mid = (a + b) >> 1;
@@ -917,13 +1009,20 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 else
                     a = mid + 1;
             }
-            const int wl = d.ls_new[l] - n0;
-            const int stay_total = (d.ls_new[l + 1] - d.ls_new[l]) - (jh - jl);
+            const int wl = LN(l) - n0;
+            const int stay_total = (LN(l + 1) - LN(l)) - (jh - jl);
             const int f = (a < hi) ? (int)o_p[a] : stay_total;
             const int pos = wl + f + q;
             if (pos >= 0 && pos < nw) {
                 w_src[pos] = kTagJ | (uint32_t)e;
                 w_ln[pos] = l;
+                const int g = n0 + pos;
+                d.S.a[g] = ja;
+                d.S.id[g] = j_id[e];
+                d.S.lane[g] = l;
+                d.S.ptr[g] = jptr;
+                d.S.next[g] = jnext;
+                d.S.v0[g] = jv0;
             } else {
                 atomicOr(d.err, 1u);
             }
@@ -932,25 +1031,36 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         }
         __syncthreads();
         // ---- stayers: joiners with a smaller key than their prefix maximum
-        for (int r = tid; r < no; r += kMT) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int r = tid + k * kMT;
+            if (r >= no)
+                continue;
             const uint32_t ln = o_ln[r];
             if (ln & kJoinBit)
                 continue;
             const uint64_t pm = ((uint64_t)o_pmh[r] << 32) | o_pml[r];
-            const int jl = d.joff[ln] - j0, jh = d.joff[ln + 1] - j0;
+            const int jl = JO(ln) - j0, jh = JO(ln + 1) - j0;
             int a = jl, b = jh;       // joiners of the lane with key < pm (sorted keys)
             while (a < b) {
                 const int mid = (a + b) >> 1;
-                const uint64_t k = ((uint64_t)j_kh[mid] << 32) | j_kl[mid];
-                if (k < pm)
+                const uint64_t kk = ((uint64_t)j_kh[mid] << 32) | j_kl[mid];
+                if (kk < pm)
                     a = mid + 1;
                 else
                     b = mid;
             }
-            const int pos = (d.ls_new[ln] - n0) + (int)o_p[r] + (a - jl);
+            const int pos = (LN(ln) - n0) + (int)o_p[r] + (a - jl);
             if (pos >= 0 && pos < nw) {
                 w_src[pos] = (uint32_t)r;
                 w_ln[pos] = ln;
+                const int g = n0 + pos;
+                d.S.a[g] = ra[k];
+                d.S.id[g] = o_id[r];
+                d.S.lane[g] = ln;
+                d.S.ptr[g] = rptr[k];
+                d.S.next[g] = rnext[k];
+                d.S.v0[g] = rv0[k];
             } else {
                 atomicOr(d.err, 1u);
             }
@@ -968,7 +1078,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 const float sk = (x & kTagJ) ? j_s[x & ~kTagJ] : o_s[x];
                 const float sn = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
                 if (sk > sn - len)
-                    atomicMax(&w_top[d.ls_new[w_ln[k]] - n0], k);
+                    atomicMax(&w_top[LN((int)w_ln[k]) - n0], k);
             }
         }
         __syncthreads();
@@ -1003,7 +1113,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         __syncthreads();
         // ---- lane tails (empty lanes too)
         for (int l = la + tid; l < lb; l += kMT) {
-            const int wl = d.ls_new[l] - n0, wh = d.ls_new[l + 1] - n0;
+            const int wl = LN(l) - n0, wh = LN(l + 1) - n0;
             if (wh > wl && w_src[wl] != kNoSrc) {
                 const uint32_t x = w_src[wl];
                 if (x & kTagJ)
@@ -1014,24 +1124,17 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 write_tail(d, l, false, 0.0f, 0.0f, kNone);
             }
         }
-        // ---- coalesced write-out of the chunk's new rows
+        // ---- positions and speeds of the chunk's rows, coalesced
         for (int k = tid; k < nw; k += kMT) {
             const uint32_t x = w_src[k];
             if (x == kNoSrc)
                 continue;
-            float s, v;
-            uint32_t src;
-            if (x & kTagJ) {
-                const uint32_t e = x & ~kTagJ;
-                src = j_src[e];
-                s = j_s[e];
-                v = j_v[e];
-            } else {
-                src = (uint32_t)o0 + x;
-                s = o_s[x];
-                v = o_v[x];
-            }
-            write_row(d, n0 + k, src, w_ln[k], s, v);
+            const bool jx = (x & kTagJ) != 0;
+            const uint32_t e = x & ~kTagJ;
+            const float s = jx ? j_s[e] : o_s[e];
+            const float v = jx ? j_v[e] : o_v[e];
+            d.S.s[n0 + k] = s;
+            d.S.v[n0 + k] = v;
             if (one_scen) {
                 vsum += (double)v;
             } else {
@@ -1043,29 +1146,33 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     }
 
     if (one_scen) {
-        red_d[tid] = vsum;
-        red_k[tid] = clamps;
-        __syncthreads();
-        for (int off = kMT / 2; off > 0; off >>= 1) {
-            if (tid < off) {
-                red_d[tid] += red_d[tid + off];
-                red_k[tid] += red_k[tid + off];
-            }
-            __syncthreads();
+        for (int off = 32; off > 0; off >>= 1) {
+            vsum += __shfl_down(vsum, off);
+            clamps += __shfl_down(clamps, off);
         }
+        if (lane == 0) {
+            red_d[wv] = vsum;
+            red_k[wv] = clamps;
+        }
+        __syncthreads();
         if (tid == 0 && lb > la) {
+            double sv = 0.0;
+            unsigned long long ck = 0;
+            for (int q = 0; q < kMT / 64; ++q) {
+                sv += red_d[q];
+                ck += red_k[q];
+            }
             const int sc = d.lanes[la].scen;
             unsigned long long *c = d.cnt + (size_t)sc * C_N;
             if (nw) atomicAdd(c + C_VEH_STEPS, (unsigned long long)nw);
-            if (red_k[0]) atomicAdd(c + C_CLAMPS, red_k[0]);
-            if (nw) atomicAdd(d.sumv + sc, red_d[0]);
+            if (ck) atomicAdd(c + C_CLAMPS, ck);
+            if (nw) atomicAdd(d.sumv + sc, sv);
         }
     }
     if (w == 0 && tid == 0) {
         *d.n_dbg = *d.n_cur;
         *d.n_cur = n_next;
         *d.n_ins = 0u;
-        *d.n_join = 0u;
         *d.t = *d.t + 1;
     }
 }
@@ -1140,8 +1247,8 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     mark(3);
     hipLaunchKernelGGL(k_scan_apply, dim3(gs), dim3(kScanThreads), 0, st, d);
     mark(4);
-    unsigned gj = blocks_for((long long)d.cap, 256);
-    if (gj > 4096) gj = 4096;
+    unsigned gj = blocks_for((long long)d.cap / kUpdateRows + 1, 4);
+    if (gj > 2048) gj = 2048;
     hipLaunchKernelGGL(k_jscatter, dim3(gj), dim3(256), 0, st, d);
     mark(5);
     hipLaunchKernelGGL(k_merge, dim3((unsigned)(d.cap / kMC + 1)), dim3(kMT), 0, st, d);
