@@ -13,7 +13,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,14 +38,6 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_sources_sha():
-    h = hashlib.sha256()
-    for f in ("moss_kernels.hip", "moss_internal.h"):
-        with open(os.path.join(ROOT, "paper_2405_12520_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(kernel):
     """Measured HBM bytes per launch from the committed counter summary, if it
     was taken on the current kernel sources."""
@@ -55,6 +46,7 @@ def load_traffic(kernel):
         return None
     with open(path) as f:
         rec = json.load(f)
+    from paper_2405_12520_amd.profile_summary import kernel_sources_sha
     if rec.get("source_sha") != kernel_sources_sha():
         return None
     k = rec.get("kernels", {}).get(kernel)

@@ -46,7 +46,7 @@ struct Layout {
     int64_t n_route;
     bool debug;
     size_t total;
-    size_t S[8], Pr[8], ls[2], tails, chunk_lane, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
+    size_t S[8], Pr[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor;
 
@@ -64,7 +64,7 @@ struct Layout {
         for (auto &x : ls) x = take(4 * ((size_t)n_lanes + 1));
         tails = take(sizeof(Tail) * (size_t)n_lanes);
         leave = take(4 * (size_t)n_lanes);
-        chunk_lane = take(4 * ((size_t)c / kMergeRows + 3));
+        chunk = take(sizeof(int4) * ((size_t)c / kMergeRows + 3));
         jcount = take(4 * (size_t)n_lanes);
         joff = take(4 * ((size_t)n_lanes + 1));
         blk = take(8 * (size_t)nblk);
@@ -295,7 +295,7 @@ static void fill_dev(moss_sim *h)
     d.route = I(L.route);
     d.tails = (Tail *)(w + L.tails);
     d.leave = I(L.leave);
-    d.chunk_lane = I(L.chunk_lane);
+    d.chunk = (int4 *)(w + L.chunk);
     d.jcount = I(L.jcount);
     d.joff = I(L.joff);
     d.blk = I(L.blk);
@@ -367,7 +367,7 @@ static void plan_layout(const moss_network *net, const moss_vehicles *veh, const
     }
     L->n_pend = veh->n - n_pl;
     L->n_qlanes = (int32_t)std::count(is_q.begin(), is_q.end(), 1);
-    L->nblk = (net->n_lanes + 2047) / 2048;
+    L->nblk = (net->n_lanes + 511) / 512;
     L->debug = (prm->flags & MOSS_FLAG_DEBUG) != 0;
     L->plan();
 }

@@ -80,7 +80,10 @@ struct Dev {
     int32_t *leave, *jcount;      // vehicles leaving / joining each lane (zeroed by the scan)
     int32_t *joff;                // exclusive scan of jcount
     int32_t *blk;                 // scan block sums
-    int32_t *chunk_lane;          // [cap / kMergeRows + 3]
+    // chunk[w] = (first lane, its new start, its old start, its joiner
+    // offset) of merge chunk w: the first lane whose new start is >= w *
+    // kMergeRows (written by the lane-count scan); [cap / kMergeRows + 3]
+    int4 *chunk;
     // joiners (lane changers, road transfers, insertions).  Update tile b
     // (rows [b*kUpdateRows, (b+1)*kUpdateRows)) lists its jcnt[b] joiners in
     // jlist/jlane[b*kUpdateRows ...]; insertions go to jins_list/jins_lane;
@@ -116,8 +119,7 @@ struct Dev {
     float *d_margin;
 };
 
-// New rows per merge block; chunk_lane[w] is the first lane whose first new
-// row is >= w * kMergeRows (written by the lane-count scan).
+// New rows per merge block.
 constexpr int kMergeRows = 512;
 // Rows per update block (one joiner region per such tile).
 constexpr int kUpdateRows = 256;

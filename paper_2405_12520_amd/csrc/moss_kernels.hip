@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
 // --------------------------------------------------------- lane-count scan --
 
 constexpr int kScanThreads = 256;
-constexpr int kScanPer = 8;
+constexpr int kScanPer = 2;
 constexpr int kScanLanes = kScanThreads * kScanPer;
 
 // inclusive scan of two ints over a 256-thread block
@@ -639,21 +639,23 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
                 red = (int)ph != (int)li.group;
             }
             d.lane_red[l] = red;
-            // chunks whose first row lies in (start, end] of lane l begin at lane l+1
+            // chunks whose first row lies in (start, end] of lane l begin at
+            // lane l+1: record its lane, new start, old start and joiner offset
             for (int w = run / kMergeRows + 1; w * kMergeRows <= run + cnt[q]; ++w)
-                d.chunk_lane[w] = l + 1;
+                d.chunk[w] = make_int4(l + 1, run + cnt[q], d.ls_old[l + 1], runj + jc[q]);
         }
         run += cnt[q];
         runj += jc[q];
     }
     if (b == 0 && threadIdx.x == 0)
-        d.chunk_lane[0] = 0;
+        d.chunk[0] = make_int4(0, 0, 0, 0);
     if (b == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
         d.ls_new[d.n_lanes] = run;
         d.joff[d.n_lanes] = runj;
         *d.n_next = run;
+        const int4 end = make_int4(d.n_lanes, run, d.ls_old[d.n_lanes], runj);
         for (int w = run / kMergeRows + 1; w <= d.cap / kMergeRows + 1; ++w)
-            d.chunk_lane[w] = d.n_lanes;
+            d.chunk[w] = end;
     }
 }
 
@@ -846,7 +848,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     __shared__ float j_s[kJCap], j_v[kJCap];
     __shared__ uint32_t j_id[kJCap], j_ln[kJCap], j_kh[kJCap], j_kl[kJCap];
     __shared__ uint32_t w_src[kNewCap], w_ln[kNewCap];
-    __shared__ int w_top[kNewCap];
+    __shared__ int w_top[kNewCap], w_bot[kNewCap];
     __shared__ int lt_old[kLaneCap + 1], lt_new[kLaneCap + 1], lt_jo[kLaneCap + 1];
     __shared__ int sh_i[8];
     __shared__ int wave_start[5];
@@ -861,15 +863,15 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     if (w > n_next / kMC)
         return;
     if (tid == 0) {
-        const int la = d.chunk_lane[w], lb = d.chunk_lane[w + 1];
-        sh_i[0] = la;
-        sh_i[1] = lb;
-        sh_i[2] = d.ls_new[la];
-        sh_i[3] = d.ls_new[lb];
-        sh_i[4] = d.ls_old[la];
-        sh_i[5] = d.ls_old[lb];
-        sh_i[6] = d.joff[la];
-        sh_i[7] = d.joff[lb];
+        const int4 ca = d.chunk[w], cb = d.chunk[w + 1];
+        sh_i[0] = ca.x;
+        sh_i[1] = cb.x;
+        sh_i[2] = ca.y;
+        sh_i[3] = cb.y;
+        sh_i[4] = ca.z;
+        sh_i[5] = cb.z;
+        sh_i[6] = ca.w;
+        sh_i[7] = cb.w;
     }
     __syncthreads();
     const int la = sh_i[0], lb = sh_i[1];
@@ -947,20 +949,31 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         for (int k = tid; k < nw; k += kMT) {
             w_src[k] = kNoSrc;
             w_top[k] = -1;
+            w_bot[k] = 0x7FFFFFFF;
         }
         __syncthreads();
-        // ---- split the old rows among the 4 waves at lane boundaries
-        if (lane == 0) {
+        // ---- split the old rows among the 4 waves at lane boundaries (first
+        // lane start at or after an even share, found 64 rows at a time)
+        {
             int r = (no * wv) / 4;
-            if (wv == 0) {
-                r = 0;
-            } else {
-                while (r < no && r > 0 && (o_ln[r] & ~kJoinBit) == (o_ln[r - 1] & ~kJoinBit))
-                    ++r;
+            if (wv > 0 && r > 0) {
+                for (;;) {
+                    const int q = r + lane;
+                    const bool bnd = q >= no ||
+                                     (o_ln[q] & ~kJoinBit) != (o_ln[q - 1] & ~kJoinBit);
+                    const unsigned long long m = __ballot(bnd);
+                    if (m) {
+                        r += __ffsll((long long)m) - 1;
+                        break;
+                    }
+                    r += 64;
+                }
             }
-            wave_start[wv] = r;
-            if (wv == 3)
-                wave_start[4] = no;
+            if (lane == 0) {
+                wave_start[wv] = (wv == 0) ? 0 : min(r, no);
+                if (wv == 3)
+                    wave_start[4] = no;
+            }
         }
         __syncthreads();
         // ---- stayer ranks and prefix maxima, one wave per row range
@@ -1077,16 +1090,22 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 const uint32_t y = w_src[k + 1];
                 const float sk = (x & kTagJ) ? j_s[x & ~kTagJ] : o_s[x];
                 const float sn = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
-                if (sk > sn - len)
-                    atomicMax(&w_top[LN((int)w_ln[k]) - n0], k);
+                if (sk > sn - len) {
+                    const int first = LN((int)w_ln[k]) - n0;
+                    atomicMax(&w_top[first], k);
+                    atomicMin(&w_bot[first], k);
+                }
             }
         }
         __syncthreads();
-        // ---- sequential removal from there down to the lane tail
+        // ---- sequential removal from there down towards the lane tail.  Below
+        // the lowest offending pair of raw positions, a row left unchanged
+        // leaves every row behind it unchanged, so the walk stops there.
         for (int k = tid; k < nw; k += kMT) {
             const int top = w_top[k];
             if (top < 0)
                 continue;     // set only at a lane's first row
+            const int bot = w_bot[k];
             const uint32_t y = w_src[top + 1];
             float sl = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
             float vl = (y & kTagJ) ? j_v[y & ~kTagJ] : o_v[y];
@@ -1105,6 +1124,8 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                     ++clamps;
                     if (!one_scen)
                         atomicAdd(d.cnt + (size_t)d.lanes[w_ln[k]].scen * C_N + C_CLAMPS, 1ull);
+                } else if (f < bot) {
+                    break;
                 }
                 sl = sf;
                 vl = vf;
