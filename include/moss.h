@@ -141,6 +141,8 @@ enum {
     MOSS_CNT_CLAMPS,         /* overlap corrections */
     MOSS_CNT_LANE_CHANGES,
     MOSS_CNT_VEH_STEPS,      /* sum over steps of active vehicles after the step */
+    MOSS_CNT_MLP_EVAL,       /* learned-closure evaluations inside its envelope */
+    MOSS_CNT_MLP_FALLBACK,   /* vehicle-steps that fell back to IDM */
     MOSS_N_COUNTERS
 };
 

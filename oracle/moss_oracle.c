@@ -91,6 +91,49 @@ float orc_idm(float v, float v0e, int has_leader, float v_lead, float gap, float
     return a_max * (free_term - q * q);
 }
 
+/* ---------------------------------------------------- learned closure --- */
+
+/* bfloat16 rounding of a float (nearest, ties to even), as a double */
+static double bf16r(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    float r;
+    memcpy(&r, &u, 4);
+    return (double)r;
+}
+
+/* GELU, tanh form (Hendrycks & Gimpel 2016) */
+static double gelu_d(double x)
+{
+    const double k0 = 0.7978845608028654, k1 = 0.044715;
+    return 0.5 * x * (1.0 + tanh(k0 * (x + k1 * x * x * x)));
+}
+
+/* 8 -> 64 -> 64 -> 1 network; weights and layer inputs rounded to bfloat16,
+ * sums in double. */
+double orc_mlp_forward(const float *theta, const float *z)
+{
+    const float *W1 = theta, *b1 = theta + 512, *W2 = theta + 576, *b2 = theta + 4672,
+                *w3 = theta + 4736, *b3 = theta + 4800;
+    double zq[8], h1[64], h2[64];
+    for (int i = 0; i < 8; ++i) zq[i] = bf16r(z[i]);
+    for (int j = 0; j < 64; ++j) {
+        double acc = b1[j];
+        for (int i = 0; i < 8; ++i) acc += bf16r(W1[j * 8 + i]) * zq[i];
+        h1[j] = bf16r((float)gelu_d(acc));
+    }
+    for (int j = 0; j < 64; ++j) {
+        double acc = b2[j];
+        for (int i = 0; i < 64; ++i) acc += bf16r(W2[j * 64 + i]) * h1[i];
+        h2[j] = bf16r((float)gelu_d(acc));
+    }
+    double y = b3[0];
+    for (int i = 0; i < 64; ++i) y += bf16r(w3[i]) * h2[i];
+    return y;
+}
+
 /* -------------------------------------------------------------- model --- */
 
 typedef struct {
@@ -136,6 +179,10 @@ struct orc_sim {
     int64_t t;
     int64_t *cnt;      /* [n_scen][ORC_N_COUNTERS] */
     double *sumv;
+    double *mlp_sq;    /* [n_scen] */
+    int32_t mode;
+    float mlp_theta[4801];
+    float mlp_norm[32];
     /* decisions of the last step, indexed by slot at step start */
     int32_t dbg_n;
     uint32_t *d_id, *d_leader, *d_tl, *d_tf;
@@ -165,7 +212,7 @@ static void free_sim(orc_sim *m)
                     m->lane_vlim, m->lane_scen, m->lane_road, m->lane_k, m->node_cycle,
                     m->node_phase, m->node_offset, m->road_group, m->vid, m->depart, m->v0,
                     m->route_off, m->route_len, m->routes, m->ls, m->sl, m->vi, m->s, m->v,
-                    m->a, m->cur, m->q_start, m->q_end, m->q_head, m->q_list, m->cnt, m->sumv,
+                    m->a, m->cur, m->q_start, m->q_end, m->q_head, m->q_list, m->cnt, m->sumv, m->mlp_sq,
                     m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i)
         free(ptrs[i]);
@@ -305,6 +352,12 @@ orc_sim *orc_create(const orc_input *in)
     free(pe);
     m->cnt = calloc((size_t)m->n_scen * ORC_N_COUNTERS, 8);
     m->sumv = calloc((size_t)m->n_scen, 8);
+    m->mlp_sq = calloc((size_t)m->n_scen, 8);
+    m->mode = in->mode;
+    if (in->mode == 1) {
+        memcpy(m->mlp_theta, in->mlp_theta, sizeof m->mlp_theta);
+        memcpy(m->mlp_norm, in->mlp_norm, sizeof m->mlp_norm);
+    }
     return m;
 }
 
@@ -489,6 +542,43 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
         m->d_flags[i] |= 4;
     }
     float a = fmax32(-P->b_max, acc);
+
+    /* --- learned closure [reading]: inputs are the leader gap (d_look when
+     * there is none or farther), own speed, leader speed (own speed when
+     * none), effective desired speed, distance to a red stop line (d_look
+     * when none), previous acceleration, distance to the lane end (at most
+     * d_look) and the speed limit; inside the training envelope the network's
+     * output, limited to [-b_max, a_max], replaces the IDM acceleration. --- */
+    if (m->mode == 1) {
+        float f[8];
+        f[0] = ld.has ? fmin32(ld.gap, P->d_look) : P->d_look;
+        f[1] = v;
+        f[2] = ld.has ? ld.v : v;
+        f[3] = v0e;
+        f[4] = red ? fmin32(L - s, P->d_look) : P->d_look;
+        f[5] = m->a[i];
+        f[6] = fmin32(L - s, P->d_look);
+        f[7] = m->lane_vlim[lf];
+        const float *mean = m->mlp_norm, *inv = m->mlp_norm + 8, *lo = m->mlp_norm + 16,
+                    *hi = m->mlp_norm + 24;
+        int inside = 1;
+        float z[8];
+        for (int q = 0; q < 8; ++q) {
+            if (!(f[q] >= lo[q] && f[q] <= hi[q])) inside = 0;
+            z[q] = (f[q] - mean[q]) * inv[q];
+        }
+        size_t sc = (size_t)m->lane_scen[l];
+        if (inside) {
+            float am = (float)orc_mlp_forward(m->mlp_theta, z);
+            am = fmax32(-P->b_max, fmin32(am, P->a_max));
+            double e = (double)am - (double)a;
+            m->mlp_sq[sc] += e * e;
+            m->cnt[sc * ORC_N_COUNTERS + ORC_MLP_EVAL]++;
+            a = am;
+        } else {
+            m->cnt[sc * ORC_N_COUNTERS + ORC_MLP_FALLBACK]++;
+        }
+    }
 
     /* --- Newton's equations over one step, stopping at v = 0 --- */
     float vn = v + a * P->dt;
@@ -703,6 +793,11 @@ int32_t orc_read_debug(const orc_sim *m, uint32_t *id, uint32_t *leader, int32_t
         if (t_follower) t_follower[q] = m->d_tf[q];
     }
     return m->dbg_n;
+}
+
+void orc_mlp_sq(const orc_sim *m, double *sum_sq)
+{
+    memcpy(sum_sq, m->mlp_sq, sizeof(double) * (size_t)m->n_scen);
 }
 
 void orc_counters(const orc_sim *m, int64_t *cnt, double *sum_v)

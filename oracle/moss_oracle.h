@@ -49,13 +49,19 @@ typedef struct {
     int32_t h_look;
     int32_t t0;
     uint64_t seed;
+    /* learned car-following closure (mode 1): parameters W1[64][8], b1[64],
+     * W2[64][64], b2[64], w3[64], b3 (4801 floats) and norm = mean[8],
+     * inv_std[8], lo[8], hi[8] of the inputs */
+    int32_t mode;
+    const float *mlp_theta;
+    const float *mlp_norm;
 } orc_input;
 
 typedef struct orc_sim orc_sim;
 
 /* counters per scenario, in this order */
 enum { ORC_INSERTED = 0, ORC_INSERT_FAIL, ORC_ARRIVED, ORC_TRIP_TIME, ORC_CLAMPS,
-       ORC_LANE_CHANGES, ORC_VEH_STEPS, ORC_N_COUNTERS };
+       ORC_LANE_CHANGES, ORC_VEH_STEPS, ORC_MLP_EVAL, ORC_MLP_FALLBACK, ORC_N_COUNTERS };
 
 #define ORC_NONE 0xFFFFFFFFu
 
@@ -78,6 +84,11 @@ int32_t orc_read_debug(const orc_sim *m, uint32_t *id, uint32_t *leader, int32_t
                        float *margin, uint32_t *t_leader, uint32_t *t_follower);
 /* counters: int64 [n_scen][ORC_N_COUNTERS], sum of speeds [n_scen] */
 void orc_counters(const orc_sim *m, int64_t *cnt, double *sum_v);
+/* sum over network evaluations of (a_mlp - a_idm)^2 [n_scen] */
+void orc_mlp_sq(const orc_sim *m, double *sum_sq);
+/* network output for one normalised input vector z[8] (FP64 with bfloat16
+ * rounding of weights and layer inputs) */
+double orc_mlp_forward(const float *theta, const float *z);
 int32_t orc_pending(const orc_sim *m);
 
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11). */

@@ -30,6 +30,7 @@ class OrcInput(C.Structure):
         ("politeness", C.c_float), ("a_thr", C.c_float), ("p_lc", C.c_float),
         ("d_look", C.c_float),
         ("h_look", C.c_int32), ("t0", C.c_int32), ("seed", C.c_uint64),
+        ("mode", C.c_int32), ("mlp_theta", C.c_void_p), ("mlp_norm", C.c_void_p),
     ]
 
 
@@ -52,6 +53,9 @@ def lib():
         L.orc_read_debug.argtypes = [C.c_void_p] + [C.c_void_p] * 6
         L.orc_read_debug.restype = C.c_int32
         L.orc_counters.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_mlp_sq.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_mlp_forward.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_mlp_forward.restype = C.c_double
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_idm.restype = C.c_float
         L.orc_idm.argtypes = [C.c_float, C.c_float, C.c_int, C.c_float, C.c_float, C.c_float,
@@ -65,7 +69,7 @@ def _p(a: np.ndarray):
 
 
 COUNTER_NAMES = ("inserted", "insert_fail", "arrived", "trip_time", "clamps", "lane_changes",
-                 "veh_steps")
+                 "veh_steps", "mlp_eval", "mlp_fallback")
 
 
 class OracleSim:
@@ -112,6 +116,11 @@ class OracleSim:
         inp.h_look = int(p["h_look"])
         inp.t0 = int(p["t0"])
         inp.seed = int(p["seed"])
+        mlp_cfg = p.get("mlp")
+        if mlp_cfg is not None:
+            inp.mode = 1
+            inp.mlp_theta = arr(mlp_cfg["theta"], np.float32)
+            inp.mlp_norm = arr(mlp_cfg["norm"], np.float32)
         h = L.orc_create(C.byref(inp))
         if not h:
             raise ValueError("oracle create failed: " + L.orc_error().decode())
@@ -163,6 +172,11 @@ class OracleSim:
         lib().orc_counters(self._h, _p(c), _p(sv))
         return c, sv
 
+    def mlp_sq(self):
+        out = np.zeros(self.n_scen, np.float64)
+        lib().orc_mlp_sq(self._h, _p(out))
+        return out
+
 
 def philox4x32_10(ctr, key):
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
@@ -170,6 +184,12 @@ def philox4x32_10(ctr, key):
     out = np.empty(4, np.uint32)
     lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
     return out
+
+
+def mlp_forward(theta, z):
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    zz = np.ascontiguousarray(z, dtype=np.float32)
+    return float(lib().orc_mlp_forward(_p(th), _p(zz)))
 
 
 def idm(v, v0e, has_leader, v_lead, gap, a_max=2.0, two_sqrt_ab=None, s0=2.0, T=1.5, b=4.5,

@@ -110,7 +110,7 @@ struct Dev {
     const int32_t *vt_dep;
     const uint32_t *vt_rstart;
     // observables
-    unsigned long long *cnt;      // [n_scen][7]
+    unsigned long long *cnt;      // [n_scen][C_N]
     double *sumv;                 // [n_scen]
     uint32_t *err;
     // debug per row at step start
@@ -125,7 +125,7 @@ constexpr int kMergeRows = 512;
 constexpr int kUpdateRows = 256;
 
 enum { C_INSERTED = 0, C_INSERT_FAIL, C_ARRIVED, C_TRIP_TIME, C_CLAMPS, C_LANE_CHANGES,
-       C_VEH_STEPS, C_N };
+       C_VEH_STEPS, C_MLP_EVAL, C_MLP_FALLBACK, C_N };
 
 // Kernel launchers (moss_kernels.hip).
 hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libmoss.so")
 MOSS_OK, MOSS_EINVAL, MOSS_ENOMEM, MOSS_EDEVICE, MOSS_ESTATE = 0, -1, -2, -3, -4
 MOSS_FLAG_DEBUG = 1
 COUNTER_NAMES = ("inserted", "insert_fail", "arrived", "trip_time", "clamps", "lane_changes",
-                 "veh_steps")
+                 "veh_steps", "mlp_eval", "mlp_fallback")
 NONE = 0xFFFFFFFF
 
 vp = C.c_void_p
