@@ -45,6 +45,11 @@ extern "C" {
 
 /* Flags for moss_params.flags */
 #define MOSS_FLAG_DEBUG 1u /* record per-vehicle decisions of each step (moss_read_debug) */
+#define MOSS_FLAG_TRACE 2u /* record the closure's inputs and IDM label (moss_read_trace) */
+
+/* moss_params.mode */
+#define MOSS_MODE_IDM 0
+#define MOSS_MODE_MLP 1    /* learned closure inside its envelope, IDM outside */
 
 /* Road network.  Roads are directed; road r has road_nlanes[r] lanes numbered
  * road_lane0[r] .. road_lane0[r]+road_nlanes[r]-1 (lane index k inside the
@@ -112,6 +117,9 @@ typedef struct {
     int32_t t0;        /* index of the first step, >= 0 */
     uint64_t seed;
     uint32_t flags;    /* MOSS_FLAG_* */
+    int32_t mode;      /* MOSS_MODE_* */
+    const float *mlp_theta;  /* host float[MOSS_MLP_PARAMS], used when mode = MLP */
+    const float *mlp_norm;   /* host float[MOSS_MLP_NORM] */
 } moss_params;
 
 typedef struct moss_sim moss_sim;
@@ -192,6 +200,52 @@ int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leade
 int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
                     int32_t *n_kernels);
 const char *moss_kernel_name(int32_t i);
+
+/* ---- learned car-following closure (the project's extension) ----
+ * An 8 -> 64 -> 64 -> 1 network with GELU (tanh form) that, inside its
+ * training envelope, replaces the IDM acceleration of the vehicle update
+ * (moss_params.mode = MOSS_MODE_MLP).  Parameters: float[MOSS_MLP_PARAMS] =
+ * W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3; input description:
+ * float[MOSS_MLP_NORM] = mean[8], inv_std[8], lo[8], hi[8] of the inputs
+ * (leader gap, speed, leader speed, effective desired speed, distance to a red
+ * stop line, previous acceleration, distance to the lane end, speed limit).
+ * The simulator evaluates it with bfloat16 weights and activations and FP32
+ * accumulation on the matrix cores.  All pointers below are device pointers
+ * and all calls are asynchronous on the given stream. */
+#define MOSS_MLP_PARAMS 4801
+#define MOSS_MLP_NORM 32
+
+/* Scratch bytes moss_mlp_grad needs for a batch of n samples. */
+size_t moss_mlp_scratch_bytes(int32_t n);
+
+/* Mean squared error of the network on n samples (features feat[idx[b]][8],
+ * labels label[idx[b]]; idx = NULL means b itself) and its gradient with
+ * respect to theta (float[MOSS_MLP_PARAMS]).  bf16 = 1 rounds weights and
+ * layer inputs to bfloat16 as the simulator does.  loss may be NULL.
+ * MOSS_EINVAL on bad arguments, MOSS_ENOMEM if scratch is too small. */
+int moss_mlp_grad(const float *feat, const float *label, const int32_t *idx, int32_t n,
+                  const float *theta, const float *norm, int32_t bf16, float *grad, float *loss,
+                  void *scratch, size_t scratch_bytes, void *hip_stream);
+
+/* One Adam step (Kingma & Ba) on theta with moments m, v (all
+ * float[MOSS_MLP_PARAMS]); step counts from 1. */
+int moss_mlp_adam(float *theta, float *m, float *v, const float *grad, int32_t step, float lr,
+                  float beta1, float beta2, float eps, void *hip_stream);
+
+/* Network outputs for n feature rows with the simulator's inference path. */
+int moss_mlp_predict(const float *feat, int32_t n, const float *theta, const float *norm,
+                     float *out, void *hip_stream);
+
+/* With MOSS_FLAG_TRACE: the inputs of the network and the IDM acceleration of
+ * every vehicle in the most recent step, in the row order of the state that
+ * step started from, copied to feat[n][8] and label[n] (host or device
+ * pointers per device flag). */
+int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, float *label,
+                    int32_t *n);
+
+/* Sum over the network's evaluations of (a_network - a_IDM)^2, per scenario
+ * (host array double[n_scen]). */
+int moss_read_mlp_error(moss_sim *h, double *sum_sq);
 
 /* Frees host-side resources of the handle (the workspace stays the caller's). */
 int moss_destroy(moss_sim *h);

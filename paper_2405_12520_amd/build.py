@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libmoss.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("moss_api.hip", "moss_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("moss_api.hip", "moss_kernels.hip", "moss_mlp.hip")]
 ARCH = os.environ.get("MOSS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",

@@ -44,11 +44,11 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     int32_t cap, n_lanes, n_roads, n_scen, n_qlanes, n_pend, n_veh, nblk;
     int64_t n_route;
-    bool debug;
+    bool debug, trace, mlp;
     size_t total;
     size_t S[8], Pr[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
-        vt_rstart, cnt, sumv, dbg[6], cursor;
+        vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_sq, tr_feat, tr_label;
 
     void plan()
     {
@@ -97,6 +97,11 @@ struct Layout {
         sumv = take(8 * (size_t)n_scen);
         for (auto &x : dbg) x = take(debug ? 4 * c : 4);
         cursor = take(4 * c);
+        mlp_theta = take(4 * (size_t)MOSS_MLP_PARAMS);
+        mlp_norm = take(4 * (size_t)MOSS_MLP_NORM);
+        mlp_sq = take(8 * (size_t)n_scen);
+        tr_feat = take(trace ? 4 * 8 * c : 4);
+        tr_label = take(trace ? 4 * c : 4);
         total = off;
     }
 };
@@ -166,6 +171,18 @@ int validate(const moss_network *net, const moss_signals *sig, const moss_vehicl
         return fail(MOSS_EINVAL, "a_thr must be finite and p_lc in [0, 1]");
     if (p.h_look < 0 || p.t0 < 0)
         return fail(MOSS_EINVAL, "h_look and t0 must be >= 0");
+    if (p.mode != MOSS_MODE_IDM && p.mode != MOSS_MODE_MLP)
+        return fail(MOSS_EINVAL, "unknown mode %d", p.mode);
+    if (p.mode == MOSS_MODE_MLP) {
+        if (!p.mlp_theta || !p.mlp_norm)
+            return fail(MOSS_EINVAL, "MLP mode needs mlp_theta and mlp_norm");
+        for (int q = 0; q < MOSS_MLP_PARAMS; ++q)
+            if (!std::isfinite(p.mlp_theta[q]))
+                return fail(MOSS_EINVAL, "non-finite network parameter %d", q);
+        for (int q = 0; q < MOSS_MLP_NORM; ++q)
+            if (!std::isfinite(p.mlp_norm[q]))
+                return fail(MOSS_EINVAL, "non-finite input description entry %d", q);
+    }
     // vehicles
     std::vector<uint32_t> ids(veh->id, veh->id + veh->n);
     std::sort(ids.begin(), ids.end());
@@ -330,6 +347,11 @@ static void fill_dev(moss_sim *h)
     d.vt_rstart = U(L.vt_rstart);
     d.cnt = (unsigned long long *)(w + L.cnt);
     d.sumv = (double *)(w + L.sumv);
+    d.mlp_theta = F(L.mlp_theta);
+    d.mlp_norm = F(L.mlp_norm);
+    d.mlp_sq = (double *)(w + L.mlp_sq);
+    d.tr_feat = F(L.tr_feat);
+    d.tr_label = F(L.tr_label);
     d.d_id = U(L.dbg[0]);
     d.d_leader = U(L.dbg[1]);
     d.d_flags = I(L.dbg[2]);
@@ -369,6 +391,8 @@ static void plan_layout(const moss_network *net, const moss_vehicles *veh, const
     L->n_qlanes = (int32_t)std::count(is_q.begin(), is_q.end(), 1);
     L->nblk = (net->n_lanes + 511) / 512;
     L->debug = (prm->flags & MOSS_FLAG_DEBUG) != 0;
+    L->trace = (prm->flags & MOSS_FLAG_TRACE) != 0;
+    L->mlp = prm->mode == MOSS_MODE_MLP;
     L->plan();
 }
 
@@ -579,6 +603,8 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     P.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
     P.key1 = (uint32_t)(p.seed >> 32);
     P.debug = L.debug ? 1u : 0u;
+    P.trace = L.trace ? 1u : 0u;
+    h->dev.mode = L.mlp ? 1 : 0;
 
     hipStream_t st = h->stream;
     char *w = h->ws;
@@ -618,6 +644,10 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     chk(up(L.vt_id, vtid.data(), 4 * (size_t)N));
     chk(up(L.vt_dep, vtdep.data(), 4 * (size_t)N));
     chk(up(L.vt_rstart, vtr.data(), 4 * (size_t)N));
+    if (L.mlp) {
+        chk(up(L.mlp_theta, p.mlp_theta, 4 * (size_t)MOSS_MLP_PARAMS));
+        chk(up(L.mlp_norm, p.mlp_norm, 4 * (size_t)MOSS_MLP_NORM));
+    }
     if (e == hipSuccess)
         e = launch_tails(step_dev(h, 0), st);
     if (e == hipSuccess)
@@ -799,6 +829,42 @@ int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leade
         if (t_leader) HIP_TRY(hipMemcpy(t_leader, h->dev.d_tl, b, hipMemcpyDeviceToHost));
         if (t_follower) HIP_TRY(hipMemcpy(t_follower, h->dev.d_tf, b, hipMemcpyDeviceToHost));
     }
+    return MOSS_OK;
+}
+
+int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, float *label,
+                    int32_t *n)
+{
+    g_err.clear();
+    if (!h || !n)
+        return fail(MOSS_EINVAL, "null argument");
+    if (!h->lay.trace)
+        return fail(MOSS_EINVAL, "created without MOSS_FLAG_TRACE");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    int32_t m = 0;
+    HIP_TRY(hipMemcpy(&m, h->dev.n_dbg, 4, hipMemcpyDeviceToHost));
+    *n = m;
+    if (m > capacity)
+        return fail(MOSS_ENOMEM, "%d rows, capacity %d", m, capacity);
+    const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (m > 0) {
+        if (feat) HIP_TRY(hipMemcpy(feat, h->dev.tr_feat, 4 * 8 * (size_t)m, kind));
+        if (label) HIP_TRY(hipMemcpy(label, h->dev.tr_label, 4 * (size_t)m, kind));
+    }
+    return MOSS_OK;
+}
+
+int moss_read_mlp_error(moss_sim *h, double *sum_sq)
+{
+    g_err.clear();
+    if (!h || !sum_sq)
+        return fail(MOSS_EINVAL, "null argument");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    HIP_TRY(hipMemcpy(sum_sq, h->dev.mlp_sq, 8 * (size_t)h->n_scen, hipMemcpyDeviceToHost));
     return MOSS_OK;
 }
 

@@ -63,6 +63,7 @@ struct Params {
     int32_t h_look;
     uint32_t key0, key1;
     uint32_t debug;
+    uint32_t trace;
 };
 
 // Everything a kernel needs, passed by value.
@@ -113,6 +114,11 @@ struct Dev {
     unsigned long long *cnt;      // [n_scen][C_N]
     double *sumv;                 // [n_scen]
     uint32_t *err;
+    // learned closure (mode 1) and its training trace
+    int32_t mode;
+    const float *mlp_theta, *mlp_norm;
+    double *mlp_sq;               // [n_scen]
+    float *tr_feat, *tr_label;    // [cap][8], [cap]
     // debug per row at step start
     uint32_t *d_id, *d_leader, *d_tl, *d_tf;
     int32_t *d_flags;

@@ -13,6 +13,7 @@
 // Arithmetic is FP32 in the source order, compiled without contraction, so
 // that decisions (leaders, lane changes, lanes) reproduce bit for bit.
 #include "moss_internal.h"
+#include "moss_mlp.h"
 
 namespace moss {
 
@@ -240,7 +241,9 @@ __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int h
 // the lane does not fit in it.  Records needed later (the side lane, the next
 // road of lane heads) are loaded up front so that their latencies overlap.
 // Joiners are listed in the tile's own region of jlist, so no atomic result
-// is waited for.
+// is waited for.  MODE 1 evaluates the learned closure for the wave's 64
+// vehicles on the matrix cores between the acceleration and the integration.
+template <int MODE>
 __global__ void __launch_bounds__(kUT) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
@@ -253,6 +256,17 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
     const uint32_t tt = (uint32_t)t;
     const int tid = threadIdx.x;
     const int side = ((t & 1) == 0) ? -1 : 1;     // MOBIL looks at lane k-1 on even steps
+    const bool want_feat = MODE == 1 || P.trace;
+
+    MlpLds *mw = nullptr;
+    uint16_t *mz = nullptr;
+    if constexpr (MODE == 1) {
+        __shared__ MlpLds s_mlp;
+        __shared__ uint16_t s_z[(kUT / 64) * 64 * kMlpIn];
+        mlp_load(s_mlp, d.mlp_theta, d.mlp_norm);
+        mw = &s_mlp;
+        mz = s_z + (tid >> 6) * 64 * kMlpIn;
+    }
 
     for (int base = blockIdx.x * kUT; base < n; base += gridDim.x * kUT) {
         const int ws = max(base - kUH, 0), we = min(base + kUT + kUH, n);
@@ -260,9 +274,12 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
         const bool act = i < n;
         uint32_t ptr = 0;
         int32_t nxt = -1;
+        float a_prev = 0.0f;
         if (act) {
             ptr = d.S.ptr[i];
             nxt = d.S.next[i];
+            if (want_feat)
+                a_prev = d.S.a[i];
         }
         __syncthreads();
         if (tid == 0)
@@ -293,22 +310,28 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
         }
         const int scen0 = __shfl(li.scen, 0);
         const bool uni_scen = __all(!act || li.scen == scen0);
+
+        // values carried from the acceleration to the integration
         bool arrived = false, change = false, joins = false;
-        int x = 0;
+        int x = 0, lf = (int)l;
         uint32_t p = ptr;
-        float sp = 0.0f, vn = 0.0f, a = 0.0f;
+        float sp = 0.0f, vn = 0.0f, a = 0.0f, a_idm = 0.0f;
         int32_t nr = nxt;
-        uint32_t id = 0;
-        float v0 = 0.0f;
+        uint32_t id = 0, lead_id = kNone, tl_id = kNone, tf_id = kNone;
+        float v0 = 0.0f, s = 0.0f, v = 0.0f, margin = 0.0f;
+        int32_t flags = 0;
+        LaneInfo lif = li;
+        float feat[kMlpIn];
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q)
+            feat[q] = 0.0f;
 
         if (act) {
-            const float s = w_s[x_i], v = w_v[x_i];
+            s = w_s[x_i];
+            v = w_v[x_i];
             id = w_id[x_i];
             v0 = w_v0[x_i];
             const float L = li.L;
-            int32_t flags = 0;
-            float margin = 0.0f;
-            uint32_t tl_id = kNone, tf_id = kNone;
 
             // red light at the stop line, applied if the vehicle can still stop
             bool red = false;
@@ -414,8 +437,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             }
 
             // car-following in the final lane
-            const int lf = change ? lt : (int)l;
-            LaneInfo lif = li;
+            lf = change ? lt : (int)l;
             if (change) {
                 lif.vlim = vlim_side;
                 lif.k = (uint8_t)((int)li.k + side);
@@ -423,11 +445,14 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             const float free_f = change ? free_t : free_c;
             const bool inlane = change ? hasLt : hasLc;
             float acc;
-            uint32_t lead_id;
+            bool has_lead;
+            float lead_v, lead_gap;
             if (inlane) {
                 // same operands as MOBIL's own-lane / target-lane evaluation
-                acc = mobil ? (change ? acc_t : acc_c)
-                            : idm_lead(P, free_f, v, vLc, (sLc - P.len) - s);
+                has_lead = true;
+                lead_v = change ? vLt : vLc;
+                lead_gap = ((change ? sLt : sLc) - P.len) - s;
+                acc = mobil ? (change ? acc_t : acc_c) : idm_lead(P, free_f, v, vLc, lead_gap);
                 lead_id = change ? idLt : w_id[x_i + 1];
             } else {
                 if (!rd_ok && nxt >= 0) {
@@ -436,6 +461,9 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 }
                 const Lead ld = lookahead(d, lif, s, id, ptr, nxt, rd_next);
                 if (ld.has) flags |= 8;
+                has_lead = ld.has;
+                lead_v = ld.v;
+                lead_gap = ld.gap;
                 acc = idm_any(P, free_f, ld.has, v, ld.v, ld.gap);
                 lead_id = ld.id;
             }
@@ -445,7 +473,53 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 flags |= 4;
             }
             a = fmax32(-P.b_max, acc);
+            a_idm = a;
+            if (want_feat) {
+                // inputs of the learned closure
+                feat[0] = has_lead ? fmin32(lead_gap, P.d_look) : P.d_look;
+                feat[1] = v;
+                feat[2] = has_lead ? lead_v : v;
+                feat[3] = fmin32(v0, lif.vlim);
+                feat[4] = red ? fmin32(L - s, P.d_look) : P.d_look;
+                feat[5] = a_prev;
+                feat[6] = fmin32(L - s, P.d_look);
+                feat[7] = lif.vlim;
+            }
+        }
 
+        if constexpr (MODE == 1) {
+            // learned closure for the whole wave; inside the envelope it
+            // replaces the IDM acceleration, limited to [-b_max, a_max]
+            const float *nm = mw->norm;
+            bool inside = act;
+            float z[kMlpIn];
+#pragma unroll
+            for (int q = 0; q < kMlpIn; ++q) {
+                if (!(feat[q] >= nm[16 + q] && feat[q] <= nm[24 + q]))
+                    inside = false;
+                z[q] = act ? (feat[q] - nm[q]) * nm[8 + q] : 0.0f;
+            }
+            const float y = wave_mlp(*mw, mz, z);
+            double e2 = 0.0;
+            if (inside) {
+                const float am = fmax32(-P.b_max, fmin32(y, P.a_max));
+                const double e = (double)am - (double)a;
+                e2 = e * e;
+                a = am;
+            }
+            wave_count(d.cnt + C_MLP_EVAL, inside, li.scen, scen0, uni_scen);
+            wave_count(d.cnt + C_MLP_FALLBACK, act && !inside, li.scen, scen0, uni_scen);
+            if (uni_scen) {
+                for (int off = 32; off > 0; off >>= 1)
+                    e2 += __shfl_xor(e2, off);
+                if (__lane_id() == 0 && e2 != 0.0)
+                    atomicAdd(d.mlp_sq + scen0, e2);
+            } else if (inside) {
+                atomicAdd(d.mlp_sq + li.scen, e2);
+            }
+        }
+
+        if (act) {
             // Newton's equations over one step, stopping at v = 0
             vn = v + a * P.dt;
             float dx;
@@ -486,6 +560,12 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 d.d_margin[i] = margin;
                 d.d_tl[i] = tl_id;
                 d.d_tf[i] = tf_id;
+            }
+            if (P.trace) {
+#pragma unroll
+                for (int q = 0; q < kMlpIn; ++q)
+                    d.tr_feat[(size_t)i * kMlpIn + q] = feat[q];
+                d.tr_label[i] = a_idm;
             }
         }
 
@@ -792,8 +872,8 @@ constexpr int kMT = 256;          // threads per merge block (4 waves)
 constexpr int kMC = kMergeRows;   // new rows per chunk
 constexpr int kOldCap = 3 * kMT;  // old rows staged per chunk (3 per thread)
 constexpr int kNewCap = 3 * kMT;  // new rows staged per chunk
-constexpr int kJCap = kMT;        // joiners staged per chunk (1 per thread)
-constexpr int kLaneCap = 256;     // owned lanes whose starts are cached in LDS
+constexpr int kJCap = 192;        // joiners staged per chunk (at most 1 per thread)
+constexpr int kLaneCap = 128;     // owned lanes whose starts are cached in LDS
 constexpr uint32_t kTagJ = 0x80000000u;
 constexpr uint32_t kNoSrc = 0xFFFFFFFFu;
 
@@ -1260,8 +1340,14 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
         hipLaunchKernelGGL(k_insert, dim3(blocks_for(d.n_qlanes, 256)), dim3(256), 0, st, d);
     mark(1);
     unsigned gu = blocks_for(d.cap, kUT);
-    if (gu > 16384) gu = 16384;
-    hipLaunchKernelGGL(k_update, dim3(gu), dim3(kUT), 0, st, d);
+    if (d.mode == 1) {
+        // fewer, longer-lived blocks: each converts the network weights once
+        if (gu > 1024) gu = 1024;
+        hipLaunchKernelGGL(k_update<1>, dim3(gu), dim3(kUT), 0, st, d);
+    } else {
+        if (gu > 16384) gu = 16384;
+        hipLaunchKernelGGL(k_update<0>, dim3(gu), dim3(kUT), 0, st, d);
+    }
     mark(2);
     const unsigned gs = blocks_for(d.n_lanes, kScanLanes);
     hipLaunchKernelGGL(k_scan_reduce, dim3(gs), dim3(kScanThreads), 0, st, d);

@@ -1,0 +1,285 @@
+// Training and batch inference of the learned car-following closure.
+//
+// Training step on a batch of n samples (features x[8], label a_idm):
+//   k_mlp_fwdbwd  one wave per sample, lane j = hidden unit j: forward pass,
+//                 squared error, and the per-sample deltas of both hidden
+//                 layers (backpropagation through GELU);
+//   k_mlp_partial one thread per parameter and slice of the batch: sums of
+//                 delta x input over the slice;
+//   k_mlp_sum     adds the slices into the gradient and the loss;
+//   k_mlp_adam    Adam update of the FP32 master parameters.
+// In bfloat16 mode the weights and layer inputs are rounded to bfloat16 as in
+// the simulator's inference; gradients are taken with respect to the rounded
+// weights and applied to the master copy.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "../../include/moss.h"
+#include "moss_mlp.h"
+
+using namespace moss;
+
+namespace {
+
+constexpr int kSlice = 256;         // samples per partial gradient sum
+
+__device__ __forceinline__ float rnd(float x, bool bf) { return bf ? bf2f(f2bf(x)) : x; }
+
+// exact tanh-form GELU and its derivative for training (FP32)
+__device__ __forceinline__ float gelu_t(float x, float &dgdx)
+{
+    const float k0 = 0.7978845608f, k1 = 0.044715f;
+    const float u = k0 * (x + k1 * (x * x * x));
+    const float t = tanhf(u);
+    dgdx = 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * k0 * (1.0f + 3.0f * k1 * (x * x));
+    return 0.5f * x * (1.0f + t);
+}
+
+// Scratch per sample: z[8], h1q[64], h2q[64], da1[64], da2[64], dy, sq.
+struct Scratch {
+    float *z, *h1, *h2, *da1, *da2, *dy, *sq, *part;
+};
+
+__global__ void __launch_bounds__(256) k_mlp_fwdbwd(const float *feat, const float *label,
+                                                   const int32_t *idx, int n, const float *theta,
+                                                   const float *norm, int bf, Scratch sc)
+{
+    __shared__ float W2s[kMlpH * kMlpH];
+    const bool b16 = bf != 0;
+    for (int q = threadIdx.x; q < kMlpH * kMlpH; q += blockDim.x)
+        W2s[q] = rnd(theta[kOffW2 + q], b16);
+    __syncthreads();
+    const int j = __lane_id();
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    float w1[kMlpIn];
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i)
+        w1[i] = rnd(theta[kOffW1 + j * kMlpIn + i], b16);
+    const float b1 = theta[kOffB1 + j], b2 = theta[kOffB2 + j];
+    const float w3 = rnd(theta[kOffW3 + j], b16), b3 = theta[kOffB3];
+    for (int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < n; b += waves) {
+        const int src = idx ? idx[b] : b;
+        float z[kMlpIn];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i)
+            z[i] = rnd((feat[(size_t)src * kMlpIn + i] - norm[i]) * norm[kMlpIn + i], b16);
+        float a1 = b1;
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i)
+            a1 += w1[i] * z[i];
+        float g1;
+        const float h1 = rnd(gelu_t(a1, g1), b16);
+        float a2 = b2;
+        for (int i = 0; i < kMlpH; ++i)
+            a2 += W2s[j * kMlpH + i] * __shfl(h1, i);
+        float g2;
+        const float h2 = rnd(gelu_t(a2, g2), b16);
+        float y = w3 * h2;
+        for (int off = 32; off > 0; off >>= 1)
+            y += __shfl_xor(y, off);
+        y += b3;
+        const float r = y - label[src];
+        const float dy = 2.0f * r / (float)n;
+        const float da2 = dy * w3 * g2;
+        float s = 0.0f;
+        for (int k = 0; k < kMlpH; ++k)
+            s += __shfl(da2, k) * W2s[k * kMlpH + j];
+        const float da1 = s * g1;
+        const size_t o = (size_t)b * kMlpH + j;
+        sc.h1[o] = h1;
+        sc.h2[o] = h2;
+        sc.da1[o] = da1;
+        sc.da2[o] = da2;
+        if (j < kMlpIn)
+            sc.z[(size_t)b * kMlpIn + j] = z[j];
+        if (j == 0) {
+            sc.dy[b] = dy;
+            sc.sq[b] = r * r;
+        }
+    }
+}
+
+// part[slice][param]: sum over the slice's samples of the parameter's gradient
+__global__ void __launch_bounds__(256) k_mlp_partial(int n, Scratch sc)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int slice = blockIdx.y;
+    if (p >= kMlpParams)
+        return;
+    const int b0 = slice * kSlice, b1 = min(n, b0 + kSlice);
+    float acc = 0.0f;
+    if (p < kOffB1) {                     // W1[j][i]
+        const int jj = p / kMlpIn, ii = p % kMlpIn;
+        for (int b = b0; b < b1; ++b)
+            acc += sc.da1[(size_t)b * kMlpH + jj] * sc.z[(size_t)b * kMlpIn + ii];
+    } else if (p < kOffW2) {              // b1[j]
+        const int jj = p - kOffB1;
+        for (int b = b0; b < b1; ++b)
+            acc += sc.da1[(size_t)b * kMlpH + jj];
+    } else if (p < kOffB2) {              // W2[j][i]
+        const int q = p - kOffW2, jj = q / kMlpH, ii = q % kMlpH;
+        for (int b = b0; b < b1; ++b)
+            acc += sc.da2[(size_t)b * kMlpH + jj] * sc.h1[(size_t)b * kMlpH + ii];
+    } else if (p < kOffW3) {              // b2[j]
+        const int jj = p - kOffB2;
+        for (int b = b0; b < b1; ++b)
+            acc += sc.da2[(size_t)b * kMlpH + jj];
+    } else if (p < kOffB3) {              // w3[i]
+        const int ii = p - kOffW3;
+        for (int b = b0; b < b1; ++b)
+            acc += sc.dy[b] * sc.h2[(size_t)b * kMlpH + ii];
+    } else {                              // b3
+        for (int b = b0; b < b1; ++b)
+            acc += sc.dy[b];
+    }
+    sc.part[(size_t)slice * kMlpParams + p] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_sum(int n, int nslice, Scratch sc, float *grad,
+                                                float *loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kMlpParams) {
+        float acc = 0.0f;
+        for (int s = 0; s < nslice; ++s)
+            acc += sc.part[(size_t)s * kMlpParams + p];
+        grad[p] = acc;
+    }
+    if (blockIdx.x == 0) {
+        __shared__ float red[256];
+        float s = 0.0f;
+        for (int b = threadIdx.x; b < n; b += blockDim.x)
+            s += sc.sq[b];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off)
+                red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && loss)
+            *loss = red[0] / (float)n;
+    }
+}
+
+__global__ void k_mlp_adam(float *theta, float *m, float *v, const float *grad, float lr,
+                           float beta1, float beta2, float eps, float c1, float c2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams)
+        return;
+    const float g = grad[p];
+    const float mm = beta1 * m[p] + (1.0f - beta1) * g;
+    const float vv = beta2 * v[p] + (1.0f - beta2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float mh = mm / c1, vh = vv / c2;
+    theta[p] = theta[p] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// Batch inference with the simulator's matrix-core path (one wave per 64
+// samples).
+__global__ void __launch_bounds__(256) k_mlp_predict(const float *feat, int n, const float *theta,
+                                                    const float *norm, float *out)
+{
+    __shared__ MlpLds w;
+    __shared__ uint16_t zs[4 * 64 * kMlpIn];
+    mlp_load(w, theta, norm);
+    __syncthreads();
+    const int wv = threadIdx.x >> 6;
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int i = base + threadIdx.x;
+        float z[kMlpIn];
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k)
+            z[k] = (i < n) ? (feat[(size_t)i * kMlpIn + k] - w.norm[k]) * w.norm[kMlpIn + k] : 0.0f;
+        const float y = wave_mlp(w, zs + wv * 64 * kMlpIn, z);
+        if (i < n)
+            out[i] = y;
+        __syncthreads();
+    }
+}
+
+thread_local std::string g_mlp_err;
+
+}  // namespace
+
+extern "C" {
+
+size_t moss_mlp_scratch_bytes(int32_t n)
+{
+    const size_t b = n > 0 ? (size_t)n : 1;
+    const size_t nslice = (b + kSlice - 1) / kSlice;
+    return 4 * (b * (kMlpIn + 4 * kMlpH + 2) + nslice * kMlpParams) + 1024;
+}
+
+int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_idx, int32_t n,
+                  const float *d_theta, const float *d_norm, int32_t bf16, float *d_grad,
+                  float *d_loss, void *d_scratch, size_t scratch_bytes, void *stream)
+{
+    if (n <= 0 || !d_feat || !d_label || !d_theta || !d_norm || !d_grad || !d_scratch)
+        return MOSS_EINVAL;
+    if (scratch_bytes < moss_mlp_scratch_bytes(n))
+        return MOSS_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t b = (size_t)n;
+    const int nslice = (n + kSlice - 1) / kSlice;
+    Scratch sc;
+    float *f = (float *)d_scratch;
+    sc.z = f;
+    f += b * kMlpIn;
+    sc.h1 = f;
+    f += b * kMlpH;
+    sc.h2 = f;
+    f += b * kMlpH;
+    sc.da1 = f;
+    f += b * kMlpH;
+    sc.da2 = f;
+    f += b * kMlpH;
+    sc.dy = f;
+    f += b;
+    sc.sq = f;
+    f += b;
+    sc.part = f;
+    unsigned g = (unsigned)((n + 3) / 4);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(g), dim3(256), 0, st, d_feat, d_label, d_idx, n,
+                       d_theta, d_norm, bf16, sc);
+    hipLaunchKernelGGL(k_mlp_partial, dim3((kMlpParams + 255) / 256, nslice), dim3(256), 0, st,
+                       n, sc);
+    hipLaunchKernelGGL(k_mlp_sum, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, n, nslice,
+                       sc, d_grad, d_loss);
+    return hipGetLastError() == hipSuccess ? MOSS_OK : MOSS_EDEVICE;
+}
+
+int moss_mlp_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int32_t step,
+                  float lr, float beta1, float beta2, float eps, void *stream)
+{
+    if (!d_theta || !d_m || !d_v || !d_grad || step < 1)
+        return MOSS_EINVAL;
+    const double c1 = 1.0 - std::pow((double)beta1, (double)step);
+    const double c2 = 1.0 - std::pow((double)beta2, (double)step);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, d_theta, d_m, d_v, d_grad, lr, beta1, beta2, eps,
+                       (float)c1, (float)c2);
+    return hipGetLastError() == hipSuccess ? MOSS_OK : MOSS_EDEVICE;
+}
+
+int moss_mlp_predict(const float *d_feat, int32_t n, const float *d_theta, const float *d_norm,
+                     float *d_out, void *stream)
+{
+    if (n < 0 || !d_feat || !d_theta || !d_norm || !d_out)
+        return MOSS_EINVAL;
+    if (n == 0)
+        return MOSS_OK;
+    unsigned g = (unsigned)((n + 255) / 256);
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_mlp_predict, dim3(g), dim3(256), 0, (hipStream_t)stream, d_feat, n,
+                       d_theta, d_norm, d_out);
+    return hipGetLastError() == hipSuccess ? MOSS_OK : MOSS_EDEVICE;
+}
+
+}  // extern "C"

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "_build", "libmoss.so")
 
 MOSS_OK, MOSS_EINVAL, MOSS_ENOMEM, MOSS_EDEVICE, MOSS_ESTATE = 0, -1, -2, -3, -4
 MOSS_FLAG_DEBUG = 1
+MOSS_FLAG_TRACE = 2
+MOSS_MODE_IDM, MOSS_MODE_MLP = 0, 1
+MLP_PARAMS, MLP_NORM = 4801, 32
 COUNTER_NAMES = ("inserted", "insert_fail", "arrived", "trip_time", "clamps", "lane_changes",
                  "veh_steps", "mlp_eval", "mlp_fallback")
 NONE = 0xFFFFFFFF
@@ -46,7 +49,8 @@ class moss_params(C.Structure):
                 ("T", C.c_float), ("length", C.c_float), ("b_max", C.c_float),
                 ("b_safe", C.c_float), ("politeness", C.c_float), ("a_thr", C.c_float),
                 ("p_lc", C.c_float), ("d_look", C.c_float), ("h_look", C.c_int32),
-                ("t0", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32)]
+                ("t0", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32),
+                ("mode", C.c_int32), ("mlp_theta", vp), ("mlp_norm", vp)]
 
 
 class moss_state_out(C.Structure):
@@ -57,7 +61,8 @@ class moss_state_out(C.Structure):
 
 EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state",
            "moss_read_counters", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
-           "moss_destroy", "moss_last_error")
+           "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_adam", "moss_mlp_predict",
+           "moss_read_trace", "moss_read_mlp_error", "moss_destroy", "moss_last_error")
 
 _lib = None
 
@@ -84,9 +89,18 @@ def load(path: str = LIB_PATH):
     L.moss_step_timed.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
     L.moss_kernel_name.argtypes = [C.c_int32]
     L.moss_destroy.argtypes = [vp]
+    L.moss_mlp_scratch_bytes.argtypes = [C.c_int32]
+    L.moss_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, vp, C.c_int32, vp, vp, vp, C.c_size_t,
+                                vp]
+    L.moss_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                C.c_float, vp]
+    L.moss_mlp_predict.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    L.moss_read_trace.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]
+    L.moss_read_mlp_error.argtypes = [vp, vp]
     for f in EXPORTS:
         getattr(L, f).restype = C.c_char_p if f in ("moss_last_error", "moss_kernel_name") \
             else C.c_int
+    L.moss_mlp_scratch_bytes.restype = C.c_size_t
     _lib = L
     return L
 
@@ -106,7 +120,7 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(vp)
 
 
-def marshal(sc, debug: bool = False):
+def marshal(sc, debug: bool = False, trace: bool = False):
     """C structs (and the numpy arrays they point to) for a Scenario."""
     keep = []
 
@@ -128,10 +142,14 @@ def marshal(sc, debug: bool = False):
                         arr(sc.lane, np.int32), arr(sc.cursor, np.int32), arr(sc.s, np.float32),
                         arr(sc.v, np.float32), arr(sc.a, np.float32))
     p = sc.params
+    flags = (MOSS_FLAG_DEBUG if debug else 0) | (MOSS_FLAG_TRACE if trace else 0)
+    mlp_cfg = p.get("mlp")
     prm = moss_params(p["dt"], p["a_max"], p["b"], p["s0"], p["T"], p["length"], p["b_max"],
                       p["b_safe"], p["politeness"], p["a_thr"], p["p_lc"], p["d_look"],
-                      int(p["h_look"]), int(p["t0"]), int(p["seed"]),
-                      MOSS_FLAG_DEBUG if debug else 0)
+                      int(p["h_look"]), int(p["t0"]), int(p["seed"]), flags,
+                      MOSS_MODE_MLP if mlp_cfg is not None else MOSS_MODE_IDM,
+                      arr(mlp_cfg["theta"], np.float32) if mlp_cfg is not None else None,
+                      arr(mlp_cfg["norm"], np.float32) if mlp_cfg is not None else None)
     return net, sig, veh, prm, keep
 
 
@@ -185,6 +203,40 @@ def moss_step_timed(h: int, n: int):
     return {load().moss_kernel_name(i).decode(): float(ms[i]) for i in range(k.value)}
 
 
+def _dp(x):
+    return None if x is None else vp(x.data_ptr())
+
+
+def mlp_grad(feat, label, theta, norm, *, idx=None, bf16=True, stream=None):
+    """(loss, grad) of the closure on a batch of device tensors."""
+    import torch
+    n = int(idx.shape[0]) if idx is not None else int(feat.shape[0])
+    nb = int(load().moss_mlp_scratch_bytes(n))
+    scratch = torch.empty(nb, dtype=torch.uint8, device=feat.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feat.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    st = (stream or torch.cuda.current_stream(feat.device)).cuda_stream
+    _check(load().moss_mlp_grad(_dp(feat), _dp(label), _dp(idx), n, _dp(theta), _dp(norm),
+                                1 if bf16 else 0, _dp(grad), _dp(loss), _dp(scratch), nb, vp(st)))
+    return loss, grad
+
+
+def mlp_adam(theta, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    import torch
+    st = (stream or torch.cuda.current_stream(theta.device)).cuda_stream
+    _check(load().moss_mlp_adam(_dp(theta), _dp(m), _dp(v), _dp(grad), int(step), lr, beta1,
+                                beta2, eps, vp(st)))
+
+
+def mlp_predict(feat, theta, norm, stream=None):
+    import torch
+    out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+    st = (stream or torch.cuda.current_stream(feat.device)).cuda_stream
+    _check(load().moss_mlp_predict(_dp(feat), int(feat.shape[0]), _dp(theta), _dp(norm),
+                                   _dp(out), vp(st)))
+    return out
+
+
 def moss_destroy(h: int):
     _check(load().moss_destroy(vp(h)))
 
@@ -196,13 +248,14 @@ def moss_last_error() -> str:
 class Simulator:
     """A simulation of one Scenario on the current torch device and stream."""
 
-    def __init__(self, sc, *, debug: bool = False, device: Optional[int] = None, stream=None):
+    def __init__(self, sc, *, debug: bool = False, trace: bool = False,
+                 device: Optional[int] = None, stream=None):
         import torch
         load()
         self.sc = sc
         self.n_scen = sc.n_scen
         self.cap = max(sc.n_veh, 1)
-        net, sig, veh, prm, keep = marshal(sc, debug)
+        net, sig, veh, prm, keep = marshal(sc, debug, trace)
         nbytes = moss_query_workspace(net, sig, veh, prm)
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -266,6 +319,28 @@ class Simulator:
 
     def step_timed(self, n: int):
         return moss_step_timed(self.h, n)
+
+    def trace(self, device: bool = True):
+        """(features [n, 8], IDM labels [n]) of the last step."""
+        import torch
+        c = self.cap
+        if device:
+            f = torch.empty((c, MLP_NORM // 4), dtype=torch.float32, device=self.ws.device)
+            y = torch.empty(c, dtype=torch.float32, device=self.ws.device)
+            fp, yp = f.data_ptr(), y.data_ptr()
+        else:
+            f = np.empty((c, MLP_NORM // 4), np.float32)
+            y = np.empty(c, np.float32)
+            fp, yp = f.ctypes.data, y.ctypes.data
+        n = C.c_int32(0)
+        _check(load().moss_read_trace(vp(self.h), c, 1 if device else 0, vp(fp), vp(yp),
+                                      C.byref(n)))
+        return f[:n.value], y[:n.value]
+
+    def mlp_error(self):
+        out = np.zeros(self.n_scen, np.float64)
+        _check(load().moss_read_mlp_error(vp(self.h), _ptr(out)))
+        return out
 
     def debug(self):
         return moss_read_debug(self.h, self.cap)

@@ -18,7 +18,7 @@ def declared_functions():
     for f in os.listdir(os.path.join(ROOT, "include")):
         if f.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", f)).read()
-            names |= set(re.findall(r"^\s*(?:int|const char \*|void)\s*\*?\s*(moss_\w+)\s*\(",
+            names |= set(re.findall(r"^\s*(?:int|size_t|const char \*|void)\s*\*?\s*(moss_\w+)\s*\(",
                                     txt, re.M))
     return sorted(names)
 
