@@ -67,6 +67,87 @@ def cpu_baseline(sc, steps):
                        f"({dt:.1f} s)")
 
 
+MLP_FLOP = 2 * (8 * 64 + 64 * 64 + 64)      # multiply-adds of one evaluation, x2
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def timed_steps(sim, steps):
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    c0 = sim.counters()[0]
+    ev0.record(sim.stream)
+    sim.step(steps)
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    c1 = sim.counters()[0]
+    return ev0.elapsed_time(ev1), c1 - c0
+
+
+def bench_mlp(sc, args):
+    """Same city snapshot with the learned closure (trained on the 10x10 grid
+    workload) in place of IDM inside its envelope."""
+    import torch
+    from paper_2405_12520_amd import closure
+    from paper_2405_12520_amd.moss import Simulator
+    path = closure.DEFAULT_PATH
+    if os.path.exists(path):
+        theta, norm = closure.load(path)
+        src = "loaded " + os.path.relpath(path, ROOT)
+    else:
+        say("[bench] training the closure on the grid workload")
+        theta, norm, _ = closure.build_closure(path, log=say)
+        src = "trained in this run"
+    sim = Simulator(sc.with_params(mlp=dict(theta=theta, norm=norm)))
+    sim.step(args.warmup)
+    sq0 = sim.mlp_error().sum()
+    ms, dc = timed_steps(sim, args.steps)
+    sq1 = sim.mlp_error().sum()
+    veh_steps = int(dc[:, 6].sum())
+    n_eval = int(dc[:, 7].sum())
+    n_fb = int(dc[:, 8].sum())
+    kms = sim.step_timed(20)
+    upd_ms = kms["k_update"] / 20
+    evals_per_launch = n_eval / args.steps
+    tflops = evals_per_launch * MLP_FLOP / (upd_ms * 1e-3) / 1e12
+    sim.close()
+    torch.cuda.empty_cache()
+    rms = float(np.sqrt((sq1 - sq0) / max(n_eval, 1)))
+    say(f"[bench] mlp mode: {veh_steps / (ms / 1e3):.4g} vehicle-steps/s, RMS vs IDM {rms:.4f}, "
+        f"fallback {n_fb / max(veh_steps, 1):.4f}")
+    return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
+                ms_per_step=round(ms / args.steps, 5), rms_accel_error_vs_idm=round(rms, 5),
+                fallback_rate=round(n_fb / max(veh_steps, 1), 5), weights=src,
+                roofline=dict(bound="mfma", kernel="k_update<mlp>", dtype="bf16",
+                              achieved=round(tflops, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=round(tflops / BF16_PEAK_TFLOPS, 5),
+                              flop_per_eval=MLP_FLOP, kernel_ms=round(upd_ms, 5)))
+
+
+def bench_batch(args):
+    """Disjoint union of independent grid scenarios (4x4 .. 16x16, 1k..50k
+    vehicles each, departures over 1800 s) stepped as one network through the
+    captured step graphs; timed after a warm-up into the departure period."""
+    import torch
+    from paper_2405_12520_amd import scenarios as S
+    from paper_2405_12520_amd.moss import Simulator
+    t0 = time.time()
+    sc = S.batch(args.batch_scenarios)
+    say(f"[bench] batch generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    sim = Simulator(sc)
+    sim.step(600)
+    ms, dc = timed_steps(sim, args.steps)
+    veh_steps = int(dc[:, 6].sum())
+    sim.close()
+    torch.cuda.empty_cache()
+    say(f"[bench] batch: {veh_steps / (ms / 1e3):.4g} vehicle-steps/s")
+    return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
+                ms_per_step=round(ms / args.steps, 5), scenarios=int(sc.n_scen),
+                vehicles_total=int(sc.n_veh), active_mean=round(veh_steps / args.steps, 1),
+                window="steps 600..600+K of 1800", lanes=int(sc.n_lanes))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +158,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3)")
+    ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-scenarios", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also copy a device buffer of this size once (calibrates the HBM "
                          "byte counters of a profiler run against a known transfer)")
@@ -148,6 +232,11 @@ def main():
     del sim
     torch.cuda.empty_cache()
 
+    extras = {}
+    if not args.no_mlp:
+        extras["mlp"] = bench_mlp(sc, args)
+    if not args.no_batch:
+        extras["batch"] = bench_batch(args)
     cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_steps)
     out = dict(metric=METRIC, value=round(value, 1), unit="vehicle-steps/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms / args.steps, 5),
@@ -157,7 +246,7 @@ def main():
                                     "IDM car-following + randomised MOBIL, dt = 1 s",
                            vehicles=int(sc.n_veh), lanes=int(sc.n_lanes), roads=int(sc.n_roads),
                            nodes=int(sc.n_nodes), active_vehicles=int(n_act)),
-               roofline=roofline, cpu_baseline=cpu)
+               roofline=roofline, cpu_baseline=cpu, **extras)
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,146 @@
+"""Training pipeline of the learned car-following closure.
+
+1. Trajectories: the 10 x 10 grid workload (20k vehicles, shortest-path
+   demand over an hour) runs in IDM mode with the trace on; every step yields,
+   for each active vehicle, the 8 closure inputs and the IDM acceleration
+   (the label).  Steps are split into training and held-out sets by step
+   index (every 10th step is held out).
+2. Input description: per-input mean and standard deviation for the
+   normalisation, and the [0.1, 99.9] percentile range as the envelope
+   outside which the simulator keeps IDM.
+3. Training: Adam on mean squared error with batches drawn on the GPU,
+   forward/backward through the project's kernels (moss_mlp_grad), in
+   bfloat16 mode so that training sees the simulator's rounding.
+
+All arithmetic runs in libmoss kernels; this module only sequences calls and
+keeps tensors.
+"""
+from __future__ import annotations
+
+import os
+import time
+from typing import Dict
+
+import numpy as np
+
+from . import moss
+from . import scenarios as S
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "data", "closure_grid10.npz")
+MLP_PARAMS = moss.MLP_PARAMS
+
+
+def collect(steps: int = 3600, n_veh: int = 20000, hold_every: int = 10, log=print):
+    """Traces the grid workload; returns device tensors (features, labels,
+    step index) of all vehicle-steps."""
+    import torch
+    sc = S.grid(10, n_veh)
+    sim = moss.Simulator(sc, trace=True)
+    feats, labs, steps_idx = [], [], []
+    t0 = time.time()
+    for k in range(steps):
+        sim.step(1)
+        f, y = sim.trace(device=True)
+        if f.shape[0]:
+            feats.append(f.clone())
+            labs.append(y.clone())
+            steps_idx.append(torch.full((f.shape[0],), k, dtype=torch.int32, device=f.device))
+        if log and (k + 1) % 600 == 0:
+            log(f"[closure] traced {k + 1} steps, {sum(x.shape[0] for x in labs)} samples, "
+                f"{time.time() - t0:.1f} s")
+    sim.close()
+    F = torch.cat(feats)
+    Y = torch.cat(labs)
+    K = torch.cat(steps_idx)
+    return F, Y, K
+
+
+def describe(F) -> np.ndarray:
+    """mean[8], inv_std[8], lo[8], hi[8] of the training inputs."""
+    import torch
+    f = F.double()
+    mean = f.mean(0)
+    std = f.std(0).clamp_min(1e-3)
+    q = torch.tensor([0.001, 0.999], dtype=torch.float64, device=F.device)
+    # torch.quantile limits its input size; every k-th row of each input
+    step = max(1, f.shape[0] // 1_000_000)
+    lohi = torch.stack([torch.quantile(f[::step, c], q) for c in range(f.shape[1])], dim=1)
+    out = torch.cat([mean, 1.0 / std, lohi[0], lohi[1]]).float().cpu().numpy()
+    return out
+
+
+def he_init(seed: int) -> np.ndarray:
+    """He-style uniform initialisation of the parameter vector (seeded)."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, 64 * 8) * np.sqrt(3.0 / 8), np.zeros(64),
+             rng.uniform(-1, 1, 64 * 64) * np.sqrt(3.0 / 64), np.zeros(64),
+             rng.uniform(-1, 1, 64) * np.sqrt(3.0 / 64), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fit(F, Y, norm: np.ndarray, *, steps: int = 6000, batch: int = 4096, lr: float = 1e-3,
+        seed: int = 0, bf16: bool = True, log=print):
+    """Adam training on the GPU through moss_mlp_grad / moss_mlp_adam;
+    cosine-decayed learning rate; returns the FP32 master parameters."""
+    import torch
+    dev = F.device
+    N = torch.from_numpy(norm).to(dev)
+    th = torch.from_numpy(he_init(seed)).to(dev)
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    n = F.shape[0]
+    t0 = time.time()
+    for s in range(1, steps + 1):
+        idx = torch.randint(0, n, (batch,), device=dev, generator=gen, dtype=torch.int32)
+        loss, g = moss.mlp_grad(F, Y, th, N, idx=idx, bf16=bf16)
+        lr_s = lr * 0.5 * (1.0 + np.cos(np.pi * (s - 1) / steps)) + 1e-5
+        moss.mlp_adam(th, m, v, g, s, lr=float(lr_s))
+        if log and s % 1000 == 0:
+            log(f"[closure] step {s}: batch loss {float(loss.item()):.4f} "
+                f"({time.time() - t0:.1f} s)")
+    return th.cpu().numpy()
+
+
+def rms(F, Y, theta: np.ndarray, norm: np.ndarray, inside_only: bool = True) -> Dict[str, float]:
+    """RMS error of the network (simulator inference path) against the labels."""
+    import torch
+    dev = F.device
+    pred = moss.mlp_predict(F, torch.from_numpy(theta).to(dev), torch.from_numpy(norm).to(dev))
+    lo = torch.from_numpy(norm[16:24]).to(dev)
+    hi = torch.from_numpy(norm[24:32]).to(dev)
+    inside = ((F >= lo) & (F <= hi)).all(1)
+    amax, bmax = S.DEFAULT_PARAMS["a_max"], S.DEFAULT_PARAMS["b_max"]
+    p = pred.clamp(-bmax, amax)
+    e = (p - Y)[inside] if inside_only else (p - Y)
+    return dict(rms=float(torch.sqrt((e.double() ** 2).mean()).item()),
+                inside=float(inside.double().mean().item()), n=int(e.shape[0]))
+
+
+def build_closure(path: str = DEFAULT_PATH, *, steps_trace: int = 3600, train_steps: int = 6000,
+                  log=print):
+    """Full pipeline; writes theta and norm to path (npz) and returns them."""
+    import torch
+    F, Y, K = collect(steps_trace, log=log)
+    held = (K % 10) == 9
+    Ftr, Ytr = F[~held], Y[~held]
+    norm = describe(Ftr)
+    theta = fit(Ftr, Ytr, norm, steps=train_steps, log=log)
+    ev = rms(F[held], Y[held], theta, norm)
+    if log:
+        log(f"[closure] held-out RMS {ev['rms']:.4f} m/s^2 on {ev['n']} samples, "
+            f"{100 * ev['inside']:.2f} % inside the envelope")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, theta=theta, norm=norm, heldout_rms=ev["rms"], inside=ev["inside"])
+    del torch
+    return theta, norm, ev
+
+
+def load(path: str = DEFAULT_PATH):
+    z = np.load(path)
+    return z["theta"].astype(np.float32), z["norm"].astype(np.float32)
+
+
+if __name__ == "__main__":
+    build_closure()
