@@ -218,14 +218,17 @@ const char *moss_kernel_name(int32_t i);
 /* Scratch bytes moss_mlp_grad needs for a batch of n samples. */
 size_t moss_mlp_scratch_bytes(int32_t n);
 
-/* Mean squared error of the network on n samples (features feat[idx[b]][8],
- * labels label[idx[b]]; idx = NULL means b itself) and its gradient with
- * respect to theta (float[MOSS_MLP_PARAMS]).  bf16 = 1 rounds weights and
- * layer inputs to bfloat16 as the simulator does.  loss may be NULL.
- * MOSS_EINVAL on bad arguments, MOSS_ENOMEM if scratch is too small. */
+/* Mean squared error of the network's output limited to [out_lo, out_hi]
+ * (as the simulator limits it: -b_max, a_max) on n samples (features
+ * feat[idx[b]][8], labels label[idx[b]]; idx = NULL means b itself) and its
+ * gradient with respect to theta (float[MOSS_MLP_PARAMS]); the distance inputs
+ * 0, 4 and 6 enter as ln(max(x, 0.5)) before normalisation.  bf16 = 1 rounds
+ * weights and layer inputs to bfloat16 as the simulator does.  loss may be
+ * NULL.  MOSS_EINVAL on bad arguments, MOSS_ENOMEM if scratch is too small. */
 int moss_mlp_grad(const float *feat, const float *label, const int32_t *idx, int32_t n,
-                  const float *theta, const float *norm, int32_t bf16, float *grad, float *loss,
-                  void *scratch, size_t scratch_bytes, void *hip_stream);
+                  const float *theta, const float *norm, int32_t bf16, float out_lo,
+                  float out_hi, float *grad, float *loss, void *scratch, size_t scratch_bytes,
+                  void *hip_stream);
 
 /* One Adam step (Kingma & Ba) on theta with moments m, v (all
  * float[MOSS_MLP_PARAMS]); step counts from 1. */

@@ -30,6 +30,21 @@ K0 = math.sqrt(2.0 / math.pi)
 K1 = 0.044715
 
 
+LOG_INPUTS = (0, 4, 6)      # leader gap, red stop line, lane end: distances
+
+
+def normalise(feat, norm):
+    """Network input from the 8 raw inputs: the distances enter as
+    ln(max(x, 0.5 m)), then z = (x' - mean) * inv_std (FP32 as the simulator
+    computes it; the log in FP64 then rounded)."""
+    f = np.asarray(feat, dtype=np.float32).copy()
+    for q in LOG_INPUTS:
+        f[:, q] = np.log(np.maximum(f[:, q].astype(np.float64), 0.5)).astype(np.float32)
+    mean = np.asarray(norm[:8], np.float32)
+    inv = np.asarray(norm[8:16], np.float32)
+    return ((f - mean) * inv).astype(np.float32)
+
+
 def unpack(theta):
     theta = np.asarray(theta)
     out, o = {}, 0

@@ -565,7 +565,9 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
         float z[8];
         for (int q = 0; q < 8; ++q) {
             if (!(f[q] >= lo[q] && f[q] <= hi[q])) inside = 0;
-            z[q] = (f[q] - mean[q]) * inv[q];
+            /* distances (inputs 0, 4, 6) enter as ln(max(x, 0.5)) */
+            float xt = (q == 0 || q == 4 || q == 6) ? (float)log(fmax32(f[q], 0.5f)) : f[q];
+            z[q] = (xt - mean[q]) * inv[q];
         }
         size_t sc = (size_t)m->lane_scen[l];
         if (inside) {

@@ -56,12 +56,19 @@ def collect(steps: int = 3600, n_veh: int = 20000, hold_every: int = 10, log=pri
     return F, Y, K
 
 
+LOG_INPUTS = (0, 4, 6)      # distances enter the network as ln(max(x, 0.5 m))
+
+
 def describe(F) -> np.ndarray:
-    """mean[8], inv_std[8], lo[8], hi[8] of the training inputs."""
+    """mean[8], inv_std[8] of the network inputs (distances log-transformed)
+    and lo[8], hi[8] of the raw inputs (the envelope)."""
     import torch
     f = F.double()
-    mean = f.mean(0)
-    std = f.std(0).clamp_min(1e-3)
+    ft = f.clone()
+    for q in LOG_INPUTS:
+        ft[:, q] = torch.log(ft[:, q].clamp_min(0.5))
+    mean = ft.mean(0)
+    std = ft.std(0).clamp_min(1e-3)
     q = torch.tensor([0.001, 0.999], dtype=torch.float64, device=F.device)
     # torch.quantile limits its input size; every k-th row of each input
     step = max(1, f.shape[0] // 1_000_000)
@@ -79,10 +86,13 @@ def he_init(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def fit(F, Y, norm: np.ndarray, *, steps: int = 6000, batch: int = 4096, lr: float = 1e-3,
+def fit(F, Y, norm: np.ndarray, *, steps: int = 60000, batch: int = 4096, lr: float = 2e-3,
         seed: int = 0, bf16: bool = True, log=print):
-    """Adam training on the GPU through moss_mlp_grad / moss_mlp_adam;
-    cosine-decayed learning rate; returns the FP32 master parameters."""
+    """Adam training on the GPU through moss_mlp_grad / moss_mlp_adam with a
+    cosine-decayed learning rate, on the output limited as the simulator
+    limits it; the last quarter of the steps (all of them unless bf16)
+    rounds weights and activations to bfloat16 as the simulator does.
+    Returns the FP32 master parameters."""
     import torch
     dev = F.device
     N = torch.from_numpy(norm).to(dev)
@@ -94,10 +104,12 @@ def fit(F, Y, norm: np.ndarray, *, steps: int = 6000, batch: int = 4096, lr: flo
     t0 = time.time()
     for s in range(1, steps + 1):
         idx = torch.randint(0, n, (batch,), device=dev, generator=gen, dtype=torch.int32)
-        loss, g = moss.mlp_grad(F, Y, th, N, idx=idx, bf16=bf16)
+        q = bf16 and s > (3 * steps) // 4
+        loss, g = moss.mlp_grad(F, Y, th, N, idx=idx, bf16=q, out_lo=-S.DEFAULT_PARAMS["b_max"],
+                                out_hi=S.DEFAULT_PARAMS["a_max"])
         lr_s = lr * 0.5 * (1.0 + np.cos(np.pi * (s - 1) / steps)) + 1e-5
         moss.mlp_adam(th, m, v, g, s, lr=float(lr_s))
-        if log and s % 1000 == 0:
+        if log and s % 10000 == 0:
             log(f"[closure] step {s}: batch loss {float(loss.item()):.4f} "
                 f"({time.time() - t0:.1f} s)")
     return th.cpu().numpy()
@@ -118,7 +130,7 @@ def rms(F, Y, theta: np.ndarray, norm: np.ndarray, inside_only: bool = True) -> 
                 inside=float(inside.double().mean().item()), n=int(e.shape[0]))
 
 
-def build_closure(path: str = DEFAULT_PATH, *, steps_trace: int = 3600, train_steps: int = 6000,
+def build_closure(path: str = DEFAULT_PATH, *, steps_trace: int = 3600, train_steps: int = 60000,
                   log=print):
     """Full pipeline; writes theta and norm to path (npz) and returns them."""
     import torch

@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             for (int q = 0; q < kMlpIn; ++q) {
                 if (!(feat[q] >= nm[16 + q] && feat[q] <= nm[24 + q]))
                     inside = false;
-                z[q] = act ? (feat[q] - nm[q]) * nm[8 + q] : 0.0f;
+                z[q] = act ? mlp_in(q, feat[q], nm) : 0.0f;
             }
             const float y = wave_mlp(*mw, mz, z);
             double e2 = 0.0;

@@ -46,6 +46,15 @@ __device__ __forceinline__ float gelu_fast(float x)
     return 0.5f * x * (1.0f + t);
 }
 
+// Input preparation: the three distances (leader gap, red stop line, lane
+// end; inputs 0, 4, 6) enter as ln(max(x, 0.5 m)), the other inputs as they
+// are; then z = (x' - mean) * inv_std.  The envelope applies to the raw x.
+__device__ __forceinline__ float mlp_in(int q, float x, const float *norm)
+{
+    const float xt = (q == 0 || q == 4 || q == 6) ? logf(fmaxf(x, 0.5f)) : x;
+    return (xt - norm[q]) * norm[kMlpIn + q];
+}
+
 // Weights of one block, converted to bfloat16 once per block.
 struct MlpLds {
     uint16_t W1[kMlpH * kMlpIn];   // [hidden][input]

@@ -45,7 +45,8 @@ struct Scratch {
 
 __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const float *feat, const float *label,
                                                    const int32_t *idx, int n, const float *theta,
-                                                   const float *norm, int bf, Scratch sc)
+                                                   const float *norm, int bf, float out_lo,
+                                                   float out_hi, Scratch sc)
 {
     __shared__ float W2s[kMlpH * kMlpH];
     const bool b16 = bf != 0;
@@ -65,7 +66,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const float *feat, const flo
         float z[kMlpIn];
 #pragma unroll
         for (int i = 0; i < kMlpIn; ++i)
-            z[i] = rnd((feat[(size_t)src * kMlpIn + i] - norm[i]) * norm[kMlpIn + i], b16);
+            z[i] = rnd(mlp_in(i, feat[(size_t)src * kMlpIn + i], norm), b16);
         float a1 = b1;
 #pragma unroll
         for (int i = 0; i < kMlpIn; ++i)
@@ -81,8 +82,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const float *feat, const flo
         for (int off = 32; off > 0; off >>= 1)
             y += __shfl_xor(y, off);
         y += b3;
-        const float r = y - label[src];
-        const float dy = 2.0f * r / (float)n;
+        // residual of the output as the simulator uses it, limited to
+        // [lo_out, hi_out]; beyond the limits on the label's side the limit
+        // already matches and no gradient flows
+        const float lab = label[src];
+        const float yc = fminf(fmaxf(y, out_lo), out_hi);
+        const float r = yc - lab;
+        const float dy = (y == yc) ? 2.0f * r / (float)n : 0.0f;
         const float da2 = dy * w3 * g2;
         float s = 0.0f;
         for (int k = 0; k < kMlpH; ++k)
@@ -195,7 +201,7 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *feat, int n, c
         float z[kMlpIn];
 #pragma unroll
         for (int k = 0; k < kMlpIn; ++k)
-            z[k] = (i < n) ? (feat[(size_t)i * kMlpIn + k] - w.norm[k]) * w.norm[kMlpIn + k] : 0.0f;
+            z[k] = (i < n) ? mlp_in(k, feat[(size_t)i * kMlpIn + k], w.norm) : 0.0f;
         const float y = wave_mlp(w, zs + wv * 64 * kMlpIn, z);
         if (i < n)
             out[i] = y;
@@ -217,10 +223,12 @@ size_t moss_mlp_scratch_bytes(int32_t n)
 }
 
 int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_idx, int32_t n,
-                  const float *d_theta, const float *d_norm, int32_t bf16, float *d_grad,
-                  float *d_loss, void *d_scratch, size_t scratch_bytes, void *stream)
+                  const float *d_theta, const float *d_norm, int32_t bf16, float out_lo,
+                  float out_hi, float *d_grad, float *d_loss, void *d_scratch,
+                  size_t scratch_bytes, void *stream)
 {
-    if (n <= 0 || !d_feat || !d_label || !d_theta || !d_norm || !d_grad || !d_scratch)
+    if (n <= 0 || !d_feat || !d_label || !d_theta || !d_norm || !d_grad || !d_scratch ||
+        !(out_lo < out_hi))
         return MOSS_EINVAL;
     if (scratch_bytes < moss_mlp_scratch_bytes(n))
         return MOSS_ENOMEM;
@@ -247,7 +255,7 @@ int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_id
     unsigned g = (unsigned)((n + 3) / 4);
     if (g > 4096) g = 4096;
     hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(g), dim3(256), 0, st, d_feat, d_label, d_idx, n,
-                       d_theta, d_norm, bf16, sc);
+                       d_theta, d_norm, bf16, out_lo, out_hi, sc);
     hipLaunchKernelGGL(k_mlp_partial, dim3((kMlpParams + 255) / 256, nslice), dim3(256), 0, st,
                        n, sc);
     hipLaunchKernelGGL(k_mlp_sum, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, n, nslice,

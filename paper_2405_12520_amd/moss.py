@@ -90,8 +90,8 @@ def load(path: str = LIB_PATH):
     L.moss_kernel_name.argtypes = [C.c_int32]
     L.moss_destroy.argtypes = [vp]
     L.moss_mlp_scratch_bytes.argtypes = [C.c_int32]
-    L.moss_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, vp, C.c_int32, vp, vp, vp, C.c_size_t,
-                                vp]
+    L.moss_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, vp, C.c_int32, C.c_float, C.c_float,
+                                vp, vp, vp, C.c_size_t, vp]
     L.moss_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
                                 C.c_float, vp]
     L.moss_mlp_predict.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
@@ -207,7 +207,8 @@ def _dp(x):
     return None if x is None else vp(x.data_ptr())
 
 
-def mlp_grad(feat, label, theta, norm, *, idx=None, bf16=True, stream=None):
+def mlp_grad(feat, label, theta, norm, *, idx=None, bf16=True, out_lo=-1e30, out_hi=1e30,
+             stream=None):
     """(loss, grad) of the closure on a batch of device tensors."""
     import torch
     n = int(idx.shape[0]) if idx is not None else int(feat.shape[0])
@@ -217,7 +218,8 @@ def mlp_grad(feat, label, theta, norm, *, idx=None, bf16=True, stream=None):
     loss = torch.empty(1, dtype=torch.float32, device=feat.device)
     st = (stream or torch.cuda.current_stream(feat.device)).cuda_stream
     _check(load().moss_mlp_grad(_dp(feat), _dp(label), _dp(idx), n, _dp(theta), _dp(norm),
-                                1 if bf16 else 0, _dp(grad), _dp(loss), _dp(scratch), nb, vp(st)))
+                                1 if bf16 else 0, out_lo, out_hi, _dp(grad), _dp(loss),
+                                _dp(scratch), nb, vp(st)))
     return loss, grad
 
 

@@ -34,7 +34,7 @@ def trained():
     held = (K % 10) == 9
     norm = closure.describe(F[~held])
     _say("closure: training")
-    theta = closure.fit(F[~held], Y[~held], norm, steps=3000, log=_say)
+    theta = closure.fit(F[~held], Y[~held], norm, log=_say)
     return F[held], Y[held], theta, norm
 
 

@@ -44,8 +44,11 @@ def _features(rng, n):
 
 
 def _norm_for(f):
-    mean = f.mean(0)
-    inv = 1.0 / np.maximum(f.std(0), 1e-3)
+    ft = f.astype(np.float64).copy()
+    for q in M.LOG_INPUTS:
+        ft[:, q] = np.log(np.maximum(ft[:, q], 0.5))
+    mean = ft.mean(0)
+    inv = 1.0 / np.maximum(ft.std(0), 1e-3)
     lo = np.full(8, -1e9, np.float32)
     hi = np.full(8, 1e9, np.float32)
     return np.concatenate([mean, inv, lo, hi]).astype(np.float32)
@@ -63,7 +66,7 @@ def test_predict_matches_oracle_forward(torch_dev):
     _say("mlp predict")
     out = moss.mlp_predict(torch.from_numpy(f).cuda(), torch.from_numpy(th).cuda(),
                            torch.from_numpy(nrm).cuda()).cpu().numpy()
-    z = ((f - nrm[:8]) * nrm[8:16]).astype(np.float32)
+    z = M.normalise(f, nrm)
     ref = np.array([mlp_forward(th, z[i]) for i in range(f.shape[0])])
     err = np.abs(out - ref)
     assert err.max() < 1e-2, err.max()
@@ -84,7 +87,7 @@ def test_gradient_matches_fp64_reference(torch_dev, bf16):
     loss, g = moss.mlp_grad(torch.from_numpy(f).cuda(), torch.from_numpy(lab).cuda(),
                             torch.from_numpy(th).cuda(), torch.from_numpy(nrm).cuda(), bf16=bf16)
     g = g.cpu().numpy().astype(np.float64)
-    z = ((f - nrm[:8]) * nrm[8:16]).astype(np.float32)
+    z = M.normalise(f, nrm)
     ref_loss, ref = M.loss_and_grad(th.astype(np.float64), z, lab, bf16_mode=bf16)
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     tol = 2e-2 if bf16 else 1e-4
@@ -119,7 +122,7 @@ def test_gpu_training_fits_smooth_target(torch_dev):
     n = 8192
     f = _features(rng, n)
     nrm = _norm_for(f)
-    z = (f - nrm[:8]) * nrm[8:16]
+    z = M.normalise(f, nrm)
     lab = (np.tanh(z[:, 0]) - 0.5 * z[:, 1] * z[:, 2]).astype(np.float32)
     F = torch.from_numpy(f).cuda()
     Y = torch.from_numpy(lab).cuda()
@@ -163,8 +166,8 @@ def _snapshot_from(sc, st, t):
 def _mlp_cfg():
     th = M.init_params(21)
     th[M.N_PARAMS - 1] = -0.2
-    mean = np.array([50, 8, 8, 13, 250, 0, 150, 14], np.float32)
-    inv = 1.0 / np.array([60, 5, 5, 2, 80, 2, 100, 2], np.float32)
+    mean = np.array([3.5, 8, 8, 13, 5.0, 0, 4.5, 14], np.float32)
+    inv = 1.0 / np.array([1.5, 5, 5, 2, 1.0, 2, 1.2, 2], np.float32)
     lo = np.array([-10, 0, 0, 0, 0, -10, 0, 0], np.float32)
     hi = np.array([250, 25, 25, 25, 300, 3, 300, 20], np.float32)
     return dict(theta=th, norm=np.concatenate([mean, inv, lo, hi]).astype(np.float32))
