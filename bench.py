@@ -226,6 +226,7 @@ def main():
                     traffic=None if traffic is None else round(traffic / per_launch[dom] / 1e6, 1),
                     kernel=dom, kernel_ms=round(per_launch[dom], 5),
                     algo_bytes_per_launch=int(algo),
+                    traffic_bytes_per_launch=None if traffic is None else int(traffic),
                     kernel_ms_all={k: round(v, 5) for k, v in per_launch.items()})
     say(f"[bench] per-kernel ms: {roofline['kernel_ms_all']}")
     sim.close()

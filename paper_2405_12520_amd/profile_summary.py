@@ -34,6 +34,8 @@ def kernel_sources_sha() -> str:
 
 def short(name: str) -> str:
     name = name.split("(")[0]
+    if name.startswith("void "):
+        name = name[5:]
     return name.replace("moss::", "")
 
 

@@ -108,8 +108,11 @@ def test_adam_matches_reference(torch_dev):
     g = rng.normal(0, 1e-2, M.N_PARAMS).astype(np.float32)
     T = [torch.from_numpy(x.copy()).cuda() for x in (th, m, v, g)]
     moss.mlp_adam(T[0], T[1], T[2], T[3], step=5, lr=1e-3)
+    # the ABI takes the hyperparameters as float32: the reference uses those values
+    f32 = lambda x: float(np.float32(x))
     ref_t, ref_m, ref_v = M.adam(th.astype(np.float64), m.astype(np.float64),
-                                 v.astype(np.float64), g.astype(np.float64), 5, lr=1e-3)
+                                 v.astype(np.float64), g.astype(np.float64), 5, lr=f32(1e-3),
+                                 b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
     np.testing.assert_allclose(T[0].cpu().numpy(), ref_t, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(T[1].cpu().numpy(), ref_m, rtol=1e-5, atol=1e-9)
     np.testing.assert_allclose(T[2].cpu().numpy(), ref_v, rtol=1e-5, atol=1e-12)
