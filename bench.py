@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--mlp", action="store_true",
+                    help="with --profile-only: step the city snapshot with the learned closure")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-scenarios", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -189,6 +191,10 @@ def main():
     t0 = time.time()
     sc = S.city_snapshot(args.vehicles)
     say(f"[bench] generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    if args.mlp:
+        from paper_2405_12520_amd import closure
+        theta, norm = closure.load(closure.DEFAULT_PATH)
+        sc = sc.with_params(mlp=dict(theta=theta, norm=norm))
     sim = Simulator(sc)
     stream = sim.stream
     say("[bench] created; warmup")

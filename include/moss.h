@@ -201,6 +201,35 @@ int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
                     int32_t *n_kernels);
 const char *moss_kernel_name(int32_t i);
 
+/* Launch shape of the step kernels (batch APIs, Sec. III-C: the same step
+ * serves many scenarios, so its shape is tuned per workload class).  Every
+ * setting computes bit-identical states; the fields change only how the step
+ * is grouped into graphs and workgroups:
+ *   graph_steps     steps per captured hipGraph replay: even, 2..256; 0 turns
+ *                   graphs off (every step launched directly).  Default 16.
+ *   update_blocks   workgroups of the update kernel; each loops over 256-row
+ *                   tiles.  0 = one per tile (capped at 16384).  1..65535.
+ *   scatter_blocks  workgroups of the joiner scatter (4 tiles per workgroup
+ *                   per pass).  0 = default (capped at 2048).  1..65535.
+ *   xcd_remap       1: workgroup b of the update and merge kernels takes tile
+ *                   (b mod 8) * (G / 8) + b / 8 when the grid G is a multiple
+ *                   of 8, so that each of the 8 XCDs (which receive
+ *                   workgroups round-robin) works on one contiguous range of
+ *                   rows and its L2 holds the halo rows its tiles share.
+ *                   0: tile = b.  Default 0.
+ * moss_set_launch validates (MOSS_EINVAL, state unchanged) and drops captured
+ * graphs; it must not be called while steps enqueued on the handle's stream
+ * are being captured elsewhere. */
+typedef struct {
+    int32_t graph_steps;
+    int32_t update_blocks;
+    int32_t scatter_blocks;
+    int32_t xcd_remap;
+} moss_launch;
+
+int moss_set_launch(moss_sim *h, const moss_launch *cfg);
+int moss_get_launch(const moss_sim *h, moss_launch *cfg);
+
 /* ---- learned car-following closure (the project's extension) ----
  * An 8 -> 64 -> 64 -> 1 network with GELU (tanh form) that, inside its
  * training envelope, replaces the IDM acceleration of the vehicle update

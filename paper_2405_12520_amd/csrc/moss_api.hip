@@ -48,7 +48,8 @@ struct Layout {
     size_t total;
     size_t S[8], Pr[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
-        vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_sq, tr_feat, tr_label;
+        vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq, tr_feat,
+        tr_label;
 
     void plan()
     {
@@ -99,6 +100,7 @@ struct Layout {
         cursor = take(4 * c);
         mlp_theta = take(4 * (size_t)MOSS_MLP_PARAMS);
         mlp_norm = take(4 * (size_t)MOSS_MLP_NORM);
+        mlp_pack = take(mlp ? mlp_pack_bytes() : 16);
         mlp_sq = take(8 * (size_t)n_scen);
         tr_feat = take(trace ? 4 * 8 * c : 4);
         tr_label = take(trace ? 4 * c : 4);
@@ -236,15 +238,14 @@ struct moss_sim {
     int32_t n_scen;
     uint32_t err_seen;
     char *ws;
-    // captured step loops: kGraphSteps steps starting at lane-start parity p
+    // captured step loops: graph_steps steps starting at lane-start parity p
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graphs_ok = true;
+    int32_t graph_steps = 16;      // even; 0 = no graphs
 };
 
 static Dev step_dev(const moss_sim *h, int parity);
 
-// Steps per captured graph (even, so a replay returns to the same parity).
-static constexpr int32_t kGraphSteps = 16;
 
 static void drop_graphs(moss_sim *h)
 {
@@ -255,7 +256,8 @@ static void drop_graphs(moss_sim *h)
         }
 }
 
-// Captures kGraphSteps steps on the simulator's stream into an executable
+// Captures graph_steps steps (an even count, so that a replay returns to the
+// same lane-start parity) on the simulator's stream into an executable
 // graph.  The kernels read the step index and vehicle counts from device
 // memory, so one graph serves every replay.
 static hipError_t capture_graph(moss_sim *h, int parity, hipGraphExec_t *out)
@@ -266,7 +268,7 @@ static hipError_t capture_graph(moss_sim *h, int parity, hipGraphExec_t *out)
         return e;
     int p = parity;
     hipError_t le = hipSuccess;
-    for (int32_t k = 0; k < kGraphSteps && le == hipSuccess; ++k) {
+    for (int32_t k = 0; k < h->graph_steps && le == hipSuccess; ++k) {
         le = launch_step(step_dev(h, p), h->stream);
         p ^= 1;
     }
@@ -349,6 +351,7 @@ static void fill_dev(moss_sim *h)
     d.sumv = (double *)(w + L.sumv);
     d.mlp_theta = F(L.mlp_theta);
     d.mlp_norm = F(L.mlp_norm);
+    d.mlp_pack = w + L.mlp_pack;
     d.mlp_sq = (double *)(w + L.mlp_sq);
     d.tr_feat = F(L.tr_feat);
     d.tr_label = F(L.tr_label);
@@ -650,6 +653,8 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     }
     if (e == hipSuccess)
         e = launch_tails(step_dev(h, 0), st);
+    if (e == hipSuccess && L.mlp)
+        e = launch_mlp_pack(step_dev(h, 0), st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -674,7 +679,8 @@ int moss_step(moss_sim *h, int32_t n)
     HIP_TRY(hipSetDevice(h->device));
     int32_t left = n;
     // whole graphs first (not on the legacy null stream, which cannot capture)
-    while (left >= kGraphSteps && h->graphs_ok && h->stream != nullptr) {
+    const int32_t gs = h->graph_steps;
+    while (gs > 0 && left >= gs && h->graphs_ok && h->stream != nullptr) {
         hipGraphExec_t &g = h->graph[h->parity];
         if (!g && capture_graph(h, h->parity, &g) != hipSuccess) {
             (void)hipGetLastError();
@@ -683,14 +689,52 @@ int moss_step(moss_sim *h, int32_t n)
             break;
         }
         HIP_TRY(hipGraphLaunch(g, h->stream));
-        left -= kGraphSteps;
-        h->t += kGraphSteps;
+        left -= gs;
+        h->t += gs;
     }
     for (; left > 0; --left) {
         HIP_TRY(launch_step(step_dev(h, h->parity), h->stream));
         h->parity ^= 1;
         h->t += 1;
     }
+    return MOSS_OK;
+}
+
+int moss_set_launch(moss_sim *h, const moss_launch *cfg)
+{
+    g_err.clear();
+    if (!h || !cfg)
+        return fail(MOSS_EINVAL, "null argument");
+    if (cfg->graph_steps < 0 || cfg->graph_steps > 256 || (cfg->graph_steps & 1))
+        return fail(MOSS_EINVAL, "graph_steps %d: even, 0..256", cfg->graph_steps);
+    if (cfg->update_blocks < 0 || cfg->update_blocks > 65535)
+        return fail(MOSS_EINVAL, "update_blocks %d: 0..65535", cfg->update_blocks);
+    if (cfg->scatter_blocks < 0 || cfg->scatter_blocks > 65535)
+        return fail(MOSS_EINVAL, "scatter_blocks %d: 0..65535", cfg->scatter_blocks);
+    if (cfg->xcd_remap != 0 && cfg->xcd_remap != 1)
+        return fail(MOSS_EINVAL, "xcd_remap %d: 0 or 1", cfg->xcd_remap);
+    HIP_TRY(hipSetDevice(h->device));
+    // replays already enqueued keep their own executable graphs alive until
+    // they finish only if the stream is drained first
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->graphs_ok = true;
+    h->graph_steps = cfg->graph_steps;
+    h->dev.upd_blocks = cfg->update_blocks;
+    h->dev.jsc_blocks = cfg->scatter_blocks;
+    h->dev.xcd_remap = cfg->xcd_remap;
+    return MOSS_OK;
+}
+
+int moss_get_launch(const moss_sim *h, moss_launch *cfg)
+{
+    g_err.clear();
+    if (!h || !cfg)
+        return fail(MOSS_EINVAL, "null argument");
+    cfg->graph_steps = h->graph_steps;
+    cfg->update_blocks = h->dev.upd_blocks;
+    cfg->scatter_blocks = h->dev.jsc_blocks;
+    cfg->xcd_remap = h->dev.xcd_remap;
     return MOSS_OK;
 }
 

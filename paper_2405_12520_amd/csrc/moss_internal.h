@@ -114,9 +114,13 @@ struct Dev {
     unsigned long long *cnt;      // [n_scen][C_N]
     double *sumv;                 // [n_scen]
     uint32_t *err;
+    // launch shape (results do not depend on it): update and scatter grid
+    // sizes (0 = default) and XCD-contiguous tile order
+    int32_t upd_blocks, jsc_blocks, xcd_remap;
     // learned closure (mode 1) and its training trace
     int32_t mode;
     const float *mlp_theta, *mlp_norm;
+    const void *mlp_pack;         // network image in the kernels' layout (mlp_pack_bytes())
     double *mlp_sq;               // [n_scen]
     float *tr_feat, *tr_label;    // [cap][8], [cap]
     // debug per row at step start
@@ -138,6 +142,9 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);
 int step_kernel_count();
 const char *step_kernel_name(int i);
 hipError_t launch_tails(const Dev &d, hipStream_t st);
+// Builds the packed network image from mlp_theta / mlp_norm (once per simulator).
+hipError_t launch_mlp_pack(const Dev &d, hipStream_t st);
+size_t mlp_pack_bytes();
 hipError_t launch_cursor(const Dev &d, const uint32_t *ids, const uint32_t *ptrs, int32_t *out,
                          int32_t n, hipStream_t st);
 

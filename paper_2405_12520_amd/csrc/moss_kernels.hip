@@ -234,6 +234,18 @@ __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int h
     return lo;
 }
 
+// Tile taken by workgroup blockIdx.x.  Workgroups are dealt round-robin to
+// the 8 XCDs; with remap on (and a grid that is a multiple of 8) each XCD
+// gets one contiguous range of tiles, so neighbouring tiles' shared rows meet
+// in the same L2.  A bijection of [0, gridDim.x) either way.
+__device__ __forceinline__ int xcd_block(int remap)
+{
+    const int b = blockIdx.x, g = gridDim.x;
+    if (!remap || (g & 7))
+        return b;
+    return (b & 7) * (g >> 3) + (b >> 3);
+}
+
 // Update phase for kUT rows per block.  The block stages the rows around its
 // own (s, v, v0, id, lane of rows [base-kUH, base+kUT+kUH)) in LDS; in-lane
 // neighbours are the adjacent rows and the target lane of a lane change is
@@ -244,7 +256,7 @@ __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int h
 // is waited for.  MODE 1 evaluates the learned closure for the wave's 64
 // vehicles on the matrix cores between the acceleration and the integration.
 template <int MODE>
-__global__ void __launch_bounds__(kUT) k_update(Dev d)
+__global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
     __shared__ uint32_t w_id[kUW], w_ln[kUW];
@@ -262,13 +274,13 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
     uint16_t *mz = nullptr;
     if constexpr (MODE == 1) {
         __shared__ MlpLds s_mlp;
-        __shared__ uint16_t s_z[(kUT / 64) * 64 * kMlpIn];
-        mlp_load(s_mlp, d.mlp_theta, d.mlp_norm);
+        __shared__ __attribute__((aligned(16))) uint16_t s_z[(kUT / 64) * 64 * kMlpIn];
+        mlp_copy(s_mlp, static_cast<const MlpLds *>(d.mlp_pack));
         mw = &s_mlp;
         mz = s_z + (tid >> 6) * 64 * kMlpIn;
     }
 
-    for (int base = blockIdx.x * kUT; base < n; base += gridDim.x * kUT) {
+    for (int base = xcd_block(d.xcd_remap) * kUT; base < n; base += gridDim.x * kUT) {
         const int ws = max(base - kUH, 0), we = min(base + kUT + kUH, n);
         const int i = base + tid;
         const bool act = i < n;
@@ -487,7 +499,23 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
             }
         }
 
+        uint32_t ptr0 = ptr;     // route position at step start
         if constexpr (MODE == 1) {
+            // records that do not depend on the network are written first,
+            // so that little of the update's state is held across it
+            if (act && P.trace) {
+#pragma unroll
+                for (int q = 0; q < kMlpIn; ++q)
+                    d.tr_feat[(size_t)i * kMlpIn + q] = feat[q];
+                d.tr_label[i] = a_idm;
+            }
+            if (act && P.debug) {
+                d.d_id[i] = id;
+                d.d_leader[i] = lead_id;
+                d.d_margin[i] = margin;
+                d.d_tl[i] = tl_id;
+                d.d_tf[i] = tf_id;
+            }
             // learned closure for the whole wave; inside the envelope it
             // replaces the IDM acceleration, limited to [-b_max, a_max]
             const float *nm = mw->norm;
@@ -516,6 +544,21 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                     atomicAdd(d.mlp_sq + scen0, e2);
             } else if (inside) {
                 atomicAdd(d.mlp_sq + li.scen, e2);
+            }
+            // the rest of the update re-reads its inputs: the window rows are
+            // unchanged until the next tile, the rest comes from the tables
+            if (act) {
+                s = w_s[x_i];
+                v = w_v[x_i];
+                id = w_id[x_i];
+                v0 = w_v0[x_i];
+                ptr0 = d.S.ptr[i];
+                p = ptr0;
+                nr = d.S.next[i];
+                rd_ok = false;
+                const LaneInfo lr = d.lanes[l];
+                lif.L = lr.L;
+                lif.k = (uint8_t)((int)lr.k + (change ? side : 0));
             }
         }
 
@@ -548,20 +591,22 @@ __global__ void __launch_bounds__(kUT) k_update(Dev d)
                 nr = d.route[p + 1];
             }
             arrived = sp >= Lx;
-            joins = !arrived && !(x == (int)l && p == ptr);
+            joins = !arrived && !(x == (int)l && p == ptr0);
             if (!(isfinite(sp) && isfinite(vn)))
                 atomicOr(d.err, 2u);
             if (arrived)
                 flags |= 16;
             if (P.debug) {
-                d.d_id[i] = id;
-                d.d_leader[i] = lead_id;
                 d.d_flags[i] = flags;
-                d.d_margin[i] = margin;
-                d.d_tl[i] = tl_id;
-                d.d_tf[i] = tf_id;
+                if constexpr (MODE == 0) {
+                    d.d_id[i] = id;
+                    d.d_leader[i] = lead_id;
+                    d.d_margin[i] = margin;
+                    d.d_tl[i] = tl_id;
+                    d.d_tf[i] = tf_id;
+                }
             }
-            if (P.trace) {
+            if (MODE == 0 && P.trace) {
 #pragma unroll
                 for (int q = 0; q < kMlpIn; ++q)
                     d.tr_feat[(size_t)i * kMlpIn + q] = feat[q];
@@ -939,7 +984,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     const int lane = __lane_id();
     const int wv = tid >> 6;
     const int n_next = *d.n_next;
-    const int w = blockIdx.x;
+    const int w = xcd_block(d.xcd_remap);
     if (w > n_next / kMC)
         return;
     if (tid == 0) {
@@ -1340,14 +1385,13 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
         hipLaunchKernelGGL(k_insert, dim3(blocks_for(d.n_qlanes, 256)), dim3(256), 0, st, d);
     mark(1);
     unsigned gu = blocks_for(d.cap, kUT);
-    if (d.mode == 1) {
-        // fewer, longer-lived blocks: each converts the network weights once
-        if (gu > 1024) gu = 1024;
+    if (gu > 16384) gu = 16384;
+    if (d.upd_blocks > 0) gu = (unsigned)d.upd_blocks;
+    if (d.xcd_remap) gu = (gu + 7u) & ~7u;     // workgroups past the last tile find no work
+    if (d.mode == 1)
         hipLaunchKernelGGL(k_update<1>, dim3(gu), dim3(kUT), 0, st, d);
-    } else {
-        if (gu > 16384) gu = 16384;
+    else
         hipLaunchKernelGGL(k_update<0>, dim3(gu), dim3(kUT), 0, st, d);
-    }
     mark(2);
     const unsigned gs = blocks_for(d.n_lanes, kScanLanes);
     hipLaunchKernelGGL(k_scan_reduce, dim3(gs), dim3(kScanThreads), 0, st, d);
@@ -1356,10 +1400,26 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     mark(4);
     unsigned gj = blocks_for((long long)d.cap / kUpdateRows + 1, 4);
     if (gj > 2048) gj = 2048;
+    if (d.jsc_blocks > 0) gj = (unsigned)d.jsc_blocks;
     hipLaunchKernelGGL(k_jscatter, dim3(gj), dim3(256), 0, st, d);
     mark(5);
-    hipLaunchKernelGGL(k_merge, dim3((unsigned)(d.cap / kMC + 1)), dim3(kMT), 0, st, d);
+    unsigned gm = (unsigned)(d.cap / kMC + 1);
+    if (d.xcd_remap) gm = (gm + 7u) & ~7u;     // chunks past the last one return at once
+    hipLaunchKernelGGL(k_merge, dim3(gm), dim3(kMT), 0, st, d);
     mark(6);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_mlp_pack(Dev d)
+{
+    mlp_pack(*static_cast<MlpLds *>(const_cast<void *>(d.mlp_pack)), d.mlp_theta, d.mlp_norm);
+}
+
+size_t mlp_pack_bytes() { return sizeof(MlpLds); }
+
+hipError_t launch_mlp_pack(const Dev &d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(256), 0, st, d);
     return hipGetLastError();
 }
 

@@ -8,10 +8,12 @@
 //   mean[8], inv_std[8], lo[8], hi[8]   (normalisation and envelope).
 //
 // The network is evaluated transposed, H^T = W * X^T, with the weights as the
-// A operand of v_mfma_f32_16x16x16_bf16 and the activations as B.  With that
+// A operand of the matrix-core products (16x16x16 for the 8-input layer,
+// 16x16x32 for the 64-wide ones) and the activations as B.  With that
 // orientation the 16x16 FP32 result tile a lane holds (column = its lane mod
-// 16, rows 4*(lane/16)+j) is exactly the B fragment the next layer needs, so
-// activations never leave registers between layers.
+// 16, rows 4*(lane/16)+j) supplies the B fragment the next layer needs (with
+// the K order of mlp_khid), so activations never leave registers between
+// layers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +27,9 @@ constexpr int kMlpNorm = 4 * kMlpIn;
 constexpr int kOffW1 = 0, kOffB1 = 512, kOffW2 = 576, kOffB2 = 4672, kOffW3 = 4736, kOffB3 = 4800;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 
 // float -> bfloat16 bits, round to nearest even (inputs are finite)
 __device__ __forceinline__ uint16_t f2bf(float x)
@@ -37,13 +41,18 @@ __device__ __forceinline__ uint16_t f2bf(float x)
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// GELU, tanh form (Hendrycks & Gimpel 2016), with tanh(u) = 1 - 2/(1 + e^{2u})
+// GELU, tanh form (Hendrycks & Gimpel 2016), written as
+//   g(x) = 0.5 x (1 + tanh u) = x / (1 + e^{-2u}),  u = sqrt(2/pi) (x + 0.044715 x^3),
+// with e^{-2u} = 2^{x (c0 + c1 x^2)}: five VALU operations, one exp2, one rcp.
+// For large |x| the exp2 saturates to 0 or +inf and g tends to x or -0.
 __device__ __forceinline__ float gelu_fast(float x)
 {
-    const float u = 0.7978845608f * (x + 0.044715f * (x * x * x));
-    const float e = __expf(2.0f * u);
-    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
-    return 0.5f * x * (1.0f + t);
+    constexpr float kLog2e = 1.4426950408889634f;
+    constexpr float c0 = -2.0f * 0.7978845608028654f * kLog2e;
+    constexpr float c1 = -2.0f * 0.7978845608028654f * 0.044715f * kLog2e;
+    const float p = __builtin_fmaf(x * x, c1, c0);
+    const float e = __builtin_amdgcn_exp2f(x * p);
+    return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
 // Input preparation: the three distances (leader gap, red stop line, lane
@@ -55,109 +64,141 @@ __device__ __forceinline__ float mlp_in(int q, float x, const float *norm)
     return (xt - norm[q]) * norm[kMlpIn + q];
 }
 
-// Weights of one block, converted to bfloat16 once per block.
-struct MlpLds {
-    uint16_t W1[kMlpH * kMlpIn];   // [hidden][input]
-    uint16_t W2[kMlpH * kMlpH];    // [out][in]
-    uint16_t w3[kMlpH];
-    float b1[kMlpH], b2[kMlpH], b3;
-    float norm[kMlpNorm];
-};
-
-// Cooperative load of the parameters into LDS (all threads of the block).
-__device__ __forceinline__ void mlp_load(MlpLds &w, const float *theta, const float *norm)
+// Hidden-unit order of the K dimension in the 16x16x32 products.  Lane group
+// g (= lane / 16) supplies elements e = 0..7 of K block kb; with
+//   hidden(kb, g, e) = 32 kb + 4 g + e          (e < 4)
+//                      32 kb + 16 + 4 g + e - 4  (e >= 4)
+// the four values a lane holds of each of two consecutive 16-row result
+// tiles of the previous layer form its B fragment directly.  The weight
+// rows are stored in the same order (A fragment = one 16-byte LDS read).
+__host__ __device__ constexpr int mlp_khid(int p)      // p = 32 kb + 8 g + e
 {
+    return 32 * (p >> 5) + ((p & 7) < 4 ? 4 * ((p >> 3) & 3) + (p & 7)
+                                         : 16 + 4 * ((p >> 3) & 3) + (p & 7) - 4);
+}
+
+constexpr int kW2Stride = kMlpH + 8;    // padded row (bf16): 144 B, no bank aliasing of rows
+
+// Network image in the layout the kernels read: bfloat16 weights in the K
+// order above, FP32 biases and input description.  Built once per network
+// (in global memory at creation, or directly in LDS) by mlp_pack.
+struct __attribute__((aligned(16))) MlpLds {
+    uint16_t W2[kMlpH * kW2Stride];   // [out][K position], padded
+    uint16_t W1[kMlpH * kMlpIn];      // [hidden][input]
+    uint16_t w3[kMlpH];               // [K position]
+    float b1[kMlpH], b2[kMlpH];
+    float norm[kMlpNorm];
+    float b3, pad_[3];
+};
+static_assert(sizeof(MlpLds) % 16 == 0, "MlpLds is copied in 16-byte units");
+
+// Cooperative build of the image from the FP32 parameters (all threads of
+// the block).
+__device__ __forceinline__ void mlp_pack(MlpLds &w, const float *theta, const float *norm)
+{
+    for (int q = threadIdx.x; q < kMlpH * kW2Stride; q += blockDim.x) {
+        const int o = q / kW2Stride, p = q - o * kW2Stride;
+        w.W2[q] = p < kMlpH ? f2bf(theta[kOffW2 + o * kMlpH + mlp_khid(p)]) : (uint16_t)0;
+    }
     for (int q = threadIdx.x; q < kMlpH * kMlpIn; q += blockDim.x)
         w.W1[q] = f2bf(theta[kOffW1 + q]);
-    for (int q = threadIdx.x; q < kMlpH * kMlpH; q += blockDim.x)
-        w.W2[q] = f2bf(theta[kOffW2 + q]);
     for (int q = threadIdx.x; q < kMlpH; q += blockDim.x) {
-        w.w3[q] = f2bf(theta[kOffW3 + q]);
+        w.w3[q] = f2bf(theta[kOffW3 + mlp_khid(q)]);
         w.b1[q] = theta[kOffB1 + q];
         w.b2[q] = theta[kOffB2 + q];
     }
     for (int q = threadIdx.x; q < kMlpNorm; q += blockDim.x)
         w.norm[q] = norm[q];
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         w.b3 = theta[kOffB3];
+        w.pad_[0] = w.pad_[1] = w.pad_[2] = 0.0f;
+    }
 }
 
-__device__ __forceinline__ bf16x4 load4(const uint16_t *p)
+// Cooperative copy of a packed image from global memory (all threads).
+__device__ __forceinline__ void mlp_copy(MlpLds &w, const MlpLds *g)
 {
-    bf16x4 r;
-    r.x = (short)p[0];
-    r.y = (short)p[1];
-    r.z = (short)p[2];
-    r.w = (short)p[3];
-    return r;
+    const uint4 *src = reinterpret_cast<const uint4 *>(g);
+    uint4 *dst = reinterpret_cast<uint4 *>(&w);
+    for (int q = threadIdx.x; q < (int)(sizeof(MlpLds) / 16); q += blockDim.x)
+        dst[q] = src[q];
 }
 
-__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d)
+__device__ __forceinline__ bf16x8 cvt8(const f32x4 &a, const f32x4 &b)
 {
-    bf16x4 r;
-    r.x = (short)f2bf(a);
-    r.y = (short)f2bf(b);
-    r.z = (short)f2bf(c);
-    r.w = (short)f2bf(d);
-    return r;
+    const f32x8 v = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    return __builtin_convertvector(v, bf16x8);
+}
+
+__device__ __forceinline__ f32x4 gelu4(f32x4 c)
+{
+    return f32x4{gelu_fast(c.x), gelu_fast(c.y), gelu_fast(c.z), gelu_fast(c.w)};
 }
 
 // Network output for the 64 vehicles of a wave: lane L passes the
 // normalised inputs z[8] of its vehicle and receives that vehicle's output.
 // zs is this wave's 64*8 bfloat16 staging area in LDS.  Every thread of the
 // block must call it (it synchronises the block; inactive vehicles pass
-// zeros).
+// zeros).  The wave works through its four 16-vehicle blocks one at a time;
+// biases enter as the accumulators' initial values.
 __device__ __forceinline__ float wave_mlp(const MlpLds &w, uint16_t *zs, const float z[8])
 {
     const int lane = __lane_id();
     const int r16 = lane & 15, q4 = lane >> 4;
-#pragma unroll
-    for (int k = 0; k < kMlpIn; ++k)
-        zs[lane * kMlpIn + k] = f2bf(z[k]);
+    {
+        const f32x4 lo = {z[0], z[1], z[2], z[3]}, hi = {z[4], z[5], z[6], z[7]};
+        *reinterpret_cast<bf16x8 *>(zs + lane * kMlpIn) = cvt8(lo, hi);
+    }
     __syncthreads();
 
     const bf16x4 zero4 = {0, 0, 0, 0};
-    const f32x4 zf = {0.0f, 0.0f, 0.0f, 0.0f};
-    // layer 1: H1^T[hidden][veh] = W1[hidden][in16] * Z^T[in16][veh]
-    bf16x4 h1[4][4];      // [k-block of hidden][vehicle block]
+    const bf16x8 zero8 = {};
+    // layer-1 weights (A fragments, K = 8 inputs padded to 16) and bias rows
+    bf16x4 a1[4];
 #pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        a1[mt] = (q4 < 2) ? *reinterpret_cast<const bf16x4 *>(w.W1 + (16 * mt + r16) * kMlpIn + 4 * q4)
+                          : zero4;
+    float out = 0.0f;
+#pragma unroll 1
     for (int nt = 0; nt < 4; ++nt) {
-        const bf16x4 bz = (q4 < 2) ? load4(zs + (16 * nt + r16) * kMlpIn + 4 * q4) : zero4;
+        // layer 1: H1^T[16 hidden][16 veh] per tile mt
+        const bf16x4 bz = (q4 < 2) ? *reinterpret_cast<const bf16x4 *>(zs + (16 * nt + r16) * kMlpIn + 4 * q4)
+                                   : zero4;
+        f32x4 g[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            const bf16x4 aw = (q4 < 2) ? load4(w.W1 + (16 * mt + r16) * kMlpIn + 4 * q4) : zero4;
-            f32x4 c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw, bz, zf, 0, 0, 0);
-            const int hr = 16 * mt + 4 * q4;
-            h1[mt][nt] = pack4(gelu_fast(c.x + w.b1[hr]), gelu_fast(c.y + w.b1[hr + 1]),
-                               gelu_fast(c.z + w.b1[hr + 2]), gelu_fast(c.w + w.b1[hr + 3]));
+            const f32x4 b = *reinterpret_cast<const f32x4 *>(w.b1 + 16 * mt + 4 * q4);
+            g[mt] = gelu4(__builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[mt], bz, b, 0, 0, 0));
         }
-    }
-    // layers 2 and 3: H2^T = W2 * H1^T, then y = w3 * H2^T one hidden block at a time
-    f32x4 y[4] = {zf, zf, zf, zf};
+        const bf16x8 h1[2] = {cvt8(g[0], g[1]), cvt8(g[2], g[3])};
+        // layer 2 per pair of 16-row output tiles, then layer 3 (row 0 = w3)
+        // on the pair
+        f32x4 y = {w.b3, w.b3, w.b3, w.b3};
+#pragma unroll 1
+        for (int kb3 = 0; kb3 < 2; ++kb3) {
+            f32x4 h2[2];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        bf16x4 a2[4];
+            for (int h = 0; h < 2; ++h) {
+                const int mo = 2 * kb3 + h;
+                f32x4 c = *reinterpret_cast<const f32x4 *>(w.b2 + 16 * mo + 4 * q4);
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
-            a2[kt] = load4(w.W2 + (16 * mt + r16) * kMlpH + 16 * kt + 4 * q4);
-        const bf16x4 a3 = (r16 == 0) ? load4(w.w3 + 16 * mt + 4 * q4) : zero4;
-        const int hr = 16 * mt + 4 * q4;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            f32x4 c = zf;
-#pragma unroll
-            for (int kt = 0; kt < 4; ++kt)
-                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[kt], h1[kt][nt], c, 0, 0, 0);
-            const bf16x4 h2 = pack4(gelu_fast(c.x + w.b2[hr]), gelu_fast(c.y + w.b2[hr + 1]),
-                                    gelu_fast(c.z + w.b2[hr + 2]), gelu_fast(c.w + w.b2[hr + 3]));
-            y[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, h2, y[nt], 0, 0, 0);
+                for (int kb = 0; kb < 2; ++kb) {
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(w.W2 + (16 * mo + r16) * kW2Stride + 32 * kb + 8 * q4);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h1[kb], c, 0, 0, 0);
+                }
+                h2[h] = gelu4(c);
+            }
+            const bf16x8 a3 = (r16 == 0) ? *reinterpret_cast<const bf16x8 *>(w.w3 + 32 * kb3 + 8 * q4)
+                                         : zero8;
+            y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, cvt8(h2[0], h2[1]), y, 0, 0, 0);
         }
+        // output row 0 of this vehicle block: lanes 0..15, element x
+        const float yn = __shfl(y.x, r16);
+        if (q4 == nt)
+            out = yn;
     }
-    // row 0 of output block nt sits in lanes 0..15, element x
-    const float y0 = __shfl(y[0].x, r16), y1 = __shfl(y[1].x, r16);
-    const float y2 = __shfl(y[2].x, r16), y3 = __shfl(y[3].x, r16);
-    const float out = (q4 == 0) ? y0 : (q4 == 1) ? y1 : (q4 == 2) ? y2 : y3;
-    return out + w.b3;
+    return out;
 }
 
 }  // namespace moss

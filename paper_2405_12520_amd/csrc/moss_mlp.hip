@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *feat, int n, c
                                                     const float *norm, float *out)
 {
     __shared__ MlpLds w;
-    __shared__ uint16_t zs[4 * 64 * kMlpIn];
-    mlp_load(w, theta, norm);
+    __shared__ __attribute__((aligned(16))) uint16_t zs[4 * 64 * kMlpIn];
+    mlp_pack(w, theta, norm);
     __syncthreads();
     const int wv = threadIdx.x >> 6;
     for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {

@@ -59,10 +59,18 @@ class moss_state_out(C.Structure):
                 ("t", C.c_int64)]
 
 
+class moss_launch(C.Structure):
+    _fields_ = [("graph_steps", C.c_int32), ("update_blocks", C.c_int32),
+                ("scatter_blocks", C.c_int32), ("xcd_remap", C.c_int32)]
+
+
+LAUNCH_FIELDS = tuple(f for f, _ in moss_launch._fields_)
+
 EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state",
            "moss_read_counters", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
            "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_adam", "moss_mlp_predict",
-           "moss_read_trace", "moss_read_mlp_error", "moss_destroy", "moss_last_error")
+           "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
+           "moss_destroy", "moss_last_error")
 
 _lib = None
 
@@ -97,6 +105,8 @@ def load(path: str = LIB_PATH):
     L.moss_mlp_predict.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.moss_read_trace.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]
     L.moss_read_mlp_error.argtypes = [vp, vp]
+    L.moss_set_launch.argtypes = [vp, C.POINTER(moss_launch)]
+    L.moss_get_launch.argtypes = [vp, C.POINTER(moss_launch)]
     for f in EXPORTS:
         getattr(L, f).restype = C.c_char_p if f in ("moss_last_error", "moss_kernel_name") \
             else C.c_int
@@ -201,6 +211,17 @@ def moss_step_timed(h: int, n: int):
     k = C.c_int32(0)
     _check(load().moss_step_timed(vp(h), int(n), _ptr(ms), 32, C.byref(k)))
     return {load().moss_kernel_name(i).decode(): float(ms[i]) for i in range(k.value)}
+
+
+def moss_set_launch(h: int, cfg: Dict[str, int]):
+    c = moss_launch(**{k: int(cfg[k]) for k in LAUNCH_FIELDS})
+    _check(load().moss_set_launch(vp(h), C.byref(c)))
+
+
+def moss_get_launch(h: int) -> Dict[str, int]:
+    c = moss_launch()
+    _check(load().moss_get_launch(vp(h), C.byref(c)))
+    return {k: int(getattr(c, k)) for k in LAUNCH_FIELDS}
 
 
 def _dp(x):
@@ -321,6 +342,19 @@ class Simulator:
 
     def step_timed(self, n: int):
         return moss_step_timed(self.h, n)
+
+    def set_launch(self, **cfg):
+        """Changes the launch shape (fields of moss_launch; omitted ones keep
+        their value).  Results do not depend on it."""
+        cur = moss_get_launch(self.h)
+        unknown = set(cfg) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown launch fields {sorted(unknown)}")
+        cur.update(cfg)
+        moss_set_launch(self.h, cur)
+
+    def launch(self) -> Dict[str, int]:
+        return moss_get_launch(self.h)
 
     def trace(self, device: bool = True):
         """(features [n, 8], IDM labels [n]) of the last step."""
