@@ -135,7 +135,18 @@ def bench_batch(args):
     t0 = time.time()
     sc = S.batch(args.batch_scenarios)
     say(f"[bench] batch generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    # launch shape: tuned on a second copy at the same point of the run
+    from paper_2405_12520_amd import autotune
+    tsim = Simulator(sc)
+    tsim.step(600)
+    t0 = time.time()
+    rec = autotune.tune(tsim, sc, log=say)
+    tsim.close()
+    del tsim
+    say(f"[bench] batch launch shape {rec['launch']} ({'cached' if rec['cached'] else 'searched'}"
+        f" in {time.time() - t0:.1f} s)")
     sim = Simulator(sc)
+    autotune.apply(sim, rec)
     sim.step(600)
     ms, dc = timed_steps(sim, args.steps)
     veh_steps = int(dc[:, 6].sum())
@@ -145,7 +156,8 @@ def bench_batch(args):
     return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
                 ms_per_step=round(ms / args.steps, 5), scenarios=int(sc.n_scen),
                 vehicles_total=int(sc.n_veh), active_mean=round(veh_steps / args.steps, 1),
-                window="steps 600..600+K of 1800", lanes=int(sc.n_lanes))
+                window="steps 600..600+K of 1800", lanes=int(sc.n_lanes),
+                launch=rec["launch"], launch_tuned_ms_per_step=rec["ms_per_step"])
 
 
 def main():

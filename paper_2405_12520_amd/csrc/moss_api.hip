@@ -94,14 +94,14 @@ struct Layout {
         vt_id = take(4 * (size_t)n_veh);
         vt_dep = take(4 * (size_t)n_veh);
         vt_rstart = take(4 * (size_t)n_veh);
-        cnt = take(8 * (size_t)n_scen * C_N);
-        sumv = take(8 * (size_t)n_scen);
+        cnt = take(8 * (size_t)kStripes * stripe_elems((int64_t)n_scen * C_N));
+        sumv = take(8 * (size_t)kStripes * stripe_elems(n_scen));
         for (auto &x : dbg) x = take(debug ? 4 * c : 4);
         cursor = take(4 * c);
         mlp_theta = take(4 * (size_t)MOSS_MLP_PARAMS);
         mlp_norm = take(4 * (size_t)MOSS_MLP_NORM);
         mlp_pack = take(mlp ? mlp_pack_bytes() : 16);
-        mlp_sq = take(8 * (size_t)n_scen);
+        mlp_sq = take(8 * (size_t)kStripes * stripe_elems(n_scen));
         tr_feat = take(trace ? 4 * 8 * c : 4);
         tr_label = take(trace ? 4 * c : 4);
         total = off;
@@ -349,6 +349,8 @@ static void fill_dev(moss_sim *h)
     d.vt_rstart = U(L.vt_rstart);
     d.cnt = (unsigned long long *)(w + L.cnt);
     d.sumv = (double *)(w + L.sumv);
+    d.cnt_stride = stripe_elems((int64_t)h->n_scen * C_N);
+    d.sv_stride = stripe_elems(h->n_scen);
     d.mlp_theta = F(L.mlp_theta);
     d.mlp_norm = F(L.mlp_norm);
     d.mlp_pack = w + L.mlp_pack;
@@ -829,6 +831,25 @@ int moss_read_state(moss_sim *h, moss_state_out *out)
     return MOSS_OK;
 }
 
+// Per-scenario sums of the kStripes copies of a double observable, added in
+// stripe order (a fixed order, so that a read is reproducible for a given
+// device state).
+static hipError_t sum_stripes(const moss_sim *h, const double *dev, double *out)
+{
+    const size_t st = (size_t)h->dev.sv_stride;
+    std::vector<double> all(kStripes * st);
+    hipError_t e = hipMemcpy(all.data(), dev, 8 * all.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return e;
+    for (int32_t q = 0; q < h->n_scen; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < kStripes; ++k)
+            s += all[k * st + q];
+        out[q] = s;
+    }
+    return hipSuccess;
+}
+
 int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *error_word)
 {
     g_err.clear();
@@ -837,11 +858,19 @@ int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *
     int rc = sync_and_check(h);
     if (rc)
         return rc;
-    if (counters)
-        HIP_TRY(hipMemcpy(counters, h->dev.cnt, 8 * (size_t)h->n_scen * C_N,
-                          hipMemcpyDeviceToHost));
+    if (counters) {
+        const size_t m = (size_t)h->n_scen * C_N, st = (size_t)h->dev.cnt_stride;
+        std::vector<unsigned long long> all(kStripes * st);
+        HIP_TRY(hipMemcpy(all.data(), h->dev.cnt, 8 * all.size(), hipMemcpyDeviceToHost));
+        for (size_t q = 0; q < m; ++q) {
+            unsigned long long s = 0;
+            for (int k = 0; k < kStripes; ++k)
+                s += all[k * st + q];
+            counters[q] = (int64_t)s;
+        }
+    }
     if (sum_v)
-        HIP_TRY(hipMemcpy(sum_v, h->dev.sumv, 8 * (size_t)h->n_scen, hipMemcpyDeviceToHost));
+        HIP_TRY(sum_stripes(h, h->dev.sumv, sum_v));
     if (error_word)
         *error_word = h->err_seen;
     return MOSS_OK;
@@ -908,7 +937,7 @@ int moss_read_mlp_error(moss_sim *h, double *sum_sq)
     int rc = sync_and_check(h);
     if (rc)
         return rc;
-    HIP_TRY(hipMemcpy(sum_sq, h->dev.mlp_sq, 8 * (size_t)h->n_scen, hipMemcpyDeviceToHost));
+    HIP_TRY(sum_stripes(h, h->dev.mlp_sq, sum_sq));
     return MOSS_OK;
 }
 

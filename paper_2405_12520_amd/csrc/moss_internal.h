@@ -110,9 +110,12 @@ struct Dev {
     const uint32_t *vt_id;
     const int32_t *vt_dep;
     const uint32_t *vt_rstart;
-    // observables
-    unsigned long long *cnt;      // [n_scen][C_N]
-    double *sumv;                 // [n_scen]
+    // observables, each in kStripes copies (stripe k at k * cnt_stride /
+    // sv_stride elements) so that concurrent waves add to different lines;
+    // readers sum the copies
+    unsigned long long *cnt;      // [kStripes][n_scen][C_N]
+    double *sumv;                 // [kStripes][n_scen]
+    int32_t cnt_stride, sv_stride;
     uint32_t *err;
     // launch shape (results do not depend on it): update and scatter grid
     // sizes (0 = default) and XCD-contiguous tile order
@@ -121,7 +124,7 @@ struct Dev {
     int32_t mode;
     const float *mlp_theta, *mlp_norm;
     const void *mlp_pack;         // network image in the kernels' layout (mlp_pack_bytes())
-    double *mlp_sq;               // [n_scen]
+    double *mlp_sq;               // [kStripes][n_scen] (stride sv_stride)
     float *tr_feat, *tr_label;    // [cap][8], [cap]
     // debug per row at step start
     uint32_t *d_id, *d_leader, *d_tl, *d_tf;
@@ -131,6 +134,12 @@ struct Dev {
 
 // New rows per merge block.
 constexpr int kMergeRows = 512;
+// Copies of the counters and sums; a wave adds to copy (4 * block + wave)
+// mod kStripes.
+constexpr int kStripes = 64;
+// Elements per copy, padded to whole 256-byte lines.
+inline int32_t stripe_elems(int64_t n) { return (int32_t)((n + 31) / 32 * 32); }
+
 // Rows per update block (one joiner region per such tile).
 constexpr int kUpdateRows = 256;
 

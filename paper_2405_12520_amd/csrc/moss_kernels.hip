@@ -139,15 +139,31 @@ __device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool pred)
 
 // Wave-aggregated counter increment for waves whose vehicles are all in one
 // scenario (the common case); other waves use one atomic per lane.
-__device__ __forceinline__ void wave_count(unsigned long long *c, bool pred, int scen,
-                                           int scen0, bool uniform)
+// This wave's copy of the counters and sums.
+__device__ __forceinline__ int wave_stripe()
+{
+    return (int)(((blockIdx.x << 2) + (threadIdx.x >> 6)) & (kStripes - 1));
+}
+__device__ __forceinline__ unsigned long long *cnt_at(const Dev &d, int scen, int c)
+{
+    return d.cnt + (size_t)wave_stripe() * d.cnt_stride + (size_t)scen * C_N + c;
+}
+__device__ __forceinline__ double *sv_at(const Dev &d, double *base, int scen)
+{
+    return base + (size_t)wave_stripe() * d.sv_stride + scen;
+}
+
+// Adds the wave's count of pred to counter c (one atomic per wave when the
+// wave's vehicles are all of one scenario).
+__device__ __forceinline__ void wave_count(const Dev &d, int c, bool pred, int scen, int scen0,
+                                           bool uniform)
 {
     if (uniform) {
         const unsigned long long m = __ballot(pred);
         if (m && __lane_id() == __ffsll((long long)m) - 1)
-            atomicAdd(c + (size_t)scen0 * C_N, (unsigned long long)__popcll(m));
+            atomicAdd(cnt_at(d, scen0, c), (unsigned long long)__popcll(m));
     } else if (pred) {
-        atomicAdd(c + (size_t)scen * C_N, 1ull);
+        atomicAdd(cnt_at(d, scen, c), 1ull);
     }
 }
 
@@ -182,7 +198,7 @@ __global__ void k_insert(Dev d)
         vins = fmin32(v0e, d.S.v[lo]);
         ok = (d.S.s[lo] - P.len) >= (P.s0 + vins * P.T);
     }
-    unsigned long long *c = d.cnt + (size_t)li.scen * C_N;
+    unsigned long long *c = cnt_at(d, li.scen, 0);
     if (!ok) {
         atomicAdd(c + C_INSERT_FAIL, 1ull);
         return;
@@ -255,7 +271,7 @@ __device__ __forceinline__ int xcd_block(int remap)
 // Joiners are listed in the tile's own region of jlist, so no atomic result
 // is waited for.  MODE 1 evaluates the learned closure for the wave's 64
 // vehicles on the matrix cores between the acceleration and the integration.
-template <int MODE>
+template <int MODE, bool AUX>
 __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
@@ -268,7 +284,10 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
     const uint32_t tt = (uint32_t)t;
     const int tid = threadIdx.x;
     const int side = ((t & 1) == 0) ? -1 : 1;     // MOBIL looks at lane k-1 on even steps
-    const bool want_feat = MODE == 1 || P.trace;
+    // AUX instantiations carry the debug and trace records (P.debug, P.trace);
+    // the others never touch those buffers
+    const bool dbg = AUX && P.debug, trc = AUX && P.trace;
+    const bool want_feat = MODE == 1 || trc;
 
     MlpLds *mw = nullptr;
     uint16_t *mz = nullptr;
@@ -503,13 +522,13 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         if constexpr (MODE == 1) {
             // records that do not depend on the network are written first,
             // so that little of the update's state is held across it
-            if (act && P.trace) {
+            if (act && trc) {
 #pragma unroll
                 for (int q = 0; q < kMlpIn; ++q)
                     d.tr_feat[(size_t)i * kMlpIn + q] = feat[q];
                 d.tr_label[i] = a_idm;
             }
-            if (act && P.debug) {
+            if (act && dbg) {
                 d.d_id[i] = id;
                 d.d_leader[i] = lead_id;
                 d.d_margin[i] = margin;
@@ -535,15 +554,15 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 e2 = e * e;
                 a = am;
             }
-            wave_count(d.cnt + C_MLP_EVAL, inside, li.scen, scen0, uni_scen);
-            wave_count(d.cnt + C_MLP_FALLBACK, act && !inside, li.scen, scen0, uni_scen);
+            wave_count(d, C_MLP_EVAL, inside, li.scen, scen0, uni_scen);
+            wave_count(d, C_MLP_FALLBACK, act && !inside, li.scen, scen0, uni_scen);
             if (uni_scen) {
                 for (int off = 32; off > 0; off >>= 1)
                     e2 += __shfl_xor(e2, off);
                 if (__lane_id() == 0 && e2 != 0.0)
-                    atomicAdd(d.mlp_sq + scen0, e2);
+                    atomicAdd(sv_at(d, d.mlp_sq, scen0), e2);
             } else if (inside) {
-                atomicAdd(d.mlp_sq + li.scen, e2);
+                atomicAdd(sv_at(d, d.mlp_sq, li.scen), e2);
             }
             // the rest of the update re-reads its inputs: the window rows are
             // unchanged until the next tile, the rest comes from the tables
@@ -596,7 +615,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 atomicOr(d.err, 2u);
             if (arrived)
                 flags |= 16;
-            if (P.debug) {
+            if (dbg) {
                 d.d_flags[i] = flags;
                 if constexpr (MODE == 0) {
                     d.d_id[i] = id;
@@ -606,7 +625,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                     d.d_tf[i] = tf_id;
                 }
             }
-            if (MODE == 0 && P.trace) {
+            if (MODE == 0 && trc) {
 #pragma unroll
                 for (int q = 0; q < kMlpIn; ++q)
                     d.tr_feat[(size_t)i * kMlpIn + q] = feat[q];
@@ -631,7 +650,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 // the route array stores the departure step after the -1 that
                 // ends the route
                 const int32_t dep = d.route[p + 2];
-                atomicAdd(d.cnt + (size_t)li.scen * C_N + C_TRIP_TIME,
+                atomicAdd(cnt_at(d, li.scen, C_TRIP_TIME),
                           (unsigned long long)((t + 1) - (int64_t)dep));
             } else if (joins) {
                 const int lane_id = __lane_id();
@@ -650,8 +669,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             d.Pr.next[i] = nr;
             d.Pr.v0[i] = v0;
         }
-        wave_count(d.cnt + C_ARRIVED, arrived, li.scen, scen0, uni_scen);
-        wave_count(d.cnt + C_LANE_CHANGES, change, li.scen, scen0, uni_scen);
+        wave_count(d, C_ARRIVED, arrived, li.scen, scen0, uni_scen);
+        wave_count(d, C_LANE_CHANGES, change, li.scen, scen0, uni_scen);
         __syncthreads();
         if (tid == 0)
             d.jcnt[base / kUT] = (int32_t)s_jn;
@@ -923,11 +942,15 @@ constexpr uint32_t kTagJ = 0x80000000u;
 constexpr uint32_t kNoSrc = 0xFFFFFFFFu;
 
 // Segmented scan over one wave of old rows: inclusive prefix maximum of the
-// stayer keys and exclusive count of stayers, restarting at lane heads and
-// continuing from the carry when the wave's first rows continue a lane.
+// stayer keys (returned as the row index holding it, kNoRow before the
+// lane's first stayer) and exclusive count of stayers, restarting at lane
+// heads and continuing from the carry when the wave's first rows continue a
+// lane.
+constexpr uint32_t kNoRow = 0xFFFFu;
+
 __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, uint64_t key,
-                                              uint64_t &c_pm, uint32_t &c_p, uint64_t &pm_out,
-                                              uint32_t &p_out)
+                                              uint32_t row, uint64_t &c_pm, uint32_t &c_pi,
+                                              uint32_t &c_p, uint32_t &pi_out, uint32_t &p_out)
 {
     const int lane = __lane_id();
     const unsigned long long hm = __ballot(valid && head);
@@ -938,25 +961,29 @@ __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, ui
     const unsigned long long seg = (h < 0) ? below : (below & ~((1ull << h) - 1ull));
     uint32_t p = (uint32_t)__popcll(sm & seg);
     uint64_t v = (valid && st) ? key : 0ull;
+    uint32_t vi = (valid && st) ? row : kNoRow;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t lo = __shfl_up((uint32_t)v, off), hi = __shfl_up((uint32_t)(v >> 32), off);
+        const uint32_t oi = __shfl_up(vi, off);
         const uint64_t o = ((uint64_t)hi << 32) | lo;
-        if (lane >= off && lane - off >= h && o > v)
+        if (lane >= off && lane - off >= h && o > v) {
             v = o;
+            vi = oi;
+        }
     }
     if (h < 0) {
         p += c_p;
-        if (c_pm > v)
+        if (c_pm > v) {
             v = c_pm;
+            vi = c_pi;
+        }
     }
-    pm_out = v;
+    pi_out = vi;
     p_out = p;
     // carry for the next wave of rows: the state after row 63
-    const uint64_t last_v = ((uint64_t)__shfl((uint32_t)(v >> 32), 63) << 32) |
-                            __shfl((uint32_t)v, 63);
-    const uint32_t last_p = __shfl(p, 63) + (uint32_t)((sm >> 63) & 1ull);
-    c_pm = last_v;
-    c_p = last_p;
+    c_pm = ((uint64_t)__shfl((uint32_t)(v >> 32), 63) << 32) | __shfl((uint32_t)v, 63);
+    c_pi = __shfl(vi, 63);
+    c_p = __shfl(p, 63) + (uint32_t)((sm >> 63) & 1ull);
 }
 
 // Next state, one chunk of kMC new rows per block.  A block owns the lanes
@@ -968,12 +995,18 @@ __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, ui
 __global__ void __launch_bounds__(kMT) k_merge(Dev d)
 {
     __shared__ float o_s[kOldCap], o_v[kOldCap];
-    __shared__ uint32_t o_ln[kOldCap], o_id[kOldCap], o_p[kOldCap];
-    __shared__ uint32_t o_pmh[kOldCap], o_pml[kOldCap];
+    __shared__ uint32_t o_ln[kOldCap], o_id[kOldCap];
+    // stayer ranks and prefix-maximum rows (scan to stayer placement), then
+    // the overlap markers of the lanes' first rows (overlap removal)
+    __shared__ uint32_t u_buf[2 * kNewCap];
+    uint16_t *const o_p = reinterpret_cast<uint16_t *>(u_buf);
+    uint16_t *const o_pi = o_p + kOldCap;
+    int *const w_top = reinterpret_cast<int *>(u_buf);
+    int *const w_bot = w_top + kNewCap;
     __shared__ float j_s[kJCap], j_v[kJCap];
-    __shared__ uint32_t j_id[kJCap], j_ln[kJCap], j_kh[kJCap], j_kl[kJCap];
-    __shared__ uint32_t w_src[kNewCap], w_ln[kNewCap];
-    __shared__ int w_top[kNewCap], w_bot[kNewCap];
+    __shared__ uint32_t j_id[kJCap], j_ln[kJCap];
+    __shared__ uint16_t j_ord[kJCap];      // the lane's joiners in key order
+    __shared__ uint32_t w_src[kNewCap];
     __shared__ int lt_old[kLaneCap + 1], lt_new[kLaneCap + 1], lt_jo[kLaneCap + 1];
     __shared__ int sh_i[8];
     __shared__ int wave_start[5];
@@ -1017,10 +1050,10 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 vsum += ls;
                 clamps += lc;
             } else {
-                unsigned long long *c = d.cnt + (size_t)d.lanes[l].scen * C_N;
+                unsigned long long *c = cnt_at(d, d.lanes[l].scen, 0);
                 if (cnt) {
                     atomicAdd(c + C_VEH_STEPS, (unsigned long long)cnt);
-                    atomicAdd(d.sumv + d.lanes[l].scen, ls);
+                    atomicAdd(sv_at(d, d.sumv, d.lanes[l].scen), ls);
                 }
                 if (lc) atomicAdd(c + C_CLAMPS, lc);
             }
@@ -1071,11 +1104,8 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             jnext = d.Pr.next[src];
             jv0 = d.Pr.v0[src];
         }
-        for (int k = tid; k < nw; k += kMT) {
+        for (int k = tid; k < nw; k += kMT)
             w_src[k] = kNoSrc;
-            w_top[k] = -1;
-            w_bot[k] = 0x7FFFFFFF;
-        }
         __syncthreads();
         // ---- split the old rows among the 4 waves at lane boundaries (first
         // lane start at or after an even share, found 64 rows at a time)
@@ -1105,7 +1135,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         {
             const int ra0 = wave_start[wv], rb0 = max(wave_start[wv + 1], ra0);
             uint64_t c_pm = 0;
-            uint32_t c_p = 0;
+            uint32_t c_pi = kNoRow, c_p = 0;
             for (int r0 = ra0; r0 < rb0; r0 += 64) {
                 const int r = r0 + lane;
                 const bool valid = r < rb0;
@@ -1117,13 +1147,11 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                     head = (r == ra0) || ((o_ln[r - 1] & ~kJoinBit) != (ln & ~kJoinBit));
                     key = okey(o_s[r], o_id[r]);
                 }
-                uint64_t pm;
-                uint32_t p;
-                wave_seg_scan(valid, head, st, key, c_pm, c_p, pm, p);
+                uint32_t pi, p;
+                wave_seg_scan(valid, head, st, key, (uint32_t)r, c_pm, c_pi, c_p, pi, p);
                 if (valid) {
-                    o_p[r] = p;
-                    o_pmh[r] = (uint32_t)(pm >> 32);
-                    o_pml[r] = (uint32_t)pm;
+                    o_p[r] = (uint16_t)p;
+                    o_pi[r] = (uint16_t)pi;
                 }
             }
         }
@@ -1141,7 +1169,8 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             int a = lo, b = hi;       // first old row of l with prefix max > key
             while (a < b) {
                 const int mid = (a + b) >> 1;
-                const uint64_t pm = ((uint64_t)o_pmh[mid] << 32) | o_pml[mid];
+                const uint32_t pr = o_pi[mid];
+                const uint64_t pm = (pr == kNoRow) ? 0ull : okey(o_s[pr], o_id[pr]);
                 if (pm > key)
                     b = mid;
                 else
@@ -1153,7 +1182,6 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             const int pos = wl + f + q;
             if (pos >= 0 && pos < nw) {
                 w_src[pos] = kTagJ | (uint32_t)e;
-                w_ln[pos] = l;
                 const int g = n0 + pos;
                 d.S.a[g] = ja;
                 d.S.id[g] = j_id[e];
@@ -1164,8 +1192,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             } else {
                 atomicOr(d.err, 1u);
             }
-            j_kh[jl + q] = (uint32_t)(key >> 32);
-            j_kl[jl + q] = (uint32_t)key;
+            j_ord[jl + q] = (uint16_t)e;
         }
         __syncthreads();
         // ---- stayers: joiners with a smaller key than their prefix maximum
@@ -1177,12 +1204,14 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             const uint32_t ln = o_ln[r];
             if (ln & kJoinBit)
                 continue;
-            const uint64_t pm = ((uint64_t)o_pmh[r] << 32) | o_pml[r];
+            const uint32_t pr = o_pi[r];    // a stayer: its own row or one before it
+            const uint64_t pm = okey(o_s[pr], o_id[pr]);
             const int jl = JO(ln) - j0, jh = JO(ln + 1) - j0;
             int a = jl, b = jh;       // joiners of the lane with key < pm (sorted keys)
             while (a < b) {
                 const int mid = (a + b) >> 1;
-                const uint64_t kk = ((uint64_t)j_kh[mid] << 32) | j_kl[mid];
+                const uint32_t je = j_ord[mid];
+                const uint64_t kk = okey(j_s[je], j_id[je]);
                 if (kk < pm)
                     a = mid + 1;
                 else
@@ -1191,7 +1220,6 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             const int pos = (LN(ln) - n0) + (int)o_p[r] + (a - jl);
             if (pos >= 0 && pos < nw) {
                 w_src[pos] = (uint32_t)r;
-                w_ln[pos] = ln;
                 const int g = n0 + pos;
                 d.S.a[g] = ra[k];
                 d.S.id[g] = o_id[r];
@@ -1204,6 +1232,13 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             }
         }
         __syncthreads();
+        // lane of a placed row (stayers carry no join bit)
+        auto lane_of = [&](uint32_t x) { return (x & kTagJ) ? j_ln[x & ~kTagJ] : o_ln[x]; };
+        for (int k = tid; k < nw; k += kMT) {
+            w_top[k] = -1;
+            w_bot[k] = 0x7FFFFFFF;
+        }
+        __syncthreads();
         // ---- overlaps: highest offending pair of each lane
         for (int k = tid; k < nw; k += kMT) {
             const uint32_t x = w_src[k];
@@ -1211,12 +1246,13 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 atomicOr(d.err, 1u);
                 continue;
             }
-            if (k + 1 < nw && w_src[k + 1] != kNoSrc && w_ln[k + 1] == w_ln[k]) {
+            const uint32_t lk = lane_of(x);
+            if (k + 1 < nw && w_src[k + 1] != kNoSrc && lane_of(w_src[k + 1]) == lk) {
                 const uint32_t y = w_src[k + 1];
                 const float sk = (x & kTagJ) ? j_s[x & ~kTagJ] : o_s[x];
                 const float sn = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
                 if (sk > sn - len) {
-                    const int first = LN((int)w_ln[k]) - n0;
+                    const int first = LN((int)lk) - n0;
                     atomicMax(&w_top[first], k);
                     atomicMin(&w_bot[first], k);
                 }
@@ -1248,7 +1284,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                     else { o_s[kf] = sf; o_v[kf] = vf; }
                     ++clamps;
                     if (!one_scen)
-                        atomicAdd(d.cnt + (size_t)d.lanes[w_ln[k]].scen * C_N + C_CLAMPS, 1ull);
+                        atomicAdd(cnt_at(d, d.lanes[lane_of(w_src[k])].scen, C_CLAMPS), 1ull);
                 } else if (f < bot) {
                     break;
                 }
@@ -1284,9 +1320,9 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             if (one_scen) {
                 vsum += (double)v;
             } else {
-                const int sc = d.lanes[w_ln[k]].scen;
-                atomicAdd(d.cnt + (size_t)sc * C_N + C_VEH_STEPS, 1ull);
-                atomicAdd(d.sumv + sc, (double)v);
+                const int sc = d.lanes[lane_of(x)].scen;
+                atomicAdd(cnt_at(d, sc, C_VEH_STEPS), 1ull);
+                atomicAdd(sv_at(d, d.sumv, sc), (double)v);
             }
         }
     }
@@ -1309,10 +1345,10 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 ck += red_k[q];
             }
             const int sc = d.lanes[la].scen;
-            unsigned long long *c = d.cnt + (size_t)sc * C_N;
+            unsigned long long *c = cnt_at(d, sc, 0);
             if (nw) atomicAdd(c + C_VEH_STEPS, (unsigned long long)nw);
             if (ck) atomicAdd(c + C_CLAMPS, ck);
-            if (nw) atomicAdd(d.sumv + sc, sv);
+            if (nw) atomicAdd(sv_at(d, d.sumv, sc), sv);
         }
     }
     if (w == 0 && tid == 0) {
@@ -1388,10 +1424,10 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     if (gu > 16384) gu = 16384;
     if (d.upd_blocks > 0) gu = (unsigned)d.upd_blocks;
     if (d.xcd_remap) gu = (gu + 7u) & ~7u;     // workgroups past the last tile find no work
-    if (d.mode == 1)
-        hipLaunchKernelGGL(k_update<1>, dim3(gu), dim3(kUT), 0, st, d);
-    else
-        hipLaunchKernelGGL(k_update<0>, dim3(gu), dim3(kUT), 0, st, d);
+    const bool aux = d.P.debug || d.P.trace;
+    void (*ku)(Dev) = d.mode == 1 ? (aux ? k_update<1, true> : k_update<1, false>)
+                                  : (aux ? k_update<0, true> : k_update<0, false>);
+    hipLaunchKernelGGL(ku, dim3(gu), dim3(kUT), 0, st, d);
     mark(2);
     const unsigned gs = blocks_for(d.n_lanes, kScanLanes);
     hipLaunchKernelGGL(k_scan_reduce, dim3(gs), dim3(kScanThreads), 0, st, d);
