@@ -125,6 +125,37 @@ def bench_mlp(sc, args):
                               flop_per_eval=MLP_FLOP, kernel_ms=round(upd_ms, 5)))
 
 
+def bench_big(args):
+    """City network tiled 2 x 2 (160k nodes, 482k lanes) with 8M vehicles
+    pre-placed: a working set (state + proposals + joiner records, 96 B per
+    vehicle) far beyond the 256 MB Infinity Cache, so the kernels' bytes come
+    from HBM."""
+    import torch
+    from paper_2405_12520_amd import scenarios as S
+    from paper_2405_12520_amd.moss import Simulator
+    t0 = time.time()
+    sc = S.city_snapshot(8_000_000, side=400, target_undirected=184_000, hops=24)
+    say(f"[bench] 8M city generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    sim = Simulator(sc)
+    sim.step(args.warmup)
+    ms, dc = timed_steps(sim, args.steps)
+    veh_steps = int(dc[:, 6].sum())
+    kms = sim.step_timed(20)
+    n_act = sim.n_active
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    per = {k: v / 20 for k, v in kms.items()}
+    frac = {k: round(ALGO_BYTES[k] * n_act / (per[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            for k in ALGO_BYTES}
+    say(f"[bench] 8M city: {veh_steps / (ms / 1e3):.4g} vehicle-steps/s, per-kernel ms "
+        f"{ {k: round(v, 4) for k, v in per.items()} }")
+    return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
+                ms_per_step=round(ms / args.steps, 5), vehicles=int(sc.n_veh),
+                lanes=int(sc.n_lanes), kernel_ms={k: round(v, 5) for k, v in per.items()},
+                hbm_frac=frac)
+
+
 def bench_batch(args):
     """Disjoint union of independent grid scenarios (4x4 .. 16x16, 1k..50k
     vehicles each, departures over 1800 s) stepped as one network through the
@@ -174,6 +205,8 @@ def main():
     ap.add_argument("--mlp", action="store_true",
                     help="with --profile-only: step the city snapshot with the learned closure")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-big", action="store_true",
+                    help="skip the 8M-vehicle city (beyond the Infinity Cache)")
     ap.add_argument("--batch-scenarios", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also copy a device buffer of this size once (calibrates the HBM "
@@ -256,6 +289,8 @@ def main():
         extras["mlp"] = bench_mlp(sc, args)
     if not args.no_batch:
         extras["batch"] = bench_batch(args)
+    if not args.no_big:
+        extras["city8M"] = bench_big(args)
     cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_steps)
     out = dict(metric=METRIC, value=round(value, 1), unit="vehicle-steps/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms / args.steps, 5),

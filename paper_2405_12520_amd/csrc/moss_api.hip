@@ -46,7 +46,7 @@ struct Layout {
     int64_t n_route;
     bool debug, trace, mlp;
     size_t total;
-    size_t S[8], Pr[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
+    size_t S[8], Pr[8], J[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq, tr_feat,
         tr_label;
@@ -75,6 +75,8 @@ struct Layout {
         jcnt = take(4 * tiles);
         jidx = take(4 * c);
         jslane = take(4 * c);
+        for (int k = 0; k < 8; ++k)
+            J[k] = (k == 4) ? 0 : take(4 * c);      // J.lane is jslane
         jins_list = take(4 * (size_t)n_lanes);
         jins_lane = take(4 * (size_t)n_lanes);
         jcur = take(4 * (size_t)n_lanes);
@@ -292,9 +294,9 @@ static void fill_dev(moss_sim *h)
     auto F = [&](size_t o) { return (float *)(w + o); };
     auto U = [&](size_t o) { return (uint32_t *)(w + o); };
     auto I = [&](size_t o) { return (int32_t *)(w + o); };
-    SoA *sets[2] = {&d.S, &d.Pr};
-    const size_t *offs[2] = {L.S, L.Pr};
-    for (int k = 0; k < 2; ++k) {
+    SoA *sets[3] = {&d.S, &d.Pr, &d.J};
+    const size_t *offs[3] = {L.S, L.Pr, L.J};
+    for (int k = 0; k < 3; ++k) {
         SoA &x = *sets[k];
         x.s = F(offs[k][0]);
         x.v = F(offs[k][1]);
@@ -305,6 +307,7 @@ static void fill_dev(moss_sim *h)
         x.next = I(offs[k][6]);
         x.v0 = F(offs[k][7]);
     }
+    d.J.lane = U(L.jslane);
     d.n_lanes = L.n_lanes;
     d.n_scen = L.n_scen;
     d.cap = L.cap;

@@ -91,6 +91,9 @@ struct Dev {
     // k_jscatter groups all of them by target lane into jidx/jslane using the
     // per-lane cursors jcur (initialised to joff by the scan).
     uint32_t *jlist, *jlane, *jidx, *jslane, *jins_list, *jins_lane;
+    // the joiners' proposal records in the same lane-grouped order (J.lane is
+    // jslane), copied by k_jscatter so that the merge reads them coalesced
+    SoA J;
     int32_t *jcnt, *jcur;
     uint8_t *lane_red;            // red light for the lane's road at the current step
     int32_t *n_cur, *n_next, *n_dbg;

@@ -819,10 +819,21 @@ __global__ void __launch_bounds__(256) k_jscatter(Dev d)
         const uint32_t *lst = ins ? d.jins_list : d.jlist + (size_t)tile * kUpdateRows;
         const uint32_t *lan = ins ? d.jins_lane : d.jlane + (size_t)tile * kUpdateRows;
         for (int k = lane; k < cnt; k += 64) {
-            const uint32_t x = lan[k];
+            const uint32_t x = lan[k], src = lst[k];
+            // the record's loads do not wait for the slot
+            const float s = d.Pr.s[src], v = d.Pr.v[src], a = d.Pr.a[src], v0 = d.Pr.v0[src];
+            const uint32_t id = d.Pr.id[src], ptr = d.Pr.ptr[src];
+            const int32_t next = d.Pr.next[src];
             const int pos = atomicAdd(d.jcur + x, 1);
-            d.jidx[pos] = lst[k];
-            d.jslane[pos] = x;
+            d.jidx[pos] = src;
+            d.J.lane[pos] = x;
+            d.J.s[pos] = s;
+            d.J.v[pos] = v;
+            d.J.a[pos] = a;
+            d.J.id[pos] = id;
+            d.J.ptr[pos] = ptr;
+            d.J.next[pos] = next;
+            d.J.v0[pos] = v0;
         }
     }
 }
@@ -1008,7 +1019,6 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     __shared__ uint16_t j_ord[kJCap];      // the lane's joiners in key order
     __shared__ uint32_t w_src[kNewCap];
     __shared__ int lt_old[kLaneCap + 1], lt_new[kLaneCap + 1], lt_jo[kLaneCap + 1];
-    __shared__ int sh_i[8];
     __shared__ int wave_start[5];
     __shared__ double red_d[kMT / 64];
     __shared__ unsigned long long red_k[kMT / 64];
@@ -1020,20 +1030,10 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     const int w = xcd_block(d.xcd_remap);
     if (w > n_next / kMC)
         return;
-    if (tid == 0) {
-        const int4 ca = d.chunk[w], cb = d.chunk[w + 1];
-        sh_i[0] = ca.x;
-        sh_i[1] = cb.x;
-        sh_i[2] = ca.y;
-        sh_i[3] = cb.y;
-        sh_i[4] = ca.z;
-        sh_i[5] = cb.z;
-        sh_i[6] = ca.w;
-        sh_i[7] = cb.w;
-    }
-    __syncthreads();
-    const int la = sh_i[0], lb = sh_i[1];
-    const int n0 = sh_i[2], n1 = sh_i[3], o0 = sh_i[4], o1 = sh_i[5], j0 = sh_i[6], j1 = sh_i[7];
+    // chunk bounds (w is uniform: every thread reads the same two records)
+    const int4 ca = d.chunk[w], cb = d.chunk[w + 1];
+    const int la = ca.x, lb = cb.x;
+    const int n0 = ca.y, n1 = cb.y, o0 = ca.z, o1 = cb.z, j0 = ca.w, j1 = cb.w;
     const int no = o1 - o0, nw = n1 - n0, nj = j1 - j0;
     const float len = d.P.len;
     const bool one_scen = (lb <= la) || d.lanes[la].scen == d.lanes[lb - 1].scen;
@@ -1094,15 +1094,15 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         uint32_t jptr = 0;
         int32_t jnext = 0;
         if (tid < nj) {
-            const uint32_t src = d.jidx[j0 + tid];
-            j_s[tid] = d.Pr.s[src];
-            j_v[tid] = d.Pr.v[src];
-            j_id[tid] = d.Pr.id[src];
-            j_ln[tid] = d.jslane[j0 + tid];
-            ja = d.Pr.a[src];
-            jptr = d.Pr.ptr[src];
-            jnext = d.Pr.next[src];
-            jv0 = d.Pr.v0[src];
+            const int q = j0 + tid;
+            j_s[tid] = d.J.s[q];
+            j_v[tid] = d.J.v[q];
+            j_id[tid] = d.J.id[q];
+            j_ln[tid] = d.J.lane[q];
+            ja = d.J.a[q];
+            jptr = d.J.ptr[q];
+            jnext = d.J.next[q];
+            jv0 = d.J.v0[q];
         }
         for (int k = tid; k < nw; k += kMT)
             w_src[k] = kNoSrc;
