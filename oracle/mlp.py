@@ -9,9 +9,12 @@ fallback.)
 
 Parameter vector layout (float32, 4801 values):
     W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3[1]
-BF16 mode rounds W1, W2, w3 and the layer inputs (z, h1, h2) to bfloat16
-(round to nearest even) before each product; sums are exact here (FP64), FP32
-on the GPU.  Gradients in BF16 mode are those of the rounded network with
+BF16 mode rounds W1, W2, w3 and the hidden layer inputs (h1, h2) to bfloat16
+(round to nearest even) before each product, and represents each network
+input z as a pair of bfloat16 numbers, hi = bf16(z) and lo = bf16(z - hi)
+(the difference in float32, where it is exact), so that the first layer sees
+hi + lo: about 16 significant bits instead of 8.  Sums are exact here (FP64),
+FP32 on the GPU.  Gradients in BF16 mode are those of the rounded network with
 respect to the rounded weights (straight-through for the master weights).
 
 GELU is the tanh form of Hendrycks & Gimpel (2016):
@@ -66,6 +69,14 @@ def bf16(x):
     return r.view(np.float32).astype(np.float64)
 
 
+def bf16x2(x):
+    """A float32 value as the sum of two bfloat16 numbers (as float64)."""
+    x32 = np.asarray(x, dtype=np.float32)
+    hi = bf16(x32)
+    lo = bf16((x32 - hi.astype(np.float32)).astype(np.float32))
+    return hi + lo
+
+
 def gelu(x):
     return 0.5 * x * (1.0 + np.tanh(K0 * (x + K1 * x ** 3)))
 
@@ -95,7 +106,7 @@ def forward(theta, z, bf16_mode=False):
     W1, W2, w3 = p["W1"], p["W2"], p["w3"]
     if bf16_mode:
         W1, W2, w3 = bf16(W1), bf16(W2), bf16(w3)
-        z = bf16(z)
+        z = bf16x2(z)
     a1 = z @ W1.T + p["b1"]
     h1 = gelu(a1)
     h1q = bf16(h1) if bf16_mode else h1

@@ -111,14 +111,23 @@ static double gelu_d(double x)
     return 0.5 * x * (1.0 + tanh(k0 * (x + k1 * x * x * x)));
 }
 
-/* 8 -> 64 -> 64 -> 1 network; weights and layer inputs rounded to bfloat16,
- * sums in double. */
+/* Network input as a pair of bfloat16 numbers: hi = bf16(z), lo = bf16(z - hi)
+ * (the difference taken in float, where it is exact); the first layer sees
+ * hi + lo. */
+static double bf16x2r(float z)
+{
+    const float hi = (float)bf16r(z);
+    return (double)hi + bf16r(z - hi);
+}
+
+/* 8 -> 64 -> 64 -> 1 network; inputs as bfloat16 pairs, weights and hidden
+ * layer inputs rounded to bfloat16, sums in double. */
 double orc_mlp_forward(const float *theta, const float *z)
 {
     const float *W1 = theta, *b1 = theta + 512, *W2 = theta + 576, *b2 = theta + 4672,
                 *w3 = theta + 4736, *b3 = theta + 4800;
     double zq[8], h1[64], h2[64];
-    for (int i = 0; i < 8; ++i) zq[i] = bf16r(z[i]);
+    for (int i = 0; i < 8; ++i) zq[i] = bf16x2r(z[i]);
     for (int j = 0; j < 64; ++j) {
         double acc = b1[j];
         for (int i = 0; i < 8; ++i) acc += bf16r(W1[j * 8 + i]) * zq[i];

@@ -86,8 +86,9 @@ int32_t orc_read_debug(const orc_sim *m, uint32_t *id, uint32_t *leader, int32_t
 void orc_counters(const orc_sim *m, int64_t *cnt, double *sum_v);
 /* sum over network evaluations of (a_mlp - a_idm)^2 [n_scen] */
 void orc_mlp_sq(const orc_sim *m, double *sum_sq);
-/* network output for one normalised input vector z[8] (FP64 with bfloat16
- * rounding of weights and layer inputs) */
+/* network output for one normalised input vector z[8] (FP64; weights and
+ * hidden layer inputs rounded to bfloat16, each input z as the pair
+ * bf16(z) + bf16(z - bf16(z))) */
 double orc_mlp_forward(const float *theta, const float *z);
 int32_t orc_pending(const orc_sim *m);
 

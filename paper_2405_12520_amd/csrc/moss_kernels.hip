@@ -293,10 +293,10 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
     uint16_t *mz = nullptr;
     if constexpr (MODE == 1) {
         __shared__ MlpLds s_mlp;
-        __shared__ __attribute__((aligned(16))) uint16_t s_z[(kUT / 64) * 64 * kMlpIn];
+        __shared__ __attribute__((aligned(16))) uint16_t s_z[(kUT / 64) * kMlpStage];
         mlp_copy(s_mlp, static_cast<const MlpLds *>(d.mlp_pack));
         mw = &s_mlp;
-        mz = s_z + (tid >> 6) * 64 * kMlpIn;
+        mz = s_z + (tid >> 6) * kMlpStage;
     }
 
     for (int base = xcd_block(d.xcd_remap) * kUT; base < n; base += gridDim.x * kUT) {

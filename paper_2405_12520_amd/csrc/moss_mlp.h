@@ -135,36 +135,54 @@ __device__ __forceinline__ f32x4 gelu4(f32x4 c)
     return f32x4{gelu_fast(c.x), gelu_fast(c.y), gelu_fast(c.z), gelu_fast(c.w)};
 }
 
+// Staging elements of one wave's network inputs (64 vehicles x 8 inputs as
+// bfloat16 pairs).
+constexpr int kMlpStage = 64 * 2 * kMlpIn;
+
 // Network output for the 64 vehicles of a wave: lane L passes the
 // normalised inputs z[8] of its vehicle and receives that vehicle's output.
-// zs is this wave's 64*8 bfloat16 staging area in LDS.  Every thread of the
-// block must call it (it synchronises the block; inactive vehicles pass
-// zeros).  The wave works through its four 16-vehicle blocks one at a time;
-// biases enter as the accumulators' initial values.
+// zs is this wave's kMlpStage-element bfloat16 staging area in LDS.  Every
+// thread of the block must call it (it synchronises the block; inactive
+// vehicles pass zeros).  The wave works through its four 16-vehicle blocks
+// one at a time; biases enter as the accumulators' initial values.
+//
+// Inputs as bfloat16 pairs: the first product has K = 16 for 8 inputs, so
+// its second half carries the rounding remainders, z = bf16(z) +
+// bf16(z - bf16(z)), against a second copy of W1.  Relative input precision
+// is about 2^-16 instead of 2^-8 at no extra cost; it matters where IDM's
+// interaction term (s*/gap)^2 is large, which amplifies small gap and speed
+// errors.
 __device__ __forceinline__ float wave_mlp(const MlpLds &w, uint16_t *zs, const float z[8])
 {
     const int lane = __lane_id();
     const int r16 = lane & 15, q4 = lane >> 4;
     {
-        const f32x4 lo = {z[0], z[1], z[2], z[3]}, hi = {z[4], z[5], z[6], z[7]};
-        *reinterpret_cast<bf16x8 *>(zs + lane * kMlpIn) = cvt8(lo, hi);
+        const f32x4 z0 = {z[0], z[1], z[2], z[3]}, z1 = {z[4], z[5], z[6], z[7]};
+        const bf16x8 hi = cvt8(z0, z1);
+        f32x4 r0, r1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r0[k] = z0[k] - (float)hi[k];
+            r1[k] = z1[k] - (float)hi[4 + k];
+        }
+        bf16x8 *dst = reinterpret_cast<bf16x8 *>(zs + lane * 2 * kMlpIn);
+        dst[0] = hi;
+        dst[1] = cvt8(r0, r1);
     }
     __syncthreads();
 
-    const bf16x4 zero4 = {0, 0, 0, 0};
     const bf16x8 zero8 = {};
-    // layer-1 weights (A fragments, K = 8 inputs padded to 16) and bias rows
+    // layer-1 weights (A fragments: lane groups 0-1 and 2-3 hold the same W1
+    // columns, against the high and low parts of the inputs) and bias rows
     bf16x4 a1[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
-        a1[mt] = (q4 < 2) ? *reinterpret_cast<const bf16x4 *>(w.W1 + (16 * mt + r16) * kMlpIn + 4 * q4)
-                          : zero4;
+        a1[mt] = *reinterpret_cast<const bf16x4 *>(w.W1 + (16 * mt + r16) * kMlpIn + 4 * (q4 & 1));
     float out = 0.0f;
 #pragma unroll 1
     for (int nt = 0; nt < 4; ++nt) {
         // layer 1: H1^T[16 hidden][16 veh] per tile mt
-        const bf16x4 bz = (q4 < 2) ? *reinterpret_cast<const bf16x4 *>(zs + (16 * nt + r16) * kMlpIn + 4 * q4)
-                                   : zero4;
+        const bf16x4 bz = *reinterpret_cast<const bf16x4 *>(zs + (16 * nt + r16) * 2 * kMlpIn + 4 * q4);
         f32x4 g[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {

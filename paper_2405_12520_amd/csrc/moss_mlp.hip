@@ -28,6 +28,15 @@ constexpr int kSlice = 256;         // samples per partial gradient sum
 
 __device__ __forceinline__ float rnd(float x, bool bf) { return bf ? bf2f(f2bf(x)) : x; }
 
+// network input as the simulator feeds it: a pair of bfloat16 numbers
+__device__ __forceinline__ float rnd2(float x, bool bf)
+{
+    if (!bf)
+        return x;
+    const float hi = bf2f(f2bf(x));
+    return hi + bf2f(f2bf(x - hi));
+}
+
 // exact tanh-form GELU and its derivative for training (FP32)
 __device__ __forceinline__ float gelu_t(float x, float &dgdx)
 {
@@ -66,7 +75,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const float *feat, const flo
         float z[kMlpIn];
 #pragma unroll
         for (int i = 0; i < kMlpIn; ++i)
-            z[i] = rnd(mlp_in(i, feat[(size_t)src * kMlpIn + i], norm), b16);
+            z[i] = rnd2(mlp_in(i, feat[(size_t)src * kMlpIn + i], norm), b16);
         float a1 = b1;
 #pragma unroll
         for (int i = 0; i < kMlpIn; ++i)
@@ -192,7 +201,7 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *feat, int n, c
                                                     const float *norm, float *out)
 {
     __shared__ MlpLds w;
-    __shared__ __attribute__((aligned(16))) uint16_t zs[4 * 64 * kMlpIn];
+    __shared__ __attribute__((aligned(16))) uint16_t zs[4 * kMlpStage];
     mlp_pack(w, theta, norm);
     __syncthreads();
     const int wv = threadIdx.x >> 6;
@@ -202,7 +211,7 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *feat, int n, c
 #pragma unroll
         for (int k = 0; k < kMlpIn; ++k)
             z[k] = (i < n) ? mlp_in(k, feat[(size_t)i * kMlpIn + k], w.norm) : 0.0f;
-        const float y = wave_mlp(w, zs + wv * 64 * kMlpIn, z);
+        const float y = wave_mlp(w, zs + wv * kMlpStage, z);
         if (i < n)
             out[i] = y;
         __syncthreads();

@@ -38,6 +38,40 @@ def test_bf16_rounding_rules():
     assert np.all((u & 0xFFFF) == 0)
 
 
+def test_bf16_pair_inputs():
+    """A network input as two bfloat16 numbers: exact for values that are
+    already bfloat16, within 2^-16 relative otherwise (each part drops 8
+    mantissa bits of what is left), and both parts representable."""
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(100000) * np.exp(rng.uniform(-6, 6, 100000))).astype(np.float32)
+    got = mlp.bf16x2(x)
+    assert np.all(np.abs(got - x.astype(np.float64)) <= 2.0**-16 * np.abs(x))
+    b = mlp.bf16(x).astype(np.float32)
+    assert np.array_equal(mlp.bf16x2(b), b.astype(np.float64))
+    hi = mlp.bf16(x)
+    lo = got - hi
+    for part in (hi, lo):
+        u = part.astype(np.float32).view(np.uint32)
+        assert np.all((u & 0xFFFF) == 0)
+    # about 8 more bits than one bfloat16: mean relative errors ~2^-17 vs ~2^-9
+    rel = lambda y: np.mean(np.abs(y - x) / np.abs(x))
+    assert rel(got) < 2.0**-7 * rel(hi)
+
+
+def test_c_oracle_forward_equals_fp64_reference():
+    """The C oracle's network (MLP mode) and the numpy reference implement
+    the same rounded network: equal to FP64 summation-order differences."""
+    from oracle import mlp_forward
+    rng = np.random.default_rng(9)
+    for k in range(5):
+        th = mlp.init_params(30 + k)
+        th[mlp.N_PARAMS - 65:mlp.N_PARAMS] = rng.normal(0, 0.3, 65).astype(np.float32)
+        z = rng.normal(0, 1.5, (50, 8)).astype(np.float32)
+        ref, _ = mlp.forward(th.astype(np.float64), z, bf16_mode=True)
+        got = np.array([mlp_forward(th, z[i]) for i in range(z.shape[0])])
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_gradient_central_differences(seed):
     """Analytic gradient of the FP64 network equals central differences of
