@@ -170,7 +170,10 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
  * found the device error word set. */
 int moss_step(moss_sim *h, int32_t n);
 
-/* Synchronises the stream and copies the requested state rows. */
+/* Synchronises the stream and copies the requested state rows.  The copies
+ * run on the simulator's stream and are complete on return; with device
+ * destinations the whole device is synchronised first, so that a destination
+ * just released by work on another stream is not written early. */
 int moss_read_state(moss_sim *h, moss_state_out *out);
 
 /* Synchronises and copies host arrays counters[n_scen][MOSS_N_COUNTERS] and
@@ -271,7 +274,8 @@ int moss_mlp_predict(const float *feat, int32_t n, const float *theta, const flo
 /* With MOSS_FLAG_TRACE: the inputs of the network and the IDM acceleration of
  * every vehicle in the most recent step, in the row order of the state that
  * step started from, copied to feat[n][8] and label[n] (host or device
- * pointers per device flag). */
+ * pointers per device flag).  Copies are ordered and completed as in
+ * moss_read_state. */
 int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, float *label,
                     int32_t *n);
 

@@ -31,6 +31,27 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+namespace moss {
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+}  // namespace moss
+
+namespace {
+
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -799,6 +820,34 @@ static int sync_and_check(moss_sim *h)
     return MOSS_OK;
 }
 
+// Copies made by the read functions run on the simulator's stream, so that
+// they are ordered before every later step (whose kernels rewrite the buffers
+// being read), and the read waits for them before it returns.  A device
+// destination may be memory that work on another stream used until just now
+// (a caching allocator's block), so device reads drain the device first.
+struct ReadCopies {
+    moss_sim *h;
+    hipMemcpyKind kind;
+    hipError_t e;
+    ReadCopies(moss_sim *h_, bool device)
+        : h(h_), kind(device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost), e(hipSuccess)
+    {
+        if (device)
+            e = hipDeviceSynchronize();
+    }
+    void copy(void *dst, const void *src, size_t bytes)
+    {
+        if (e == hipSuccess && dst && bytes)
+            e = hipMemcpyAsync(dst, src, bytes, kind, h->stream);
+    }
+    hipError_t finish()
+    {
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(h->stream);
+        return e;
+    }
+};
+
 int moss_read_state(moss_sim *h, moss_state_out *out)
 {
     g_err.clear();
@@ -813,21 +862,21 @@ int moss_read_state(moss_sim *h, moss_state_out *out)
     out->t = h->t;
     if (n > out->capacity)
         return fail(MOSS_ENOMEM, "%d active vehicles, capacity %d", n, out->capacity);
-    const hipMemcpyKind kind = out->device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const size_t b = 4 * (size_t)n;
     const SoA &S = h->dev.S;
     if (n > 0) {
-        if (out->id) HIP_TRY(hipMemcpy(out->id, S.id, b, kind));
-        if (out->lane) HIP_TRY(hipMemcpy(out->lane, S.lane, b, kind));
-        if (out->s) HIP_TRY(hipMemcpy(out->s, S.s, b, kind));
-        if (out->v) HIP_TRY(hipMemcpy(out->v, S.v, b, kind));
-        if (out->a) HIP_TRY(hipMemcpy(out->a, S.a, b, kind));
-        if (out->cursor) {
+        ReadCopies rc_(h, out->device != 0);
+        rc_.copy(out->id, S.id, b);
+        rc_.copy(out->lane, S.lane, b);
+        rc_.copy(out->s, S.s, b);
+        rc_.copy(out->v, S.v, b);
+        rc_.copy(out->a, S.a, b);
+        if (out->cursor && rc_.e == hipSuccess) {
             int32_t *tmp = (int32_t *)(h->ws + h->lay.cursor);
-            HIP_TRY(launch_cursor(h->dev, S.id, S.ptr, tmp, n, h->stream));
-            HIP_TRY(hipStreamSynchronize(h->stream));
-            HIP_TRY(hipMemcpy(out->cursor, tmp, b, kind));
+            rc_.e = launch_cursor(h->dev, S.id, S.ptr, tmp, n, h->stream);
+            rc_.copy(out->cursor, tmp, b);
         }
+        HIP_TRY(rc_.finish());
     }
     if (h->err_seen)
         return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
@@ -924,10 +973,11 @@ int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, 
     *n = m;
     if (m > capacity)
         return fail(MOSS_ENOMEM, "%d rows, capacity %d", m, capacity);
-    const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (m > 0) {
-        if (feat) HIP_TRY(hipMemcpy(feat, h->dev.tr_feat, 4 * 8 * (size_t)m, kind));
-        if (label) HIP_TRY(hipMemcpy(label, h->dev.tr_label, 4 * (size_t)m, kind));
+        ReadCopies rc_(h, device != 0);
+        rc_.copy(feat, h->dev.tr_feat, 4 * 8 * (size_t)m);
+        rc_.copy(label, h->dev.tr_label, 4 * (size_t)m);
+        HIP_TRY(rc_.finish());
     }
     return MOSS_OK;
 }

@@ -149,6 +149,11 @@ constexpr int kUpdateRows = 256;
 enum { C_INSERTED = 0, C_INSERT_FAIL, C_ARRIVED, C_TRIP_TIME, C_CLAMPS, C_LANE_CHANGES,
        C_VEH_STEPS, C_MLP_EVAL, C_MLP_FALLBACK, C_N };
 
+// Error text of the calling thread (moss_last_error): set_error stores a
+// formatted message and returns code; clear_error empties it.
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+
 // Kernel launchers (moss_kernels.hip).
 hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);
 int step_kernel_count();

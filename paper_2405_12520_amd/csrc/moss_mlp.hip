@@ -18,6 +18,7 @@
 #include <string>
 
 #include "../../include/moss.h"
+#include "moss_internal.h"
 #include "moss_mlp.h"
 
 using namespace moss;
@@ -218,7 +219,6 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *feat, int n, c
     }
 }
 
-thread_local std::string g_mlp_err;
 
 }  // namespace
 
@@ -236,11 +236,17 @@ int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_id
                   float out_hi, float *d_grad, float *d_loss, void *d_scratch,
                   size_t scratch_bytes, void *stream)
 {
-    if (n <= 0 || !d_feat || !d_label || !d_theta || !d_norm || !d_grad || !d_scratch ||
-        !(out_lo < out_hi))
-        return MOSS_EINVAL;
+    clear_error();
+    if (n <= 0)
+        return set_error(MOSS_EINVAL, "moss_mlp_grad: n = %d, needs at least one sample", n);
+    if (!d_feat || !d_label || !d_theta || !d_norm || !d_grad || !d_scratch)
+        return set_error(MOSS_EINVAL, "moss_mlp_grad: null buffer");
+    if (!(out_lo < out_hi))
+        return set_error(MOSS_EINVAL, "moss_mlp_grad: out_lo %g not below out_hi %g", out_lo,
+                         out_hi);
     if (scratch_bytes < moss_mlp_scratch_bytes(n))
-        return MOSS_ENOMEM;
+        return set_error(MOSS_ENOMEM, "moss_mlp_grad: scratch of %zu bytes, needs %zu",
+                         scratch_bytes, moss_mlp_scratch_bytes(n));
     hipStream_t st = (hipStream_t)stream;
     const size_t b = (size_t)n;
     const int nslice = (n + kSlice - 1) / kSlice;
@@ -269,34 +275,46 @@ int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_id
                        n, sc);
     hipLaunchKernelGGL(k_mlp_sum, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, n, nslice,
                        sc, d_grad, d_loss);
-    return hipGetLastError() == hipSuccess ? MOSS_OK : MOSS_EDEVICE;
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MOSS_OK
+                           : set_error(MOSS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
 }
 
 int moss_mlp_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int32_t step,
                   float lr, float beta1, float beta2, float eps, void *stream)
 {
-    if (!d_theta || !d_m || !d_v || !d_grad || step < 1)
-        return MOSS_EINVAL;
+    clear_error();
+    if (!d_theta || !d_m || !d_v || !d_grad)
+        return set_error(MOSS_EINVAL, "moss_mlp_adam: null buffer");
+    if (step < 1)
+        return set_error(MOSS_EINVAL, "moss_mlp_adam: step %d, counts from 1", step);
     const double c1 = 1.0 - std::pow((double)beta1, (double)step);
     const double c2 = 1.0 - std::pow((double)beta2, (double)step);
     hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0,
                        (hipStream_t)stream, d_theta, d_m, d_v, d_grad, lr, beta1, beta2, eps,
                        (float)c1, (float)c2);
-    return hipGetLastError() == hipSuccess ? MOSS_OK : MOSS_EDEVICE;
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MOSS_OK
+                           : set_error(MOSS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
 }
 
 int moss_mlp_predict(const float *d_feat, int32_t n, const float *d_theta, const float *d_norm,
                      float *d_out, void *stream)
 {
-    if (n < 0 || !d_feat || !d_theta || !d_norm || !d_out)
-        return MOSS_EINVAL;
+    clear_error();
+    if (n < 0)
+        return set_error(MOSS_EINVAL, "moss_mlp_predict: n = %d", n);
     if (n == 0)
         return MOSS_OK;
+    if (!d_feat || !d_theta || !d_norm || !d_out)
+        return set_error(MOSS_EINVAL, "moss_mlp_predict: null buffer");
     unsigned g = (unsigned)((n + 255) / 256);
     if (g > 1024) g = 1024;
     hipLaunchKernelGGL(k_mlp_predict, dim3(g), dim3(256), 0, (hipStream_t)stream, d_feat, n,
                        d_theta, d_norm, d_out);
-    return hipGetLastError() == hipSuccess ? MOSS_OK : MOSS_EDEVICE;
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MOSS_OK
+                           : set_error(MOSS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"
