@@ -1,10 +1,14 @@
 """Training pipeline of the learned car-following closure.
 
-1. Trajectories: the 10 x 10 grid workload (20k vehicles, shortest-path
-   demand over an hour) runs in IDM mode with the trace on; every step yields,
-   for each active vehicle, the 8 closure inputs and the IDM acceleration
-   (the label).  Steps are split into training and held-out sets by step
-   index (every 10th step is held out).
+1. Trajectories on the 10 x 10 grid network, in IDM mode with the trace on:
+   the grid workload itself (20k vehicles, shortest-path demand over an
+   hour), whose traffic is light, and two dense starts on the same network
+   (18k and 9k vehicles pre-placed at random speeds, 600 steps each), which
+   supply the congested states (short gaps at low speed, stop-and-go) that the
+   light workload rarely reaches.  Every step yields, for each active
+   vehicle, the 8 closure inputs and the IDM acceleration (the label).
+   Steps are split into training and held-out sets by step index (every 10th
+   step of each run is held out).
 2. Input description: per-input mean and standard deviation for the
    normalisation, and the [0.1, 99.9] percentile range as the envelope
    outside which the simulator keeps IDM.
@@ -31,13 +35,12 @@ DEFAULT_PATH = os.path.join(HERE, "data", "closure_grid10.npz")
 MLP_PARAMS = moss.MLP_PARAMS
 
 
-def collect(steps: int = 3600, n_veh: int = 20000, hold_every: int = 10, log=print):
-    """Traces the grid workload; returns device tensors (features, labels,
-    step index) of all vehicle-steps."""
+DENSE_STARTS = ((18000, 600), (9000, 600))    # (vehicles, steps) pre-placed on the grid
+
+
+def _trace_run(sc, steps, k0, feats, labs, steps_idx, log, name):
     import torch
-    sc = S.grid(10, n_veh)
     sim = moss.Simulator(sc, trace=True)
-    feats, labs, steps_idx = [], [], []
     t0 = time.time()
     for k in range(steps):
         sim.step(1)
@@ -45,15 +48,28 @@ def collect(steps: int = 3600, n_veh: int = 20000, hold_every: int = 10, log=pri
         if f.shape[0]:
             feats.append(f.clone())
             labs.append(y.clone())
-            steps_idx.append(torch.full((f.shape[0],), k, dtype=torch.int32, device=f.device))
+            steps_idx.append(torch.full((f.shape[0],), k0 + k, dtype=torch.int32,
+                                        device=f.device))
         if log and (k + 1) % 600 == 0:
-            log(f"[closure] traced {k + 1} steps, {sum(x.shape[0] for x in labs)} samples, "
-                f"{time.time() - t0:.1f} s")
+            log(f"[closure] {name}: traced {k + 1} steps, "
+                f"{sum(x.shape[0] for x in labs)} samples, {time.time() - t0:.1f} s")
     sim.close()
-    F = torch.cat(feats)
-    Y = torch.cat(labs)
-    K = torch.cat(steps_idx)
-    return F, Y, K
+
+
+def collect(steps: int = 3600, n_veh: int = 20000, dense=DENSE_STARTS, log=print):
+    """Traces the grid workload and the dense starts on the same network;
+    returns device tensors (features, labels, step index) of all
+    vehicle-steps.  Step indices of the runs follow one another, each run
+    starting at a multiple of 10."""
+    import torch
+    feats, labs, steps_idx = [], [], []
+    _trace_run(S.grid(10, n_veh), steps, 0, feats, labs, steps_idx, log, "grid workload")
+    k0 = (steps + 9) // 10 * 10
+    for nv, st in dense:
+        _trace_run(S.grid_snapshot(10, nv), st, k0, feats, labs, steps_idx, log,
+                   f"dense start {nv}")
+        k0 += (st + 9) // 10 * 10
+    return torch.cat(feats), torch.cat(labs), torch.cat(steps_idx)
 
 
 LOG_INPUTS = (0, 4, 6)      # distances enter the network as ln(max(x, 0.5 m))
@@ -130,8 +146,8 @@ def rms(F, Y, theta: np.ndarray, norm: np.ndarray, inside_only: bool = True) -> 
                 inside=float(inside.double().mean().item()), n=int(e.shape[0]))
 
 
-def build_closure(path: str = DEFAULT_PATH, *, steps_trace: int = 3600, train_steps: int = 60000,
-                  log=print):
+def build_closure(path: str = DEFAULT_PATH, *, steps_trace: int = 3600,
+                  train_steps: int = 150000, log=print):
     """Full pipeline; writes theta and norm to path (npz) and returns them."""
     import torch
     F, Y, K = collect(steps_trace, log=log)
