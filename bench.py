@@ -49,8 +49,12 @@ def load_traffic(kernel):
     from paper_2405_12520_amd.profile_summary import kernel_sources_sha
     if rec.get("source_sha") != kernel_sources_sha():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    # the summary names template kernels with their arguments: the benchmark's
+    # kernel is the one whose base name matches (the IDM variant)
+    for name, k in rec.get("kernels", {}).items():
+        if name.split("<")[0] == kernel:
+            return k.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(sc, steps):

@@ -226,18 +226,6 @@ constexpr int kUT = kUpdateRows;       // rows per update block
 constexpr int kUH = 96;                // rows staged before and after them
 constexpr int kUW = kUT + 2 * kUH;
 
-__device__ __forceinline__ int lds_lower_bound_u32(const uint32_t *a, int lo, int hi, uint32_t x)
-{
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < x)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int hi, float x)
 {
     while (lo < hi) {
@@ -331,8 +319,11 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         const LaneInfo li = d.lanes[l];
         const bool red_now = act && d.lane_red[l] != 0;
         const int ls_side = (int)l + side;
-        const float vlim_side = (act && ls_side >= 0 && ls_side < d.n_lanes)
-                                    ? d.lanes[ls_side].vlim : 0.0f;
+        const bool side_ok = act && ls_side >= 0 && ls_side < d.n_lanes;
+        const float vlim_side = side_ok ? d.lanes[ls_side].vlim : 0.0f;
+        // rows of the side lane (the MOBIL target when it is on the same road)
+        const int side_r0 = side_ok ? d.ls_old[ls_side] : 0;
+        const int side_r1 = side_ok ? d.ls_old[ls_side + 1] : 0;
         RoadInfo rd_next = {0, 1, 0.0f, 0};
         bool rd_ok = false;       // rd_next holds roads[nxt]
         if (act && !hasLc && nxt >= 0) {
@@ -396,10 +387,11 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                     lt = ls_side;
                     float sN = 0.0f, vN = 0.0f, v0N = 0.0f;
                     uint32_t idN = kNone;
-                    int a0 = lds_lower_bound_u32(w_ln, 0, we - ws, (uint32_t)lt);
-                    int a1 = lds_lower_bound_u32(w_ln, a0, we - ws, (uint32_t)lt + 1u);
-                    const bool inside = (a0 > 0 || ws == 0) && (a1 < we - ws || we == n);
-                    if (inside) {
+                    // the target lane's rows from the lane starts; searched in
+                    // the window when they all lie in it
+                    const int g0 = side_r0, g1 = side_r1;
+                    const int a0 = g0 - ws, a1 = g1 - ws;
+                    if (g0 >= ws && g1 <= we) {
                         const int j = lds_lower_bound_f32(w_s, a0, a1, s);
                         if (j < a1) {
                             hasLt = true; sLt = w_s[j]; vLt = w_v[j]; idLt = w_id[j];
@@ -409,7 +401,6 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                             idN = w_id[j - 1];
                         }
                     } else {
-                        const int g0 = d.ls_old[lt], g1 = d.ls_old[lt + 1];
                         int lo2 = g0, hi2 = g1;
                         while (lo2 < hi2) {
                             int mid = (lo2 + hi2) >> 1;

@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def kernel_sources_sha() -> str:
     h = hashlib.sha256()
-    for f in ("moss_kernels.hip", "moss_internal.h"):
+    for f in ("moss_kernels.hip", "moss_internal.h", "moss_mlp.h"):
         with open(os.path.join(ROOT, "paper_2405_12520_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
