@@ -172,12 +172,9 @@ def bench_batch(args):
     say(f"[bench] batch generated in {time.time() - t0:.1f} s: {sc.summary()}")
     # launch shape: tuned on a second copy at the same point of the run
     from paper_2405_12520_amd import autotune
-    tsim = Simulator(sc)
-    tsim.step(600)
     t0 = time.time()
-    rec = autotune.tune(tsim, sc, log=say)
-    tsim.close()
-    del tsim
+    rec = autotune.tune(lambda: Simulator(sc), sc, 600, log=say)
+    torch.cuda.empty_cache()
     say(f"[bench] batch launch shape {rec['launch']} ({'cached' if rec['cached'] else 'searched'}"
         f" in {time.time() - t0:.1f} s)")
     sim = Simulator(sc)
@@ -209,6 +206,11 @@ def main():
     ap.add_argument("--mlp", action="store_true",
                     help="with --profile-only: step the city snapshot with the learned closure")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shape instead of tuning it (profiling runs "
+                         "never tune)")
+    ap.add_argument("--launch", default="", metavar="JSON",
+                    help='launch shape to use, e.g. \'{"xcd_remap": 1}\' (fields of moss_launch)')
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 8M-vehicle city (beyond the Infinity Cache)")
     ap.add_argument("--batch-scenarios", type=int, default=256)
@@ -244,7 +246,21 @@ def main():
         from paper_2405_12520_amd import closure
         theta, norm = closure.load(closure.DEFAULT_PATH)
         sc = sc.with_params(mlp=dict(theta=theta, norm=norm))
+    launch = None
+    if args.launch:
+        from paper_2405_12520_amd import autotune
+        launch = dict(launch=json.loads(args.launch), cached=True, ms_per_step=None)
+    elif not (args.no_tune or args.profile_only):
+        # launch shape tuned on a second copy at the same point of the run
+        from paper_2405_12520_amd import autotune
+        t0 = time.time()
+        launch = autotune.tune(lambda: Simulator(sc), sc, args.warmup, log=say)
+        torch.cuda.empty_cache()
+        say(f"[bench] launch shape {launch['launch']} "
+            f"({'cached' if launch['cached'] else 'searched'} in {time.time() - t0:.1f} s)")
     sim = Simulator(sc)
+    if launch:
+        autotune.apply(sim, launch)
     stream = sim.stream
     say("[bench] created; warmup")
     sim.step(args.warmup)
@@ -303,7 +319,8 @@ def main():
                config=dict(workload="city-scale synthetic network, 2M vehicles pre-placed, "
                                     "IDM car-following + randomised MOBIL, dt = 1 s",
                            vehicles=int(sc.n_veh), lanes=int(sc.n_lanes), roads=int(sc.n_roads),
-                           nodes=int(sc.n_nodes), active_vehicles=int(n_act)),
+                           nodes=int(sc.n_nodes), active_vehicles=int(n_act),
+                           launch=(launch or {}).get("launch", "default")),
                roofline=roofline, cpu_baseline=cpu, **extras)
     print(json.dumps(out), flush=True)
 

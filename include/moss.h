@@ -214,11 +214,12 @@ const char *moss_kernel_name(int32_t i);
  *                   tiles.  0 = one per tile (capped at 16384).  1..65535.
  *   scatter_blocks  workgroups of the joiner scatter (4 tiles per workgroup
  *                   per pass).  0 = default (capped at 2048).  1..65535.
- *   xcd_remap       1: workgroup b of the update and merge kernels takes tile
- *                   (b mod 8) * (G / 8) + b / 8 when the grid G is a multiple
- *                   of 8, so that each of the 8 XCDs (which receive
- *                   workgroups round-robin) works on one contiguous range of
- *                   rows and its L2 holds the halo rows its tiles share.
+ *   xcd_remap       1: the tiles that have work in a step are split into 8
+ *                   contiguous ranges, one per XCD (XCDs receive workgroups
+ *                   round-robin, so workgroup b takes tile (b mod 8) * (g / 8)
+ *                   + b / 8 with g the tile count rounded up to 8, or the grid
+ *                   if smaller), so that each XCD's L2 holds the halo rows its
+ *                   tiles share; applies to the update and merge kernels.
  *                   0: tile = b.  Default 0.
  * moss_set_launch validates (MOSS_EINVAL, state unchanged) and drops captured
  * graphs; it must not be called while steps enqueued on the handle's stream

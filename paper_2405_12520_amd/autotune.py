@@ -3,12 +3,15 @@
 The step's launch shape (``moss_launch``: steps per captured graph, workgroups
 of the update and of the joiner scatter, XCD-contiguous tile order) changes
 how the work is grouped, never what is computed, so it can be chosen by
-measurement alone.  The tuner starts from the current shape and tries one
-field at a time, keeping a change only when it is faster than the incumbent
-measured right next to it (paired windows, so that the state's drift over
-the tuning run does not decide).  Winners are cached per (GPU architecture,
-workload class) in a JSON file (``MOSS_TUNE_CACHE`` or ``_build/autotune.json``
-beside the library).
+measurement alone.  The tuner starts from the default shape and tries one
+field at a time, keeping a change when it is faster.  Every candidate is
+timed on a fresh simulator created from the same scenario and stepped to the
+same point, so all of them time exactly the same work (timing one simulator
+while its state evolves confounds the shape with the state: in a dense city
+the step cost moves by 20 % within a few hundred steps as queues form and
+dissolve).  Winners are cached per (GPU architecture, workload class) in a
+JSON file (``MOSS_TUNE_CACHE`` or ``_build/autotune.json`` beside the
+library).
 
 All timing runs the simulator's own kernels; this module only sequences
 calls.
@@ -22,14 +25,15 @@ from typing import Dict, Optional, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# Candidate values per field, tried in this order.
+# Candidate values per field, tried in this order after the default shape.
+DEFAULT = dict(graph_steps=16, update_blocks=0, scatter_blocks=0, xcd_remap=0)
 SPACE = {
-    "graph_steps": [8, 16, 32, 64],
-    "xcd_remap": [0, 1],
-    "update_blocks": [0, 512, 1024, 2048, 4096],
-    "scatter_blocks": [0, 256, 1024, 4096],
+    "xcd_remap": [1],
+    "graph_steps": [32],
+    "update_blocks": [1024, 4096],
+    "scatter_blocks": [256],
 }
-WINDOW = 64          # steps per measurement (a multiple of every graph length)
+WINDOW = 128         # steps per measurement (a multiple of every graph length)
 MARGIN = 0.02        # a change must be this much faster to be kept
 
 
@@ -84,36 +88,47 @@ def measure(sim, cfg: Dict[str, int], steps: int = WINDOW) -> float:
     return ev0.elapsed_time(ev1) / steps
 
 
-def search(sim, *, steps: int = WINDOW, log=None) -> Tuple[Dict[str, int], float]:
-    """One pass of coordinate search from the simulator's current shape."""
-    best = sim.launch()
-    t_best = measure(sim, best, steps)
+def search(make_sim, warmup: int, *, steps: int = WINDOW,
+           log=None) -> Tuple[Dict[str, int], float]:
+    """Coordinate search from the default shape; make_sim() returns a new
+    simulator at the scenario's first step."""
+    def trial(cfg):
+        sim = make_sim()
+        try:
+            sim.set_launch(**cfg)
+            sim.step(warmup)
+            return measure(sim, cfg, steps)
+        finally:
+            sim.close()
+
+    best = dict(DEFAULT)
+    t_best = trial(best)
+    if log:
+        log(f"[tune] default {best}: {t_best:.4f} ms/step")
     for field, values in SPACE.items():
         for v in values:
             if v == best[field]:
                 continue
             cand = dict(best, **{field: v})
-            t_inc = measure(sim, best, steps)
-            t_c = measure(sim, cand, steps)
+            t_c = trial(cand)
             if log:
-                log(f"[tune] {field}={v}: {t_c:.4f} ms/step vs {t_inc:.4f}")
-            if t_c < (1.0 - MARGIN) * t_inc:
+                log(f"[tune] {field}={v}: {t_c:.4f} ms/step vs {t_best:.4f}")
+            if t_c < (1.0 - MARGIN) * t_best:
                 best, t_best = cand, t_c
-    sim.set_launch(**best)
     return best, t_best
 
 
-def tune(sim, sc, *, use_cache: bool = True, steps: int = WINDOW, log=None) -> Dict[str, object]:
-    """Applies the cached shape for this workload class, or searches for one
-    on `sim` (which advances its state) and caches it.  Returns the record
-    {"launch": cfg, "ms_per_step": t, "cached": bool, "key": key}."""
+def tune(make_sim, sc, warmup: int, *, use_cache: bool = True, steps: int = WINDOW,
+         log=None) -> Dict[str, object]:
+    """The cached shape for this workload class, or one found by search (and
+    then cached).  Returns {"launch": cfg, "ms_per_step": t, "cached": bool,
+    "key": key}; apply it to a simulator with apply()."""
     key = f"{_arch()}|{workload_class(sc)}"
     if use_cache:
         rec = _load_cache().get(key)
         if rec is not None:
-            sim.set_launch(**rec["launch"])
             return dict(rec, cached=True, key=key)
-    cfg, t = search(sim, steps=steps, log=log)
+    cfg, t = search(make_sim, warmup, steps=steps, log=log)
     rec = dict(launch=cfg, ms_per_step=round(t, 5))
     _store_cache(key, rec)
     return dict(rec, cached=False, key=key)

@@ -238,14 +238,21 @@ __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int h
     return lo;
 }
 
-// Tile taken by workgroup blockIdx.x.  Workgroups are dealt round-robin to
-// the 8 XCDs; with remap on (and a grid that is a multiple of 8) each XCD
-// gets one contiguous range of tiles, so neighbouring tiles' shared rows meet
-// in the same L2.  A bijection of [0, gridDim.x) either way.
-__device__ __forceinline__ int xcd_block(int remap)
+// Tile taken by workgroup blockIdx.x when ntiles tiles have work.
+// Workgroups are dealt round-robin to the 8 XCDs; with remap on (and a grid
+// that is a multiple of 8) the first g = min(grid, ntiles rounded up to 8)
+// workgroups split those tiles into 8 contiguous ranges, one per XCD, so that
+// neighbouring tiles' shared rows meet in the same L2.  Workgroups from g on
+// keep their own index, which is past the last tile (g >= ntiles there).  A
+// bijection of [0, gridDim.x) either way; with a persistent loop (grid below
+// ntiles) each round adds gridDim.x.
+__device__ __forceinline__ int xcd_tile(int remap, int ntiles)
 {
-    const int b = blockIdx.x, g = gridDim.x;
-    if (!remap || (g & 7))
+    const int b = blockIdx.x, grid = gridDim.x;
+    if (!remap || (grid & 7))
+        return b;
+    const int g = min(grid, ((ntiles + 7) >> 3) << 3);
+    if (b >= g)
         return b;
     return (b & 7) * (g >> 3) + (b >> 3);
 }
@@ -287,7 +294,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         mz = s_z + (tid >> 6) * kMlpStage;
     }
 
-    for (int base = xcd_block(d.xcd_remap) * kUT; base < n; base += gridDim.x * kUT) {
+    for (int base = xcd_tile(d.xcd_remap, (n + kUT - 1) / kUT) * kUT; base < n;
+         base += gridDim.x * kUT) {
         const int ws = max(base - kUH, 0), we = min(base + kUT + kUH, n);
         const int i = base + tid;
         const bool act = i < n;
@@ -1018,7 +1026,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     const int lane = __lane_id();
     const int wv = tid >> 6;
     const int n_next = *d.n_next;
-    const int w = xcd_block(d.xcd_remap);
+    const int w = xcd_tile(d.xcd_remap, n_next / kMC + 1);
     if (w > n_next / kMC)
         return;
     // chunk bounds (w is uniform: every thread reads the same two records)

@@ -94,15 +94,21 @@ def test_tuner_searches_then_reuses_cache(torch_dev, tmp_path, monkeypatch):
     from paper_2405_12520_amd import autotune
     from paper_2405_12520_amd.moss import Simulator
     monkeypatch.setenv("MOSS_TUNE_CACHE", str(tmp_path / "tune.json"))
-    monkeypatch.setattr(autotune, "SPACE", {"graph_steps": [8, 32], "xcd_remap": [0, 1]})
+    monkeypatch.setattr(autotune, "SPACE", {"graph_steps": [32], "xcd_remap": [1]})
     sc = S.batch(8, horizon=300)
-    g = Simulator(sc)
-    g.step(100)
+    made = []
+
+    def make():
+        made.append(1)
+        return Simulator(sc)
+
     _say("tuner search")
-    rec = autotune.tune(g, sc, steps=32)
-    assert not rec["cached"] and rec["launch"] == g.launch()
-    g.close()
+    rec = autotune.tune(make, sc, 100, steps=32)
+    assert not rec["cached"] and len(made) == 3
+    assert set(rec["launch"]) == set(autotune.DEFAULT)
+    rec2 = autotune.tune(make, sc, 100)
+    assert rec2["cached"] and rec2["launch"] == rec["launch"] and len(made) == 3
     g = Simulator(sc)
-    rec2 = autotune.tune(g, sc)
-    assert rec2["cached"] and rec2["launch"] == rec["launch"] == g.launch()
+    autotune.apply(g, rec2)
+    assert g.launch() == rec["launch"]
     g.close()
