@@ -80,6 +80,10 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--title", default="city snapshot, 2M vehicles")
     ap.add_argument("--command", default="")
+    ap.add_argument("--sq", help="counter CSV of a pass over SQ_WAVES, SQ_WAVE_CYCLES, "
+                                 "SQ_BUSY_CYCLES, SQ_WAIT_INST_ANY, SQ_INSTS_VALU, "
+                                 "SQ_INSTS_LDS, SQ_INSTS_SALU, SQ_ACTIVE_INST_VALU")
+    ap.add_argument("--sq-command", default="")
     args = ap.parse_args()
 
     rows = list(csv.DictReader(open(args.trace)))
@@ -125,6 +129,23 @@ def main():
                    kernels=traffic)
         with open(os.path.join(os.path.dirname(args.out) or ".", "traffic.json"), "w") as fh:
             json.dump(rec, fh, indent=1)
+    if args.sq:
+        names = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+                 "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU")
+        per = {n: counter_means(args.sq, n) for n in names}
+        lines += ["", "## Instruction counters per wave (rocprofv3 --pmc, one pass)", ""]
+        if args.sq_command:
+            lines += ["```", args.sq_command, "```", ""]
+        lines += ["| kernel | waves | VALU | SALU | LDS | wave cycles | waiting on instructions |",
+                  "|---|---|---|---|---|---|---|"]
+        for k in sorted(per["SQ_WAVES"]):
+            if not k.startswith("k_"):
+                continue
+            w = per["SQ_WAVES"][k] or 1.0
+            g = lambda n: per[n].get(k, 0.0) / w
+            lines.append(f"| {k} | {per['SQ_WAVES'][k]:.0f} | {g('SQ_INSTS_VALU'):.0f} | "
+                         f"{g('SQ_INSTS_SALU'):.0f} | {g('SQ_INSTS_LDS'):.0f} | "
+                         f"{g('SQ_WAVE_CYCLES'):.0f} | {g('SQ_WAIT_INST_ANY'):.0f} |")
     with open(args.out + ".md", "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
