@@ -67,6 +67,8 @@ typedef struct {
     const float *road_length;    /* [n_roads] m, > 0 */
     const float *lane_vlim;      /* [n_lanes] speed limit, m/s, > 0 */
     const int32_t *lane_scen;    /* [n_lanes] or NULL (all 0) */
+    const double *node_x;        /* [n_nodes] m, or NULL (then moss_read_positions fails) */
+    const double *node_y;        /* [n_nodes] m, or NULL */
 } moss_network;
 
 /* Fixed-time signal plans.  Node j with node_cycle[j] > 0 shows phase
@@ -279,6 +281,25 @@ int moss_mlp_predict(const float *feat, int32_t n, const float *theta, const flo
  * moss_read_state. */
 int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, float *label,
                     int32_t *n);
+
+/* Road measures of the current state (the simulator's road outputs, Sec.
+ * III-A: average speed per road): count[r] vehicles on road r (all lanes) and
+ * mean_v[r] their mean speed (0 for an empty road), the sum taken in FP64
+ * over the road's rows in state order.  Arrays of n_roads, host or device
+ * pointers per the device flag; either may be NULL.  Synchronises like
+ * moss_read_state. */
+int moss_read_road_stats(moss_sim *h, int32_t device, int32_t *count, float *mean_v);
+
+/* Position and heading of every vehicle of the current state (the
+ * simulator's per-vehicle outputs, Sec. III-A), in state row order: a road is
+ * the straight segment from its upstream to its downstream node; a vehicle
+ * at s on lane k of road r (length L) is at A + (B - A) s / L, moved
+ * (k + 1/2) * 3.5 m to the right of the direction of travel; heading =
+ * atan2(By - Ay, Bx - Ax) in radians.  FP64.  Needs node_x / node_y at
+ * creation (MOSS_EINVAL otherwise).  Arrays of capacity >= n rows, host or
+ * device pointers per the device flag; *n receives the row count. */
+int moss_read_positions(moss_sim *h, int32_t capacity, int32_t device, double *x, double *y,
+                        double *heading, int32_t *n);
 
 /* Sum over the network's evaluations of (a_network - a_IDM)^2, per scenario
  * (host array double[n_scen]). */

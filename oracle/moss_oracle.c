@@ -168,6 +168,7 @@ struct orc_sim {
     int32_t *road_from, *road_to, *road_nlanes, *road_lane0;
     float *road_length, *lane_vlim;
     int32_t *lane_scen, *lane_road, *lane_k;
+    double *node_x, *node_y;          /* NULL without coordinates */
     int32_t *node_cycle, *node_phase, *node_offset;
     int8_t *road_group;
     uint32_t *vid;
@@ -222,7 +223,8 @@ static void free_sim(orc_sim *m)
                     m->node_phase, m->node_offset, m->road_group, m->vid, m->depart, m->v0,
                     m->route_off, m->route_len, m->routes, m->ls, m->sl, m->vi, m->s, m->v,
                     m->a, m->cur, m->q_start, m->q_end, m->q_head, m->q_list, m->cnt, m->sumv, m->mlp_sq,
-                    m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin};
+                    m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin,
+                    m->node_x, m->node_y};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i)
         free(ptrs[i]);
     free(m);
@@ -267,6 +269,10 @@ orc_sim *orc_create(const orc_input *in)
     m->road_length = dup_arr(in->road_length, R, 4);
     m->lane_vlim = dup_arr(in->lane_vlim, Lc, 4);
     m->lane_scen = dup_arr(in->lane_scen, Lc, 4);
+    if (in->node_x && in->node_y) {
+        m->node_x = dup_arr(in->node_x, m->n_nodes, 8);
+        m->node_y = dup_arr(in->node_y, m->n_nodes, 8);
+    }
     m->node_cycle = dup_arr(in->node_cycle, m->n_nodes, 4);
     m->node_phase = dup_arr(in->node_phase, m->n_nodes, 4);
     m->node_offset = dup_arr(in->node_offset, m->n_nodes, 4);
@@ -790,6 +796,41 @@ void orc_read(const orc_sim *m, uint32_t *id, int32_t *lane, float *s, float *v,
         if (a) a[q] = m->a[q];
         if (cursor) cursor[q] = m->cur[q];
     }
+}
+
+void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v)
+{
+    double *sum = calloc((size_t)m->n_roads + 1, sizeof(double));
+    for (int32_t r = 0; r < m->n_roads; ++r)
+        count[r] = 0;
+    for (int32_t q = 0; q < m->n_act; ++q) {
+        const int32_t r = m->lane_road[m->sl[q]];
+        count[r] += 1;
+        sum[r] += (double)m->v[q];
+    }
+    for (int32_t r = 0; r < m->n_roads; ++r)
+        mean_v[r] = count[r] > 0 ? (float)(sum[r] / (double)count[r]) : 0.0f;
+    free(sum);
+}
+
+int orc_positions(const orc_sim *m, double *x, double *y, double *heading)
+{
+    if (!m->node_x || !m->node_y)
+        return -1;
+    for (int32_t q = 0; q < m->n_act; ++q) {
+        const int32_t l = m->sl[q], r = m->lane_road[l];
+        const double ax = m->node_x[m->road_from[r]], ay = m->node_y[m->road_from[r]];
+        const double bx = m->node_x[m->road_to[r]], by = m->node_y[m->road_to[r]];
+        const double dx = bx - ax, dy = by - ay;
+        const double len = sqrt(dx * dx + dy * dy);
+        const double ux = len > 0.0 ? dx / len : 1.0, uy = len > 0.0 ? dy / len : 0.0;
+        const double f = (double)m->s[q] / (double)m->road_length[r];
+        const double off = ((double)m->lane_k[l] + 0.5) * 3.5;   /* lane width 3.5 m */
+        x[q] = ax + dx * f + uy * off;
+        y[q] = ay + dy * f - ux * off;
+        heading[q] = atan2(dy, dx);
+    }
+    return 0;
 }
 
 int32_t orc_read_debug(const orc_sim *m, uint32_t *id, uint32_t *leader, int32_t *flags,

@@ -31,6 +31,7 @@ typedef struct {
     const int32_t *road_from, *road_to, *road_nlanes, *road_lane0;
     const float *road_length, *lane_vlim;
     const int32_t *lane_scen;          /* may be NULL: one scenario */
+    const double *node_x, *node_y;     /* may be NULL: no positions */
     /* signals */
     const int32_t *node_cycle, *node_phase, *node_offset;
     const int8_t *road_group;
@@ -91,6 +92,13 @@ void orc_mlp_sq(const orc_sim *m, double *sum_sq);
  * bf16(z) + bf16(z - bf16(z))) */
 double orc_mlp_forward(const float *theta, const float *z);
 int32_t orc_pending(const orc_sim *m);
+/* Vehicles and mean speed (FP64 sum in state order, 0 if empty) per road. */
+void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v);
+/* Position and heading of each state row: on the segment from the road's
+ * upstream node A to its downstream node B at A + (B - A) s / L, moved
+ * (k + 1/2) * 3.5 m to the right of the direction of travel; heading
+ * atan2(By - Ay, Bx - Ax).  Returns -1 without node coordinates. */
+int orc_positions(const orc_sim *m, double *x, double *y, double *heading);
 
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -17,7 +17,7 @@ class OrcInput(C.Structure):
         ("n_scen", C.c_int32),
         ("road_from", C.c_void_p), ("road_to", C.c_void_p), ("road_nlanes", C.c_void_p),
         ("road_lane0", C.c_void_p), ("road_length", C.c_void_p), ("lane_vlim", C.c_void_p),
-        ("lane_scen", C.c_void_p),
+        ("lane_scen", C.c_void_p), ("node_x", C.c_void_p), ("node_y", C.c_void_p),
         ("node_cycle", C.c_void_p), ("node_phase", C.c_void_p), ("node_offset", C.c_void_p),
         ("road_group", C.c_void_p),
         ("n_veh", C.c_int32),
@@ -53,6 +53,9 @@ def lib():
         L.orc_read_debug.argtypes = [C.c_void_p] + [C.c_void_p] * 6
         L.orc_read_debug.restype = C.c_int32
         L.orc_counters.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_road_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_positions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_positions.restype = C.c_int
         L.orc_mlp_sq.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_mlp_forward.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_mlp_forward.restype = C.c_double
@@ -94,6 +97,8 @@ class OracleSim:
         inp.road_length = arr(sc.road_length, np.float32)
         inp.lane_vlim = arr(sc.lane_vlim, np.float32)
         inp.lane_scen = arr(sc.lane_scen, np.int32)
+        inp.node_x = arr(sc.node_x, np.float64)
+        inp.node_y = arr(sc.node_y, np.float64)
         inp.node_cycle = arr(sc.node_cycle, np.int32)
         inp.node_phase = arr(sc.node_phase, np.int32)
         inp.node_offset = arr(sc.node_offset, np.int32)
@@ -126,6 +131,7 @@ class OracleSim:
             raise ValueError("oracle create failed: " + L.orc_error().decode())
         self._h = h
         self.n_scen = sc.n_scen
+        self.n_roads = sc.n_roads
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -171,6 +177,21 @@ class OracleSim:
         sv = np.zeros(self.n_scen, np.float64)
         lib().orc_counters(self._h, _p(c), _p(sv))
         return c, sv
+
+    def road_stats(self):
+        """(vehicles per road, mean speed per road)."""
+        cnt = np.empty(self.n_roads, np.int32)
+        mv = np.empty(self.n_roads, np.float32)
+        lib().orc_road_stats(self._h, _p(cnt), _p(mv))
+        return cnt, mv
+
+    def positions(self):
+        """(x, y, heading) per state row."""
+        n = self.n_active
+        x, y, h = (np.empty(n, np.float64) for _ in range(3))
+        if lib().orc_positions(self._h, _p(x), _p(y), _p(h)) != 0:
+            raise RuntimeError("oracle created without node coordinates")
+        return x, y, h
 
     def mlp_sq(self):
         out = np.zeros(self.n_scen, np.float64)

@@ -65,12 +65,12 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     int32_t cap, n_lanes, n_roads, n_scen, n_qlanes, n_pend, n_veh, nblk;
     int64_t n_route;
-    bool debug, trace, mlp;
+    bool debug, trace, mlp, xy;
     size_t total;
     size_t S[8], Pr[8], J[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq, tr_feat,
-        tr_label;
+        tr_label, road_ab, out_buf;
 
     void plan()
     {
@@ -127,6 +127,9 @@ struct Layout {
         mlp_sq = take(8 * (size_t)kStripes * stripe_elems(n_scen));
         tr_feat = take(trace ? 4 * 8 * c : 4);
         tr_label = take(trace ? 4 * c : 4);
+        road_ab = take(xy ? 32 * (size_t)n_roads : 32);
+        // staging of the read functions' results for host destinations
+        out_buf = take(std::max(8 * (size_t)n_roads, xy ? 24 * c : (size_t)8));
         total = off;
     }
 };
@@ -169,6 +172,12 @@ int validate(const moss_network *net, const moss_signals *sig, const moss_vehicl
     }
     if (lanes != net->n_lanes)
         return fail(MOSS_EINVAL, "lane count %lld != n_lanes %d", (long long)lanes, net->n_lanes);
+    if ((net->node_x == nullptr) != (net->node_y == nullptr))
+        return fail(MOSS_EINVAL, "node_x and node_y must be given together");
+    if (net->node_x)
+        for (int32_t j = 0; j < net->n_nodes; ++j)
+            if (!std::isfinite(net->node_x[j]) || !std::isfinite(net->node_y[j]))
+                return fail(MOSS_EINVAL, "node %d: coordinates must be finite", j);
     for (int32_t l = 0; l < net->n_lanes; ++l) {
         if (!finite_pos(net->lane_vlim[l]))
             return fail(MOSS_EINVAL, "lane %d: speed limit must be finite and > 0", l);
@@ -422,6 +431,7 @@ static void plan_layout(const moss_network *net, const moss_vehicles *veh, const
     L->debug = (prm->flags & MOSS_FLAG_DEBUG) != 0;
     L->trace = (prm->flags & MOSS_FLAG_TRACE) != 0;
     L->mlp = prm->mode == MOSS_MODE_MLP;
+    L->xy = net->node_x != nullptr && net->node_y != nullptr;
     L->plan();
 }
 
@@ -661,6 +671,17 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     chk(up(L.lanes, lanes.data(), sizeof(LaneInfo) * NL));
     chk(up(L.lane_red, red0.data(), (size_t)NL));
     chk(up(L.roads, roads.data(), sizeof(RoadInfo) * NR));
+    if (L.xy) {
+        // each road's segment (upstream node, downstream node) for positions
+        std::vector<double> ab(4 * (size_t)NR);
+        for (int32_t r = 0; r < NR; ++r) {
+            ab[4 * r + 0] = net->node_x[net->road_from[r]];
+            ab[4 * r + 1] = net->node_y[net->road_from[r]];
+            ab[4 * r + 2] = net->node_x[net->road_to[r]];
+            ab[4 * r + 3] = net->node_y[net->road_to[r]];
+        }
+        chk(up(L.road_ab, ab.data(), 8 * ab.size()));
+    }
     chk(up(L.route, route.data(), 4 * route.size()));
     chk(up(L.qlanes, qlanes.data(), 4 * qlanes.size()));
     chk(up(L.q_head, qhead.data(), 4 * (size_t)NL));
@@ -979,6 +1000,73 @@ int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, 
         rc_.copy(label, h->dev.tr_label, 4 * (size_t)m);
         HIP_TRY(rc_.finish());
     }
+    return MOSS_OK;
+}
+
+int moss_read_road_stats(moss_sim *h, int32_t device, int32_t *count, float *mean_v)
+{
+    g_err.clear();
+    if (!h)
+        return fail(MOSS_EINVAL, "null handle");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    const int32_t R = h->lay.n_roads;
+    const Dev d = step_dev(h, h->parity);
+    if (device) {
+        HIP_TRY(hipDeviceSynchronize());     // destinations may have been in use elsewhere
+        HIP_TRY(launch_road_stats(d, R, count, mean_v, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    } else {
+        int32_t *dc = (int32_t *)(h->ws + h->lay.out_buf);
+        float *dm = (float *)(dc + R);
+        HIP_TRY(launch_road_stats(d, R, dc, dm, h->stream));
+        ReadCopies rc_(h, false);
+        rc_.copy(count, dc, 4 * (size_t)R);
+        rc_.copy(mean_v, dm, 4 * (size_t)R);
+        HIP_TRY(rc_.finish());
+    }
+    if (h->err_seen)
+        return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
+    return MOSS_OK;
+}
+
+int moss_read_positions(moss_sim *h, int32_t capacity, int32_t device, double *x, double *y,
+                        double *heading, int32_t *n)
+{
+    g_err.clear();
+    if (!h || !n || !x || !y || !heading)
+        return fail(MOSS_EINVAL, "null argument");
+    if (!h->lay.xy)
+        return fail(MOSS_EINVAL, "created without node coordinates (node_x, node_y)");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    int32_t m = 0;
+    HIP_TRY(hipMemcpy(&m, h->dev.n_cur, 4, hipMemcpyDeviceToHost));
+    *n = m;
+    if (m > capacity)
+        return fail(MOSS_ENOMEM, "%d active vehicles, capacity %d", m, capacity);
+    const Dev d = step_dev(h, h->parity);
+    const double *ab = (const double *)(h->ws + h->lay.road_ab);
+    if (m > 0) {
+        if (device) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(launch_positions(d, m, ab, x, y, heading, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+        } else {
+            double *bx = (double *)(h->ws + h->lay.out_buf);
+            double *by = bx + m, *bh = by + m;
+            HIP_TRY(launch_positions(d, m, ab, bx, by, bh, h->stream));
+            ReadCopies rc_(h, false);
+            rc_.copy(x, bx, 8 * (size_t)m);
+            rc_.copy(y, by, 8 * (size_t)m);
+            rc_.copy(heading, bh, 8 * (size_t)m);
+            HIP_TRY(rc_.finish());
+        }
+    }
+    if (h->err_seen)
+        return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
     return MOSS_OK;
 }
 

@@ -159,6 +159,11 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);
 int step_kernel_count();
 const char *step_kernel_name(int i);
 hipError_t launch_tails(const Dev &d, hipStream_t st);
+// Road measures and positions of the current state (read functions).
+hipError_t launch_road_stats(const Dev &d, int32_t n_roads, int32_t *count, float *mean_v,
+                             hipStream_t st);
+hipError_t launch_positions(const Dev &d, int32_t n, const double *road_ab, double *x,
+                            double *y, double *heading, hipStream_t st);
 // Builds the packed network image from mlp_theta / mlp_norm (once per simulator).
 hipError_t launch_mlp_pack(const Dev &d, hipStream_t st);
 size_t mlp_pack_bytes();

@@ -1452,6 +1452,65 @@ __global__ void __launch_bounds__(256) k_mlp_pack(Dev d)
 
 size_t mlp_pack_bytes() { return sizeof(MlpLds); }
 
+// Vehicles and mean speed per road of the current state: the rows of road r
+// are those of its lanes, [ls[lane0], ls[lane0 + nlanes]); the speeds are
+// summed in FP64 in row order.
+__global__ void k_road_stats(Dev d, int32_t n_roads, int32_t *count, float *mean_v)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_roads)
+        return;
+    const RoadInfo rd = d.roads[r];
+    const int a = d.ls_old[rd.lane0], b = d.ls_old[rd.lane0 + rd.nlanes];
+    double sum = 0.0;
+    for (int i = a; i < b; ++i)
+        sum += (double)d.S.v[i];
+    if (count)
+        count[r] = b - a;
+    if (mean_v)
+        mean_v[r] = b > a ? (float)(sum / (double)(b - a)) : 0.0f;
+}
+
+// Position and heading of each state row: along the straight segment from
+// the road's upstream node A to its downstream node B in proportion s / L,
+// (k + 1/2) lane widths of 3.5 m to the right of the direction of travel.
+// road_ab[r] = (Ax, Ay, Bx, By).
+__global__ void k_positions(Dev d, int32_t n, const double4 *road_ab, double *x, double *y,
+                            double *heading)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const LaneInfo li = d.lanes[d.S.lane[i]];
+    const double4 ab = road_ab[li.road];
+    const double dx = ab.z - ab.x, dy = ab.w - ab.y;
+    const double len = sqrt(dx * dx + dy * dy);
+    const double ux = len > 0.0 ? dx / len : 1.0, uy = len > 0.0 ? dy / len : 0.0;
+    const double f = (double)d.S.s[i] / (double)li.L;
+    const double off = ((double)li.k + 0.5) * 3.5;
+    x[i] = ab.x + dx * f + uy * off;
+    y[i] = ab.y + dy * f - ux * off;
+    heading[i] = atan2(dy, dx);
+}
+
+hipError_t launch_road_stats(const Dev &d, int32_t n_roads, int32_t *count, float *mean_v,
+                             hipStream_t st)
+{
+    if (n_roads > 0)
+        hipLaunchKernelGGL(k_road_stats, dim3(blocks_for(n_roads, 256)), dim3(256), 0, st, d,
+                           n_roads, count, mean_v);
+    return hipGetLastError();
+}
+
+hipError_t launch_positions(const Dev &d, int32_t n, const double *road_ab, double *x,
+                            double *y, double *heading, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_positions, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, n,
+                           (const double4 *)road_ab, x, y, heading);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_pack(const Dev &d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(256), 0, st, d);

@@ -31,7 +31,8 @@ vp = C.c_void_p
 class moss_network(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_roads", C.c_int32), ("n_lanes", C.c_int32),
                 ("n_scen", C.c_int32), ("road_from", vp), ("road_to", vp), ("road_nlanes", vp),
-                ("road_lane0", vp), ("road_length", vp), ("lane_vlim", vp), ("lane_scen", vp)]
+                ("road_lane0", vp), ("road_length", vp), ("lane_vlim", vp), ("lane_scen", vp),
+                ("node_x", vp), ("node_y", vp)]
 
 
 class moss_signals(C.Structure):
@@ -70,16 +71,22 @@ EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state"
            "moss_read_counters", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
            "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_adam", "moss_mlp_predict",
            "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
+           "moss_read_road_stats", "moss_read_positions",
            "moss_destroy", "moss_last_error")
 
 _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Loads libmoss.so; raises FileNotFoundError if it was not built."""
+    """Loads libmoss.so; raises FileNotFoundError if it was not built.
+
+    torch is imported first: its HIP runtime must be the one the library
+    binds to, or the process would hold two runtimes and device pointers from
+    torch would be foreign to the library."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (loads torch's HIP runtime before the library)
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: build it with paper_2405_12520_amd.build")
     L = C.CDLL(path)
@@ -106,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.moss_read_trace.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int32)]
     L.moss_read_mlp_error.argtypes = [vp, vp]
     L.moss_set_launch.argtypes = [vp, C.POINTER(moss_launch)]
+    L.moss_read_road_stats.argtypes = [vp, C.c_int32, vp, vp]
+    L.moss_read_positions.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.POINTER(C.c_int32)]
     L.moss_get_launch.argtypes = [vp, C.POINTER(moss_launch)]
     for f in EXPORTS:
         getattr(L, f).restype = C.c_char_p if f in ("moss_last_error", "moss_kernel_name") \
@@ -143,7 +152,8 @@ def marshal(sc, debug: bool = False, trace: bool = False):
                        arr(sc.road_from, np.int32), arr(sc.road_to, np.int32),
                        arr(sc.road_nlanes, np.int32), arr(sc.road_lane0, np.int32),
                        arr(sc.road_length, np.float32), arr(sc.lane_vlim, np.float32),
-                       arr(sc.lane_scen, np.int32))
+                       arr(sc.lane_scen, np.int32), arr(sc.node_x, np.float64),
+                       arr(sc.node_y, np.float64))
     sig = moss_signals(arr(sc.node_cycle, np.int32), arr(sc.node_phase, np.int32),
                        arr(sc.node_offset, np.int32), arr(sc.road_group, np.int8))
     veh = moss_vehicles(sc.n_veh, arr(sc.veh_id, np.uint32), arr(sc.depart, np.int32),
@@ -272,13 +282,18 @@ class Simulator:
     """A simulation of one Scenario on the current torch device and stream."""
 
     def __init__(self, sc, *, debug: bool = False, trace: bool = False,
-                 device: Optional[int] = None, stream=None):
+                 device: Optional[int] = None, stream=None, coords: bool = True):
+        """coords=False creates the simulator without node coordinates
+        (positions are then unavailable)."""
         import torch
         load()
         self.sc = sc
         self.n_scen = sc.n_scen
+        self.sc_n_roads = sc.n_roads
         self.cap = max(sc.n_veh, 1)
         net, sig, veh, prm, keep = marshal(sc, debug, trace)
+        if not coords:
+            net.node_x = net.node_y = None
         nbytes = moss_query_workspace(net, sig, veh, prm)
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -342,6 +357,22 @@ class Simulator:
 
     def step_timed(self, n: int):
         return moss_step_timed(self.h, n)
+
+    def road_stats(self):
+        """(vehicles per road [n_roads] int32, mean speed per road [n_roads] float32)."""
+        cnt = np.empty(self.sc_n_roads, np.int32)
+        mv = np.empty(self.sc_n_roads, np.float32)
+        _check(load().moss_read_road_stats(vp(self.h), 0, _ptr(cnt), _ptr(mv)))
+        return cnt, mv
+
+    def positions(self):
+        """(x, y, heading) of every state row, float64 (host)."""
+        c = self.cap
+        x, y, hd = (np.empty(c, np.float64) for _ in range(3))
+        n = C.c_int32(0)
+        _check(load().moss_read_positions(vp(self.h), c, 0, _ptr(x), _ptr(y), _ptr(hd),
+                                          C.byref(n)))
+        return x[:n.value], y[:n.value], hd[:n.value]
 
     def set_launch(self, **cfg):
         """Changes the launch shape (fields of moss_launch; omitted ones keep

@@ -196,3 +196,29 @@ def test_graph_replay_matches_direct_steps(sim_cls):
             assert np.array_equal(sa[f], sb[f]), f
     a.close()
     b.close()
+
+
+def test_device_reads_are_ordered_before_later_steps(sim_cls):
+    """Device-pointer reads of the state and of the trace are complete when
+    they return, so a step enqueued right after them cannot change what they
+    copied (a device-to-device copy left unordered with the simulator's
+    stream was overwritten by the next step's kernels).  2M vehicles, so
+    that the copies take long enough for a race to show."""
+    import torch
+    sc = S.city_snapshot()
+    _say("device reads vs later steps")
+    g = sim_cls(sc, trace=True)
+    for k in range(4):
+        g.step(1)
+        host = g.state(cursor=False)
+        hf, hy = g.trace(device=False)
+        dev = g.state_device()
+        df, dy = g.trace(device=True)
+        g.step(1)                       # enqueued at once: must not touch the copies
+        torch.cuda.synchronize()
+        for f in ("id", "lane", "s", "v", "a"):
+            assert np.array_equal(dev[f].cpu().numpy().view(np.uint32),
+                                  host[f].view(np.uint32)), (k, f)
+        assert np.array_equal(df.cpu().numpy().view(np.uint32), hf.view(np.uint32)), k
+        assert np.array_equal(dy.cpu().numpy().view(np.uint32), hy.view(np.uint32)), k
+    g.close()
