@@ -282,6 +282,21 @@ int moss_mlp_predict(const float *feat, int32_t n, const float *theta, const flo
 int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, float *label,
                     int32_t *n);
 
+/* Runtime control (batch writes between steps, Sec. III-C).  Both calls
+ * synchronise the handle's stream and take effect from the next step.
+ *
+ * moss_set_signal_phase: for each of the n signalised nodes node[i],
+ * phase[i] >= 0 holds that phase (roads whose signal group differs wait)
+ * until changed; phase[i] = -1 returns the node to its fixed-time plan.
+ * MOSS_EINVAL for a node out of range or without a signal, or a phase
+ * outside -1..32767 (nothing is changed then).  A node named twice takes
+ * the last phase given.
+ *
+ * moss_set_lane_vlim: speed limits (m/s, finite, > 0) of n lanes; a lane
+ * named twice takes the last value.  Host arrays for both. */
+int moss_set_signal_phase(moss_sim *h, const int32_t *node, const int32_t *phase, int32_t n);
+int moss_set_lane_vlim(moss_sim *h, const int32_t *lane, const float *vlim, int32_t n);
+
 /* Road measures of the current state (the simulator's road outputs, Sec.
  * III-A: average speed per road): count[r] vehicles on road r (all lanes) and
  * mean_v[r] their mean speed (0 for an empty road), the sum taken in FP64

@@ -170,6 +170,7 @@ struct orc_sim {
     int32_t *lane_scen, *lane_road, *lane_k;
     double *node_x, *node_y;          /* NULL without coordinates */
     int32_t *node_cycle, *node_phase, *node_offset;
+    int32_t *node_manual;             /* phase held by control, -1: fixed-time plan */
     int8_t *road_group;
     uint32_t *vid;
     int32_t *depart;
@@ -224,7 +225,7 @@ static void free_sim(orc_sim *m)
                     m->route_off, m->route_len, m->routes, m->ls, m->sl, m->vi, m->s, m->v,
                     m->a, m->cur, m->q_start, m->q_end, m->q_head, m->q_list, m->cnt, m->sumv, m->mlp_sq,
                     m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin,
-                    m->node_x, m->node_y};
+                    m->node_x, m->node_y, m->node_manual};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i)
         free(ptrs[i]);
     free(m);
@@ -273,6 +274,9 @@ orc_sim *orc_create(const orc_input *in)
         m->node_x = dup_arr(in->node_x, m->n_nodes, 8);
         m->node_y = dup_arr(in->node_y, m->n_nodes, 8);
     }
+    m->node_manual = malloc(sizeof(int32_t) * ((size_t)m->n_nodes + 1));
+    for (int32_t j = 0; j < m->n_nodes; ++j)
+        m->node_manual[j] = -1;
     m->node_cycle = dup_arr(in->node_cycle, m->n_nodes, 4);
     m->node_phase = dup_arr(in->node_phase, m->n_nodes, 4);
     m->node_offset = dup_arr(in->node_offset, m->n_nodes, 4);
@@ -390,6 +394,8 @@ static int red_for(const orc_sim *m, int32_t road, int64_t t)
     int32_t node = m->road_to[road];
     if (g < 0 || m->node_cycle[node] <= 0)
         return 0;
+    if (m->node_manual[node] >= 0)        /* held by signal control */
+        return m->node_manual[node] != g;
     int64_t c = m->node_cycle[node];
     int64_t ph = ((t + m->node_offset[node]) % c) / m->node_phase[node];
     return ph != g;
@@ -796,6 +802,19 @@ void orc_read(const orc_sim *m, uint32_t *id, int32_t *lane, float *s, float *v,
         if (a) a[q] = m->a[q];
         if (cursor) cursor[q] = m->cur[q];
     }
+}
+
+int orc_set_signal_phase(orc_sim *m, int32_t node, int32_t phase)
+{
+    if (node < 0 || node >= m->n_nodes || m->node_cycle[node] <= 0)
+        return -1;
+    m->node_manual[node] = phase < 0 ? -1 : phase;
+    return 0;
+}
+
+void orc_set_lane_vlim(orc_sim *m, int32_t lane, float vlim)
+{
+    m->lane_vlim[lane] = vlim;
 }
 
 void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v)

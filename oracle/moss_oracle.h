@@ -92,6 +92,11 @@ void orc_mlp_sq(const orc_sim *m, double *sum_sq);
  * bf16(z) + bf16(z - bf16(z))) */
 double orc_mlp_forward(const float *theta, const float *z);
 int32_t orc_pending(const orc_sim *m);
+/* Signal control: node shows `phase` from the next step on (-1: its
+ * fixed-time plan again).  Returns -1 for a node without a signal. */
+int orc_set_signal_phase(orc_sim *m, int32_t node, int32_t phase);
+/* Speed limit of a lane from the next step on. */
+void orc_set_lane_vlim(orc_sim *m, int32_t lane, float vlim);
 /* Vehicles and mean speed (FP64 sum in state order, 0 if empty) per road. */
 void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v);
 /* Position and heading of each state row: on the segment from the road's

@@ -54,6 +54,9 @@ def lib():
         L.orc_read_debug.restype = C.c_int32
         L.orc_counters.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_road_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_set_signal_phase.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.orc_set_signal_phase.restype = C.c_int
+        L.orc_set_lane_vlim.argtypes = [C.c_void_p, C.c_int32, C.c_float]
         L.orc_positions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_positions.restype = C.c_int
         L.orc_mlp_sq.argtypes = [C.c_void_p, C.c_void_p]
@@ -177,6 +180,15 @@ class OracleSim:
         sv = np.zeros(self.n_scen, np.float64)
         lib().orc_counters(self._h, _p(c), _p(sv))
         return c, sv
+
+    def set_signal_phase(self, nodes, phases):
+        for j, p in zip(np.atleast_1d(nodes), np.atleast_1d(phases)):
+            if lib().orc_set_signal_phase(self._h, int(j), int(p)) != 0:
+                raise ValueError(f"node {j} has no signal")
+
+    def set_lane_vlim(self, lanes, vlims):
+        for l, v in zip(np.atleast_1d(lanes), np.atleast_1d(vlims)):
+            lib().orc_set_lane_vlim(self._h, int(l), float(np.float32(v)))
 
     def road_stats(self):
         """(vehicles per road, mean speed per road)."""

@@ -70,7 +70,7 @@ struct Layout {
     size_t S[8], Pr[8], J[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq, tr_feat,
-        tr_label, road_ab, out_buf;
+        tr_label, road_ab, out_buf, ctl_idx, ctl_rec;
 
     void plan()
     {
@@ -128,6 +128,8 @@ struct Layout {
         tr_feat = take(trace ? 4 * 8 * c : 4);
         tr_label = take(trace ? 4 * c : 4);
         road_ab = take(xy ? 32 * (size_t)n_roads : 32);
+        ctl_idx = take(4 * (size_t)n_lanes);
+        ctl_rec = take(sizeof(LaneInfo) * (size_t)n_lanes);
         // staging of the read functions' results for host destinations
         out_buf = take(std::max(8 * (size_t)n_roads, xy ? 24 * c : (size_t)8));
         total = off;
@@ -274,6 +276,13 @@ struct moss_sim {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graphs_ok = true;
     int32_t graph_steps = 16;      // even; 0 = no graphs
+    // control: host copy of the lane records, each signalised node's incoming
+    // lanes (CSR), staging of the records a control call changes
+    std::vector<LaneInfo> lanes_h;
+    std::vector<int32_t> in_off, in_lanes;
+    std::vector<uint8_t> node_sig;
+    std::vector<int32_t> patch_idx;
+    std::vector<LaneInfo> patch_rec;
 };
 
 static Dev step_dev(const moss_sim *h, int parity);
@@ -505,6 +514,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
             li.cycle = (uint16_t)(signalised ? sig->node_cycle[j] : 1);
             li.phase = (uint16_t)(signalised ? sig->node_phase[j] : 1);
             li.offset = (uint16_t)(signalised ? sig->node_offset[j] % sig->node_cycle[j] : 0);
+            li.manual = -1;
             li.road = r;
         }
     }
@@ -512,13 +522,8 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     // --- red lights at the first step: phase ((t + offset) mod cycle) div
     // phase_len differs from the road's group
     std::vector<uint8_t> red0(NL, 0);
-    for (int32_t l = 0; l < NL; ++l) {
-        const LaneInfo &li = lanes[l];
-        if (li.group >= 0) {
-            uint32_t ph = (((uint32_t)p.t0 + li.offset) % li.cycle) / li.phase;
-            red0[l] = (int)ph != (int)li.group;
-        }
-    }
+    for (int32_t l = 0; l < NL; ++l)
+        red0[l] = lane_red_at(lanes[l], (uint32_t)p.t0) ? 1 : 0;
 
     // --- routes, each followed by -1 and the vehicle's departure step
     std::vector<int32_t> route((size_t)L.n_route + 2 * (size_t)N + 1);
@@ -671,6 +676,24 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     chk(up(L.lanes, lanes.data(), sizeof(LaneInfo) * NL));
     chk(up(L.lane_red, red0.data(), (size_t)NL));
     chk(up(L.roads, roads.data(), sizeof(RoadInfo) * NR));
+    {
+        // incoming lanes of each node, for signal control
+        const int32_t NN = net->n_nodes;
+        h->in_off.assign((size_t)NN + 1, 0);
+        h->node_sig.assign((size_t)NN, 0);
+        for (int32_t j = 0; j < NN; ++j)
+            h->node_sig[j] = sig->node_cycle[j] > 0;
+        for (int32_t r = 0; r < NR; ++r)
+            h->in_off[net->road_to[r] + 1] += net->road_nlanes[r];
+        for (int32_t j = 0; j < NN; ++j)
+            h->in_off[j + 1] += h->in_off[j];
+        h->in_lanes.resize((size_t)h->in_off[NN]);
+        std::vector<int32_t> fill(h->in_off.begin(), h->in_off.end() - 1);
+        for (int32_t r = 0; r < NR; ++r)
+            for (int32_t k = 0; k < net->road_nlanes[r]; ++k)
+                h->in_lanes[fill[net->road_to[r]]++] = net->road_lane0[r] + k;
+        h->lanes_h = lanes;
+    }
     if (L.xy) {
         // each road's segment (upstream node, downstream node) for positions
         std::vector<double> ab(4 * (size_t)NR);
@@ -1001,6 +1024,85 @@ int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, 
         HIP_TRY(rc_.finish());
     }
     return MOSS_OK;
+}
+
+// Uploads the staged lane records and patches them on the simulator's
+// stream (ordered with the steps around it).
+static int upload_patch(moss_sim *h)
+{
+    const int32_t n = (int32_t)h->patch_idx.size();
+    if (n == 0)
+        return MOSS_OK;
+    HIP_TRY(hipSetDevice(h->device));
+    int32_t *di = (int32_t *)(h->ws + h->lay.ctl_idx);
+    LaneInfo *dr = (LaneInfo *)(h->ws + h->lay.ctl_rec);
+    // the staging area may still be read by a patch enqueued before
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpyAsync(di, h->patch_idx.data(), 4 * (size_t)n, hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipMemcpyAsync(dr, h->patch_rec.data(), sizeof(LaneInfo) * (size_t)n,
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_lane_patch(step_dev(h, h->parity), di, dr, n, h->stream));
+    // the host staging vectors are reused by the next call
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MOSS_OK;
+}
+
+// Each changed lane once (a lane named twice carries the last change), with
+// its final record.
+static int stage_and_upload(moss_sim *h)
+{
+    std::sort(h->patch_idx.begin(), h->patch_idx.end());
+    h->patch_idx.erase(std::unique(h->patch_idx.begin(), h->patch_idx.end()),
+                       h->patch_idx.end());
+    h->patch_rec.clear();
+    for (int32_t l : h->patch_idx)
+        h->patch_rec.push_back(h->lanes_h[l]);
+    return upload_patch(h);
+}
+
+int moss_set_signal_phase(moss_sim *h, const int32_t *node, const int32_t *phase, int32_t n)
+{
+    g_err.clear();
+    if (!h || (n > 0 && (!node || !phase)) || n < 0)
+        return fail(MOSS_EINVAL, "null argument or negative count");
+    const int32_t NN = (int32_t)h->node_sig.size();
+    for (int32_t i = 0; i < n; ++i) {
+        if (node[i] < 0 || node[i] >= NN)
+            return fail(MOSS_EINVAL, "node %d out of range", node[i]);
+        if (!h->node_sig[node[i]])
+            return fail(MOSS_EINVAL, "node %d has no signal", node[i]);
+        if (phase[i] < -1 || phase[i] > 32767)
+            return fail(MOSS_EINVAL, "node %d: phase %d not in -1..32767", node[i], phase[i]);
+    }
+    h->patch_idx.clear();
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t q = h->in_off[node[i]]; q < h->in_off[node[i] + 1]; ++q) {
+            const int32_t l = h->in_lanes[q];
+            h->lanes_h[l].manual = (int16_t)phase[i];
+            h->patch_idx.push_back(l);
+        }
+    return stage_and_upload(h);
+}
+
+int moss_set_lane_vlim(moss_sim *h, const int32_t *lane, const float *vlim, int32_t n)
+{
+    g_err.clear();
+    if (!h || (n > 0 && (!lane || !vlim)) || n < 0)
+        return fail(MOSS_EINVAL, "null argument or negative count");
+    const int32_t NL = (int32_t)h->lanes_h.size();
+    for (int32_t i = 0; i < n; ++i) {
+        if (lane[i] < 0 || lane[i] >= NL)
+            return fail(MOSS_EINVAL, "lane %d out of range", lane[i]);
+        if (!finite_pos(vlim[i]))
+            return fail(MOSS_EINVAL, "lane %d: speed limit must be finite and > 0", lane[i]);
+    }
+    h->patch_idx.clear();
+    for (int32_t i = 0; i < n; ++i) {
+        h->lanes_h[lane[i]].vlim = vlim[i];
+        h->patch_idx.push_back(lane[i]);
+    }
+    return stage_and_upload(h);
 }
 
 int moss_read_road_stats(moss_sim *h, int32_t device, int32_t *count, float *mean_v)

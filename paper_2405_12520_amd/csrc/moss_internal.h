@@ -28,9 +28,23 @@ struct LaneInfo {
     uint8_t nlanes;
     int8_t group;       // signal group of the road at its downstream node, -1 none
     uint8_t pad0;
-    uint16_t cycle, phase, offset, pad1;   // plan of the downstream node (offset < cycle)
+    uint16_t cycle, phase, offset;         // plan of the downstream node (offset < cycle)
+    int16_t manual;     // phase held by signal control, -1: the fixed-time plan
     int32_t road;
 };
+
+// Red light for the lanes of a road at step t: the road waits unless the
+// phase its downstream junction shows (held by control, else of the
+// fixed-time plan) is its group.
+__host__ __device__ inline bool lane_red_at(const LaneInfo &li, uint32_t t)
+{
+    if (li.group < 0)
+        return false;
+    const int ph = li.manual >= 0 ? (int)li.manual
+                                  : (int)(((t + (uint32_t)li.offset) % (uint32_t)li.cycle) /
+                                          (uint32_t)li.phase);
+    return ph != (int)li.group;
+}
 
 // Per-road constants used when following a route.
 struct RoadInfo {
@@ -159,6 +173,10 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);
 int step_kernel_count();
 const char *step_kernel_name(int i);
 hipError_t launch_tails(const Dev &d, hipStream_t st);
+// Overwrites n lane records (signal control, speed limits) and recomputes
+// their red flags for the step about to run.
+hipError_t launch_lane_patch(const Dev &d, const int32_t *idx, const LaneInfo *rec, int32_t n,
+                             hipStream_t st);
 // Road measures and positions of the current state (read functions).
 hipError_t launch_road_stats(const Dev &d, int32_t n_roads, int32_t *count, float *mean_v,
                              hipStream_t st);

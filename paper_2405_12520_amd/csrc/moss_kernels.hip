@@ -774,14 +774,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
             d.leave[l] = 0;
             d.jcount[l] = 0;
             // red light of the lane's road at the next step
-            const LaneInfo li = d.lanes[l];
-            uint8_t red = 0;
-            if (li.group >= 0) {
-                const uint32_t ph = ((tnext + (uint32_t)li.offset) % (uint32_t)li.cycle) /
-                                    (uint32_t)li.phase;
-                red = (int)ph != (int)li.group;
-            }
-            d.lane_red[l] = red;
+            d.lane_red[l] = lane_red_at(d.lanes[l], tnext) ? 1 : 0;
             // chunks whose first row lies in (start, end] of lane l begin at
             // lane l+1: record its lane, new start, old start and joiner offset
             for (int w = run / kMergeRows + 1; w * kMergeRows <= run + cnt[q]; ++w)
@@ -1451,6 +1444,25 @@ __global__ void __launch_bounds__(256) k_mlp_pack(Dev d)
 }
 
 size_t mlp_pack_bytes() { return sizeof(MlpLds); }
+
+__global__ void k_lane_patch(Dev d, const int32_t *idx, const LaneInfo *rec, int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int l = idx[i];
+    const_cast<LaneInfo *>(d.lanes)[l] = rec[i];
+    d.lane_red[l] = lane_red_at(rec[i], (uint32_t)*d.t) ? 1 : 0;
+}
+
+hipError_t launch_lane_patch(const Dev &d, const int32_t *idx, const LaneInfo *rec, int32_t n,
+                             hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_lane_patch, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, idx, rec,
+                           n);
+    return hipGetLastError();
+}
 
 // Vehicles and mean speed per road of the current state: the rows of road r
 // are those of its lanes, [ls[lane0], ls[lane0 + nlanes]); the speeds are

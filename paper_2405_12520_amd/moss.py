@@ -71,7 +71,8 @@ EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state"
            "moss_read_counters", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
            "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_adam", "moss_mlp_predict",
            "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
-           "moss_read_road_stats", "moss_read_positions",
+           "moss_read_road_stats", "moss_read_positions", "moss_set_signal_phase",
+           "moss_set_lane_vlim",
            "moss_destroy", "moss_last_error")
 
 _lib = None
@@ -114,6 +115,8 @@ def load(path: str = LIB_PATH):
     L.moss_read_mlp_error.argtypes = [vp, vp]
     L.moss_set_launch.argtypes = [vp, C.POINTER(moss_launch)]
     L.moss_read_road_stats.argtypes = [vp, C.c_int32, vp, vp]
+    L.moss_set_signal_phase.argtypes = [vp, vp, vp, C.c_int32]
+    L.moss_set_lane_vlim.argtypes = [vp, vp, vp, C.c_int32]
     L.moss_read_positions.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.POINTER(C.c_int32)]
     L.moss_get_launch.argtypes = [vp, C.POINTER(moss_launch)]
     for f in EXPORTS:
@@ -357,6 +360,22 @@ class Simulator:
 
     def step_timed(self, n: int):
         return moss_step_timed(self.h, n)
+
+    def set_signal_phase(self, nodes, phases):
+        """Holds phases[i] at nodes[i] from the next step on (-1: fixed-time plan)."""
+        j = np.ascontiguousarray(np.atleast_1d(nodes), np.int32)
+        p = np.ascontiguousarray(np.atleast_1d(phases), np.int32)
+        if j.shape != p.shape:
+            raise ValueError("nodes and phases differ in length")
+        _check(load().moss_set_signal_phase(vp(self.h), _ptr(j), _ptr(p), int(j.shape[0])))
+
+    def set_lane_vlim(self, lanes, vlims):
+        """Speed limits of lanes from the next step on."""
+        l = np.ascontiguousarray(np.atleast_1d(lanes), np.int32)
+        v = np.ascontiguousarray(np.atleast_1d(vlims), np.float32)
+        if l.shape != v.shape:
+            raise ValueError("lanes and limits differ in length")
+        _check(load().moss_set_lane_vlim(vp(self.h), _ptr(l), _ptr(v), int(l.shape[0])))
 
     def road_stats(self):
         """(vehicles per road [n_roads] int32, mean speed per road [n_roads] float32)."""
