@@ -68,7 +68,7 @@ struct Layout {
     bool debug, trace, mlp, xy;
     size_t total;
     size_t S[8], Pr[8], J[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
-        roads, route, qlanes, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
+        roads, route, qlanes, q_hdep, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq, tr_feat,
         tr_label, road_ab, out_buf, ctl_idx, ctl_rec;
 
@@ -107,6 +107,7 @@ struct Layout {
         roads = take(sizeof(RoadInfo) * (size_t)n_roads);
         route = take(4 * ((size_t)n_route + 2 * (size_t)n_veh + 1));
         qlanes = take(4 * (size_t)n_qlanes);
+        q_hdep = take(4 * (size_t)n_qlanes);
         q_head = take(4 * (size_t)n_lanes);
         q_end = take(4 * (size_t)n_lanes);
         q_id = take(4 * (size_t)n_pend);
@@ -378,6 +379,7 @@ static void fill_dev(moss_sim *h)
     d.err = (uint32_t *)(sc + 5);
     d.t = (int64_t *)(sc + 8);
     d.qlanes = I(L.qlanes);
+    d.q_hdep = I(L.q_hdep);
     d.q_head = I(L.q_head);
     d.q_end = I(L.q_end);
     d.q_id = U(L.q_id);
@@ -707,6 +709,12 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     }
     chk(up(L.route, route.data(), 4 * route.size()));
     chk(up(L.qlanes, qlanes.data(), 4 * qlanes.size()));
+    {
+        std::vector<int32_t> hdep(qlanes.size());
+        for (size_t q = 0; q < qlanes.size(); ++q)
+            hdep[q] = qdep[qhead[qlanes[q]]];
+        chk(up(L.q_hdep, hdep.data(), 4 * hdep.size()));
+    }
     chk(up(L.q_head, qhead.data(), 4 * (size_t)NL));
     chk(up(L.q_end, qend.data(), 4 * (size_t)NL));
     chk(up(L.q_id, qid.data(), 4 * (size_t)NQ));

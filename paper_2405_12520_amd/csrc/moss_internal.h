@@ -115,6 +115,7 @@ struct Dev {
     int64_t *t;
     // departure queues
     const int32_t *qlanes;
+    int32_t *q_hdep;              // [n_qlanes] departure step of queue qlanes[q]'s head, INT32_MAX when empty
     int32_t *q_head;
     const int32_t *q_end;
     const uint32_t *q_id;

@@ -175,35 +175,51 @@ __device__ __forceinline__ void wave_count(const Dev &d, int c, bool pred, int s
 // the end of the step.
 __global__ void k_insert(Dev d)
 {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= d.n_qlanes)
-        return;
-    const int l = d.qlanes[q];
-    const int h = d.q_head[l];
-    if (h >= d.q_end[l])
-        return;
-    const int64_t t = *d.t;
-    if ((int64_t)d.q_dep[h] > t)
-        return;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const Params &P = d.P;
-    const LaneInfo li = d.lanes[l];
-    float v0e = fmin32(d.q_v0[h], li.vlim);
-    int lo = d.ls_old[l], hi = d.ls_old[l + 1];
-    bool ok;
-    float vins;
-    if (lo == hi) {
-        ok = true;
-        vins = v0e;
-    } else {
-        vins = fmin32(v0e, d.S.v[lo]);
-        ok = (d.S.s[lo] - P.len) >= (P.s0 + vins * P.T);
+    bool ins = false;
+    int l = 0, h = 0;
+    float vins = 0.0f;
+    unsigned long long *c = nullptr;
+    // the head's departure step is kept per queue, so that lanes with nothing
+    // due leave after one coalesced load
+    if (q < d.n_qlanes && (int64_t)d.q_hdep[q] <= *d.t) {
+        l = d.qlanes[q];
+        h = d.q_head[l];
+        {
+            const LaneInfo li = d.lanes[l];
+            const float v0e = fmin32(d.q_v0[h], li.vlim);
+            const int lo = d.ls_old[l], hi = d.ls_old[l + 1];
+            bool ok;
+            if (lo == hi) {
+                ok = true;
+                vins = v0e;
+            } else {
+                vins = fmin32(v0e, d.S.v[lo]);
+                ok = (d.S.s[lo] - P.len) >= (P.s0 + vins * P.T);
+            }
+            c = cnt_at(d, li.scen, 0);
+            if (ok)
+                ins = true;
+            else
+                atomicAdd(c + C_INSERT_FAIL, 1ull);
+        }
     }
-    unsigned long long *c = cnt_at(d, li.scen, 0);
-    if (!ok) {
-        atomicAdd(c + C_INSERT_FAIL, 1ull);
+    // one reservation of insertion slots per wave
+    const unsigned long long m = __ballot(ins);
+    if (m == 0)
         return;
-    }
-    const uint32_t slot = (uint32_t)(*d.n_cur) + atomicAdd(d.n_ins, 1u);
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (__lane_id() == leader)
+        base = atomicAdd(d.n_ins, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (!ins)
+        return;
+    const int lane_id = __lane_id();
+    const unsigned long long below = lane_id ? (~0ull >> (64 - lane_id)) : 0ull;
+    const uint32_t e = base + (uint32_t)__popcll(m & below);
+    const uint32_t slot = (uint32_t)(*d.n_cur) + e;
     d.Pr.s[slot] = 0.0f;
     d.Pr.v[slot] = vins;
     d.Pr.a[slot] = 0.0f;
@@ -212,11 +228,11 @@ __global__ void k_insert(Dev d)
     d.Pr.ptr[slot] = d.q_ptr[h];
     d.Pr.next[slot] = d.q_next[h];
     d.Pr.v0[slot] = d.q_v0[h];
-    const uint32_t e = slot - (uint32_t)(*d.n_cur);
     d.jins_list[e] = slot;
     d.jins_lane[e] = (uint32_t)l;
     atomicAdd(d.jcount + l, 1);
     d.q_head[l] = h + 1;
+    d.q_hdep[q] = h + 1 < d.q_end[l] ? d.q_dep[h + 1] : INT32_MAX;
     atomicAdd(c + C_INSERTED, 1ull);
 }
 
@@ -789,27 +805,31 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
         d.ls_new[d.n_lanes] = run;
         d.joff[d.n_lanes] = runj;
         *d.n_next = run;
-        const int4 end = make_int4(d.n_lanes, run, d.ls_old[d.n_lanes], runj);
-        for (int w = run / kMergeRows + 1; w <= d.cap / kMergeRows + 1; ++w)
-            d.chunk[w] = end;
+        // upper bound of the last chunk (merge blocks past it read nothing)
+        d.chunk[run / kMergeRows + 1] =
+            make_int4(d.n_lanes, run, d.ls_old[d.n_lanes], runj);
     }
 }
 
 // ----------------------------------------------------- joiners by lane --
 
-// One wave per update tile (plus one for the insertions): each joiner takes
+// One wave per update tile (then per kUpdateRows insertions): each joiner takes
 // the next slot of its target lane's bucket.
 __global__ void __launch_bounds__(256) k_jscatter(Dev d)
 {
     const int ntiles = (*d.n_cur + kUpdateRows - 1) / kUpdateRows;
+    // insertions in tiles of kUpdateRows after the update tiles
+    const int nins = (int)*d.n_ins;
+    const int itiles = (nins + kUpdateRows - 1) / kUpdateRows;
     const int lane = __lane_id();
     const int waves = gridDim.x * (blockDim.x >> 6);
-    for (int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile <= ntiles;
+    for (int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntiles + itiles;
          tile += waves) {
-        const bool ins = tile == ntiles;
-        const int cnt = ins ? (int)*d.n_ins : d.jcnt[tile];
-        const uint32_t *lst = ins ? d.jins_list : d.jlist + (size_t)tile * kUpdateRows;
-        const uint32_t *lan = ins ? d.jins_lane : d.jlane + (size_t)tile * kUpdateRows;
+        const bool ins = tile >= ntiles;
+        const int k0 = ins ? (tile - ntiles) * kUpdateRows : 0;
+        const int cnt = ins ? min(kUpdateRows, nins - k0) : d.jcnt[tile];
+        const uint32_t *lst = ins ? d.jins_list + k0 : d.jlist + (size_t)tile * kUpdateRows;
+        const uint32_t *lan = ins ? d.jins_lane + k0 : d.jlane + (size_t)tile * kUpdateRows;
         for (int k = lane; k < cnt; k += 64) {
             const uint32_t x = lan[k], src = lst[k];
             // the record's loads do not wait for the slot
