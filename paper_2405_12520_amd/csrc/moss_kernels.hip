@@ -959,10 +959,16 @@ constexpr int kMT = 256;          // threads per merge block (4 waves)
 constexpr int kMC = kMergeRows;   // new rows per chunk
 constexpr int kOldCap = 3 * kMT;  // old rows staged per chunk (3 per thread)
 constexpr int kNewCap = 3 * kMT;  // new rows staged per chunk
-constexpr int kJCap = 192;        // joiners staged per chunk (at most 1 per thread)
+constexpr int kJCap = 160;        // joiners staged per chunk (at most 1 per thread)
 constexpr int kLaneCap = 128;     // owned lanes whose starts are cached in LDS
-constexpr uint32_t kTagJ = 0x80000000u;
-constexpr uint32_t kNoSrc = 0xFFFFFFFFu;
+// Sources of placed rows (w_src): an old row index, a joiner index | kTagJ,
+// or kNoSrc; both indices are below 2^15.
+constexpr uint16_t kTagJ = 0x8000u;
+constexpr uint16_t kNoSrc = 0xFFFFu;
+// Lanes of staged rows and joiners are kept relative to the chunk's first
+// owned lane, in 15 bits, with kLeave16 marking old rows that leave the lane.
+constexpr uint16_t kLeave16 = 0x8000u;
+constexpr int kRelLanes = 0x8000;
 
 // Segmented scan over one wave of old rows: inclusive prefix maximum of the
 // stayer keys (returned as the row index holding it, kNoRow before the
@@ -970,6 +976,8 @@ constexpr uint32_t kNoSrc = 0xFFFFFFFFu;
 // heads and continuing from the carry when the wave's first rows continue a
 // lane.
 constexpr uint32_t kNoRow = 0xFFFFu;
+static_assert(2 * kOldCap + kJCap <= 4 * kNewCap, "o_p, o_pi and j_ord share u_buf");
+static_assert(kOldCap < 0x8000 && kJCap < 0x8000, "row sources are 15-bit indices");
 
 __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, uint64_t key,
                                               uint32_t row, uint64_t &c_pm, uint32_t &c_pi,
@@ -1009,31 +1017,350 @@ __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, ui
     c_p = __shfl(p, 63) + (uint32_t)((sm >> 63) & 1ull);
 }
 
-// Next state, one chunk of kMC new rows per block.  A block owns the lanes
-// whose first new row falls in its chunk; their old rows and joiners are
-// staged in LDS (their other fields in registers of the staging thread),
-// positions are computed in parallel (see above), overlaps are removed per
-// lane, and the rows are written out.  Chunks that do not fit the LDS tile
-// take merge_lane_global.
-__global__ void __launch_bounds__(kMT) k_merge(Dev d)
+// Merge of the whole lanes [la, lb) -- new rows [n0, n1), old rows [o0, o1),
+// joiners [j0, j1), which the caller has checked to fit the LDS tile.  Their
+// old rows and joiners are staged in LDS (their other fields in registers of
+// the staging thread), positions are computed in parallel (see above),
+// overlaps are removed per lane, and the rows are written out.
+__device__ __forceinline__ void merge_group(const Dev &d, const int la, const int lb, const int n0,
+                                            const int n1, const int o0, const int o1,
+                                            const int j0, const int j1, const bool one_scen,
+                                            double &vsum, unsigned long long &clamps)
 {
     __shared__ float o_s[kOldCap], o_v[kOldCap];
-    __shared__ uint32_t o_ln[kOldCap], o_id[kOldCap];
-    // stayer ranks and prefix-maximum rows (scan to stayer placement), then
-    // the overlap markers of the lanes' first rows (overlap removal)
+    __shared__ uint32_t o_id[kOldCap];
+    __shared__ uint16_t o_ln[kOldCap];
+    // stayer ranks, prefix-maximum rows and the joiners in key order per lane
+    // (scan to stayer placement), then the overlap markers of the lanes'
+    // first rows (overlap removal)
     __shared__ uint32_t u_buf[2 * kNewCap];
     uint16_t *const o_p = reinterpret_cast<uint16_t *>(u_buf);
     uint16_t *const o_pi = o_p + kOldCap;
+    uint16_t *const j_ord = o_pi + kOldCap;
     int *const w_top = reinterpret_cast<int *>(u_buf);
     int *const w_bot = w_top + kNewCap;
     __shared__ float j_s[kJCap], j_v[kJCap];
-    __shared__ uint32_t j_id[kJCap], j_ln[kJCap];
-    __shared__ uint16_t j_ord[kJCap];      // the lane's joiners in key order
-    __shared__ uint32_t w_src[kNewCap];
+    __shared__ uint32_t j_id[kJCap];
+    __shared__ uint16_t j_ln[kJCap];
+    __shared__ uint16_t w_src[kNewCap];
     __shared__ int lt_old[kLaneCap + 1], lt_new[kLaneCap + 1], lt_jo[kLaneCap + 1];
     __shared__ int wave_start[5];
+
+    const int tid = threadIdx.x;
+    const int lane = __lane_id();
+    const int wv = tid >> 6;
+    const int no = o1 - o0, nw = n1 - n0, nj = j1 - j0;
+    const float len = d.P.len;
+    // ---- owned lanes' old starts, new starts and joiner offsets
+    const bool lt_ok = lb - la <= kLaneCap;
+    if (lt_ok) {
+        for (int q = tid; q <= lb - la; q += kMT) {
+            lt_old[q] = d.ls_old[la + q];
+            lt_new[q] = d.ls_new[la + q];
+            lt_jo[q] = d.joff[la + q];
+        }
+    }
+    auto LO = [&](int l) { return lt_ok ? lt_old[l - la] : d.ls_old[l]; };
+    auto LN = [&](int l) { return lt_ok ? lt_new[l - la] : d.ls_new[l]; };
+    auto JO = [&](int l) { return lt_ok ? lt_jo[l - la] : d.joff[l]; };
+
+    // ---- stage old rows (3 per thread) and joiners (1 per thread)
+    float ra[3], rv0[3];
+    uint32_t rptr[3];
+    int32_t rnext[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int r = tid + k * kMT;
+        if (r < no) {
+            o_s[r] = d.Pr.s[o0 + r];
+            o_v[r] = d.Pr.v[o0 + r];
+            const uint32_t pl = d.Pr.lane[o0 + r];
+            o_ln[r] = (uint16_t)(((pl & ~kJoinBit) - (uint32_t)la) |
+                                 ((pl & kJoinBit) ? kLeave16 : 0u));
+            o_id[r] = d.Pr.id[o0 + r];
+            ra[k] = d.Pr.a[o0 + r];
+            rptr[k] = d.Pr.ptr[o0 + r];
+            rnext[k] = d.Pr.next[o0 + r];
+            rv0[k] = d.Pr.v0[o0 + r];
+        }
+    }
+    float ja = 0.0f, jv0 = 0.0f;
+    uint32_t jptr = 0;
+    int32_t jnext = 0;
+    if (tid < nj) {
+        const int q = j0 + tid;
+        j_s[tid] = d.J.s[q];
+        j_v[tid] = d.J.v[q];
+        j_id[tid] = d.J.id[q];
+        j_ln[tid] = (uint16_t)(d.J.lane[q] - (uint32_t)la);
+        ja = d.J.a[q];
+        jptr = d.J.ptr[q];
+        jnext = d.J.next[q];
+        jv0 = d.J.v0[q];
+    }
+    for (int k = tid; k < nw; k += kMT)
+        w_src[k] = kNoSrc;
+    __syncthreads();
+    // ---- split the old rows among the 4 waves at lane boundaries (first
+    // lane start at or after an even share, found 64 rows at a time)
+    {
+        int r = (no * wv) / 4;
+        if (wv > 0 && r > 0) {
+            for (;;) {
+                const int q = r + lane;
+                const bool bnd = q >= no || (o_ln[q] & ~kLeave16) != (o_ln[q - 1] & ~kLeave16);
+                const unsigned long long m = __ballot(bnd);
+                if (m) {
+                    r += __ffsll((long long)m) - 1;
+                    break;
+                }
+                r += 64;
+            }
+        }
+        if (lane == 0) {
+            wave_start[wv] = (wv == 0) ? 0 : min(r, no);
+            if (wv == 3)
+                wave_start[4] = no;
+        }
+    }
+    __syncthreads();
+    // ---- stayer ranks and prefix maxima, one wave per row range
+    {
+        const int ra0 = wave_start[wv], rb0 = max(wave_start[wv + 1], ra0);
+        uint64_t c_pm = 0;
+        uint32_t c_pi = kNoRow, c_p = 0;
+        for (int r0 = ra0; r0 < rb0; r0 += 64) {
+            const int r = r0 + lane;
+            const bool valid = r < rb0;
+            bool head = false, st = false;
+            uint64_t key = 0;
+            if (valid) {
+                const uint32_t ln = o_ln[r];
+                st = (ln & kLeave16) == 0;
+                head = (r == ra0) || ((o_ln[r - 1] & ~kLeave16) != (ln & ~kLeave16));
+                key = okey(o_s[r], o_id[r]);
+            }
+            uint32_t pi, p;
+            wave_seg_scan(valid, head, st, key, (uint32_t)r, c_pm, c_pi, c_p, pi, p);
+            if (valid) {
+                o_p[r] = (uint16_t)p;
+                o_pi[r] = (uint16_t)pi;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- joiners: rank among the lane's joiners, stayers before them
+    if (tid < nj) {
+        const int e = tid;
+        const uint32_t l = (uint32_t)la + j_ln[e];
+        const uint64_t key = okey(j_s[e], j_id[e]);
+        const int jl = JO(l) - j0, jh = JO(l + 1) - j0;
+        int q = 0;
+        for (int e2 = jl; e2 < jh; ++e2)
+            q += okey(j_s[e2], j_id[e2]) < key;
+        const int lo = LO(l) - o0, hi = LO(l + 1) - o0;
+        int a = lo, b = hi;       // first old row of l with prefix max > key
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            const uint32_t pr = o_pi[mid];
+            const uint64_t pm = (pr == kNoRow) ? 0ull : okey(o_s[pr], o_id[pr]);
+            if (pm > key)
+                b = mid;
+            else
+                a = mid + 1;
+        }
+        const int wl = LN(l) - n0;
+        const int stay_total = (LN(l + 1) - LN(l)) - (jh - jl);
+        const int f = (a < hi) ? (int)o_p[a] : stay_total;
+        const int pos = wl + f + q;
+        if (pos >= 0 && pos < nw) {
+            w_src[pos] = (uint16_t)(kTagJ | e);
+            const int g = n0 + pos;
+            d.S.a[g] = ja;
+            d.S.id[g] = j_id[e];
+            d.S.lane[g] = l;
+            d.S.ptr[g] = jptr;
+            d.S.next[g] = jnext;
+            d.S.v0[g] = jv0;
+        } else {
+            atomicOr(d.err, 1u);
+        }
+        j_ord[jl + q] = (uint16_t)e;
+    }
+    __syncthreads();
+    // ---- stayers: joiners with a smaller key than their prefix maximum
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int r = tid + k * kMT;
+        if (r >= no)
+            continue;
+        if (o_ln[r] & kLeave16)
+            continue;
+        const uint32_t ln = (uint32_t)la + o_ln[r];
+        const uint32_t pr = o_pi[r];    // a stayer: its own row or one before it
+        const uint64_t pm = okey(o_s[pr], o_id[pr]);
+        const int jl = JO(ln) - j0, jh = JO(ln + 1) - j0;
+        int a = jl, b = jh;       // joiners of the lane with key < pm (sorted keys)
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            const uint32_t je = j_ord[mid];
+            const uint64_t kk = okey(j_s[je], j_id[je]);
+            if (kk < pm)
+                a = mid + 1;
+            else
+                b = mid;
+        }
+        const int pos = (LN(ln) - n0) + (int)o_p[r] + (a - jl);
+        if (pos >= 0 && pos < nw) {
+            w_src[pos] = (uint16_t)r;
+            const int g = n0 + pos;
+            d.S.a[g] = ra[k];
+            d.S.id[g] = o_id[r];
+            d.S.lane[g] = ln;
+            d.S.ptr[g] = rptr[k];
+            d.S.next[g] = rnext[k];
+            d.S.v0[g] = rv0[k];
+        } else {
+            atomicOr(d.err, 1u);
+        }
+    }
+    __syncthreads();
+    // lane of a placed row (stayers carry no leave bit)
+    auto lane_of = [&](uint32_t x) {
+        return (uint32_t)la + ((x & kTagJ) ? j_ln[x & ~kTagJ] : o_ln[x]);
+    };
+    for (int k = tid; k < nw; k += kMT) {
+        w_top[k] = -1;
+        w_bot[k] = 0x7FFFFFFF;
+    }
+    __syncthreads();
+    // ---- overlaps: highest offending pair of each lane
+    for (int k = tid; k < nw; k += kMT) {
+        const uint32_t x = w_src[k];
+        if (x == kNoSrc) {
+            atomicOr(d.err, 1u);
+            continue;
+        }
+        const uint32_t lk = lane_of(x);
+        if (k + 1 < nw && w_src[k + 1] != kNoSrc && lane_of(w_src[k + 1]) == lk) {
+            const uint32_t y = w_src[k + 1];
+            const float sk = (x & kTagJ) ? j_s[x & ~kTagJ] : o_s[x];
+            const float sn = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
+            if (sk > sn - len) {
+                const int first = LN((int)lk) - n0;
+                atomicMax(&w_top[first], k);
+                atomicMin(&w_bot[first], k);
+            }
+        }
+    }
+    __syncthreads();
+    // ---- sequential removal from there down towards the lane tail.  Below
+    // the lowest offending pair of raw positions, a row left unchanged
+    // leaves every row behind it unchanged, so the walk stops there.
+    for (int k = tid; k < nw; k += kMT) {
+        const int top = w_top[k];
+        if (top < 0)
+            continue;     // set only at a lane's first row
+        const int bot = w_bot[k];
+        const uint32_t y = w_src[top + 1];
+        float sl = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
+        float vl = (y & kTagJ) ? j_v[y & ~kTagJ] : o_v[y];
+        for (int f = top; f >= k; --f) {
+            const uint32_t xf = w_src[f];
+            const bool jf = (xf & kTagJ) != 0;
+            const uint32_t kf = xf & ~kTagJ;
+            float sf = jf ? j_s[kf] : o_s[kf];
+            float vf = jf ? j_v[kf] : o_v[kf];
+            const float lim = sl - len;
+            if (sf > lim) {
+                sf = lim;
+                vf = fmin32(vf, vl);
+                if (jf) { j_s[kf] = sf; j_v[kf] = vf; }
+                else { o_s[kf] = sf; o_v[kf] = vf; }
+                ++clamps;
+                if (!one_scen)
+                    atomicAdd(cnt_at(d, d.lanes[lane_of(w_src[k])].scen, C_CLAMPS), 1ull);
+            } else if (f < bot) {
+                break;
+            }
+            sl = sf;
+            vl = vf;
+        }
+    }
+    __syncthreads();
+    // ---- lane tails (empty lanes too)
+    for (int l = la + tid; l < lb; l += kMT) {
+        const int wl = LN(l) - n0, wh = LN(l + 1) - n0;
+        if (wh > wl && w_src[wl] != kNoSrc) {
+            const uint32_t x = w_src[wl];
+            if (x & kTagJ)
+                write_tail(d, l, true, j_s[x & ~kTagJ], j_v[x & ~kTagJ], j_id[x & ~kTagJ]);
+            else
+                write_tail(d, l, true, o_s[x], o_v[x], o_id[x]);
+        } else {
+            write_tail(d, l, false, 0.0f, 0.0f, kNone);
+        }
+    }
+    // ---- positions and speeds of the chunk's rows, coalesced
+    for (int k = tid; k < nw; k += kMT) {
+        const uint32_t x = w_src[k];
+        if (x == kNoSrc)
+            continue;
+        const bool jx = (x & kTagJ) != 0;
+        const uint32_t e = x & ~kTagJ;
+        const float s = jx ? j_s[e] : o_s[e];
+        const float v = jx ? j_v[e] : o_v[e];
+        d.S.s[n0 + k] = s;
+        d.S.v[n0 + k] = v;
+        if (one_scen) {
+            vsum += (double)v;
+        } else {
+            const int sc = d.lanes[lane_of(x)].scen;
+            atomicAdd(cnt_at(d, sc, C_VEH_STEPS), 1ull);
+            atomicAdd(sv_at(d, d.sumv, sc), (double)v);
+        }
+    }
+}
+
+// Lanes [la, lb) one per thread, straight from global memory.
+__device__ void merge_lanes_global(const Dev &d, const int la, const int lb, const bool one_scen,
+                                   double &vsum, unsigned long long &clamps)
+{
+    const int tid = threadIdx.x;
+    for (int l = la + tid; l < lb; l += kMT) {
+        double ls;
+        unsigned long long lc;
+        merge_lane_global(d, l, ls, lc);
+        const int cnt = d.ls_new[l + 1] - d.ls_new[l];
+        if (one_scen) {
+            vsum += ls;
+            clamps += lc;
+        } else {
+            unsigned long long *c = cnt_at(d, d.lanes[l].scen, 0);
+            if (cnt) {
+                atomicAdd(c + C_VEH_STEPS, (unsigned long long)cnt);
+                atomicAdd(sv_at(d, d.sumv, d.lanes[l].scen), ls);
+            }
+            if (lc) atomicAdd(c + C_CLAMPS, lc);
+        }
+    }
+}
+
+__device__ __forceinline__ bool group_fits(int new_rows, int old_rows, int joiners, int lanes)
+{
+    return new_rows <= kNewCap && old_rows <= kOldCap && joiners <= kJCap && lanes < kRelLanes;
+}
+
+// Next state, one chunk of kMC new rows per block.  A block owns the lanes
+// whose first new row falls in its chunk and merges them with merge_group.
+// A chunk that does not fit the LDS tile is merged in consecutive groups of
+// whole lanes that do; only a lane that alone exceeds the tile takes
+// merge_lane_global.
+__global__ void __launch_bounds__(kMT) k_merge(Dev d)
+{
     __shared__ double red_d[kMT / 64];
     __shared__ unsigned long long red_k[kMT / 64];
+    __shared__ int s_gb;
 
     const int tid = threadIdx.x;
     const int lane = __lane_id();
@@ -1046,297 +1373,60 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     const int4 ca = d.chunk[w], cb = d.chunk[w + 1];
     const int la = ca.x, lb = cb.x;
     const int n0 = ca.y, n1 = cb.y, o0 = ca.z, o1 = cb.z, j0 = ca.w, j1 = cb.w;
-    const int no = o1 - o0, nw = n1 - n0, nj = j1 - j0;
-    const float len = d.P.len;
+    const int nw = n1 - n0;
     const bool one_scen = (lb <= la) || d.lanes[la].scen == d.lanes[lb - 1].scen;
     double vsum = 0.0;
     unsigned long long clamps = 0;
 
-    if (nw > kNewCap || no > kOldCap || nj > kJCap) {
-        for (int l = la + tid; l < lb; l += kMT) {
-            double ls;
-            unsigned long long lc;
-            merge_lane_global(d, l, ls, lc);
-            const int cnt = d.ls_new[l + 1] - d.ls_new[l];
-            if (one_scen) {
-                vsum += ls;
-                clamps += lc;
-            } else {
-                unsigned long long *c = cnt_at(d, d.lanes[l].scen, 0);
-                if (cnt) {
-                    atomicAdd(c + C_VEH_STEPS, (unsigned long long)cnt);
-                    atomicAdd(sv_at(d, d.sumv, d.lanes[l].scen), ls);
-                }
-                if (lc) atomicAdd(c + C_CLAMPS, lc);
-            }
-        }
-    } else {
-        // ---- owned lanes' old starts, new starts and joiner offsets
-        const bool lt_ok = lb - la <= kLaneCap;
-        if (lt_ok) {
-            for (int q = tid; q <= lb - la; q += kMT) {
-                lt_old[q] = d.ls_old[la + q];
-                lt_new[q] = d.ls_new[la + q];
-                lt_jo[q] = d.joff[la + q];
-            }
-        }
-        auto LO = [&](int l) { return lt_ok ? lt_old[l - la] : d.ls_old[l]; };
-        auto LN = [&](int l) { return lt_ok ? lt_new[l - la] : d.ls_new[l]; };
-        auto JO = [&](int l) { return lt_ok ? lt_jo[l - la] : d.joff[l]; };
-
-        // ---- stage old rows (3 per thread) and joiners (1 per thread)
-        float ra[3], rv0[3];
-        uint32_t rptr[3];
-        int32_t rnext[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int r = tid + k * kMT;
-            if (r < no) {
-                o_s[r] = d.Pr.s[o0 + r];
-                o_v[r] = d.Pr.v[o0 + r];
-                o_ln[r] = d.Pr.lane[o0 + r];
-                o_id[r] = d.Pr.id[o0 + r];
-                ra[k] = d.Pr.a[o0 + r];
-                rptr[k] = d.Pr.ptr[o0 + r];
-                rnext[k] = d.Pr.next[o0 + r];
-                rv0[k] = d.Pr.v0[o0 + r];
-            }
-        }
-        float ja = 0.0f, jv0 = 0.0f;
-        uint32_t jptr = 0;
-        int32_t jnext = 0;
-        if (tid < nj) {
-            const int q = j0 + tid;
-            j_s[tid] = d.J.s[q];
-            j_v[tid] = d.J.v[q];
-            j_id[tid] = d.J.id[q];
-            j_ln[tid] = d.J.lane[q];
-            ja = d.J.a[q];
-            jptr = d.J.ptr[q];
-            jnext = d.J.next[q];
-            jv0 = d.J.v0[q];
-        }
-        for (int k = tid; k < nw; k += kMT)
-            w_src[k] = kNoSrc;
-        __syncthreads();
-        // ---- split the old rows among the 4 waves at lane boundaries (first
-        // lane start at or after an even share, found 64 rows at a time)
-        {
-            int r = (no * wv) / 4;
-            if (wv > 0 && r > 0) {
-                for (;;) {
-                    const int q = r + lane;
-                    const bool bnd = q >= no ||
-                                     (o_ln[q] & ~kJoinBit) != (o_ln[q - 1] & ~kJoinBit);
-                    const unsigned long long m = __ballot(bnd);
-                    if (m) {
-                        r += __ffsll((long long)m) - 1;
-                        break;
-                    }
-                    r += 64;
-                }
-            }
-            if (lane == 0) {
-                wave_start[wv] = (wv == 0) ? 0 : min(r, no);
-                if (wv == 3)
-                    wave_start[4] = no;
-            }
-        }
-        __syncthreads();
-        // ---- stayer ranks and prefix maxima, one wave per row range
-        {
-            const int ra0 = wave_start[wv], rb0 = max(wave_start[wv + 1], ra0);
-            uint64_t c_pm = 0;
-            uint32_t c_pi = kNoRow, c_p = 0;
-            for (int r0 = ra0; r0 < rb0; r0 += 64) {
-                const int r = r0 + lane;
-                const bool valid = r < rb0;
-                bool head = false, st = false;
-                uint64_t key = 0;
-                if (valid) {
-                    const uint32_t ln = o_ln[r];
-                    st = (ln & kJoinBit) == 0;
-                    head = (r == ra0) || ((o_ln[r - 1] & ~kJoinBit) != (ln & ~kJoinBit));
-                    key = okey(o_s[r], o_id[r]);
-                }
-                uint32_t pi, p;
-                wave_seg_scan(valid, head, st, key, (uint32_t)r, c_pm, c_pi, c_p, pi, p);
-                if (valid) {
-                    o_p[r] = (uint16_t)p;
-                    o_pi[r] = (uint16_t)pi;
-                }
-            }
-        }
-        __syncthreads();
-        // ---- joiners: rank among the lane's joiners, stayers before them
-        if (tid < nj) {
-            const int e = tid;
-            const uint32_t l = j_ln[e];
-            const uint64_t key = okey(j_s[e], j_id[e]);
-            const int jl = JO(l) - j0, jh = JO(l + 1) - j0;
-            int q = 0;
-            for (int e2 = jl; e2 < jh; ++e2)
-                q += okey(j_s[e2], j_id[e2]) < key;
-            const int lo = LO(l) - o0, hi = LO(l + 1) - o0;
-            int a = lo, b = hi;       // first old row of l with prefix max > key
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                const uint32_t pr = o_pi[mid];
-                const uint64_t pm = (pr == kNoRow) ? 0ull : okey(o_s[pr], o_id[pr]);
-                if (pm > key)
-                    b = mid;
+    // the longest run of whole lanes from ga that fits the tile (ga itself
+    // when lane ga alone exceeds it); uniform, computed by one thread
+    auto longest_fit = [&](int ga, int g_n0, int g_o0, int g_j0) {
+        if (tid == 0) {
+            int lo = ga, hi = lb;      // [ga, lo) fits, [ga, hi) does not
+            while (hi - lo > 1) {
+                const int mid = lo + ((hi - lo) >> 1);
+                if (group_fits(d.ls_new[mid] - g_n0, d.ls_old[mid] - g_o0, d.joff[mid] - g_j0,
+                               mid - ga))
+                    lo = mid;
                 else
-                    a = mid + 1;
+                    hi = mid;
             }
-            const int wl = LN(l) - n0;
-            const int stay_total = (LN(l + 1) - LN(l)) - (jh - jl);
-            const int f = (a < hi) ? (int)o_p[a] : stay_total;
-            const int pos = wl + f + q;
-            if (pos >= 0 && pos < nw) {
-                w_src[pos] = kTagJ | (uint32_t)e;
-                const int g = n0 + pos;
-                d.S.a[g] = ja;
-                d.S.id[g] = j_id[e];
-                d.S.lane[g] = l;
-                d.S.ptr[g] = jptr;
-                d.S.next[g] = jnext;
-                d.S.v0[g] = jv0;
-            } else {
-                atomicOr(d.err, 1u);
-            }
-            j_ord[jl + q] = (uint16_t)e;
+            s_gb = lo;
         }
         __syncthreads();
-        // ---- stayers: joiners with a smaller key than their prefix maximum
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int r = tid + k * kMT;
-            if (r >= no)
-                continue;
-            const uint32_t ln = o_ln[r];
-            if (ln & kJoinBit)
-                continue;
-            const uint32_t pr = o_pi[r];    // a stayer: its own row or one before it
-            const uint64_t pm = okey(o_s[pr], o_id[pr]);
-            const int jl = JO(ln) - j0, jh = JO(ln + 1) - j0;
-            int a = jl, b = jh;       // joiners of the lane with key < pm (sorted keys)
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                const uint32_t je = j_ord[mid];
-                const uint64_t kk = okey(j_s[je], j_id[je]);
-                if (kk < pm)
-                    a = mid + 1;
-                else
-                    b = mid;
-            }
-            const int pos = (LN(ln) - n0) + (int)o_p[r] + (a - jl);
-            if (pos >= 0 && pos < nw) {
-                w_src[pos] = (uint32_t)r;
-                const int g = n0 + pos;
-                d.S.a[g] = ra[k];
-                d.S.id[g] = o_id[r];
-                d.S.lane[g] = ln;
-                d.S.ptr[g] = rptr[k];
-                d.S.next[g] = rnext[k];
-                d.S.v0[g] = rv0[k];
-            } else {
-                atomicOr(d.err, 1u);
-            }
+        const int gb = __builtin_amdgcn_readfirstlane(s_gb);
+        __syncthreads();               // s_gb may be written again
+        return gb;
+    };
+    // At most two groups through the tile (written out rather than looped:
+    // a loop around the tile code costs it about 40 VGPRs); lanes left after
+    // them, which only a chunk of more than twice the tile can have, are
+    // merged one per thread.
+    int ga = la;
+    int gb = group_fits(nw, o1 - o0, j1 - j0, lb - la) ? lb : longest_fit(la, n0, o0, j0);
+    if (gb > ga) {
+        const int g_n1 = gb == lb ? n1 : __builtin_amdgcn_readfirstlane(d.ls_new[gb]);
+        const int g_o1 = gb == lb ? o1 : __builtin_amdgcn_readfirstlane(d.ls_old[gb]);
+        const int g_j1 = gb == lb ? j1 : __builtin_amdgcn_readfirstlane(d.joff[gb]);
+        merge_group(d, ga, gb, n0, g_n1, o0, g_o1, j0, g_j1, one_scen, vsum, clamps);
+        ga = gb;
+    }
+    if (ga < lb) {
+        __syncthreads();               // the LDS tile is reused
+        const int g_n0 = __builtin_amdgcn_readfirstlane(d.ls_new[ga]);
+        const int g_o0 = __builtin_amdgcn_readfirstlane(d.ls_old[ga]);
+        const int g_j0 = __builtin_amdgcn_readfirstlane(d.joff[ga]);
+        gb = group_fits(n1 - g_n0, o1 - g_o0, j1 - g_j0, lb - ga) ? lb
+                                                                  : longest_fit(ga, g_n0, g_o0, g_j0);
+        if (gb > ga) {
+            const int g_n1 = __builtin_amdgcn_readfirstlane(d.ls_new[gb]);
+            const int g_o1 = __builtin_amdgcn_readfirstlane(d.ls_old[gb]);
+            const int g_j1 = __builtin_amdgcn_readfirstlane(d.joff[gb]);
+            merge_group(d, ga, gb, g_n0, g_n1, g_o0, g_o1, g_j0, g_j1, one_scen, vsum, clamps);
+            ga = gb;
         }
-        __syncthreads();
-        // lane of a placed row (stayers carry no join bit)
-        auto lane_of = [&](uint32_t x) { return (x & kTagJ) ? j_ln[x & ~kTagJ] : o_ln[x]; };
-        for (int k = tid; k < nw; k += kMT) {
-            w_top[k] = -1;
-            w_bot[k] = 0x7FFFFFFF;
-        }
-        __syncthreads();
-        // ---- overlaps: highest offending pair of each lane
-        for (int k = tid; k < nw; k += kMT) {
-            const uint32_t x = w_src[k];
-            if (x == kNoSrc) {
-                atomicOr(d.err, 1u);
-                continue;
-            }
-            const uint32_t lk = lane_of(x);
-            if (k + 1 < nw && w_src[k + 1] != kNoSrc && lane_of(w_src[k + 1]) == lk) {
-                const uint32_t y = w_src[k + 1];
-                const float sk = (x & kTagJ) ? j_s[x & ~kTagJ] : o_s[x];
-                const float sn = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
-                if (sk > sn - len) {
-                    const int first = LN((int)lk) - n0;
-                    atomicMax(&w_top[first], k);
-                    atomicMin(&w_bot[first], k);
-                }
-            }
-        }
-        __syncthreads();
-        // ---- sequential removal from there down towards the lane tail.  Below
-        // the lowest offending pair of raw positions, a row left unchanged
-        // leaves every row behind it unchanged, so the walk stops there.
-        for (int k = tid; k < nw; k += kMT) {
-            const int top = w_top[k];
-            if (top < 0)
-                continue;     // set only at a lane's first row
-            const int bot = w_bot[k];
-            const uint32_t y = w_src[top + 1];
-            float sl = (y & kTagJ) ? j_s[y & ~kTagJ] : o_s[y];
-            float vl = (y & kTagJ) ? j_v[y & ~kTagJ] : o_v[y];
-            for (int f = top; f >= k; --f) {
-                const uint32_t xf = w_src[f];
-                const bool jf = (xf & kTagJ) != 0;
-                const uint32_t kf = xf & ~kTagJ;
-                float sf = jf ? j_s[kf] : o_s[kf];
-                float vf = jf ? j_v[kf] : o_v[kf];
-                const float lim = sl - len;
-                if (sf > lim) {
-                    sf = lim;
-                    vf = fmin32(vf, vl);
-                    if (jf) { j_s[kf] = sf; j_v[kf] = vf; }
-                    else { o_s[kf] = sf; o_v[kf] = vf; }
-                    ++clamps;
-                    if (!one_scen)
-                        atomicAdd(cnt_at(d, d.lanes[lane_of(w_src[k])].scen, C_CLAMPS), 1ull);
-                } else if (f < bot) {
-                    break;
-                }
-                sl = sf;
-                vl = vf;
-            }
-        }
-        __syncthreads();
-        // ---- lane tails (empty lanes too)
-        for (int l = la + tid; l < lb; l += kMT) {
-            const int wl = LN(l) - n0, wh = LN(l + 1) - n0;
-            if (wh > wl && w_src[wl] != kNoSrc) {
-                const uint32_t x = w_src[wl];
-                if (x & kTagJ)
-                    write_tail(d, l, true, j_s[x & ~kTagJ], j_v[x & ~kTagJ], j_id[x & ~kTagJ]);
-                else
-                    write_tail(d, l, true, o_s[x], o_v[x], o_id[x]);
-            } else {
-                write_tail(d, l, false, 0.0f, 0.0f, kNone);
-            }
-        }
-        // ---- positions and speeds of the chunk's rows, coalesced
-        for (int k = tid; k < nw; k += kMT) {
-            const uint32_t x = w_src[k];
-            if (x == kNoSrc)
-                continue;
-            const bool jx = (x & kTagJ) != 0;
-            const uint32_t e = x & ~kTagJ;
-            const float s = jx ? j_s[e] : o_s[e];
-            const float v = jx ? j_v[e] : o_v[e];
-            d.S.s[n0 + k] = s;
-            d.S.v[n0 + k] = v;
-            if (one_scen) {
-                vsum += (double)v;
-            } else {
-                const int sc = d.lanes[lane_of(x)].scen;
-                atomicAdd(cnt_at(d, sc, C_VEH_STEPS), 1ull);
-                atomicAdd(sv_at(d, d.sumv, sc), (double)v);
-            }
-        }
+        if (ga < lb)
+            merge_lanes_global(d, ga, lb, one_scen, vsum, clamps);
     }
 
     if (one_scen) {

@@ -222,3 +222,40 @@ def test_device_reads_are_ordered_before_later_steps(sim_cls):
         assert np.array_equal(df.cpu().numpy().view(np.uint32), hf.view(np.uint32)), k
         assert np.array_equal(dy.cpu().numpy().view(np.uint32), hy.view(np.uint32)), k
     g.close()
+
+
+def _long_lanes():
+    """Corridor whose lanes overflow the merge kernel's LDS tile (768 old or
+    new rows, 160 joiners per 512-row chunk): lane 0 holds 900 vehicles
+    (merged one lane per thread), and lanes 1 and 2 (100 and 700 vehicles)
+    both start in the second chunk (rows 512..1023), which then only fits
+    the tile as two groups of whole lanes.  Lane 0 is dense and lane 1
+    sparse, so lane changes bring joiners into both groups."""
+    net = S.corridor([7000.0, 5400.0, 300.0], 2)
+    vehicles = []
+    k = 0
+
+    def put(lane, road, count, gap, v):
+        nonlocal k
+        for i in range(count):
+            vehicles.append(dict(id=k, route=list(range(road, 3)), lane=lane,
+                                 s=5.0 + gap * i, v=v, v0=12.0 + (k % 7)))
+            k += 1
+    put(0, 0, 900, 7.5, 2.0)
+    put(1, 0, 100, 60.0, 8.0)
+    put(2, 1, 700, 7.5, 1.0)
+    put(3, 1, 40, 100.0, 8.0)
+    return S.with_vehicles("long_lanes", net, vehicles)
+
+
+def test_lanes_beyond_the_merge_tile(sim_cls):
+    sc = _long_lanes()
+    o = _oracle(sc)
+    st = o.state()
+    size = np.bincount(st["lane"], minlength=sc.n_lanes)
+    start = np.concatenate([[0], np.cumsum(size)])[:-1]
+    assert size.max() > 768                                   # a lane alone over the tile
+    owned = [l for l in range(sc.n_lanes) if 512 <= start[l] < 1024]
+    assert sum(size[l] for l in owned) > 768                  # a chunk of two groups
+    _say("long lanes")
+    assert run_pair(sim_cls, sc, 40) == 0
