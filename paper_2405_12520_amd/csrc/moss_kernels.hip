@@ -327,31 +327,57 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         __syncthreads();
         if (tid == 0)
             s_jn = 0;
-        for (int r = ws + tid; r < we; r += kUT) {
-            w_s[r - ws] = d.S.s[r];
-            w_v[r - ws] = d.S.v[r];
-            w_v0[r - ws] = d.S.v0[r];
-            w_id[r - ws] = d.S.id[r];
-            w_ln[r - ws] = d.S.lane[r];
+        // the window (at most 2 kUT rows): every load is issued before the
+        // first LDS store waits for one; indices are clamped into the window
+        static_assert(2 * kUH <= kUT, "window rows fit two per thread");
+        {
+            const int r0 = ws + tid, r1 = ws + tid + kUT;
+            const int q0 = min(r0, we - 1), q1 = min(r1, we - 1);
+            const float s0 = d.S.s[q0], v0a = d.S.v[q0], v00 = d.S.v0[q0];
+            const uint32_t id0 = d.S.id[q0], ln0 = d.S.lane[q0];
+            const float s1 = d.S.s[q1], v1a = d.S.v[q1], v01 = d.S.v0[q1];
+            const uint32_t id1 = d.S.id[q1], ln1 = d.S.lane[q1];
+            if (r0 < we) {
+                w_s[r0 - ws] = s0;
+                w_v[r0 - ws] = v0a;
+                w_v0[r0 - ws] = v00;
+                w_id[r0 - ws] = id0;
+                w_ln[r0 - ws] = ln0;
+            }
+            if (r1 < we) {
+                w_s[r1 - ws] = s1;
+                w_v[r1 - ws] = v1a;
+                w_v0[r1 - ws] = v01;
+                w_id[r1 - ws] = id1;
+                w_ln[r1 - ws] = ln1;
+            }
         }
         __syncthreads();
 
         const int x_i = i - ws;
         const uint32_t l = act ? w_ln[x_i] : 0u;
         const bool hasLc = act && (i + 1 < n) && w_ln[x_i + 1] == l;
-        // independent loads of the second round
-        const LaneInfo li = d.lanes[l];
-        const bool red_now = act && d.lane_red[l] != 0;
+        // independent loads of the second round, all issued before any is
+        // waited for: indices are made valid (lane l, road 0) instead of
+        // skipping the load, and the values are selected afterwards
         const int ls_side = (int)l + side;
         const bool side_ok = act && ls_side >= 0 && ls_side < d.n_lanes;
-        const float vlim_side = side_ok ? d.lanes[ls_side].vlim : 0.0f;
+        const int ls_c = side_ok ? ls_side : (int)l;
+        const bool head_next = act && !hasLc && nxt >= 0;
+        const LaneInfo li = d.lanes[l];
+        const uint8_t red_raw = d.lane_red[l];
+        const float vlim_c_side = d.lanes[ls_c].vlim;
+        const int r0_c = d.ls_old[ls_c], r1_c = d.ls_old[ls_c + 1];
+        const RoadInfo rd_c = d.roads[head_next ? nxt : 0];
+        const bool red_now = act && red_raw != 0;
+        const float vlim_side = side_ok ? vlim_c_side : 0.0f;
         // rows of the side lane (the MOBIL target when it is on the same road)
-        const int side_r0 = side_ok ? d.ls_old[ls_side] : 0;
-        const int side_r1 = side_ok ? d.ls_old[ls_side + 1] : 0;
+        const int side_r0 = side_ok ? r0_c : 0;
+        const int side_r1 = side_ok ? r1_c : 0;
         RoadInfo rd_next = {0, 1, 0.0f, 0};
         bool rd_ok = false;       // rd_next holds roads[nxt]
-        if (act && !hasLc && nxt >= 0) {
-            rd_next = d.roads[nxt];
+        if (head_next) {
+            rd_next = rd_c;
             rd_ok = true;
         }
         const int scen0 = __shfl(li.scen, 0);
