@@ -724,27 +724,27 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 2;
 constexpr int kScanLanes = kScanThreads * kScanPer;
 
-// inclusive scan of two ints over a 256-thread block
-__device__ void block_scan2(int &x, int &y, int *sh)
+// Inclusive scan of two ints over the block: within each wave by shuffles,
+// then the totals of the waves before it are added (one LDS round).
+__device__ __forceinline__ void block_scan2(int &x, int &y, int *sh)
 {
-    const int tid = threadIdx.x;
-    sh[tid] = x;
-    sh[kScanThreads + tid] = y;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        int ax = 0, ay = 0;
-        if (tid >= off) {
-            ax = sh[tid - off];
-            ay = sh[kScanThreads + tid - off];
+    const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ax = __shfl_up(x, off), ay = __shfl_up(y, off);
+        if (lane >= off) {
+            x += ax;
+            y += ay;
         }
-        __syncthreads();
-        sh[tid] += ax;
-        sh[kScanThreads + tid] += ay;
-        __syncthreads();
     }
-    x = sh[tid];
-    y = sh[kScanThreads + tid];
+    if (lane == 63) {
+        sh[wv] = x;
+        sh[kScanThreads / 64 + wv] = y;
+    }
     __syncthreads();
+    for (int k = 0; k < wv; ++k) {
+        x += sh[k];
+        y += sh[kScanThreads / 64 + k];
+    }
 }
 
 // new lane size = old size - vehicles leaving + vehicles joining
