@@ -1077,52 +1077,59 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
     const int wv = tid >> 6;
     const int no = o1 - o0, nw = n1 - n0, nj = j1 - j0;
     const float len = d.P.len;
-    // ---- owned lanes' old starts, new starts and joiner offsets
+    // ---- owned lanes' old starts, new starts and joiner offsets, old rows
+    // (3 per thread) and joiners (1 per thread): every load is issued before
+    // the first LDS store waits for one, from indices clamped to valid
+    // entries, rows and joiners (row 0 and joiner 0 when there are none)
     const bool lt_ok = lb - la <= kLaneCap;
-    if (lt_ok) {
-        for (int q = tid; q <= lb - la; q += kMT) {
-            lt_old[q] = d.ls_old[la + q];
-            lt_new[q] = d.ls_new[la + q];
-            lt_jo[q] = d.joff[la + q];
-        }
+    static_assert(kLaneCap + 1 <= kMT, "one lane-table entry per thread");
+    const int qc = la + min(tid, lb - la);
+    const int lt_o = d.ls_old[qc], lt_n = d.ls_new[qc], lt_j = d.joff[qc];
+    float rs[3], rv[3], ra[3], rv0[3];
+    uint32_t rl[3], rid[3], rptr[3];
+    int32_t rnext[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int r = no > 0 ? o0 + min(tid + k * kMT, no - 1) : 0;
+        rs[k] = d.Pr.s[r];
+        rv[k] = d.Pr.v[r];
+        rl[k] = d.Pr.lane[r];
+        rid[k] = d.Pr.id[r];
+        ra[k] = d.Pr.a[r];
+        rptr[k] = d.Pr.ptr[r];
+        rnext[k] = d.Pr.next[r];
+        rv0[k] = d.Pr.v0[r];
+    }
+    const int qj = nj > 0 ? j0 + min(tid, nj - 1) : 0;
+    const float js = d.J.s[qj], jv = d.J.v[qj];
+    const uint32_t jid = d.J.id[qj], jl = d.J.lane[qj];
+    const float ja = d.J.a[qj], jv0 = d.J.v0[qj];
+    const uint32_t jptr = d.J.ptr[qj];
+    const int32_t jnext = d.J.next[qj];
+    if (lt_ok && tid <= lb - la) {
+        lt_old[tid] = lt_o;
+        lt_new[tid] = lt_n;
+        lt_jo[tid] = lt_j;
     }
     auto LO = [&](int l) { return lt_ok ? lt_old[l - la] : d.ls_old[l]; };
     auto LN = [&](int l) { return lt_ok ? lt_new[l - la] : d.ls_new[l]; };
     auto JO = [&](int l) { return lt_ok ? lt_jo[l - la] : d.joff[l]; };
-
-    // ---- stage old rows (3 per thread) and joiners (1 per thread)
-    float ra[3], rv0[3];
-    uint32_t rptr[3];
-    int32_t rnext[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int r = tid + k * kMT;
         if (r < no) {
-            o_s[r] = d.Pr.s[o0 + r];
-            o_v[r] = d.Pr.v[o0 + r];
-            const uint32_t pl = d.Pr.lane[o0 + r];
-            o_ln[r] = (uint16_t)(((pl & ~kJoinBit) - (uint32_t)la) |
-                                 ((pl & kJoinBit) ? kLeave16 : 0u));
-            o_id[r] = d.Pr.id[o0 + r];
-            ra[k] = d.Pr.a[o0 + r];
-            rptr[k] = d.Pr.ptr[o0 + r];
-            rnext[k] = d.Pr.next[o0 + r];
-            rv0[k] = d.Pr.v0[o0 + r];
+            o_s[r] = rs[k];
+            o_v[r] = rv[k];
+            o_ln[r] = (uint16_t)(((rl[k] & ~kJoinBit) - (uint32_t)la) |
+                                 ((rl[k] & kJoinBit) ? kLeave16 : 0u));
+            o_id[r] = rid[k];
         }
     }
-    float ja = 0.0f, jv0 = 0.0f;
-    uint32_t jptr = 0;
-    int32_t jnext = 0;
     if (tid < nj) {
-        const int q = j0 + tid;
-        j_s[tid] = d.J.s[q];
-        j_v[tid] = d.J.v[q];
-        j_id[tid] = d.J.id[q];
-        j_ln[tid] = (uint16_t)(d.J.lane[q] - (uint32_t)la);
-        ja = d.J.a[q];
-        jptr = d.J.ptr[q];
-        jnext = d.J.next[q];
-        jv0 = d.J.v0[q];
+        j_s[tid] = js;
+        j_v[tid] = jv;
+        j_id[tid] = jid;
+        j_ln[tid] = (uint16_t)(jl - (uint32_t)la);
     }
     for (int k = tid; k < nw; k += kMT)
         w_src[k] = kNoSrc;
