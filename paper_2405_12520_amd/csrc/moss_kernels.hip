@@ -1005,6 +1005,63 @@ constexpr uint32_t kNoRow = 0xFFFFu;
 static_assert(2 * kOldCap + kJCap <= 4 * kNewCap, "o_p, o_pi and j_ord share u_buf");
 static_assert(kOldCap < 0x8000 && kJCap < 0x8000, "row sources are 15-bit indices");
 
+// DPP lane moves (row_shr:n reads lane - n of the same row of 16,
+// row_bcast:15 / :31 read lane 15 / 31 of the row before), so that the wave
+// scans below stay in the vector ALU instead of going through LDS.  Lanes
+// that the move does not write (no source lane, or a row outside ROWS) get
+// `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROWS, 0xF, false);
+}
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+constexpr int kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
+// One step of the segmented prefix maximum: take the (key, row) the move
+// reads if it is larger and its lane lies in this lane's segment.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_max_step(uint64_t &v, uint32_t &vi, bool in_seg)
+{
+    const uint32_t lo = dpp_move<CTRL, ROWS>((uint32_t)v, (uint32_t)v);
+    const uint32_t hi = dpp_move<CTRL, ROWS>((uint32_t)(v >> 32), (uint32_t)(v >> 32));
+    const uint32_t oi = dpp_move<CTRL, ROWS>(vi, vi);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    if (in_seg && o > v) {
+        v = o;
+        vi = oi;
+    }
+}
+
+// Sum over the wave, complete in lane 63 (inclusive scan by row shifts, then
+// row broadcasts).
+__device__ __forceinline__ double wave_sum_f64_l63(double x)
+{
+    auto step = [&](auto mv) {
+        const uint64_t b = (uint64_t)__double_as_longlong(x);
+        const uint32_t lo = mv((uint32_t)b), hi = mv((uint32_t)(b >> 32));
+        x += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    };
+    step([](uint32_t u) { return dpp_move<kDppShr1, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr2, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr4, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr8, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppBcast15, 0xA>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppBcast31, 0xC>(0u, u); });
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32_l63(uint32_t x)
+{
+    x += dpp_move<kDppShr1, 0xF>(0u, x);
+    x += dpp_move<kDppShr2, 0xF>(0u, x);
+    x += dpp_move<kDppShr4, 0xF>(0u, x);
+    x += dpp_move<kDppShr8, 0xF>(0u, x);
+    x += dpp_move<kDppBcast15, 0xA>(0u, x);
+    x += dpp_move<kDppBcast31, 0xC>(0u, x);
+    return x;
+}
+
 __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, uint64_t key,
                                               uint32_t row, uint64_t &c_pm, uint32_t &c_pi,
                                               uint32_t &c_p, uint32_t &pi_out, uint32_t &p_out)
@@ -1019,15 +1076,14 @@ __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, ui
     uint32_t p = (uint32_t)__popcll(sm & seg);
     uint64_t v = (valid && st) ? key : 0ull;
     uint32_t vi = (valid && st) ? row : kNoRow;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t lo = __shfl_up((uint32_t)v, off), hi = __shfl_up((uint32_t)(v >> 32), off);
-        const uint32_t oi = __shfl_up(vi, off);
-        const uint64_t o = ((uint64_t)hi << 32) | lo;
-        if (lane >= off && lane - off >= h && o > v) {
-            v = o;
-            vi = oi;
-        }
-    }
+    // Hillis-Steele within rows of 16, then across rows; a lane without a
+    // source keeps its own value, which never wins (o > v fails)
+    seg_max_step<kDppShr1, 0xF>(v, vi, lane - 1 >= h);
+    seg_max_step<kDppShr2, 0xF>(v, vi, lane - 2 >= h);
+    seg_max_step<kDppShr4, 0xF>(v, vi, lane - 4 >= h);
+    seg_max_step<kDppShr8, 0xF>(v, vi, lane - 8 >= h);
+    seg_max_step<kDppBcast15, 0xA>(v, vi, (lane & ~15) - 1 >= h);
+    seg_max_step<kDppBcast31, 0xC>(v, vi, 31 >= h);
     if (h < 0) {
         p += c_p;
         if (c_pm > v) {
@@ -1463,13 +1519,11 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     }
 
     if (one_scen) {
-        for (int off = 32; off > 0; off >>= 1) {
-            vsum += __shfl_down(vsum, off);
-            clamps += __shfl_down(clamps, off);
-        }
-        if (lane == 0) {
+        vsum = wave_sum_f64_l63(vsum);
+        const uint32_t ck32 = wave_sum_u32_l63((uint32_t)clamps);
+        if (lane == 63) {
             red_d[wv] = vsum;
-            red_k[wv] = clamps;
+            red_k[wv] = ck32;
         }
         __syncthreads();
         if (tid == 0 && lb > la) {
