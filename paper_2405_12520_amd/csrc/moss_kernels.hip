@@ -75,6 +75,65 @@ __device__ __forceinline__ uint32_t philox_x0(uint32_t c0, uint32_t c1, uint32_t
     return c0;
 }
 
+// DPP lane moves (row_shr:n reads lane - n of the same row of 16,
+// row_bcast:15 / :31 read lane 15 / 31 of the row before), so that the wave
+// scans below stay in the vector ALU instead of going through LDS.  Lanes
+// that the move does not write (no source lane, or a row outside ROWS) get
+// `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROWS, 0xF, false);
+}
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+constexpr int kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
+// One step of the segmented prefix maximum: take the (key, row) the move
+// reads if it is larger and its lane lies in this lane's segment.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_max_step(uint64_t &v, uint32_t &vi, bool in_seg)
+{
+    const uint32_t lo = dpp_move<CTRL, ROWS>((uint32_t)v, (uint32_t)v);
+    const uint32_t hi = dpp_move<CTRL, ROWS>((uint32_t)(v >> 32), (uint32_t)(v >> 32));
+    const uint32_t oi = dpp_move<CTRL, ROWS>(vi, vi);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    if (in_seg && o > v) {
+        v = o;
+        vi = oi;
+    }
+}
+
+// Sum over the wave, complete in lane 63 (inclusive scan by row shifts, then
+// row broadcasts).
+__device__ __forceinline__ double wave_sum_f64_l63(double x)
+{
+    auto step = [&](auto mv) {
+        const uint64_t b = (uint64_t)__double_as_longlong(x);
+        const uint32_t lo = mv((uint32_t)b), hi = mv((uint32_t)(b >> 32));
+        x += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    };
+    step([](uint32_t u) { return dpp_move<kDppShr1, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr2, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr4, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr8, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppBcast15, 0xA>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppBcast31, 0xC>(0u, u); });
+    return x;
+}
+
+// Inclusive scan over the wave: lane i gets the sum of lanes 0..i (lane 63
+// the wave's sum).
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x)
+{
+    x += dpp_move<kDppShr1, 0xF>(0u, x);
+    x += dpp_move<kDppShr2, 0xF>(0u, x);
+    x += dpp_move<kDppShr4, 0xF>(0u, x);
+    x += dpp_move<kDppShr8, 0xF>(0u, x);
+    x += dpp_move<kDppBcast15, 0xA>(0u, x);
+    x += dpp_move<kDppBcast31, 0xC>(0u, x);
+    return x;
+}
+
 struct Lead {
     bool has;
     float v, gap;
@@ -132,7 +191,7 @@ __device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool pred)
     uint32_t base = 0;
     if (lane == leader)
         base = atomicAdd(ctr, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     return base + (uint32_t)__popcll(m & lt);
 }
@@ -213,7 +272,7 @@ __global__ void k_insert(Dev d)
     uint32_t base = 0;
     if (__lane_id() == leader)
         base = atomicAdd(d.n_ins, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
     if (!ins)
         return;
     const int lane_id = __lane_id();
@@ -380,7 +439,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             rd_next = rd_c;
             rd_ok = true;
         }
-        const int scen0 = __shfl(li.scen, 0);
+        const int scen0 = __builtin_amdgcn_readlane(li.scen, 0);
         const bool uni_scen = __all(!act || li.scen == scen0);
 
         // values carried from the acceleration to the integration
@@ -598,9 +657,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             wave_count(d, C_MLP_EVAL, inside, li.scen, scen0, uni_scen);
             wave_count(d, C_MLP_FALLBACK, act && !inside, li.scen, scen0, uni_scen);
             if (uni_scen) {
-                for (int off = 32; off > 0; off >>= 1)
-                    e2 += __shfl_xor(e2, off);
-                if (__lane_id() == 0 && e2 != 0.0)
+                e2 = wave_sum_f64_l63(e2);
+                if (__lane_id() == 63 && e2 != 0.0)
                     atomicAdd(sv_at(d, d.mlp_sq, scen0), e2);
             } else if (inside) {
                 atomicAdd(sv_at(d, d.mlp_sq, li.scen), e2);
@@ -682,7 +740,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             const int leader = __ffsll((long long)jm) - 1;
             if (__lane_id() == leader)
                 jbase = atomicAdd(&s_jn, (uint32_t)__popcll(jm));
-            jbase = __shfl(jbase, leader);
+            jbase = (uint32_t)__builtin_amdgcn_readlane((int)jbase, leader);
         }
         if (act) {
             if (arrived || joins)
@@ -724,18 +782,13 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 2;
 constexpr int kScanLanes = kScanThreads * kScanPer;
 
-// Inclusive scan of two ints over the block: within each wave by shuffles,
+// Inclusive scan of two ints over the block: within each wave by DPP moves,
 // then the totals of the waves before it are added (one LDS round).
 __device__ __forceinline__ void block_scan2(int &x, int &y, int *sh)
 {
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int ax = __shfl_up(x, off), ay = __shfl_up(y, off);
-        if (lane >= off) {
-            x += ax;
-            y += ay;
-        }
-    }
+    x = (int)wave_scan_u32((uint32_t)x);
+    y = (int)wave_scan_u32((uint32_t)y);
     if (lane == 63) {
         sh[wv] = x;
         sh[kScanThreads / 64 + wv] = y;
@@ -1005,63 +1058,6 @@ constexpr uint32_t kNoRow = 0xFFFFu;
 static_assert(2 * kOldCap + kJCap <= 4 * kNewCap, "o_p, o_pi and j_ord share u_buf");
 static_assert(kOldCap < 0x8000 && kJCap < 0x8000, "row sources are 15-bit indices");
 
-// DPP lane moves (row_shr:n reads lane - n of the same row of 16,
-// row_bcast:15 / :31 read lane 15 / 31 of the row before), so that the wave
-// scans below stay in the vector ALU instead of going through LDS.  Lanes
-// that the move does not write (no source lane, or a row outside ROWS) get
-// `old`.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t x)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROWS, 0xF, false);
-}
-constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
-constexpr int kDppBcast15 = 0x142, kDppBcast31 = 0x143;
-
-// One step of the segmented prefix maximum: take the (key, row) the move
-// reads if it is larger and its lane lies in this lane's segment.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void seg_max_step(uint64_t &v, uint32_t &vi, bool in_seg)
-{
-    const uint32_t lo = dpp_move<CTRL, ROWS>((uint32_t)v, (uint32_t)v);
-    const uint32_t hi = dpp_move<CTRL, ROWS>((uint32_t)(v >> 32), (uint32_t)(v >> 32));
-    const uint32_t oi = dpp_move<CTRL, ROWS>(vi, vi);
-    const uint64_t o = ((uint64_t)hi << 32) | lo;
-    if (in_seg && o > v) {
-        v = o;
-        vi = oi;
-    }
-}
-
-// Sum over the wave, complete in lane 63 (inclusive scan by row shifts, then
-// row broadcasts).
-__device__ __forceinline__ double wave_sum_f64_l63(double x)
-{
-    auto step = [&](auto mv) {
-        const uint64_t b = (uint64_t)__double_as_longlong(x);
-        const uint32_t lo = mv((uint32_t)b), hi = mv((uint32_t)(b >> 32));
-        x += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-    };
-    step([](uint32_t u) { return dpp_move<kDppShr1, 0xF>(0u, u); });
-    step([](uint32_t u) { return dpp_move<kDppShr2, 0xF>(0u, u); });
-    step([](uint32_t u) { return dpp_move<kDppShr4, 0xF>(0u, u); });
-    step([](uint32_t u) { return dpp_move<kDppShr8, 0xF>(0u, u); });
-    step([](uint32_t u) { return dpp_move<kDppBcast15, 0xA>(0u, u); });
-    step([](uint32_t u) { return dpp_move<kDppBcast31, 0xC>(0u, u); });
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32_l63(uint32_t x)
-{
-    x += dpp_move<kDppShr1, 0xF>(0u, x);
-    x += dpp_move<kDppShr2, 0xF>(0u, x);
-    x += dpp_move<kDppShr4, 0xF>(0u, x);
-    x += dpp_move<kDppShr8, 0xF>(0u, x);
-    x += dpp_move<kDppBcast15, 0xA>(0u, x);
-    x += dpp_move<kDppBcast31, 0xC>(0u, x);
-    return x;
-}
-
 __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, uint64_t key,
                                               uint32_t row, uint64_t &c_pm, uint32_t &c_pi,
                                               uint32_t &c_p, uint32_t &pi_out, uint32_t &p_out)
@@ -1094,9 +1090,10 @@ __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, ui
     pi_out = vi;
     p_out = p;
     // carry for the next wave of rows: the state after row 63
-    c_pm = ((uint64_t)__shfl((uint32_t)(v >> 32), 63) << 32) | __shfl((uint32_t)v, 63);
-    c_pi = __shfl(vi, 63);
-    c_p = __shfl(p, 63) + (uint32_t)((sm >> 63) & 1ull);
+    c_pm = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    c_pi = (uint32_t)__builtin_amdgcn_readlane((int)vi, 63);
+    c_p = (uint32_t)__builtin_amdgcn_readlane((int)p, 63) + (uint32_t)((sm >> 63) & 1ull);
 }
 
 // Merge of the whole lanes [la, lb) -- new rows [n0, n1), old rows [o0, o1),
@@ -1520,7 +1517,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
 
     if (one_scen) {
         vsum = wave_sum_f64_l63(vsum);
-        const uint32_t ck32 = wave_sum_u32_l63((uint32_t)clamps);
+        const uint32_t ck32 = wave_scan_u32((uint32_t)clamps);
         if (lane == 63) {
             red_d[wv] = vsum;
             red_k[wv] = ck32;
