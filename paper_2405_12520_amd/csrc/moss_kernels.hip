@@ -1209,6 +1209,16 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
                 wave_start[4] = no;
         }
     }
+    // ---- joiners: rank among the lane's joiners, which orders them by key
+    int jq = 0;
+    if (tid < nj) {
+        const uint32_t l = (uint32_t)la + j_ln[tid];
+        const uint64_t key = okey(j_s[tid], j_id[tid]);
+        const int jl = JO(l) - j0, jh = JO(l + 1) - j0;
+        for (int e2 = jl; e2 < jh; ++e2)
+            jq += okey(j_s[e2], j_id[e2]) < key;
+        j_ord[jl + jq] = (uint16_t)tid;
+    }
     __syncthreads();
     // ---- stayer ranks and prefix maxima, one wave per row range
     {
@@ -1235,15 +1245,14 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
         }
     }
     __syncthreads();
-    // ---- joiners: rank among the lane's joiners, stayers before them
+    // ---- joiners: the stayers before them (the first old row of the lane
+    // whose prefix maximum exceeds the key); stayers below
     if (tid < nj) {
         const int e = tid;
         const uint32_t l = (uint32_t)la + j_ln[e];
         const uint64_t key = okey(j_s[e], j_id[e]);
         const int jl = JO(l) - j0, jh = JO(l + 1) - j0;
-        int q = 0;
-        for (int e2 = jl; e2 < jh; ++e2)
-            q += okey(j_s[e2], j_id[e2]) < key;
+        const int q = jq;
         const int lo = LO(l) - o0, hi = LO(l + 1) - o0;
         int a = lo, b = hi;       // first old row of l with prefix max > key
         while (a < b) {
@@ -1271,9 +1280,7 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
         } else {
             atomicOr(d.err, 1u);
         }
-        j_ord[jl + q] = (uint16_t)e;
     }
-    __syncthreads();
     // ---- stayers: joiners with a smaller key than their prefix maximum
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -1451,12 +1458,19 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wv = tid >> 6;
+    // The chunk of this block when the rows fill the grid (the usual case)
+    // is loaded together with the row count, and loaded again only when that
+    // guess is wrong; w is uniform, every thread reads the same records.
+    const int wg = min(xcd_tile(d.xcd_remap, (int)gridDim.x), d.cap / kMC + 1);
+    int4 ca = d.chunk[wg], cb = d.chunk[wg + 1];
     const int n_next = *d.n_next;
     const int w = xcd_tile(d.xcd_remap, n_next / kMC + 1);
     if (w > n_next / kMC)
         return;
-    // chunk bounds (w is uniform: every thread reads the same two records)
-    const int4 ca = d.chunk[w], cb = d.chunk[w + 1];
+    if (w != wg) {
+        ca = d.chunk[w];
+        cb = d.chunk[w + 1];
+    }
     const int la = ca.x, lb = cb.x;
     const int n0 = ca.y, n1 = cb.y, o0 = ca.z, o1 = cb.z, j0 = ca.w, j1 = cb.w;
     const int nw = n1 - n0;
