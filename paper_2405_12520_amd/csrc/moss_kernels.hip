@@ -143,9 +143,10 @@ struct Lead {
 // Leader beyond the lane end: follow the route for at most h_look roads while
 // the distance covered is within d_look; on each road take lane min(k, n-1)
 // and use its last vehicle (lane tail).  A vehicle never leads itself.
-// rd0 is the record of the next road nxt (already loaded by the caller).
+// rd0 is the record of the next road nxt (already loaded by the caller);
+// with pre, tl0 is the tail the first road gives (loaded by the caller too).
 __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id, uint32_t ptr,
-                          int32_t nxt, RoadInfo rd0)
+                          int32_t nxt, RoadInfo rd0, bool pre, Tail tl0)
 {
     Lead r = {false, 0.0f, 0.0f, kNone};
     float dist = li.L - s;
@@ -162,7 +163,11 @@ __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id
             rd = d.roads[nr];
         if (kk > rd.nlanes - 1)
             kk = rd.nlanes - 1;
-        Tail tl = d.tails[rd.lane0 + kk];
+        Tail tl;
+        if (h == 0 && pre)
+            tl = tl0;
+        else
+            tl = d.tails[rd.lane0 + kk];
         if (tl.id != kNone) {
             if (tl.id != id) {
                 r.has = true;
@@ -439,6 +444,17 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             rd_next = rd_c;
             rd_ok = true;
         }
+        // a lane head's first lookahead tail, in its own lane and in the side
+        // lane, loaded now so that the load overlaps the acceleration (entry
+        // 0 for the other vehicles)
+        Tail tl_own, tl_side;
+        {
+            const int nl1 = rd_c.nlanes - 1;
+            const int k_own = min((int)li.k, nl1);
+            const int k_side = min(max((int)li.k + side, 0), nl1);
+            tl_own = d.tails[head_next ? rd_c.lane0 + k_own : 0];
+            tl_side = d.tails[head_next ? rd_c.lane0 + k_side : 0];
+        }
         const int scen0 = __builtin_amdgcn_readlane(li.scen, 0);
         const bool uni_scen = __all(!act || li.scen == scen0);
 
@@ -590,7 +606,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                     rd_next = d.roads[nxt];
                     rd_ok = true;
                 }
-                const Lead ld = lookahead(d, lif, s, id, ptr, nxt, rd_next);
+                const Lead ld = lookahead(d, lif, s, id, ptr, nxt, rd_next, head_next,
+                                          change ? tl_side : tl_own);
                 if (ld.has) flags |= 8;
                 has_lead = ld.has;
                 lead_v = ld.v;
