@@ -1464,8 +1464,8 @@ __device__ __forceinline__ bool group_fits(int new_rows, int old_rows, int joine
 // Next state, one chunk of kMC new rows per block.  A block owns the lanes
 // whose first new row falls in its chunk and merges them with merge_group.
 // A chunk that does not fit the LDS tile is merged in consecutive groups of
-// whole lanes that do; only a lane that alone exceeds the tile takes
-// merge_lane_global.
+// whole lanes that do (at most two); the lanes from one that alone exceeds
+// the tile on, or beyond the two groups, take merge_lanes_global.
 __global__ void __launch_bounds__(kMT) k_merge(Dev d)
 {
     __shared__ double red_d[kMT / 64];
@@ -1516,9 +1516,9 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         return gb;
     };
     // At most two groups through the tile (written out rather than looped:
-    // a loop around the tile code costs it about 40 VGPRs); lanes left after
-    // them, which only a chunk of more than twice the tile can have, are
-    // merged one per thread.
+    // a loop around the tile code costs it about 40 VGPRs).  The lanes left
+    // after them -- from a lane that alone exceeds the tile on, or beyond
+    // two tiles' worth -- are merged one per thread.
     int ga = la;
     int gb = group_fits(nw, o1 - o0, j1 - j0, lb - la) ? lb : longest_fit(la, n0, o0, j0);
     if (gb > ga) {
