@@ -303,7 +303,7 @@ __global__ void k_insert(Dev d)
 // ----------------------------------------------------------------- update --
 
 constexpr int kUT = kUpdateRows;       // rows per update block
-constexpr int kUH = 96;                // rows staged before and after them
+constexpr int kUH = 128;               // rows staged before and after them
 constexpr int kUW = kUT + 2 * kUH;
 
 __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int hi, float x)
