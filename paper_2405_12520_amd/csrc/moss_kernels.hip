@@ -219,6 +219,40 @@ __device__ __forceinline__ double *sv_at(const Dev &d, double *base, int scen)
 
 // Adds the wave's count of pred to counter c (one atomic per wave when the
 // wave's vehicles are all of one scenario).
+// For each scenario among the wave's lanes with pred, adds their number to
+// counter c of that scenario: one atomic per scenario present, where
+// per-lane atomics would meet on one address 64 times.  Wave-uniform call.
+__device__ __forceinline__ void wave_count_scen(const Dev &d, int c, bool pred, int scen)
+{
+    unsigned long long todo = __ballot(pred);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int s0 = __builtin_amdgcn_readlane(scen, leader);
+        const unsigned long long mm = __ballot(pred && scen == s0);
+        if (__lane_id() == leader)
+            atomicAdd(cnt_at(d, s0, c), (unsigned long long)__popcll(mm));
+        todo &= ~mm;
+    }
+}
+
+// The same for a sum of doubles kept per scenario at base (one wave sum per
+// scenario present).  Wave-uniform call.
+__device__ __forceinline__ void wave_sum_scen(const Dev &d, double *base, bool pred, int scen,
+                                              double x)
+{
+    unsigned long long todo = __ballot(pred);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int s0 = __builtin_amdgcn_readlane(scen, leader);
+        const bool mine = pred && scen == s0;
+        const unsigned long long mm = __ballot(mine);
+        const double sum = wave_sum_f64_l63(mine ? x : 0.0);
+        if (__lane_id() == 63)
+            atomicAdd(sv_at(d, base, s0), sum);
+        todo &= ~mm;
+    }
+}
+
 __device__ __forceinline__ void wave_count(const Dev &d, int c, bool pred, int scen, int scen0,
                                            bool uniform)
 {
@@ -241,10 +275,9 @@ __global__ void k_insert(Dev d)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const Params &P = d.P;
-    bool ins = false;
-    int l = 0, h = 0;
+    bool ins = false, fail = false;
+    int l = 0, h = 0, scen = 0;
     float vins = 0.0f;
-    unsigned long long *c = nullptr;
     // the head's departure step is kept per queue, so that lanes with nothing
     // due leave after one coalesced load
     if (q < d.n_qlanes && (int64_t)d.q_hdep[q] <= *d.t) {
@@ -262,42 +295,42 @@ __global__ void k_insert(Dev d)
                 vins = fmin32(v0e, d.S.v[lo]);
                 ok = (d.S.s[lo] - P.len) >= (P.s0 + vins * P.T);
             }
-            c = cnt_at(d, li.scen, 0);
-            if (ok)
-                ins = true;
-            else
-                atomicAdd(c + C_INSERT_FAIL, 1ull);
+            scen = li.scen;
+            ins = ok;
+            fail = !ok;
         }
     }
     // one reservation of insertion slots per wave
     const unsigned long long m = __ballot(ins);
-    if (m == 0)
-        return;
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (__lane_id() == leader)
-        base = atomicAdd(d.n_ins, (uint32_t)__popcll(m));
-    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-    if (!ins)
-        return;
-    const int lane_id = __lane_id();
-    const unsigned long long below = lane_id ? (~0ull >> (64 - lane_id)) : 0ull;
-    const uint32_t e = base + (uint32_t)__popcll(m & below);
-    const uint32_t slot = (uint32_t)(*d.n_cur) + e;
-    d.Pr.s[slot] = 0.0f;
-    d.Pr.v[slot] = vins;
-    d.Pr.a[slot] = 0.0f;
-    d.Pr.id[slot] = d.q_id[h];
-    d.Pr.lane[slot] = (uint32_t)l | kJoinBit;
-    d.Pr.ptr[slot] = d.q_ptr[h];
-    d.Pr.next[slot] = d.q_next[h];
-    d.Pr.v0[slot] = d.q_v0[h];
-    d.jins_list[e] = slot;
-    d.jins_lane[e] = (uint32_t)l;
-    atomicAdd(d.jcount + l, 1);
-    d.q_head[l] = h + 1;
-    d.q_hdep[q] = h + 1 < d.q_end[l] ? d.q_dep[h + 1] : INT32_MAX;
-    atomicAdd(c + C_INSERTED, 1ull);
+    if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if (__lane_id() == leader)
+            base = atomicAdd(d.n_ins, (uint32_t)__popcll(m));
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+        if (ins) {
+            const int lane_id = __lane_id();
+            const unsigned long long below = lane_id ? (~0ull >> (64 - lane_id)) : 0ull;
+            const uint32_t e = base + (uint32_t)__popcll(m & below);
+            const uint32_t slot = (uint32_t)(*d.n_cur) + e;
+            d.Pr.s[slot] = 0.0f;
+            d.Pr.v[slot] = vins;
+            d.Pr.a[slot] = 0.0f;
+            d.Pr.id[slot] = d.q_id[h];
+            d.Pr.lane[slot] = (uint32_t)l | kJoinBit;
+            d.Pr.ptr[slot] = d.q_ptr[h];
+            d.Pr.next[slot] = d.q_next[h];
+            d.Pr.v0[slot] = d.q_v0[h];
+            d.jins_list[e] = slot;
+            d.jins_lane[e] = (uint32_t)l;
+            atomicAdd(d.jcount + l, 1);
+            d.q_head[l] = h + 1;
+            d.q_hdep[q] = h + 1 < d.q_end[l] ? d.q_dep[h + 1] : INT32_MAX;
+        }
+    }
+    // counters last: the slot reservation above waits for nothing else
+    wave_count_scen(d, C_INSERT_FAIL, fail, scen);
+    wave_count_scen(d, C_INSERTED, ins, scen);
 }
 
 // ----------------------------------------------------------------- update --
@@ -1411,23 +1444,29 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
             write_tail(d, l, false, 0.0f, 0.0f, kNone);
         }
     }
-    // ---- positions and speeds of the chunk's rows, coalesced
-    for (int k = tid; k < nw; k += kMT) {
-        const uint32_t x = w_src[k];
-        if (x == kNoSrc)
-            continue;
-        const bool jx = (x & kTagJ) != 0;
-        const uint32_t e = x & ~kTagJ;
-        const float s = jx ? j_s[e] : o_s[e];
-        const float v = jx ? j_v[e] : o_v[e];
-        d.S.s[n0 + k] = s;
-        d.S.v[n0 + k] = v;
-        if (one_scen) {
-            vsum += (double)v;
-        } else {
-            const int sc = d.lanes[lane_of(x)].scen;
-            atomicAdd(cnt_at(d, sc, C_VEH_STEPS), 1ull);
-            atomicAdd(sv_at(d, d.sumv, sc), (double)v);
+    // ---- positions and speeds of the chunk's rows, coalesced (a chunk of
+    // several scenarios counts per scenario present in each wave)
+    for (int k0 = 0; k0 < nw; k0 += kMT) {
+        const int k = k0 + tid;
+        const uint32_t x = k < nw ? w_src[k] : kNoSrc;
+        const bool ok = x != kNoSrc;
+        float v = 0.0f;
+        int sc = 0;
+        if (ok) {
+            const bool jx = (x & kTagJ) != 0;
+            const uint32_t e = x & ~kTagJ;
+            const float s = jx ? j_s[e] : o_s[e];
+            v = jx ? j_v[e] : o_v[e];
+            d.S.s[n0 + k] = s;
+            d.S.v[n0 + k] = v;
+            if (one_scen)
+                vsum += (double)v;
+            else
+                sc = d.lanes[lane_of(x)].scen;
+        }
+        if (!one_scen) {
+            wave_count_scen(d, C_VEH_STEPS, ok, sc);
+            wave_sum_scen(d, d.sumv, ok, sc, (double)v);
         }
     }
 }
