@@ -82,7 +82,8 @@ struct Layout {
         };
         const size_t c = (size_t)std::max(cap, 1);
         for (auto &x : S) x = take(4 * c);
-        for (auto &x : Pr) x = take(4 * c);
+        // proposals: one row per vehicle, then one insertion row per queue lane
+        for (auto &x : Pr) x = take(4 * (c + (size_t)std::max(n_qlanes, 0)));
         for (auto &x : ls) x = take(4 * ((size_t)n_lanes + 1));
         tails = take(sizeof(Tail) * (size_t)n_lanes);
         leave = take(4 * (size_t)n_lanes);

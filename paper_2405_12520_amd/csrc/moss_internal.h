@@ -101,7 +101,8 @@ struct Dev {
     int4 *chunk;
     // joiners (lane changers, road transfers, insertions).  Update tile b
     // (rows [b*kUpdateRows, (b+1)*kUpdateRows)) lists its jcnt[b] joiners in
-    // jlist/jlane[b*kUpdateRows ...]; insertions go to jins_list/jins_lane;
+    // jlist/jlane[b*kUpdateRows ...]; queue lane q lists its insertion (from
+    // proposal row n_cur + q) in jins_list/jins_lane[q], lane kNone if none;
     // k_jscatter groups all of them by target lane into jidx/jslane using the
     // per-lane cursors jcur (initialised to joff by the scan).
     uint32_t *jlist, *jlane, *jidx, *jslane, *jins_list, *jins_lane;

@@ -300,19 +300,16 @@ __global__ void k_insert(Dev d)
             fail = !ok;
         }
     }
-    // one reservation of insertion slots per wave
-    const unsigned long long m = __ballot(ins);
-    if (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        uint32_t base = 0;
-        if (__lane_id() == leader)
-            base = atomicAdd(d.n_ins, (uint32_t)__popcll(m));
-        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    // Queue lane q owns proposal row n_cur + q and entry q of the insertion
+    // list (a lane inserts at most one vehicle per step), so no slot is
+    // allocated (a shared slot counter, taken once per wave, serialised on
+    // one address across the grid); entries of lanes that insert nothing
+    // are marked kNone.
+    if (q < d.n_qlanes) {
+        const uint32_t slot = (uint32_t)(*d.n_cur) + (uint32_t)q;
+        d.jins_list[q] = slot;
+        d.jins_lane[q] = ins ? (uint32_t)l : kNone;
         if (ins) {
-            const int lane_id = __lane_id();
-            const unsigned long long below = lane_id ? (~0ull >> (64 - lane_id)) : 0ull;
-            const uint32_t e = base + (uint32_t)__popcll(m & below);
-            const uint32_t slot = (uint32_t)(*d.n_cur) + e;
             d.Pr.s[slot] = 0.0f;
             d.Pr.v[slot] = vins;
             d.Pr.a[slot] = 0.0f;
@@ -321,14 +318,13 @@ __global__ void k_insert(Dev d)
             d.Pr.ptr[slot] = d.q_ptr[h];
             d.Pr.next[slot] = d.q_next[h];
             d.Pr.v0[slot] = d.q_v0[h];
-            d.jins_list[e] = slot;
-            d.jins_lane[e] = (uint32_t)l;
             atomicAdd(d.jcount + l, 1);
             d.q_head[l] = h + 1;
             d.q_hdep[q] = h + 1 < d.q_end[l] ? d.q_dep[h + 1] : INT32_MAX;
         }
     }
-    // counters last: the slot reservation above waits for nothing else
+    if (q == 0)
+        *d.n_ins = (uint32_t)d.n_qlanes;
     wave_count_scen(d, C_INSERT_FAIL, fail, scen);
     wave_count_scen(d, C_INSERTED, ins, scen);
 }
@@ -961,6 +957,8 @@ __global__ void __launch_bounds__(256) k_jscatter(Dev d)
         const uint32_t *lan = ins ? d.jins_lane + k0 : d.jlane + (size_t)tile * kUpdateRows;
         for (int k = lane; k < cnt; k += 64) {
             const uint32_t x = lan[k], src = lst[k];
+            if (x == kNone)
+                continue;       // a queue lane that inserted nothing
             // the record's loads do not wait for the slot
             const float s = d.Pr.s[src], v = d.Pr.v[src], a = d.Pr.a[src], v0 = d.Pr.v0[src];
             const uint32_t id = d.Pr.id[src], ptr = d.Pr.ptr[src];
