@@ -938,12 +938,14 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
 
 // ----------------------------------------------------- joiners by lane --
 
-// One wave per update tile (then per kUpdateRows insertions): each joiner takes
+// One wave per update tile (then per kUpdateRows queue lanes' insertion
+// entries, kNone for a lane that inserted nothing): each joiner takes
 // the next slot of its target lane's bucket.
 __global__ void __launch_bounds__(256) k_jscatter(Dev d)
 {
     const int ntiles = (*d.n_cur + kUpdateRows - 1) / kUpdateRows;
-    // insertions in tiles of kUpdateRows after the update tiles
+    // insertion entries (one per queue lane) in tiles of kUpdateRows after
+    // the update tiles
     const int nins = (int)*d.n_ins;
     const int itiles = (nins + kUpdateRows - 1) / kUpdateRows;
     const int lane = __lane_id();
