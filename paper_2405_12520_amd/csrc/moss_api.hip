@@ -376,7 +376,6 @@ static void fill_dev(moss_sim *h)
     d.n_next = sc + 1;
     d.n_dbg = sc + 2;
     d.n_ins = (uint32_t *)(sc + 3);
-    d.n_join = (uint32_t *)(sc + 4);
     d.err = (uint32_t *)(sc + 5);
     d.t = (int64_t *)(sc + 8);
     d.qlanes = I(L.qlanes);

@@ -112,7 +112,7 @@ struct Dev {
     int32_t *jcnt, *jcur;
     uint8_t *lane_red;            // red light for the lane's road at the current step
     int32_t *n_cur, *n_next, *n_dbg;
-    uint32_t *n_ins, *n_join;
+    uint32_t *n_ins;
     int64_t *t;
     // departure queues
     const int32_t *qlanes;

@@ -184,25 +184,6 @@ __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id
     return r;
 }
 
-// Wave-aggregated slot allocation: every lane with pred gets a distinct
-// index from *ctr; one atomic per wave.
-__device__ __forceinline__ uint32_t wave_alloc(uint32_t *ctr, bool pred)
-{
-    const unsigned long long m = __ballot(pred);
-    if (m == 0)
-        return 0;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader)
-        base = atomicAdd(ctr, (uint32_t)__popcll(m));
-    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    return base + (uint32_t)__popcll(m & lt);
-}
-
-// Wave-aggregated counter increment for waves whose vehicles are all in one
-// scenario (the common case); other waves use one atomic per lane.
 // This wave's copy of the counters and sums.
 __device__ __forceinline__ int wave_stripe()
 {
@@ -253,6 +234,8 @@ __device__ __forceinline__ void wave_sum_scen(const Dev &d, double *base, bool p
     }
 }
 
+// Wave-aggregated counter increment for waves whose vehicles are all in one
+// scenario (the common case); other waves use one atomic per lane.
 __device__ __forceinline__ void wave_count(const Dev &d, int c, bool pred, int scen, int scen0,
                                            bool uniform)
 {
