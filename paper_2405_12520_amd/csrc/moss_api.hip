@@ -438,7 +438,7 @@ static void plan_layout(const moss_network *net, const moss_vehicles *veh, const
     }
     L->n_pend = veh->n - n_pl;
     L->n_qlanes = (int32_t)std::count(is_q.begin(), is_q.end(), 1);
-    L->nblk = (net->n_lanes + 511) / 512;
+    L->nblk = (net->n_lanes + kScanBlockLanes - 1) / kScanBlockLanes;
     L->debug = (prm->flags & MOSS_FLAG_DEBUG) != 0;
     L->trace = (prm->flags & MOSS_FLAG_TRACE) != 0;
     L->mlp = prm->mode == MOSS_MODE_MLP;

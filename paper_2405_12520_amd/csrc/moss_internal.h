@@ -161,6 +161,8 @@ inline int32_t stripe_elems(int64_t n) { return (int32_t)((n + 31) / 32 * 32); }
 
 // Rows per update block (one joiner region per such tile).
 constexpr int kUpdateRows = 256;
+// Lanes per block of the lane-count scan (one pair of block sums each).
+constexpr int kScanBlockLanes = 256;
 
 enum { C_INSERTED = 0, C_INSERT_FAIL, C_ARRIVED, C_TRIP_TIME, C_CLAMPS, C_LANE_CHANGES,
        C_VEH_STEPS, C_MLP_EVAL, C_MLP_FALLBACK, C_N };

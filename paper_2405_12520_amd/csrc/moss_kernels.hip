@@ -808,8 +808,9 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 // --------------------------------------------------------- lane-count scan --
 
 constexpr int kScanThreads = 256;
-constexpr int kScanPer = 2;
+constexpr int kScanPer = 1;
 constexpr int kScanLanes = kScanThreads * kScanPer;
+static_assert(kScanLanes == kScanBlockLanes, "block sums are sized for kScanBlockLanes");
 
 // Inclusive scan of two ints over the block: within each wave by DPP moves,
 // then the totals of the waves before it are added (one LDS round).
