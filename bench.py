@@ -29,9 +29,10 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per vehicle and launch of the two per-vehicle kernels
 # (the minimum each must move; lane tables and neighbour reads are on-chip
 # reuse): k_update reads 7 state fields (lane, s, v, id, route ptr, next road,
-# v0 = 28 B) and writes an 8-field proposal (32 B); k_merge reads the
-# proposal (32 B) and writes the 8-field state (32 B).
-ALGO_BYTES = {"k_update": 28 + 32, "k_merge": 32 + 32}
+# v0 = 28 B) and writes a 6-field proposal (24 B; id and v0 alternate between
+# two buffers by step parity instead of being copied); k_merge reads the
+# proposal and the old id/v0 (32 B) and writes the 8-field state (32 B).
+ALGO_BYTES = {"k_update": 28 + 24, "k_merge": 32 + 32}
 
 
 def say(*a):

@@ -67,7 +67,7 @@ struct Layout {
     int64_t n_route;
     bool debug, trace, mlp, xy;
     size_t total;
-    size_t S[8], Pr[8], J[8], ls[2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
+    size_t S[8], Pr[8], J[8], ls[2], idv[2][2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_hdep, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq, tr_feat,
         tr_label, road_ab, out_buf, ctl_idx, ctl_rec;
@@ -81,9 +81,17 @@ struct Layout {
             return o;
         };
         const size_t c = (size_t)std::max(cap, 1);
-        for (auto &x : S) x = take(4 * c);
-        // proposals: one row per vehicle, then one insertion row per queue lane
-        for (auto &x : Pr) x = take(4 * (c + (size_t)std::max(n_qlanes, 0)));
+        const size_t cq = c + (size_t)std::max(n_qlanes, 0);
+        // S[3] (id) and S[7] (v0) are not used: those fields live in idv
+        for (int k = 0; k < 8; ++k)
+            S[k] = take((k == 3 || k == 7) ? 4 : 4 * c);
+        // proposals: one row per vehicle, then one insertion row per queue
+        // lane; their id and v0 are idv's current buffer
+        for (int k = 0; k < 8; ++k)
+            Pr[k] = take((k == 3 || k == 7) ? 4 : 4 * cq);
+        // id and v0 by step parity ([parity][0] id, [parity][1] v0)
+        for (auto &b : idv)
+            for (auto &x : b) x = take(4 * cq);
         for (auto &x : ls) x = take(4 * ((size_t)n_lanes + 1));
         tails = take(sizeof(Tail) * (size_t)n_lanes);
         leave = take(4 * (size_t)n_lanes);
@@ -349,6 +357,11 @@ static void fill_dev(moss_sim *h)
         x.v0 = F(offs[k][7]);
     }
     d.J.lane = U(L.jslane);
+    // id and v0 of parity 0 (step_dev selects the buffers of a parity)
+    d.S.id = d.Pr.id = U(L.idv[0][0]);
+    d.S.v0 = d.Pr.v0 = F(L.idv[0][1]);
+    d.id_next = U(L.idv[1][0]);
+    d.v0_next = F(L.idv[1][1]);
     d.n_lanes = L.n_lanes;
     d.n_scen = L.n_scen;
     d.cap = L.cap;
@@ -414,6 +427,10 @@ static Dev step_dev(const moss_sim *h, int parity)
     Dev d = h->dev;
     d.ls_old = (const int32_t *)(h->ws + h->lay.ls[parity]);
     d.ls_new = (int32_t *)(h->ws + h->lay.ls[1 - parity]);
+    d.S.id = d.Pr.id = (uint32_t *)(h->ws + h->lay.idv[parity][0]);
+    d.S.v0 = d.Pr.v0 = (float *)(h->ws + h->lay.idv[parity][1]);
+    d.id_next = (uint32_t *)(h->ws + h->lay.idv[1 - parity][0]);
+    d.v0_next = (float *)(h->ws + h->lay.idv[1 - parity][1]);
     return d;
 }
 
@@ -668,11 +685,11 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     chk(up(L.S[0], hs.data(), 4 * (size_t)NP));
     chk(up(L.S[1], hv.data(), 4 * (size_t)NP));
     chk(up(L.S[2], ha.data(), 4 * (size_t)NP));
-    chk(up(L.S[3], hid.data(), 4 * (size_t)NP));
+    chk(up(L.idv[0][0], hid.data(), 4 * (size_t)NP));
     chk(up(L.S[4], hlane.data(), 4 * (size_t)NP));
     chk(up(L.S[5], hptr.data(), 4 * (size_t)NP));
     chk(up(L.S[6], hnext.data(), 4 * (size_t)NP));
-    chk(up(L.S[7], hv0.data(), 4 * (size_t)NP));
+    chk(up(L.idv[0][1], hv0.data(), 4 * (size_t)NP));
     chk(up(L.ls[0], ls.data(), 4 * (size_t)(NL + 1)));
     chk(up(L.scal, scal, sizeof scal));
     chk(up(L.lanes, lanes.data(), sizeof(LaneInfo) * NL));
@@ -915,7 +932,8 @@ int moss_read_state(moss_sim *h, moss_state_out *out)
     if (n > out->capacity)
         return fail(MOSS_ENOMEM, "%d active vehicles, capacity %d", n, out->capacity);
     const size_t b = 4 * (size_t)n;
-    const SoA &S = h->dev.S;
+    const Dev dc = step_dev(h, h->parity);
+    const SoA &S = dc.S;
     if (n > 0) {
         ReadCopies rc_(h, out->device != 0);
         rc_.copy(out->id, S.id, b);
@@ -925,7 +943,7 @@ int moss_read_state(moss_sim *h, moss_state_out *out)
         rc_.copy(out->a, S.a, b);
         if (out->cursor && rc_.e == hipSuccess) {
             int32_t *tmp = (int32_t *)(h->ws + h->lay.cursor);
-            rc_.e = launch_cursor(h->dev, S.id, S.ptr, tmp, n, h->stream);
+            rc_.e = launch_cursor(dc, S.id, S.ptr, tmp, n, h->stream);
             rc_.copy(out->cursor, tmp, b);
         }
         HIP_TRY(rc_.finish());

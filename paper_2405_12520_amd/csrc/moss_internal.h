@@ -89,6 +89,12 @@ struct Dev {
     const int32_t *route;         // routes, each followed by -1
     SoA S;                        // state at the start of a step
     SoA Pr;                       // proposals, indexed by row at step start (+ insertions)
+    // id and v0 never change in a step: they alternate between two buffers
+    // by step parity instead of passing through the proposals.  S.id / S.v0
+    // and Pr.id / Pr.v0 are the current buffer (which also holds the
+    // insertion rows), id_next / v0_next the one the merge writes.
+    uint32_t *id_next;
+    float *v0_next;
     const int32_t *ls_old;        // lane_start of the state being read
     int32_t *ls_new;              // lane_start being built
     Tail *tails;

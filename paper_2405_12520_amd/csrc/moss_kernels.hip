@@ -788,14 +788,13 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 d.jlane[slot] = (uint32_t)x;
                 atomicAdd(d.jcount + x, 1);
             }
+            // (id and v0 of the row are already in Pr: the step's id/v0 buffer)
             d.Pr.s[i] = sp;
             d.Pr.v[i] = vn;
             d.Pr.a[i] = a;
-            d.Pr.id[i] = id;
             d.Pr.lane[i] = l | ((arrived || joins) ? kJoinBit : 0u);
             d.Pr.ptr[i] = p;
             d.Pr.next[i] = nr;
-            d.Pr.v0[i] = v0;
         }
         wave_count(d, C_ARRIVED, arrived, li.scen, scen0, uni_scen);
         wave_count(d, C_LANE_CHANGES, change, li.scen, scen0, uni_scen);
@@ -998,11 +997,11 @@ __device__ __forceinline__ void write_row(const Dev &d, int w, uint32_t src, uin
     d.S.s[w] = s;
     d.S.v[w] = v;
     d.S.a[w] = d.Pr.a[src];
-    d.S.id[w] = d.Pr.id[src];
+    d.id_next[w] = d.Pr.id[src];
     d.S.lane[w] = lane;
     d.S.ptr[w] = d.Pr.ptr[src];
     d.S.next[w] = d.Pr.next[src];
-    d.S.v0[w] = d.Pr.v0[src];
+    d.v0_next[w] = d.Pr.v0[src];
 }
 
 __device__ __forceinline__ void write_tail(const Dev &d, int l, bool any, float s, float v,
@@ -1063,7 +1062,7 @@ __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned lo
             ++clamps;
         }
     }
-    write_tail(d, l, w1 > w0, d.S.s[w0], d.S.v[w0], d.S.id[w0]);
+    write_tail(d, l, w1 > w0, d.S.s[w0], d.S.v[w0], d.id_next[w0]);
     for (int f = w0; f < w1; ++f)
         vsum += (double)d.S.v[f];
 }
@@ -1306,11 +1305,11 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
             w_src[pos] = (uint16_t)(kTagJ | e);
             const int g = n0 + pos;
             d.S.a[g] = ja;
-            d.S.id[g] = j_id[e];
+            d.id_next[g] = j_id[e];
             d.S.lane[g] = l;
             d.S.ptr[g] = jptr;
             d.S.next[g] = jnext;
-            d.S.v0[g] = jv0;
+            d.v0_next[g] = jv0;
         } else {
             atomicOr(d.err, 1u);
         }
@@ -1342,11 +1341,11 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
             w_src[pos] = (uint16_t)r;
             const int g = n0 + pos;
             d.S.a[g] = ra[k];
-            d.S.id[g] = o_id[r];
+            d.id_next[g] = o_id[r];
             d.S.lane[g] = ln;
             d.S.ptr[g] = rptr[k];
             d.S.next[g] = rnext[k];
-            d.S.v0[g] = rv0[k];
+            d.v0_next[g] = rv0[k];
         } else {
             atomicOr(d.err, 1u);
         }
