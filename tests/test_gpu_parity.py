@@ -180,6 +180,29 @@ def test_city_snapshot_full_size(sim_cls):
     g.close()
 
 
+def test_city_snapshot_long_run_bench_launch(sim_cls):
+    """The benchmark workload at full size in the benchmark's launch shape
+    (XCD-contiguous tiles, 16-step graph replays, the kernels without debug
+    records): after 80 and 160 steps the whole state and the counters equal
+    the oracle's, bit for bit."""
+    sc = S.city_snapshot()
+    _say("city 2M, 160 steps in the benchmark's launch shape")
+    g = sim_cls(sc)
+    g.set_launch(xcd_remap=1)
+    o = _oracle(sc)
+    for k in range(2):
+        g.step(80)
+        o.step(80)
+        where = f"city t={80 * (k + 1)}"
+        assert compare_state(g.state(), o.state(), where) == 0
+        _say(where)
+    cg, svg, err = g.counters()
+    co, svo = o.counters()
+    assert err == 0 and np.array_equal(cg, co)
+    np.testing.assert_allclose(svg, svo, rtol=1e-9)
+    g.close()
+
+
 def test_graph_replay_matches_direct_steps(sim_cls):
     """Steps enqueued through the captured step graphs (16 at a time) give
     the same bits as steps launched one by one, replay after replay."""
