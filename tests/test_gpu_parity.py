@@ -203,6 +203,29 @@ def test_city_snapshot_long_run_bench_launch(sim_cls):
     g.close()
 
 
+def test_batch_full_size_long_run(sim_cls):
+    """The 256-grid batch at full size (3.1M vehicles, departures spread over
+    the run) in a tuned launch shape: insertions through the per-queue-lane
+    rows and counters per scenario, 300 steps, state and counters bit for
+    bit at steps 150 and 300."""
+    sc = S.batch(256)
+    _say("batch 256, 300 steps")
+    g = sim_cls(sc)
+    g.set_launch(xcd_remap=1)
+    o = _oracle(sc)
+    for k in range(2):
+        g.step(150)
+        o.step(150)
+        where = f"batch t={150 * (k + 1)}"
+        assert compare_state(g.state(), o.state(), where) == 0
+        _say(where, g.n_active)
+    cg, svg, err = g.counters()
+    co, svo = o.counters()
+    assert err == 0 and np.array_equal(cg, co)
+    np.testing.assert_allclose(svg, svo, rtol=1e-9)
+    g.close()
+
+
 def test_graph_replay_matches_direct_steps(sim_cls):
     """Steps enqueued through the captured step graphs (16 at a time) give
     the same bits as steps launched one by one, replay after replay."""
