@@ -207,6 +207,10 @@ def main():
     ap.add_argument("--mlp", action="store_true",
                     help="with --profile-only: step the city snapshot with the learned closure")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="with --profile-only: step the batch of grids (--batch-scenarios) "
+                         "instead of the city snapshot; give --warmup 600 to reach the "
+                         "departure period")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape instead of tuning it (profiling runs "
                          "never tune)")
@@ -239,6 +243,20 @@ def main():
         torch.cuda.synchronize()
         say(f"[bench] copy probe: {args.copy_probe} bytes read and written")
         del src, dst
+    if args.profile_only and args.batch:
+        sc = S.batch(args.batch_scenarios)
+        say(f"[bench] batch generated: {sc.summary()}")
+        sim = Simulator(sc)
+        if args.launch:
+            sim.set_launch(**json.loads(args.launch))
+        sim.step(args.warmup)
+        sim.step(args.steps)
+        torch.cuda.synchronize()
+        _, _, err = sim.counters()
+        say(f"[bench] batch: {args.warmup} + {args.steps} steps, {sim.n_active} active, "
+            f"error word {err}")
+        sim.close()
+        return
     say(f"[bench] generating city snapshot with {args.vehicles} vehicles")
     t0 = time.time()
     sc = S.city_snapshot(args.vehicles)
