@@ -95,7 +95,8 @@ struct Layout {
         for (auto &x : ls) x = take(4 * ((size_t)n_lanes + 1));
         tails = take(sizeof(Tail) * (size_t)n_lanes);
         leave = take(4 * (size_t)n_lanes);
-        chunk = take(sizeof(int4) * ((size_t)c / kMergeRows + 3));
+        chunk = take(sizeof(int4) *
+                     ((size_t)c / kMergeRows + (size_t)n_lanes / kMergeLanes + 3));
         jcount = take(4 * (size_t)n_lanes);
         joff = take(4 * ((size_t)n_lanes + 1));
         blk = take(8 * (size_t)nblk);

@@ -102,8 +102,9 @@ struct Dev {
     int32_t *joff;                // exclusive scan of jcount
     int32_t *blk;                 // scan block sums
     // chunk[w] = (first lane, its new start, its old start, its joiner
-    // offset) of merge chunk w: the first lane whose new start is >= w *
-    // kMergeRows (written by the lane-count scan); [cap / kMergeRows + 3]
+    // offset) of merge chunk w: the first lane l with chunk_of(l, new start)
+    // >= w (written by the lane-count scan);
+    // [cap / kMergeRows + n_lanes / kMergeLanes + 3]
     int4 *chunk;
     // joiners (lane changers, road transfers, insertions).  Update tile b
     // (rows [b*kUpdateRows, (b+1)*kUpdateRows)) lists its jcnt[b] joiners in
@@ -157,8 +158,13 @@ struct Dev {
     float *d_margin;
 };
 
-// New rows per merge block.
+// Merge chunks: a boundary every kMergeRows new rows and every kMergeLanes
+// lanes, so that a chunk of a sparse state does not own tens of thousands of
+// empty lanes.  chunk_of(l, s) is the chunk of lane l whose new start is s
+// (the boundaries at or before it; non-decreasing along the lanes).
 constexpr int kMergeRows = 512;
+constexpr int kMergeLanes = 2048;
+__host__ __device__ inline int chunk_of(int l, int s) { return s / kMergeRows + l / kMergeLanes; }
 // Copies of the counters and sums; a wave adds to copy (4 * block + wave)
 // mod kStripes.
 constexpr int kStripes = 64;

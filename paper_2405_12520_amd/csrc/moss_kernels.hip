@@ -899,9 +899,9 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
             d.jcount[l] = 0;
             // red light of the lane's road at the next step
             d.lane_red[l] = lane_red_at(d.lanes[l], tnext) ? 1 : 0;
-            // chunks whose first row lies in (start, end] of lane l begin at
-            // lane l+1: record its lane, new start, old start and joiner offset
-            for (int w = run / kMergeRows + 1; w * kMergeRows <= run + cnt[q]; ++w)
+            // chunks past lane l's and up to lane l+1's begin at lane l+1:
+            // record its lane, new start, old start and joiner offset
+            for (int w = chunk_of(l, run) + 1; w <= chunk_of(l + 1, run + cnt[q]); ++w)
                 d.chunk[w] = make_int4(l + 1, run + cnt[q], d.ls_old[l + 1], runj + jc[q]);
         }
         run += cnt[q];
@@ -914,7 +914,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
         d.joff[d.n_lanes] = runj;
         *d.n_next = run;
         // upper bound of the last chunk (merge blocks past it read nothing)
-        d.chunk[run / kMergeRows + 1] =
+        d.chunk[chunk_of(d.n_lanes, run) + 1] =
             make_int4(d.n_lanes, run, d.ls_old[d.n_lanes], runj);
     }
 }
@@ -1483,8 +1483,8 @@ __device__ __forceinline__ bool group_fits(int new_rows, int old_rows, int joine
     return new_rows <= kNewCap && old_rows <= kOldCap && joiners <= kJCap && lanes < kRelLanes;
 }
 
-// Next state, one chunk of kMC new rows per block.  A block owns the lanes
-// whose first new row falls in its chunk and merges them with merge_group.
+// Next state, one chunk per block: the lanes between two chunk boundaries
+// (every kMC new rows and every kMergeLanes lanes), merged with merge_group.
 // A chunk that does not fit the LDS tile is merged in consecutive groups of
 // whole lanes that do (at most two); the lanes from one that alone exceeds
 // the tile on, or beyond the two groups, take merge_lanes_global.
@@ -1500,11 +1500,13 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     // The chunk of this block when the rows fill the grid (the usual case)
     // is loaded together with the row count, and loaded again only when that
     // guess is wrong; w is uniform, every thread reads the same records.
-    const int wg = min(xcd_tile(d.xcd_remap, (int)gridDim.x), d.cap / kMC + 1);
+    const int wg = min(xcd_tile(d.xcd_remap, (int)gridDim.x),
+                       d.cap / kMC + d.n_lanes / kMergeLanes + 1);
     int4 ca = d.chunk[wg], cb = d.chunk[wg + 1];
     const int n_next = *d.n_next;
-    const int w = xcd_tile(d.xcd_remap, n_next / kMC + 1);
-    if (w > n_next / kMC)
+    const int nch = chunk_of(d.n_lanes, n_next);     // the last chunk
+    const int w = xcd_tile(d.xcd_remap, nch + 1);
+    if (w > nch)
         return;
     if (w != wg) {
         ca = d.chunk[w];
@@ -1678,7 +1680,7 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     if (d.jsc_blocks > 0) gj = (unsigned)d.jsc_blocks;
     hipLaunchKernelGGL(k_jscatter, dim3(gj), dim3(256), 0, st, d);
     mark(5);
-    unsigned gm = (unsigned)(d.cap / kMC + 1);
+    unsigned gm = (unsigned)(d.cap / kMC + d.n_lanes / kMergeLanes + 1);
     if (d.xcd_remap) gm = (gm + 7u) & ~7u;     // chunks past the last one return at once
     hipLaunchKernelGGL(k_merge, dim3(gm), dim3(kMT), 0, st, d);
     mark(6);
