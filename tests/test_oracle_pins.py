@@ -1,10 +1,11 @@
 """Pins of the CPU oracle against facts that do not come from the oracle.
 
-Each test checks the oracle against one of: an independent library
-implementation (rocRAND's Philox), a closed form of the IDM model
-(free-road speed and distance, homogeneous equilibrium, standing queue),
-brute-force search on tiny networks, or invariants that any correct
-simulator of these rules must satisfy.  The model readings themselves are
+Each test checks the oracle against one of: the random generator's
+published known-answer vectors and an independent library implementation
+(rocRAND's Philox), a closed form of the IDM model (free-road speed and
+distance, homogeneous equilibrium, standing queue), brute-force search on
+tiny networks, or invariants that any correct simulator of these rules must
+satisfy.  The model readings themselves are
 listed in the oracle source.
 """
 import math
@@ -50,6 +51,19 @@ def test_philox_matches_rocrand(rocrand_probe):
         ref = [int(x) for x in line.split()]
         got = philox4x32_10(row[:4], row[4:]).tolist()
         assert got == ref
+
+
+def test_philox_known_answers():
+    """Philox4x32-10 reproduces the generator's published known-answer
+    vectors (Salmon et al. SC'11), stored in tests/golden."""
+    rows = []
+    with open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x, 16) for x in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        assert philox4x32_10(r[0:4], r[4:6]).tolist() == r[6:10]
 
 
 def test_philox_uniform_chi2():
