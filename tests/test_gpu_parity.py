@@ -203,6 +203,29 @@ def test_city_snapshot_long_run_bench_launch(sim_cls):
     g.close()
 
 
+def test_city_8M_bench_launch(sim_cls):
+    """The largest city the benchmark times (city network tiled 2 x 2: 8M
+    vehicles on 482k lanes, past the on-die caches) in the benchmark's
+    launch shape: one 16-step graph replay, then 3 direct steps, the whole
+    state and the counters equal to the oracle's bit for bit."""
+    sc = S.city_snapshot(8_000_000, side=400, target_undirected=184_000, hops=24)
+    _say("city 8M, 19 steps in the benchmark's launch shape")
+    g = sim_cls(sc)
+    g.set_launch(xcd_remap=1)
+    o = _oracle(sc)
+    for k in (16, 3):
+        g.step(k)
+        o.step(k)
+        where = f"city8M t={o.t}"
+        assert compare_state(g.state(), o.state(), where) == 0
+        _say(where)
+    cg, svg, err = g.counters()
+    co, svo = o.counters()
+    assert err == 0 and np.array_equal(cg, co)
+    np.testing.assert_allclose(svg, svo, rtol=1e-9)
+    g.close()
+
+
 def test_batch_full_size_long_run(sim_cls):
     """The 256-grid batch at full size (3.1M vehicles, departures spread over
     the run) in a tuned launch shape: insertions through the per-queue-lane
