@@ -130,17 +130,23 @@ def bench_mlp(sc, args):
                               flop_per_eval=MLP_FLOP, kernel_ms=round(upd_ms, 5)))
 
 
-def bench_big(args):
+def big_city():
     """City network tiled 2 x 2 (160k nodes, 482k lanes) with 8M vehicles
     pre-placed: a working set (state + proposals + joiner records, 96 B per
     vehicle) far beyond the 256 MB Infinity Cache, so the kernels' bytes come
     from HBM."""
-    import torch
     from paper_2405_12520_amd import scenarios as S
-    from paper_2405_12520_amd.moss import Simulator
     t0 = time.time()
     sc = S.city_snapshot(8_000_000, side=400, target_undirected=184_000, hops=24)
     say(f"[bench] 8M city generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    return sc
+
+
+def bench_big(args):
+    """Throughput and per-kernel times on the 8M-vehicle city (big_city)."""
+    import torch
+    from paper_2405_12520_amd.moss import Simulator
+    sc = big_city()
     sim = Simulator(sc)
     sim.step(args.warmup)
     ms, dc = timed_steps(sim, args.steps)
@@ -211,6 +217,9 @@ def main():
                     help="with --profile-only: step the batch of grids (--batch-scenarios) "
                          "instead of the city snapshot; give --warmup 600 to reach the "
                          "departure period")
+    ap.add_argument("--big", action="store_true",
+                    help="with --profile-only: step the 8M-vehicle city instead of the "
+                         "2M snapshot")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape instead of tuning it (profiling runs "
                          "never tune)")
@@ -243,9 +252,12 @@ def main():
         torch.cuda.synchronize()
         say(f"[bench] copy probe: {args.copy_probe} bytes read and written")
         del src, dst
-    if args.profile_only and args.batch:
-        sc = S.batch(args.batch_scenarios)
-        say(f"[bench] batch generated: {sc.summary()}")
+    if args.profile_only and (args.batch or args.big):
+        if args.batch:
+            sc = S.batch(args.batch_scenarios)
+            say(f"[bench] batch generated: {sc.summary()}")
+        else:
+            sc = big_city()
         sim = Simulator(sc)
         if args.launch:
             sim.set_launch(**json.loads(args.launch))
@@ -253,9 +265,11 @@ def main():
         sim.step(args.steps)
         torch.cuda.synchronize()
         _, _, err = sim.counters()
-        say(f"[bench] batch: {args.warmup} + {args.steps} steps, {sim.n_active} active, "
+        say(f"[bench] {sc.name}: {args.warmup} + {args.steps} steps, {sim.n_active} active, "
             f"error word {err}")
         sim.close()
+        if err:
+            sys.exit(3)
         return
     say(f"[bench] generating city snapshot with {args.vehicles} vehicles")
     t0 = time.time()

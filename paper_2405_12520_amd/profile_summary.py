@@ -84,6 +84,8 @@ def main():
                                  "SQ_BUSY_CYCLES, SQ_WAIT_INST_ANY, SQ_INSTS_VALU, "
                                  "SQ_INSTS_LDS, SQ_INSTS_SALU, SQ_ACTIVE_INST_VALU")
     ap.add_argument("--sq-command", default="")
+    ap.add_argument("--no-traffic-json", action="store_true",
+                    help="keep traffic.json as it is (a workload other than the benchmark's)")
     args = ap.parse_args()
 
     rows = list(csv.DictReader(open(args.trace)))
@@ -127,8 +129,9 @@ def main():
         rec = dict(source_sha=kernel_sources_sha(), vehicles=args.vehicles,
                    calibration=dict(copy_bytes=args.copy_bytes, fetch_kib=pf, write_kib=pw),
                    kernels=traffic)
-        with open(os.path.join(os.path.dirname(args.out) or ".", "traffic.json"), "w") as fh:
-            json.dump(rec, fh, indent=1)
+        if not args.no_traffic_json:
+            with open(os.path.join(os.path.dirname(args.out) or ".", "traffic.json"), "w") as fh:
+                json.dump(rec, fh, indent=1)
     if args.sq:
         names = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
                  "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU")
