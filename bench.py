@@ -143,11 +143,21 @@ def big_city():
 
 
 def bench_big(args):
-    """Throughput and per-kernel times on the 8M-vehicle city (big_city)."""
+    """Throughput and per-kernel times on the 8M-vehicle city (big_city), in
+    the launch shape the tuner picks for it (unless --no-tune)."""
     import torch
+    from paper_2405_12520_amd import autotune
     from paper_2405_12520_amd.moss import Simulator
     sc = big_city()
+    launch = None
+    if not args.no_tune:
+        t0 = time.time()
+        launch = autotune.tune(lambda: Simulator(sc), sc, args.warmup, log=say)
+        torch.cuda.empty_cache()
+        say(f"[bench] 8M city launch shape {launch['launch']} "
+            f"({'cached' if launch['cached'] else 'searched'} in {time.time() - t0:.1f} s)")
     sim = Simulator(sc)
+    autotune.apply(sim, launch)
     sim.step(args.warmup)
     ms, dc = timed_steps(sim, args.steps)
     veh_steps = int(dc[:, 6].sum())
@@ -164,7 +174,7 @@ def bench_big(args):
     return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
                 ms_per_step=round(ms / args.steps, 5), vehicles=int(sc.n_veh),
                 lanes=int(sc.n_lanes), kernel_ms={k: round(v, 5) for k, v in per.items()},
-                hbm_frac=frac)
+                hbm_frac=frac, launch=launch["launch"] if launch else None)
 
 
 def bench_batch(args):

@@ -205,13 +205,13 @@ def test_city_snapshot_long_run_bench_launch(sim_cls):
 
 def test_city_8M_bench_launch(sim_cls):
     """The largest city the benchmark times (city network tiled 2 x 2: 8M
-    vehicles on 482k lanes, past the on-die caches) in the benchmark's
-    launch shape: one 16-step graph replay, then 3 direct steps, the whole
-    state and the counters equal to the oracle's bit for bit."""
+    vehicles on 482k lanes, past the on-die caches) in the launch shape the
+    tuner picks for it (the default: tiles in index order): one 16-step graph
+    replay, then 3 direct steps, the whole state and the counters equal to
+    the oracle's bit for bit."""
     sc = S.city_snapshot(8_000_000, side=400, target_undirected=184_000, hops=24)
-    _say("city 8M, 19 steps in the benchmark's launch shape")
+    _say("city 8M, 19 steps in the default launch shape")
     g = sim_cls(sc)
-    g.set_launch(xcd_remap=1)
     o = _oracle(sc)
     for k in (16, 3):
         g.step(k)
