@@ -184,6 +184,16 @@ int moss_read_state(moss_sim *h, moss_state_out *out);
  * state).  Any pointer may be NULL. */
 int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *error_word);
 
+/* Ids of the vehicles that have not entered the network yet (host buffer of
+ * capacity entries), lane by lane of their first road, each lane in (depart,
+ * id) order; n receives the count (MOSS_ENOMEM if above capacity, nothing
+ * written).  Together with moss_read_state (rows with cursor and previous
+ * acceleration) and the step index, this is a checkpoint: moss_create with the
+ * rows as placed vehicles, these as pending ones and t0 = that step continues
+ * the run exactly (the inputs of a step are the state and the queues, Sec.
+ * III-A; arrived vehicles leave nothing behind; counters restart at zero). */
+int moss_read_pending(moss_sim *h, int32_t capacity, uint32_t *id, int32_t *n);
+
 /* With MOSS_FLAG_DEBUG: per-vehicle decisions of the most recent step, in the
  * row order of the state that step started from (host pointers, capacity
  * rows, NULL to skip): vehicle id, leader id (0xFFFFFFFF = none), flags

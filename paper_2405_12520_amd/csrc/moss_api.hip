@@ -999,6 +999,39 @@ int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *
     return MOSS_OK;
 }
 
+int moss_read_pending(moss_sim *h, int32_t capacity, uint32_t *id, int32_t *n)
+{
+    g_err.clear();
+    if (!h || !n)
+        return fail(MOSS_EINVAL, "null argument");
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    const int32_t nl = h->lay.n_lanes, np = h->lay.n_pend;
+    *n = 0;
+    if (np == 0)
+        return MOSS_OK;
+    // each lane's queue is q_id[q_head[l] .. q_end[l]); insertion advances the head
+    std::vector<int32_t> head(nl), end(nl);
+    std::vector<uint32_t> qid(np);
+    HIP_TRY(hipMemcpy(head.data(), h->dev.q_head, 4 * (size_t)nl, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(end.data(), h->dev.q_end, 4 * (size_t)nl, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(qid.data(), h->dev.q_id, 4 * (size_t)np, hipMemcpyDeviceToHost));
+    int32_t m = 0;
+    for (int32_t l = 0; l < nl; ++l)
+        m += end[l] - head[l];
+    *n = m;
+    if (m > capacity)
+        return fail(MOSS_ENOMEM, "%d pending vehicles, capacity %d", m, capacity);
+    if (m > 0 && !id)
+        return fail(MOSS_EINVAL, "null id buffer");
+    int32_t k = 0;
+    for (int32_t l = 0; l < nl; ++l)
+        for (int32_t q = head[l]; q < end[l]; ++q)
+            id[k++] = qid[q];
+    return MOSS_OK;
+}
+
 int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leader,
                     int32_t *flags, float *margin, uint32_t *t_leader, uint32_t *t_follower,
                     int32_t *n)

@@ -68,7 +68,7 @@ class moss_launch(C.Structure):
 LAUNCH_FIELDS = tuple(f for f, _ in moss_launch._fields_)
 
 EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state",
-           "moss_read_counters", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
+           "moss_read_counters", "moss_read_pending", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
            "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_adam", "moss_mlp_predict",
            "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
            "moss_read_road_stats", "moss_read_positions", "moss_set_signal_phase",
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     L.moss_step.argtypes = [vp, C.c_int32]
     L.moss_read_state.argtypes = [vp, C.POINTER(moss_state_out)]
     L.moss_read_counters.argtypes = [vp, vp, vp, C.POINTER(C.c_uint32)]
+    L.moss_read_pending.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int32)]
     L.moss_read_debug.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp,
                                   C.POINTER(C.c_int32)]
     L.moss_step_timed.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
@@ -205,6 +206,13 @@ def moss_read_counters(h: int, n_scen: int):
     err = C.c_uint32(0)
     _check(load().moss_read_counters(vp(h), _ptr(cnt), _ptr(sv), C.byref(err)))
     return cnt, sv, int(err.value)
+
+
+def moss_read_pending(h: int, capacity: int) -> np.ndarray:
+    ids = np.empty(max(capacity, 1), np.uint32)
+    n = C.c_int32(0)
+    _check(load().moss_read_pending(vp(h), capacity, _ptr(ids), C.byref(n)))
+    return ids[:n.value].copy()
 
 
 def moss_read_debug(h: int, capacity: int):
@@ -357,6 +365,15 @@ class Simulator:
 
     def counters(self):
         return moss_read_counters(self.h, self.n_scen)
+
+    def pending(self) -> np.ndarray:
+        """Ids of the vehicles still waiting to enter (moss_read_pending)."""
+        return moss_read_pending(self.h, self.cap)
+
+    def checkpoint(self) -> Dict[str, object]:
+        """State rows, pending ids and the next step index: what
+        scenarios.resume needs to continue this run in a new simulator."""
+        return dict(state=self.state(), pending=self.pending(), t=self.t)
 
     def step_timed(self, n: int):
         return moss_step_timed(self.h, n)

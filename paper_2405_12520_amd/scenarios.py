@@ -280,6 +280,49 @@ def with_vehicles(name, net: dict, vehicles: list, params=None) -> Scenario:
                  (placed, lane, s, v, a, cur), params)
 
 
+def resume(sc: Scenario, ckpt: dict) -> Scenario:
+    """The scenario that continues a run of ``sc`` from a checkpoint (a dict
+    with the state rows ``state``, the ids still waiting ``pending`` and the
+    next step ``t``, as Simulator.checkpoint returns it).
+
+    A step reads only the vehicle state and the departure queues (Sec.
+    III-A), so the active rows become placed vehicles (lane, position, speed,
+    previous acceleration, route index), the waiting ones keep their
+    departure step, arrived vehicles are dropped and the first step is ``t``.
+    Counters of the new run start at zero."""
+    st, pend, t = ckpt["state"], np.asarray(ckpt["pending"], np.uint32), int(ckpt["t"])
+    order = np.argsort(sc.veh_id, kind="stable")
+    sorted_id = sc.veh_id[order]
+
+    def rows_of(ids):
+        k = np.searchsorted(sorted_id, ids)
+        if np.any(k >= len(sorted_id)) or np.any(sorted_id[np.minimum(k, len(sorted_id) - 1)] != ids):
+            raise ValueError("checkpoint names a vehicle the scenario does not have")
+        return order[k]
+
+    act = rows_of(np.asarray(st["id"], np.uint32))
+    keep = np.concatenate([act, rows_of(pend)])
+    if len(np.unique(keep)) != len(keep):
+        raise ValueError("a vehicle is both active and pending in the checkpoint")
+    n, na = len(keep), len(act)
+    lens = sc.route_off[keep + 1] - sc.route_off[keep]
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    src = np.repeat(sc.route_off[keep], lens) + (np.arange(off[-1]) - np.repeat(off[:-1], lens))
+    placed = np.zeros(n, np.uint8)
+    placed[:na] = 1
+    lane = np.zeros(n, np.int32)
+    cursor = np.zeros(n, np.int32)
+    s, v, a = (np.zeros(n, np.float32) for _ in range(3))
+    lane[:na] = st["lane"]
+    cursor[:na] = st["cursor"]
+    s[:na], v[:na], a[:na] = st["s"], st["v"], st["a"]
+    return dataclasses.replace(
+        sc, name=f"{sc.name}@{t}", veh_id=sc.veh_id[keep], depart=sc.depart[keep],
+        v0=sc.v0[keep], route_off=off, route_roads=sc.route_roads[src].astype(np.int32),
+        placed=placed, lane=lane, s=s, v=v, a=a, cursor=cursor, params=dict(sc.params, t0=t))
+
+
 # ---------------------------------------------------------------------------
 # grids
 # ---------------------------------------------------------------------------

@@ -226,6 +226,49 @@ def test_city_8M_bench_launch(sim_cls):
     g.close()
 
 
+def test_checkpoint_resume(sim_cls):
+    """Grid with departures over the hour, stopped at step 120: the pending
+    list equals the vehicles that have not entered in the oracle's run (found
+    by collecting every id ever active, step by step), and a new simulator
+    created from the checkpoint runs 120 more steps into the same state as
+    the uninterrupted run and as the oracle resumed from it, bit for bit; its
+    counters are the difference of the original run's."""
+    from oracle import OracleSim
+    sc = S.grid()
+    _say("checkpoint at 120, resume")
+    g = sim_cls(sc)
+    g.step(120)
+    ck = g.checkpoint()
+    assert ck["t"] == 120
+    o = OracleSim(sc)
+    seen = set(sc.veh_id[sc.placed == 1].tolist())
+    for _ in range(120):
+        o.step(1)
+        seen |= set(o.state()["id"].tolist())
+    pend = np.array(sorted(set(sc.veh_id.tolist()) - seen), np.uint32)
+    assert len(pend) > 0
+    assert np.array_equal(np.sort(ck["pending"]), pend)
+    assert compare_state(ck["state"], o.state(), "grid t=120") == 0
+    c1, _, _ = g.counters()
+    g.step(120)
+    c2, _, err = g.counters()
+    full = g.state()
+    g.close()
+    assert err == 0
+    rs = S.resume(sc, ck)
+    b = sim_cls(rs)
+    b.step(120)
+    res = b.state()
+    cb, _, errb = b.counters()
+    b.close()
+    assert errb == 0
+    assert compare_state(res, full, "resumed vs uninterrupted t=240") == 0
+    assert np.array_equal(cb, c2 - c1)
+    r = OracleSim(rs)
+    r.step(120)
+    assert compare_state(res, r.state(), "resumed vs oracle t=240") == 0
+
+
 def test_batch_full_size_long_run(sim_cls):
     """The 256-grid batch at full size (3.1M vehicles, departures spread over
     the run) in a tuned launch shape: insertions through the per-queue-lane
