@@ -191,7 +191,9 @@ int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *
  * acceleration) and the step index, this is a checkpoint: moss_create with the
  * rows as placed vehicles, these as pending ones and t0 = that step continues
  * the run exactly (the inputs of a step are the state and the queues, Sec.
- * III-A; arrived vehicles leave nothing behind; counters restart at zero). */
+ * III-A; arrived vehicles leave nothing behind; counters restart at zero).
+ * Phases held by moss_set_signal_phase and limits set by moss_set_lane_vlim
+ * are not part of it: the caller applies them again to the new simulator. */
 int moss_read_pending(moss_sim *h, int32_t capacity, uint32_t *id, int32_t *n);
 
 /* With MOSS_FLAG_DEBUG: per-vehicle decisions of the most recent step, in the
