@@ -323,6 +323,23 @@ def resume(sc: Scenario, ckpt: dict) -> Scenario:
         placed=placed, lane=lane, s=s, v=v, a=a, cursor=cursor, params=dict(sc.params, t0=t))
 
 
+_CKPT_FIELDS = ("id", "lane", "s", "v", "a", "cursor")
+
+
+def save_checkpoint(path: str, ckpt: dict) -> None:
+    """Writes a checkpoint (resume's input) to an .npz file of plain arrays."""
+    arrays = {f"state_{k}": np.asarray(ckpt["state"][k]) for k in _CKPT_FIELDS}
+    np.savez(path, pending=np.asarray(ckpt["pending"], np.uint32),
+             t=np.int64(ckpt["t"]), **arrays)
+
+
+def load_checkpoint(path: str) -> dict:
+    """Reads a checkpoint written by save_checkpoint (no pickled objects)."""
+    with np.load(path, allow_pickle=False) as z:
+        return dict(state={k: z[f"state_{k}"].copy() for k in _CKPT_FIELDS},
+                    pending=z["pending"].copy(), t=int(z["t"]))
+
+
 # ---------------------------------------------------------------------------
 # grids
 # ---------------------------------------------------------------------------

@@ -69,6 +69,22 @@ def test_resume_mid_run_oracle():
     assert np.array_equal(cr, c2 - c1)
 
 
+def test_checkpoint_file_round_trip(tmp_path):
+    """A checkpoint saved to disk and loaded back resumes into the same run."""
+    sc = S.grid()
+    o, pend = pending_after(sc, 40)
+    ck = dict(state=o.state(), pending=pend, t=o.t)
+    path = str(tmp_path / "ck.npz")
+    S.save_checkpoint(path, ck)
+    back = S.load_checkpoint(path)
+    assert back["t"] == 40 and np.array_equal(back["pending"], pend)
+    _same_state(ck["state"], back["state"])
+    a, b = OracleSim(S.resume(sc, ck)), OracleSim(S.resume(sc, back))
+    a.step(30)
+    b.step(30)
+    _same_state(a.state(), b.state())
+
+
 def test_resume_rejects_unknown_ids():
     sc = S.toy(1, n_placed=10, n_pending=5, horizon=20)
     o = OracleSim(sc)
