@@ -68,7 +68,8 @@ class moss_launch(C.Structure):
 LAUNCH_FIELDS = tuple(f for f, _ in moss_launch._fields_)
 
 EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state",
-           "moss_read_counters", "moss_read_pending", "moss_read_debug", "moss_step_timed", "moss_kernel_name",
+           "moss_read_counters", "moss_read_pending", "moss_read_debug", "moss_step_timed",
+           "moss_kernel_name",
            "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_adam", "moss_mlp_predict",
            "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
            "moss_read_road_stats", "moss_read_positions", "moss_set_signal_phase",

@@ -296,7 +296,8 @@ def resume(sc: Scenario, ckpt: dict) -> Scenario:
 
     def rows_of(ids):
         k = np.searchsorted(sorted_id, ids)
-        if np.any(k >= len(sorted_id)) or np.any(sorted_id[np.minimum(k, len(sorted_id) - 1)] != ids):
+        found = sorted_id[np.minimum(k, len(sorted_id) - 1)] == ids
+        if np.any(k >= len(sorted_id)) or not np.all(found):
             raise ValueError("checkpoint names a vehicle the scenario does not have")
         return order[k]
 
