@@ -241,3 +241,52 @@ def test_mlp_mode_step_parity(torch_dev):
         ev_o = co[0, 7] - (0 if k == 0 else prev_ev)
         assert cg[0, 7] == ev_o and cg[0, 8] == co[0, 8] - (0 if k == 0 else prev_fb)
         prev_ev, prev_fb = co[0, 7], co[0, 8]
+
+
+def test_mlp_mode_city_full_size(torch_dev):
+    """The network-mode workload the benchmark reports (2M-vehicle city, the
+    trained closure weights), one step from the same start on both sides:
+    lanes and route cursors identical for >= 99.9 % of the vehicles,
+    accelerations and positions within 1e-2 at the 99.9th percentile,
+    network evaluations and fallbacks counted identically.
+
+    No per-vehicle maximum is asserted at this size.  Both sides round the
+    hidden activations to bfloat16, but from sums taken in different
+    precision and order (FP32 on the matrix cores, FP64 in the oracle), so
+    an activation within rounding of a bfloat16 tie can land on neighbouring
+    values; with the trained weights one such flip moves the output by a few
+    hundredths.  The per-step test above bounds the maximum on a smaller
+    case."""
+    from paper_2405_12520_amd import closure
+    from paper_2405_12520_amd.moss import Simulator
+    from oracle import OracleSim
+    theta, norm = closure.load(closure.DEFAULT_PATH)
+    sc = S.city_snapshot().with_params(mlp=dict(theta=theta, norm=norm))
+    _say("mlp mode, 2M city, one step")
+    g = Simulator(sc)
+    g.set_launch(xcd_remap=1)
+    g.step(1)
+    gs = g.state()
+    cg, _, err = g.counters()
+    g.close()
+    o = OracleSim(sc)
+    o.step(1)
+    st = o.state()
+    co, _ = o.counters()
+    assert err == 0
+    assert gs["id"].shape == st["id"].shape
+    byid = {int(i): j for j, i in enumerate(st["id"])}
+    idx = np.array([byid.get(int(i), -1) for i in gs["id"]])
+    ok = idx >= 0
+    assert ok.mean() > 0.999
+    same = (gs["lane"][ok] == st["lane"][idx[ok]]) & (gs["cursor"][ok] == st["cursor"][idx[ok]])
+    assert same.mean() > 0.999
+    m = np.flatnonzero(ok)[same]
+    da = np.abs(gs["a"][m] - st["a"][idx[m]])
+    ds = np.abs(gs["s"][m] - st["s"][idx[m]])
+    _say("|da| p99 %.3g p99.9 %.3g p99.99 %.3g max %.3g, above 1e-2: %d of %d; |ds| p99.9 %.3g"
+         % (np.percentile(da, 99), np.percentile(da, 99.9), np.percentile(da, 99.99), da.max(),
+            int((da > 1e-2).sum()), len(da), np.percentile(ds, 99.9)))
+    assert np.percentile(da, 99.9) < 1e-2
+    assert np.percentile(ds, 99.9) < 1e-2
+    assert cg[0, 7] == co[0, 7] and cg[0, 8] == co[0, 8]
