@@ -269,6 +269,29 @@ def test_checkpoint_resume(sim_cls):
     assert compare_state(res, r.state(), "resumed vs oracle t=240") == 0
 
 
+def test_read_pending_capacity(sim_cls):
+    """moss_read_pending refuses a buffer shorter than the pending list
+    (MOSS_ENOMEM, count reported, nothing written), lists everything at the
+    start of a run with departures, and nothing once all vehicles are
+    placed."""
+    import ctypes as C
+    from paper_2405_12520_amd.moss import MOSS_ENOMEM, MossError, load, moss_read_pending
+    sc = S.grid()
+    g = sim_cls(sc)
+    n = C.c_int32(-1)
+    buf = np.full(4, 7, np.uint32)
+    rc = load().moss_read_pending(C.c_void_p(g.h), 3, buf.ctypes.data_as(C.c_void_p),
+                                  C.byref(n))
+    assert rc == MOSS_ENOMEM and n.value == sc.n_veh and np.all(buf == 7)
+    with pytest.raises(MossError):
+        moss_read_pending(g.h, 3)
+    assert np.array_equal(np.sort(g.pending()), np.sort(sc.veh_id))
+    g.close()
+    g = sim_cls(S.city_snapshot(20_000, side=40, target_undirected=1_800, hops=8))
+    assert g.pending().shape == (0,)
+    g.close()
+
+
 def test_batch_full_size_long_run(sim_cls):
     """The 256-grid batch at full size (3.1M vehicles, departures spread over
     the run) in a tuned launch shape: insertions through the per-queue-lane
