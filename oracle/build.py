@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "_build", "liboracle.so")
 SRC = [os.path.join(HERE, "moss_oracle.c")]
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-fno-strict-aliasing", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+          "-fno-strict-aliasing", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 
 def build(verbose: bool = False) -> str:

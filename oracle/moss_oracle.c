@@ -26,6 +26,9 @@
 #include "moss_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -160,6 +163,11 @@ typedef struct {
     int32_t veh;       /* vehicle table index */
     int32_t status;
     int32_t src_lane;  /* lane at step start (-1 for an insertion) */
+    /* per-vehicle contributions to the counters, added up in row order
+     * after the update phase: lane change made, closure use (1 evaluated,
+     * 2 fell back to IDM), squared closure-vs-IDM difference */
+    int32_t changed, mlp;
+    double mlp_e2;
 } prop_t;
 
 struct orc_sim {
@@ -192,6 +200,7 @@ struct orc_sim {
     double *sumv;
     double *mlp_sq;    /* [n_scen] */
     int32_t mode;
+    int32_t threads;   /* OpenMP threads of the update and merge loops */
     float mlp_theta[4801];
     float mlp_norm[32];
     /* decisions of the last step, indexed by slot at step start */
@@ -373,6 +382,7 @@ orc_sim *orc_create(const orc_input *in)
     m->sumv = calloc((size_t)m->n_scen, 8);
     m->mlp_sq = calloc((size_t)m->n_scen, 8);
     m->mode = in->mode;
+    m->threads = 1;
     if (in->mode == 1) {
         memcpy(m->mlp_theta, in->mlp_theta, sizeof m->mlp_theta);
         memcpy(m->mlp_norm, in->mlp_norm, sizeof m->mlp_norm);
@@ -460,6 +470,7 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
     int32_t veh = m->vi[i];
     uint32_t id = m->vid[veh];
     float s = m->s[i], v = m->v[i];
+    out->changed = 0; out->mlp = 0; out->mlp_e2 = 0.0;
     float v0 = m->v0[veh];
     int32_t c = m->cur[i];
     int has_next = c + 1 < m->route_len[veh];
@@ -590,16 +601,15 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
             float xt = (q == 0 || q == 4 || q == 6) ? (float)log(fmax32(f[q], 0.5f)) : f[q];
             z[q] = (xt - mean[q]) * inv[q];
         }
-        size_t sc = (size_t)m->lane_scen[l];
         if (inside) {
             float am = (float)orc_mlp_forward(m->mlp_theta, z);
             am = fmax32(-P->b_max, fmin32(am, P->a_max));
             double e = (double)am - (double)a;
-            m->mlp_sq[sc] += e * e;
-            m->cnt[sc * ORC_N_COUNTERS + ORC_MLP_EVAL]++;
+            out->mlp_e2 = e * e;
+            out->mlp = 1;
             a = am;
         } else {
-            m->cnt[sc * ORC_N_COUNTERS + ORC_MLP_FALLBACK]++;
+            out->mlp = 2;
         }
     }
 
@@ -629,7 +639,7 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
     out->src_lane = l;
     out->status = arrived ? ST_ARRIVE : ((x == l && c2 == c) ? ST_STAY : ST_JOIN);
     if (arrived) m->d_flags[i] |= 16;
-    if (change) m->cnt[(size_t)m->lane_scen[l] * ORC_N_COUNTERS + ORC_LANE_CHANGES]++;
+    out->changed = change;
 }
 
 /* ------------------------------------------------------- prepare phase --- */
@@ -695,9 +705,22 @@ static void one_step(orc_sim *m)
 
     /* --- update phase: every vehicle reads the snapshot --- */
     prop_t *pr = malloc(sizeof(prop_t) * ((size_t)n + 1));
+    /* vehicles are independent (each reads the snapshot and writes its own
+     * proposal and debug row), so the loop may run on several threads */
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(m->threads)
     for (int32_t i = 0; i < n; ++i)
         update_vehicle(m, i, &pr[i]);
     m->dbg_n = n;
+    for (int32_t i = 0; i < n; ++i) {
+        size_t sc = (size_t)m->lane_scen[pr[i].src_lane];
+        if (pr[i].changed) m->cnt[sc * ORC_N_COUNTERS + ORC_LANE_CHANGES]++;
+        if (pr[i].mlp == 1) {
+            m->mlp_sq[sc] += pr[i].mlp_e2;
+            m->cnt[sc * ORC_N_COUNTERS + ORC_MLP_EVAL]++;
+        } else if (pr[i].mlp == 2) {
+            m->cnt[sc * ORC_N_COUNTERS + ORC_MLP_FALLBACK]++;
+        }
+    }
 
     /* --- arrivals --- */
     for (int32_t i = 0; i < n; ++i)
@@ -728,38 +751,51 @@ static void one_step(orc_sim *m)
     int32_t *sl2 = malloc(4 * cap), *vi2 = malloc(4 * cap), *cur2 = malloc(4 * cap);
     float *s2 = malloc(4 * cap), *v2 = malloc(4 * cap), *a2 = malloc(4 * cap);
     prop_t *lanebuf = malloc(sizeof(prop_t) * ((size_t)n + nj + 1));
-    int32_t w = 0, jp = 0;
+    /* each lane's joiners are jn[js[l] .. js[l+1]) (jn is sorted by lane);
+     * its new rows start at ls2[l] = the rows of the lanes before it */
+    int32_t *js = calloc((size_t)Lc + 1, 4);
+    int64_t *clamps = calloc((size_t)Lc + 1, 8);
+    for (int32_t q = 0; q < nj; ++q) js[jn[q].lane + 1]++;
     for (int32_t l = 0; l < Lc; ++l) {
-        ls2[l] = w;
+        int32_t stay = 0;
+        for (int32_t i = m->ls[l]; i < m->ls[l + 1]; ++i) stay += pr[i].status == ST_STAY;
+        js[l + 1] += js[l];
+        ls2[l + 1] = ls2[l] + stay + (js[l + 1] - js[l]);
+    }
+    /* lanes are independent: each merges into its own rows */
+#pragma omp parallel for schedule(dynamic, 256) num_threads(m->threads)
+    for (int32_t l = 0; l < Lc; ++l) {
+        prop_t *buf = lanebuf + ls2[l];
         int32_t nb = 0;
-        int32_t ip = m->ls[l];
-        int32_t jend = jp;
-        while (jend < nj && jn[jend].lane == l) ++jend;
+        int32_t ip = m->ls[l], jp = js[l], jend = js[l + 1];
         for (;;) {
             while (ip < m->ls[l + 1] && pr[ip].status != ST_STAY) ++ip;
             int has_s = ip < m->ls[l + 1];
             int has_j = jp < jend;
             if (!has_s && !has_j) break;
             if (has_s && (!has_j || key_less(m, &pr[ip], &jn[jp])))
-                lanebuf[nb++] = pr[ip++];
+                buf[nb++] = pr[ip++];
             else
-                lanebuf[nb++] = jn[jp++];
+                buf[nb++] = jn[jp++];
         }
         for (int32_t f = nb - 2; f >= 0; --f) {
-            float lim = lanebuf[f + 1].s - P->len;
-            if (lanebuf[f].s > lim) {
-                lanebuf[f].s = lim;
-                lanebuf[f].v = fmin32(lanebuf[f].v, lanebuf[f + 1].v);
-                m->cnt[(size_t)m->lane_scen[l] * ORC_N_COUNTERS + ORC_CLAMPS]++;
+            float lim = buf[f + 1].s - P->len;
+            if (buf[f].s > lim) {
+                buf[f].s = lim;
+                buf[f].v = fmin32(buf[f].v, buf[f + 1].v);
+                clamps[l]++;
             }
         }
         for (int32_t q = 0; q < nb; ++q) {
-            sl2[w] = l; vi2[w] = lanebuf[q].veh; cur2[w] = lanebuf[q].cur;
-            s2[w] = lanebuf[q].s; v2[w] = lanebuf[q].v; a2[w] = lanebuf[q].a;
-            ++w;
+            int32_t w = ls2[l] + q;
+            sl2[w] = l; vi2[w] = buf[q].veh; cur2[w] = buf[q].cur;
+            s2[w] = buf[q].s; v2[w] = buf[q].v; a2[w] = buf[q].a;
         }
     }
-    ls2[Lc] = w;
+    for (int32_t l = 0; l < Lc; ++l)
+        m->cnt[(size_t)m->lane_scen[l] * ORC_N_COUNTERS + ORC_CLAMPS] += clamps[l];
+    int32_t w = ls2[Lc];
+    free(js); free(clamps);
     free(m->ls); free(m->sl); free(m->vi); free(m->cur); free(m->s); free(m->v); free(m->a);
     m->ls = ls2; m->sl = sl2; m->vi = vi2; m->cur = cur2; m->s = s2; m->v = v2; m->a = a2;
     m->n_act = w;
@@ -779,6 +815,17 @@ int orc_step(orc_sim *m, int32_t n)
     for (int32_t k = 0; k < n; ++k)
         one_step(m);
     return 0;
+}
+
+void orc_set_threads(orc_sim *m, int32_t n) { m->threads = n > 0 ? n : 1; }
+
+int32_t orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 int32_t orc_n_active(const orc_sim *m) { return m->n_act; }

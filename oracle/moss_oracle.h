@@ -70,6 +70,12 @@ orc_sim *orc_create(const orc_input *in);
 const char *orc_error(void);
 void orc_destroy(orc_sim *m);
 int orc_step(orc_sim *m, int32_t n);
+/* Threads for the update and merge loops (default 1).  Results are the same
+ * bits for any count: vehicles and lanes are independent within a step and
+ * every sum is taken afterwards in a fixed order. */
+void orc_set_threads(orc_sim *m, int32_t n);
+/* Threads OpenMP would use by default (1 without OpenMP). */
+int32_t orc_max_threads(void);
 int32_t orc_n_active(const orc_sim *m);
 int64_t orc_time(const orc_sim *m);
 /* State in lane order (lane ascending, then position ascending). */

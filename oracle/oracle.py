@@ -43,6 +43,8 @@ def lib():
         L.orc_error.restype = C.c_char_p
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_set_threads.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_max_threads.restype = C.c_int32
         L.orc_n_active.argtypes = [C.c_void_p]
         L.orc_n_active.restype = C.c_int32
         L.orc_time.argtypes = [C.c_void_p]
@@ -145,6 +147,11 @@ class OracleSim:
     def step(self, n: int = 1):
         lib().orc_step(self._h, int(n))
 
+    def set_threads(self, n: int):
+        """OpenMP threads of the update and merge loops (results do not
+        depend on it)."""
+        lib().orc_set_threads(self._h, int(n))
+
     @property
     def n_active(self) -> int:
         return int(lib().orc_n_active(self._h))
@@ -231,3 +238,8 @@ def idm(v, v0e, has_leader, v_lead, gap, a_max=2.0, two_sqrt_ab=None, s0=2.0, T=
         two_sqrt_ab = float(np.float32(2.0 * np.sqrt(a_max * b)))
     return float(lib().orc_idm(v, v0e, int(has_leader), v_lead, gap, a_max, two_sqrt_ab, s0, T,
                                b_max))
+
+
+def max_threads() -> int:
+    """Threads OpenMP uses by default on this host."""
+    return int(lib().orc_max_threads())

@@ -1,0 +1,127 @@
+"""Hand-built toy states whose outcome follows from the model rules alone.
+
+Each builder returns a Scenario (inputs only, no model arithmetic) and the
+expected outcome is stated, computed by hand, in the test that uses it.  The
+oracle pins (tests/test_oracle_rules.py) check the CPU oracle against those
+hand-computed outcomes; the GPU parity tests run the same states through the
+HIP library and compare with the oracle.
+
+The numbers are chosen so that the arithmetic is exact in FP32 where a test
+relies on a tie or a boundary: vehicles at their desired speed on a free road
+have acceleration a_max (1 - 1) = 0 and move exactly v per 1 s step.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from paper_2405_12520_amd import scenarios as S
+
+
+def insertion_behind_tail(s_tail: float, v_tail: float = 4.0, v0: float = 14.0,
+                          lanes: int = 1) -> S.Scenario:
+    """One vehicle already on a 500 m lane at s_tail (speed v_tail) and one
+    vehicle due to enter the same lane at step 0 (desired speed v0, limit
+    16.67 m/s).  Entry speed min(v0, limit, v_tail); the entry needs
+    s_tail - len >= s0 + v_entry * T."""
+    net = S.corridor([500.0, 100.0], lanes)
+    vs = [dict(id=lanes, route=[0, 1], lane=0, s=s_tail, v=v_tail, v0=14.0),
+          dict(id=2 * lanes, route=[0, 1], depart=0, v0=v0)]
+    return S.with_vehicles("ins_gap", net, vs)
+
+
+def empty_lane_insertion(v0: float = 20.0) -> S.Scenario:
+    """A vehicle due at step 0 on an empty lane with limit 16.67 m/s."""
+    net = S.corridor([500.0, 100.0], 1)
+    return S.with_vehicles("ins_empty", net, [dict(id=1, route=[0, 1], depart=0, v0=v0)])
+
+
+def red_approach(s: float, v: float = 15.0, route=(0, 1)) -> S.Scenario:
+    """A vehicle on a 300 m road whose downstream junction never shows its
+    group (permanently red), at position s with speed v."""
+    net = S.corridor([300.0, 100.0], 1, signal=(1, 60, 60, 0, 1))
+    return S.with_vehicles("red_approach", net,
+                           [dict(id=1, route=list(route), lane=0, s=s, v=v, v0=14.0)])
+
+
+def cut_in_behind(s_n: float, b_safe: float = 10.0) -> S.Scenario:
+    """Even step on a two-lane road: vehicle 1 (lane 1, s = 200, v = 10) has a
+    standing leader 20 m ahead; the target lane 0 holds only a standing
+    vehicle 3 at s_n.  Politeness 0, p_lc = 1, b_safe as given."""
+    net = S.corridor([1000.0, 100.0], 2)
+    vs = [dict(id=1, route=[0, 1], lane=1, s=200.0, v=10.0),
+          dict(id=2, route=[0, 1], lane=1, s=220.0, v=0.0, v0=0.5),
+          dict(id=3, route=[0, 1], lane=0, s=s_n, v=0.0, v0=0.5)]
+    return S.with_vehicles("cut_in", net, vs,
+                           params=dict(t0=0, p_lc=1.0, politeness=0.0, b_safe=b_safe))
+
+
+def limits_differ(vlim_target: float, vlim_own: float) -> S.Scenario:
+    """Even step on a two-lane road: vehicle 1 (lane 1, s = 200, v = 10,
+    v0 = 14) follows vehicle 2 (s = 265, v = 10) at a 60 m gap; the target
+    lane 0 is empty.  Lane 0 has limit vlim_target, lane 1 vlim_own."""
+    net = S.corridor([1000.0, 100.0], 2)
+    vs = [dict(id=1, route=[0, 1], lane=1, s=200.0, v=10.0, v0=14.0),
+          dict(id=2, route=[0, 1], lane=1, s=265.0, v=10.0, v0=14.0)]
+    sc = S.with_vehicles("limits", net, vs, params=dict(t0=0, p_lc=1.0))
+    vl = sc.lane_vlim.copy()
+    vl[0], vl[1] = vlim_target, vlim_own
+    return dataclasses.replace(sc, lane_vlim=vl.astype(np.float32))
+
+
+def clamp_fast_follower() -> S.Scenario:
+    """Vehicle 1 at 20 m/s one metre behind the rear of a standing vehicle 2
+    (s = 100, v0 = 0.5) on a 1000 m single lane with limit 30 m/s."""
+    net = S.corridor([1000.0, 100.0], 1, vlim=30.0)
+    vs = [dict(id=1, route=[0, 1], lane=0, s=94.0, v=20.0, v0=20.0),
+          dict(id=2, route=[0, 1], lane=0, s=100.0, v=0.0, v0=0.5)]
+    return S.with_vehicles("clamp", net, vs)
+
+
+def joiners_tie(id_lane0: int, id_lane1: int) -> S.Scenario:
+    """Two vehicles side by side (s = 95, v = v0 = 25) on the two lanes of a
+    100 m road that feeds a one-lane road; no lookahead (h_look = 0), so both
+    are on a free road at their desired speed, move exactly 25 m and enter
+    the next road at exactly s = 20."""
+    net = S.corridor([100.0, 200.0], [2, 1], vlim=30.0)
+    vs = [dict(id=id_lane0, route=[0, 1], lane=0, s=95.0, v=25.0, v0=25.0),
+          dict(id=id_lane1, route=[0, 1], lane=1, s=95.0, v=25.0, v0=25.0)]
+    return S.with_vehicles("join_tie", net, vs, params=dict(h_look=0))
+
+
+def stayer_joiner_tie(id_stayer: int, id_joiner: int) -> S.Scenario:
+    """A vehicle at s = 10 on a one-lane 200 m road (v = v0 = 10, last road of
+    its route) and one at s = 95 on the 100 m road before it (v = v0 = 25);
+    no lookahead.  Both are free at their desired speed: the first stays in
+    its lane at s = 20, the second enters that lane at s = 20."""
+    net = S.corridor([100.0, 200.0], 1, vlim=30.0)
+    vs = [dict(id=id_stayer, route=[1], lane=1, s=10.0, v=10.0, v0=10.0),
+          dict(id=id_joiner, route=[0, 1], lane=0, s=95.0, v=25.0, v0=25.0)]
+    return S.with_vehicles("stay_join_tie", net, vs, params=dict(h_look=0))
+
+
+# every case above as (name, scenario, steps) for the GPU parity test
+def all_cases():
+    f32 = np.float32
+    return [
+        ("ins_exact", insertion_behind_tail(13.0), 3),
+        ("ins_below", insertion_behind_tail(float(np.nextafter(f32(13.0), f32(0.0)))), 3),
+        ("ins_slow_tail", insertion_behind_tail(100.0), 3),
+        ("ins_fast_tail", insertion_behind_tail(100.0, v_tail=15.0), 3),
+        ("ins_two_lanes", insertion_behind_tail(13.0, lanes=2), 3),
+        ("ins_empty", empty_lane_insertion(), 3),
+        ("red_cannot_stop", red_approach(290.0), 4),
+        ("red_boundary", red_approach(287.5), 4),
+        ("red_past_boundary", red_approach(float(np.nextafter(f32(287.5), f32(1e9)))), 4),
+        ("red_last_road", red_approach(200.0, v=10.0, route=(0,)), 20),
+        ("cut_in_gap0", cut_in_behind(195.0), 2),
+        ("cut_in_gap1", cut_in_behind(194.0), 2),
+        ("limit_low_target", limits_differ(8.0, 16.67), 2),
+        ("limit_low_own", limits_differ(16.67, 8.0), 2),
+        ("clamp", clamp_fast_follower(), 3),
+        ("join_tie_12", joiners_tie(1, 2), 2),
+        ("join_tie_21", joiners_tie(2, 1), 2),
+        ("stay_join_tie_12", stayer_joiner_tie(1, 2), 2),
+        ("stay_join_tie_21", stayer_joiner_tie(2, 1), 2),
+    ]

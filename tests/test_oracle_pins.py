@@ -588,3 +588,29 @@ def test_trip_time_counts_from_departure():
             break
     # inserted at the end of its departure step with v = v0, then moves
     assert c[0, 3] == t + 1
+
+
+# ----------------------------------------------------- threaded oracle --
+
+@pytest.mark.parametrize("make", [lambda: S.grid(10, 6000, horizon=300),
+                                  lambda: S.toy(3, n=4, max_lanes=4, n_placed=300,
+                                                n_pending=100, horizon=60,
+                                                length_range=(60.0, 200.0)),
+                                  lambda: S.batch(6, horizon=200, vmin=200, vmax=2000)])
+def test_threads_give_identical_results(make):
+    """The OpenMP mode (vehicles and lanes on several threads, sums taken in
+    a fixed order afterwards) reproduces the single-thread run bit for bit:
+    state, counters and the FP64 speed sums."""
+    sc = make()
+    a, b = OracleSim(sc), OracleSim(sc)
+    b.set_threads(4)
+    for _ in range(6):
+        a.step(50)
+        b.step(50)
+        sa, sb = a.state(), b.state()
+        for f in sa:
+            assert np.array_equal(sa[f].view(np.uint32), sb[f].view(np.uint32)), f
+    ca, sva = a.counters()
+    cb, svb = b.counters()
+    assert np.array_equal(ca, cb)
+    assert np.array_equal(sva.view(np.uint64), svb.view(np.uint64))
