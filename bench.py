@@ -33,6 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # two buffers by step parity instead of being copied); k_merge reads the
 # proposal and the old id/v0 (32 B) and writes the 8-field state (32 B).
 ALGO_BYTES = {"k_update": 28 + 24, "k_merge": 32 + 32}
+# Whole step: the two per-vehicle kernels plus about 40 B per lane for the
+# lane-count scans, lane starts, tails and red flags.
+STEP_LANE_BYTES = 40
 
 
 def say(*a):
@@ -58,18 +61,46 @@ def load_traffic(kernel):
     return None
 
 
-def cpu_baseline(sc, steps):
-    from oracle import OracleSim
-    say(f"[bench] cpu oracle: {steps} steps of the same workload")
-    o = OracleSim(sc)
-    c0 = o.counters()[0][:, 6].sum()
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sc, steps, steps_mt):
+    """The oracle as it stands on the host: one thread over `steps` steps,
+    then all the threads OpenMP is given (OMP_NUM_THREADS) over `steps_mt`
+    further steps of the same run.  The two give the same bits; the
+    multi-thread rate is the reported value."""
+    from oracle import OracleSim, max_threads
+    nthr = max_threads()
+    say(f"[bench] cpu oracle: {steps} steps on 1 thread, {steps_mt} on {nthr}")
     t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    vs = o.counters()[0][:, 6].sum() - c0
-    return dict(value=float(vs / dt), unit="vehicle-steps/s", cores=1, kind="oracle",
-                sample=f"{steps} steps of the {sc.n_veh}-vehicle city snapshot, single thread "
-                       f"({dt:.1f} s)")
+    o = OracleSim(sc)
+    t_create = time.perf_counter() - t0
+
+    def run(k, threads):
+        o.set_threads(threads)
+        c0 = o.counters()[0][:, 6].sum()
+        t0 = time.perf_counter()
+        o.step(k)
+        dt = time.perf_counter() - t0
+        return (o.counters()[0][:, 6].sum() - c0) / dt, dt
+
+    v1, dt1 = run(steps, 1)
+    vn, dtn = run(steps_mt, nthr)
+    say(f"[bench] cpu oracle: 1 thread {v1:.4g}, {nthr} threads {vn:.4g} vehicle-steps/s")
+    return dict(value=float(vn), unit="vehicle-steps/s", cores=int(nthr), kind="oracle",
+                single_thread_value=float(v1), nproc=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0)), cpu_model=cpu_model(),
+                sample=f"the {sc.n_veh}-vehicle city snapshot: {steps} steps on one thread "
+                       f"({dt1:.1f} s), then {steps_mt} steps on {nthr} OpenMP threads "
+                       f"({dtn:.1f} s); create {t_create:.1f} s not timed")
 
 
 MLP_FLOP = 2 * (8 * 64 + 64 * 64 + 64)      # multiply-adds of one evaluation, x2
@@ -215,7 +246,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--vehicles", type=int, default=2_000_000)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="steps of the single-thread oracle baseline")
+    ap.add_argument("--cpu-steps-mt", type=int, default=60,
+                    help="steps of the all-threads oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3)")
@@ -342,6 +376,11 @@ def main():
                     algo_bytes_per_launch=int(algo),
                     traffic_bytes_per_launch=None if traffic is None else int(traffic),
                     kernel_ms_all={k: round(v, 5) for k, v in per_launch.items()})
+    # whole-step fraction: algorithmic bytes of one step over the timed ms per step
+    step_bytes = sum(ALGO_BYTES.values()) * n_act + STEP_LANE_BYTES * sc.n_lanes
+    step_gbs = step_bytes / (ms / args.steps * 1e-3) / 1e9
+    roofline["step"] = dict(algo_bytes=int(step_bytes), achieved=round(step_gbs, 1),
+                            frac=round(step_gbs / HBM_PEAK_GBS, 4))
     say(f"[bench] per-kernel ms: {roofline['kernel_ms_all']}")
     sim.close()
     del sim
@@ -354,7 +393,7 @@ def main():
         extras["batch"] = bench_batch(args)
     if not args.no_big:
         extras["city8M"] = bench_big(args)
-    cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_steps)
+    cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_steps, args.cpu_steps_mt)
     out = dict(metric=METRIC, value=round(value, 1), unit="vehicle-steps/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms / args.steps, 5),
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",

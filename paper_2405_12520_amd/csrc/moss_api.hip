@@ -336,6 +336,27 @@ static hipError_t capture_graph(moss_sim *h, int parity, hipGraphExec_t *out)
     return e;
 }
 
+// Captures the step graphs of both lane-start parities now (capture records
+// the launches without running them), so that the first moss_step that
+// replays one does not pay for capture and instantiation.  A failed capture
+// leaves graphs off: steps are then launched directly.
+static void prepare_graphs(moss_sim *h)
+{
+    if (h->graph_steps <= 0 || !h->graphs_ok || h->stream == nullptr)
+        return;
+    for (int p = 0; p < 2; ++p) {
+        if (h->graph[p])
+            continue;
+        if (capture_graph(h, p, &h->graph[p]) != hipSuccess) {
+            (void)hipGetLastError();
+            h->graph[p] = nullptr;
+            h->graphs_ok = false;
+            drop_graphs(h);
+            return;
+        }
+    }
+}
+
 static void fill_dev(moss_sim *h)
 {
     const Layout &L = h->lay;
@@ -757,6 +778,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
         delete h;
         return fail(MOSS_EDEVICE, "device setup failed: %s", hipGetErrorString(e));
     }
+    prepare_graphs(h);
     *out = h;
     return MOSS_OK;
 }
@@ -819,6 +841,7 @@ int moss_set_launch(moss_sim *h, const moss_launch *cfg)
     h->dev.upd_blocks = cfg->update_blocks;
     h->dev.jsc_blocks = cfg->scatter_blocks;
     h->dev.xcd_remap = cfg->xcd_remap;
+    prepare_graphs(h);
     return MOSS_OK;
 }
 
