@@ -146,6 +146,183 @@ double orc_mlp_forward(const float *theta, const float *z)
     return y;
 }
 
+/* ---------------------------- closure parity: admissible outputs --- *
+ *
+ * The closure rounds its hidden activations to bfloat16.  An evaluation that
+ * sums in FP32 in another order, evaluates GELU to within a few FP32 ulps and
+ * takes the logarithm of a distance input to within one FP32 ulp reaches each
+ * activation before rounding only to within a bounded error.  Where that
+ * interval around this oracle's FP64 value holds a bfloat16 rounding
+ * boundary, both roundings are correct results of the definition.
+ * orc_mlp_candidates lists the network outputs of every such choice (each
+ * limited to [lo, hi] like the simulator's acceleration); the first is the
+ * oracle's own value.  Error model (u = 2^-24):
+ *   - a sum of K exact products plus a bias: (K + 3) u times the sum of the
+ *     magnitudes of its terms (K = 16 bfloat16 halves in layer 1, 64 in
+ *     layer 2), the classical bound for recursive summation, any order;
+ *   - GELU: derivative times the input error, plus (4 |a| + 8) u relative
+ *     for the form x / (1 + 2^a), a = -2 sqrt(2/pi)(x + 0.044715 x^3) log2 e,
+ *     with FP32 constants, exp2 and reciprocal each within one ulp;
+ *   - ln of a distance: any float within two ulps of the exact value, i.e.
+ *     this oracle's rounded value or one of the two floats on either side. */
+
+#define ORC_U32 5.9604644775390625e-08
+
+static double gelu_tol(double x, double ex)
+{
+    const double k0 = 0.7978845608028654, k1 = 0.044715;
+    const double w = k0 * (x + k1 * x * x * x);
+    const double th = tanh(w);
+    const double g = 0.5 * x * (1.0 + th);
+    const double dg = 0.5 * (1.0 + th) + 0.5 * x * (1.0 - th * th) * k0 * (1.0 + 3.0 * k1 * x * x);
+    const double a = fabs(2.0 * w * 1.4426950408889634);
+    return fabs(dg) * ex + (4.0 * a + 8.0) * ORC_U32 * fabs(g);
+}
+
+/* bfloat16 value of g and, if some value within e of g rounds (to float, then
+ * to bfloat16) differently, that other value in *alt; returns 1 then */
+static int bf16_window(double g, double e, double *nom, double *alt)
+{
+    *nom = bf16r((float)g);
+    const double rl = bf16r((float)(g - e)), rh = bf16r((float)(g + e));
+    if (rl != *nom) { *alt = rl; return 1; }
+    if (rh != *nom) { *alt = rh; return 1; }
+    return 0;
+}
+
+typedef struct {
+    double *y;
+    int32_t n, cap;
+    double lo, hi;
+} cand_t;
+
+static void cand_add(cand_t *c, double y)
+{
+    y = y < c->lo ? c->lo : (y > c->hi ? c->hi : y);
+    for (int32_t q = 0; q < c->n; ++q)
+        if (c->y[q] == y) return;
+    if (c->n < c->cap) c->y[c->n++] = y;
+}
+
+/* choices over a layer's tied units: every subset when there are at most 4,
+ * else none and each one alone */
+static int32_t n_choices(int32_t nt) { return nt <= 4 ? (1 << nt) : nt + 1; }
+static int flipped(int32_t nt, int32_t choice, int32_t k)
+{
+    return nt <= 4 ? (choice >> k) & 1 : choice == k + 1;
+}
+
+/* all outputs from one input vector zq (bfloat16 pairs); ties of the first
+ * choice counted in info[0] (layer 1) and info[1] (layer 2), the first tied
+ * unit in info[3] (64 * layer + unit, -1 none) */
+static void mlp_tied_outputs(const float *theta, const double *zq, cand_t *c, int32_t *info)
+{
+    const float *W1 = theta, *b1 = theta + 512, *W2 = theta + 576, *b2 = theta + 4672,
+                *w3 = theta + 4736, *b3 = theta + 4800;
+    double h1n[64], h1a[64], h1[64], h2n[64], h2a[64], h2[64];
+    int32_t t1[64], nt1 = 0;
+    for (int j = 0; j < 64; ++j) {
+        double acc = b1[j], mag = fabs((double)b1[j]);
+        for (int i = 0; i < 8; ++i) {
+            const double w = bf16r(W1[j * 8 + i]);
+            acc += w * zq[i];
+            mag += fabs(w * zq[i]);
+        }
+        const double e = gelu_tol(acc, (16 + 3) * ORC_U32 * mag);
+        if (bf16_window(gelu_d(acc), e, &h1n[j], &h1a[j])) t1[nt1++] = j;
+    }
+    if (info && info[0] < 0) {
+        info[0] = nt1;
+        if (nt1 && info[3] < 0) info[3] = t1[0];
+    }
+    for (int32_t c1 = 0; c1 < n_choices(nt1); ++c1) {
+        memcpy(h1, h1n, sizeof h1);
+        for (int32_t k = 0; k < nt1; ++k)
+            if (flipped(nt1, c1, k)) h1[t1[k]] = h1a[t1[k]];
+        int32_t t2[64], nt2 = 0;
+        for (int j = 0; j < 64; ++j) {
+            double acc = b2[j], mag = fabs((double)b2[j]);
+            for (int i = 0; i < 64; ++i) {
+                const double w = bf16r(W2[j * 64 + i]);
+                acc += w * h1[i];
+                mag += fabs(w * h1[i]);
+            }
+            const double e = gelu_tol(acc, (64 + 3) * ORC_U32 * mag);
+            if (bf16_window(gelu_d(acc), e, &h2n[j], &h2a[j])) t2[nt2++] = j;
+        }
+        if (info && c1 == 0 && info[1] < 0) {
+            info[1] = nt2;
+            if (nt2 && info[3] < 0) info[3] = 64 + t2[0];
+        }
+        for (int32_t c2 = 0; c2 < n_choices(nt2); ++c2) {
+            memcpy(h2, h2n, sizeof h2);
+            for (int32_t k = 0; k < nt2; ++k)
+                if (flipped(nt2, c2, k)) h2[t2[k]] = h2a[t2[k]];
+            double y = b3[0];
+            for (int i = 0; i < 64; ++i) y += bf16r(w3[i]) * h2[i];
+            cand_add(c, y);
+        }
+    }
+}
+
+int32_t orc_mlp_candidates(const float *theta, const float *norm, const float *f, float lo,
+                           float hi, int32_t cap, double *out, int32_t *info)
+{
+    const float *mean = norm, *inv = norm + 8;
+    /* distinct input pairs per input: the five logarithm candidates of a
+     * distance may give up to five */
+    double zc[8][5];
+    int32_t nz[8];
+    for (int q = 0; q < 8; ++q) {
+        nz[q] = 0;
+        const int is_log = q == 0 || q == 4 || q == 6;
+        float xs[5];
+        int nx = 1;
+        if (is_log) {
+            const float c = (float)log(fmax32(f[q], 0.5f));
+            xs[0] = c;
+            xs[1] = nextafterf(c, -INFINITY);
+            xs[2] = nextafterf(c, INFINITY);
+            xs[3] = nextafterf(xs[1], -INFINITY);
+            xs[4] = nextafterf(xs[2], INFINITY);
+            nx = 5;
+        } else {
+            xs[0] = f[q];
+        }
+        for (int k = 0; k < nx; ++k) {
+            const double zq = bf16x2r((xs[k] - mean[q]) * inv[q]);
+            int seen = 0;
+            for (int r = 0; r < nz[q]; ++r) seen |= zc[q][r] == zq;
+            if (!seen) zc[q][nz[q]++] = zq;
+        }
+    }
+    int32_t inf[4] = {-1, -1, 1, -1};
+    for (int q = 0; q < 8; ++q) inf[2] *= nz[q];
+    cand_t c = {out, 0, cap, lo, hi};
+    /* every combination of the inputs' pairs, the oracle's own first */
+    for (int32_t combo = 0; combo < inf[2]; ++combo) {
+        double zq[8];
+        int32_t r = combo;
+        for (int q = 0; q < 8; ++q) {
+            zq[q] = zc[q][r % nz[q]];
+            r /= nz[q];
+        }
+        mlp_tied_outputs(theta, zq, &c, inf);
+    }
+    if (info) memcpy(info, inf, sizeof inf);
+    return c.n;
+}
+
+void orc_mlp_candidates_batch(const float *theta, const float *norm, int32_t n, const float *feat,
+                              float lo, float hi, int32_t cap, double *out, int32_t *n_out,
+                              int32_t *info, int32_t threads)
+{
+#pragma omp parallel for schedule(dynamic, 256) num_threads(threads > 0 ? threads : 1)
+    for (int32_t i = 0; i < n; ++i)
+        n_out[i] = orc_mlp_candidates(theta, norm, feat + (size_t)i * 8, lo, hi, cap,
+                                      out + (size_t)i * cap, info ? info + (size_t)i * 4 : NULL);
+}
+
 /* -------------------------------------------------------------- model --- */
 
 typedef struct {
@@ -208,6 +385,10 @@ struct orc_sim {
     uint32_t *d_id, *d_leader, *d_tl, *d_tf;
     int32_t *d_flags;
     float *d_margin;
+    /* network mode: raw inputs [8] of each vehicle's closure and its use
+     * (1 evaluated, 2 outside the envelope), same order */
+    float *d_feat;
+    int8_t *d_use;
 };
 
 /* copies an input array; size 0 or NULL source yields a zero-filled block */
@@ -234,7 +415,7 @@ static void free_sim(orc_sim *m)
                     m->route_off, m->route_len, m->routes, m->ls, m->sl, m->vi, m->s, m->v,
                     m->a, m->cur, m->q_start, m->q_end, m->q_head, m->q_list, m->cnt, m->sumv, m->mlp_sq,
                     m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin,
-                    m->node_x, m->node_y, m->node_manual};
+                    m->node_x, m->node_y, m->node_manual, m->d_feat, m->d_use};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i)
         free(ptrs[i]);
     free(m);
@@ -386,6 +567,9 @@ orc_sim *orc_create(const orc_input *in)
     if (in->mode == 1) {
         memcpy(m->mlp_theta, in->mlp_theta, sizeof m->mlp_theta);
         memcpy(m->mlp_norm, in->mlp_norm, sizeof m->mlp_norm);
+        size_t capd = (size_t)N + (size_t)Lc + 1;
+        m->d_feat = malloc(4 * 8 * capd);
+        m->d_use = malloc(capd);
     }
     return m;
 }
@@ -601,6 +785,8 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
             float xt = (q == 0 || q == 4 || q == 6) ? (float)log(fmax32(f[q], 0.5f)) : f[q];
             z[q] = (xt - mean[q]) * inv[q];
         }
+        memcpy(m->d_feat + (size_t)i * 8, f, sizeof f);
+        m->d_use[i] = inside ? 1 : 2;
         if (inside) {
             float am = (float)orc_mlp_forward(m->mlp_theta, z);
             am = fmax32(-P->b_max, fmin32(am, P->a_max));
@@ -910,6 +1096,14 @@ int32_t orc_read_debug(const orc_sim *m, uint32_t *id, uint32_t *leader, int32_t
         if (t_leader) t_leader[q] = m->d_tl[q];
         if (t_follower) t_follower[q] = m->d_tf[q];
     }
+    return m->dbg_n;
+}
+
+int32_t orc_read_mlp_inputs(const orc_sim *m, float *feat, int8_t *use)
+{
+    if (m->mode != 1) return 0;
+    if (feat) memcpy(feat, m->d_feat, sizeof(float) * 8 * (size_t)m->dbg_n);
+    if (use) memcpy(use, m->d_use, (size_t)m->dbg_n);
     return m->dbg_n;
 }
 

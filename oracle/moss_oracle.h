@@ -97,6 +97,24 @@ void orc_mlp_sq(const orc_sim *m, double *sum_sq);
  * hidden layer inputs rounded to bfloat16, each input z as the pair
  * bf16(z) + bf16(z - bf16(z))) */
 double orc_mlp_forward(const float *theta, const float *z);
+/* Network mode: the raw closure inputs feat[n][8] of each vehicle of the last
+ * step and their use (1 evaluated, 2 outside the envelope), in the order of
+ * orc_read_debug.  Returns n (0 outside network mode). */
+int32_t orc_read_mlp_inputs(const orc_sim *m, float *feat, int8_t *use);
+/* Every network output an FP32 evaluation of the closure may correctly give
+ * for raw inputs f[8] (normalised with norm[32] as in the step), limited to
+ * [lo, hi]: bfloat16 roundings of hidden activations whose FP32 error
+ * interval holds a rounding boundary are taken both ways, and the logarithm
+ * of a distance may be any float within two ulps.  out[0] is the oracle's own
+ * output.  info[4]: tied units of layer 1 and of layer 2 (with the oracle's
+ * own choices), input combinations, first tied unit (64 * layer + unit, -1).
+ * Returns the number of distinct outputs (at most cap). */
+int32_t orc_mlp_candidates(const float *theta, const float *norm, const float *f, float lo,
+                           float hi, int32_t cap, double *out, int32_t *info);
+/* The same for n input rows (out[n][cap], n_out[n], info[n][4]). */
+void orc_mlp_candidates_batch(const float *theta, const float *norm, int32_t n, const float *feat,
+                              float lo, float hi, int32_t cap, double *out, int32_t *n_out,
+                              int32_t *info, int32_t threads);
 int32_t orc_pending(const orc_sim *m);
 /* Signal control: node shows `phase` from the next step on (-1: its
  * fixed-time plan again).  Returns -1 for a node without a signal. */

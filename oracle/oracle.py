@@ -62,6 +62,14 @@ def lib():
         L.orc_positions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_positions.restype = C.c_int
         L.orc_mlp_sq.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_read_mlp_inputs.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_read_mlp_inputs.restype = C.c_int32
+        L.orc_mlp_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                         C.c_float, C.c_int32, C.c_void_p, C.c_void_p]
+        L.orc_mlp_candidates.restype = C.c_int32
+        L.orc_mlp_candidates_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                               C.c_float, C.c_float, C.c_int32, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_int32]
         L.orc_mlp_forward.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_mlp_forward.restype = C.c_double
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -212,6 +220,15 @@ class OracleSim:
             raise RuntimeError("oracle created without node coordinates")
         return x, y, h
 
+    def mlp_inputs(self):
+        """Network mode: (raw closure inputs [n, 8], use [n]: 1 evaluated, 2
+        outside the envelope) of the last step, in the order of debug()."""
+        n = max(self.n_active, 1) * 4 + 1024
+        f = np.empty((n, 8), np.float32)
+        u = np.empty(n, np.int8)
+        k = lib().orc_read_mlp_inputs(self._h, _p(f), _p(u))
+        return f[:k].copy(), u[:k].copy()
+
     def mlp_sq(self):
         out = np.zeros(self.n_scen, np.float64)
         lib().orc_mlp_sq(self._h, _p(out))
@@ -230,6 +247,25 @@ def mlp_forward(theta, z):
     th = np.ascontiguousarray(theta, dtype=np.float32)
     zz = np.ascontiguousarray(z, dtype=np.float32)
     return float(lib().orc_mlp_forward(_p(th), _p(zz)))
+
+
+def mlp_candidates(theta, norm, feat, lo, hi, cap=64, threads=None):
+    """Every output an FP32 evaluation of the closure may correctly give for
+    each row of raw inputs feat[n, 8], limited to [lo, hi] (oracle
+    orc_mlp_candidates): (outputs [n, cap] with the oracle's own value in
+    column 0, count [n], info [n, 4] = tied units in layers 1 and 2, input
+    combinations, first tied unit)."""
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    nm = np.ascontiguousarray(norm, dtype=np.float32)
+    f = np.ascontiguousarray(feat, dtype=np.float32).reshape(-1, 8)
+    n = f.shape[0]
+    out = np.full((n, cap), np.nan, np.float64)
+    cnt = np.zeros(n, np.int32)
+    info = np.zeros((n, 4), np.int32)
+    lib().orc_mlp_candidates_batch(_p(th), _p(nm), n, _p(f), float(lo), float(hi), int(cap),
+                                   _p(out), _p(cnt), _p(info),
+                                   int(threads if threads else max_threads()))
+    return out, cnt, info
 
 
 def idm(v, v0e, has_leader, v_lead, gap, a_max=2.0, two_sqrt_ab=None, s0=2.0, T=1.5, b=4.5,

@@ -201,16 +201,93 @@ def test_trace_labels_equal_oracle_accelerations(torch_dev):
     g.close()
 
 
+def check_network_step(gs, o, sc, theta, norm, label, list_max=400):
+    """One network-mode step of the GPU (state gs) against the oracle o,
+    which has just run the same step from the same start.  Element by
+    element, for every vehicle:
+
+    - network evaluated: the GPU's acceleration lies within 1e-3 of an
+      output the oracle admits for that vehicle's inputs (its own first;
+      others only where a hidden activation's FP32 error interval holds a
+      bfloat16 rounding boundary, see orc_mlp_candidates).  A vehicle that
+      needs another candidate than the oracle's own is excused and listed
+      with its tie;
+    - IDM (outside the envelope): the acceleration bit for bit;
+    - lane and route cursor identical, except for a vehicle whose own
+      acceleration differs and which crossed a road end on one side only
+      (its position on the far side within the resulting difference);
+    - position and speed within 1e-3 plus the largest acceleration
+      difference in its lane (a clamped follower inherits its leader's).
+    Returns the number of excused vehicles."""
+    from oracle import mlp_candidates
+    st = o.state()
+    dbg = o.debug()
+    f, use = o.mlp_inputs()
+    p = sc.params
+    assert gs["id"].shape == st["id"].shape, label
+    assert np.array_equal(np.sort(gs["id"]), np.sort(st["id"])), label
+    og = np.argsort(gs["id"], kind="stable")
+    oo = np.argsort(st["id"], kind="stable")
+    ids = st["id"][oo]
+    G = {k: gs[k][og] for k in ("lane", "cursor", "s", "v", "a")}
+    O = {k: st[k][oo] for k in ("lane", "cursor", "s", "v", "a")}
+    # the network's use per vehicle, from the oracle's own inputs
+    ev_ids = dbg["id"][use == 1]
+    out, cnt, info = mlp_candidates(theta, norm, f[use == 1], -p["b_max"], p["a_max"])
+    pos = np.searchsorted(ids, ev_ids)
+    assert np.array_equal(ids[pos], ev_ids), label
+    evaluated = np.zeros(len(ids), bool)
+    evaluated[pos] = True
+    ag, ao = G["a"].astype(np.float64), O["a"].astype(np.float64)
+    da = np.abs(ag - ao)
+    # IDM vehicles: bit for bit
+    idm = ~evaluated
+    assert np.array_equal(G["a"][idm].view(np.uint32), O["a"][idm].view(np.uint32)), label
+    # evaluated: within 1e-3 of an admissible output
+    dbest = np.nanmin(np.abs(out - ag[pos][:, None]), axis=1)
+    worst = int(np.argmax(dbest))
+    assert dbest.max() < 1e-3, (label, float(dbest.max()), int(ev_ids[worst]), out[worst, :8],
+                                float(ag[pos][worst]), info[worst])
+    exc = np.flatnonzero(da[pos] >= 1e-3)
+    lines = ["%s: %d of %d evaluated vehicles excused (output of an admissible rounding, not "
+             "the oracle's own; max |da| to the nearest admissible output %.2e)"
+             % (label, len(exc), len(pos), float(dbest.max()))]
+    for k in exc[:list_max]:
+        lines.append("  id %d: |da| %.4f, ties layer1 %d layer2 %d, input pairs %d, first tied "
+                     "unit %s, admissible %s" % (
+                         ev_ids[k], da[pos][k], info[k, 0], info[k, 1], info[k, 2],
+                         ("L%d.%d" % (1 + info[k, 3] // 64, info[k, 3] % 64))
+                         if info[k, 3] >= 0 else "-",
+                         np.round(out[k, :min(cnt[k], 6)], 4).tolist()))
+    print("\n".join(lines), flush=True)
+    # lanes and cursors
+    mis = (G["lane"] != O["lane"]) | (G["cursor"] != O["cursor"])
+    for k in np.flatnonzero(mis):
+        assert da[k] > 0, (label, "lane/cursor differ with identical acceleration", int(ids[k]))
+        far = min(float(G["s"][k]), float(O["s"][k]))
+        assert far <= 0.5 * da[k] * p["dt"] ** 2 + 1e-3, (label, int(ids[k]), far, da[k])
+    # positions and speeds in lanes, with the lane's largest acceleration difference
+    same = ~mis
+    lane = O["lane"][same]
+    mx = np.zeros(int(max(O["lane"].max(), G["lane"].max())) + 1)
+    np.maximum.at(mx, O["lane"], da)
+    bound = 1e-3 + mx[lane] * p["dt"]
+    ds = np.abs(G["s"][same].astype(np.float64) - O["s"][same])
+    dv = np.abs(G["v"][same].astype(np.float64) - O["v"][same])
+    assert (ds <= 0.5 * bound * p["dt"] + 1e-3).all(), (label, float(ds.max()))
+    assert (dv <= bound).all(), (label, float(dv.max()))
+    return len(exc)
+
+
 def test_mlp_mode_step_parity(torch_dev):
     """MLP mode, one step at a time from identical states (re-synchronised
-    from the oracle after each step): accelerations within 1e-2, positions
-    within 1e-2 m, lanes and route cursors identical for >= 99.9 % of the
-    vehicles (a transfer decided at the very end of a road can differ when
-    the two accelerations straddle it), counters of network use identical."""
+    from the oracle after each step), every vehicle checked element by
+    element (check_network_step); counters of network use identical."""
     from paper_2405_12520_amd.moss import Simulator
     from oracle import OracleSim
     base = S.grid_snapshot(10, 8000)
-    sc = base.with_params(mlp=_mlp_cfg())
+    cfg = _mlp_cfg()
+    sc = base.with_params(mlp=cfg)
     o = OracleSim(sc)
     st = o.state()
     _say("mlp mode parity")
@@ -220,23 +297,12 @@ def test_mlp_mode_step_parity(torch_dev):
         g.step(1)
         gs = g.state()
         cg, _, err = g.counters()
-        sq_g = g.mlp_error()
         g.close()
         o.step(1)
-        st = o.state()
         co, _ = o.counters()
         assert err == 0
-        byid = {int(i): j for j, i in enumerate(st["id"])}
-        idx = np.array([byid.get(int(i), -1) for i in gs["id"]])
-        ok = idx >= 0
-        assert ok.mean() > 0.999
-        same_lane = gs["lane"][ok] == st["lane"][idx[ok]]
-        assert same_lane.mean() > 0.999
-        m = np.flatnonzero(ok)[same_lane]
-        da = np.abs(gs["a"][m] - st["a"][idx[m]])
-        ds = np.abs(gs["s"][m] - st["s"][idx[m]])
-        assert da.max() < 1e-2, da.max()
-        assert np.percentile(ds, 99.9) < 1e-2
+        check_network_step(gs, o, sc, cfg["theta"], cfg["norm"], f"grid step {k}")
+        st = o.state()
         # evaluations and fallbacks of this step
         ev_o = co[0, 7] - (0 if k == 0 else prev_ev)
         assert cg[0, 7] == ev_o and cg[0, 8] == co[0, 8] - (0 if k == 0 else prev_fb)
@@ -245,21 +311,17 @@ def test_mlp_mode_step_parity(torch_dev):
 
 def test_mlp_mode_city_full_size(torch_dev):
     """The network-mode workload the benchmark reports (2M-vehicle city, the
-    trained closure weights), one step from the same start on both sides:
-    lanes and route cursors identical for >= 99.9 % of the vehicles,
-    accelerations and positions within 1e-2 at the 99.9th percentile,
-    network evaluations and fallbacks counted identically.
-
-    No per-vehicle maximum is asserted at this size.  Both sides round the
-    hidden activations to bfloat16, but from sums taken in different
-    precision and order (FP32 on the matrix cores, FP64 in the oracle), so
-    an activation within rounding of a bfloat16 tie can land on neighbouring
-    values; with the trained weights one such flip moves the output by a few
-    hundredths.  The per-step test above bounds the maximum on a smaller
-    case."""
+    trained closure weights, the benchmark's launch shape), one step from
+    the same start on both sides, every vehicle checked element by element
+    (check_network_step): accelerations within 1e-3 of an admissible output
+    of the closure's definition, IDM vehicles bit for bit, lanes and cursors
+    identical but for road-end crossings caused by an acceleration
+    difference, network evaluations and fallbacks counted identically.
+    Excused vehicles (another admissible rounding than the oracle's own) are
+    listed with their tie."""
     from paper_2405_12520_amd import closure
     from paper_2405_12520_amd.moss import Simulator
-    from oracle import OracleSim
+    from oracle import OracleSim, max_threads
     theta, norm = closure.load(closure.DEFAULT_PATH)
     sc = S.city_snapshot().with_params(mlp=dict(theta=theta, norm=norm))
     _say("mlp mode, 2M city, one step")
@@ -270,23 +332,10 @@ def test_mlp_mode_city_full_size(torch_dev):
     cg, _, err = g.counters()
     g.close()
     o = OracleSim(sc)
+    o.set_threads(max_threads())
     o.step(1)
-    st = o.state()
     co, _ = o.counters()
     assert err == 0
-    assert gs["id"].shape == st["id"].shape
-    byid = {int(i): j for j, i in enumerate(st["id"])}
-    idx = np.array([byid.get(int(i), -1) for i in gs["id"]])
-    ok = idx >= 0
-    assert ok.mean() > 0.999
-    same = (gs["lane"][ok] == st["lane"][idx[ok]]) & (gs["cursor"][ok] == st["cursor"][idx[ok]])
-    assert same.mean() > 0.999
-    m = np.flatnonzero(ok)[same]
-    da = np.abs(gs["a"][m] - st["a"][idx[m]])
-    ds = np.abs(gs["s"][m] - st["s"][idx[m]])
-    _say("|da| p99 %.3g p99.9 %.3g p99.99 %.3g max %.3g, above 1e-2: %d of %d; |ds| p99.9 %.3g"
-         % (np.percentile(da, 99), np.percentile(da, 99.9), np.percentile(da, 99.99), da.max(),
-            int((da > 1e-2).sum()), len(da), np.percentile(ds, 99.9)))
-    assert np.percentile(da, 99.9) < 1e-2
-    assert np.percentile(ds, 99.9) < 1e-2
+    n_exc = check_network_step(gs, o, sc, theta, norm, "2M city")
+    assert n_exc <= 1e-3 * int(co[0, 7])
     assert cg[0, 7] == co[0, 7] and cg[0, 8] == co[0, 8]
