@@ -240,6 +240,48 @@ def bench_batch(args):
                 launch=rec["launch"], launch_tuned_ms_per_step=rec["ms_per_step"])
 
 
+def bench_demand(args):
+    """The city with its travel demand (2M gravity-model trips over 400 zones,
+    departures over one hour, shortest-path routes), the whole hour (3600
+    steps) in IDM mode and with the learned closure: throughput over the
+    run and its macroscopic outputs (mean speed over all vehicle-steps,
+    trips, mean trip time)."""
+    import torch
+    from paper_2405_12520_amd import closure
+    from paper_2405_12520_amd import scenarios as S
+    from paper_2405_12520_amd.moss import Simulator
+    t0 = time.time()
+    sc = S.city_demand()
+    say(f"[bench] city demand generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    theta, norm = closure.load(closure.DEFAULT_PATH)
+    out = dict(vehicles=int(sc.n_veh), steps=args.demand_steps,
+               departures="uniform over steps 0..3599", zones=400)
+    for mode in ("idm", "mlp"):
+        sim = Simulator(sc if mode == "idm" else sc.with_params(mlp=dict(theta=theta, norm=norm)))
+        sim.set_launch(xcd_remap=1)
+        ms, dc = timed_steps(sim, args.demand_steps)
+        c, sv, err = sim.counters()
+        vs, arrived, ttime = int(c[:, 6].sum()), int(c[:, 2].sum()), int(c[:, 3].sum())
+        r = dict(value=round(vs / (ms / 1e3), 1), unit="vehicle-steps/s",
+                 ms_per_step=round(ms / args.demand_steps, 5), vehicle_steps=vs,
+                 active_end=int(sim.n_active), trips=arrived,
+                 mean_trip_time_s=round(ttime / max(arrived, 1), 2),
+                 mean_speed_mps=round(float(sv.sum()) / max(vs, 1), 4),
+                 insert_failures=int(c[:, 1].sum()), lane_changes=int(c[:, 5].sum()),
+                 error_word=int(err))
+        if mode == "mlp":
+            n_eval, n_fb = int(c[:, 7].sum()), int(c[:, 8].sum())
+            r["rms_accel_error_vs_idm"] = round(float(np.sqrt(sim.mlp_error().sum() /
+                                                              max(n_eval, 1))), 5)
+            r["fallback_rate"] = round(n_fb / max(vs, 1), 5)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        say(f"[bench] city demand {mode}: {r}")
+        out[mode] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +311,9 @@ def main():
                          "never tune)")
     ap.add_argument("--launch", default="", metavar="JSON",
                     help='launch shape to use, e.g. \'{"xcd_remap": 1}\' (fields of moss_launch)')
+    ap.add_argument("--no-demand", action="store_true",
+                    help="skip the city's hour with its travel demand (IDM and closure)")
+    ap.add_argument("--demand-steps", type=int, default=3600)
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 8M-vehicle city (beyond the Infinity Cache)")
     ap.add_argument("--batch-scenarios", type=int, default=256)
@@ -393,6 +438,8 @@ def main():
         extras["batch"] = bench_batch(args)
     if not args.no_big:
         extras["city8M"] = bench_big(args)
+    if not args.no_demand:
+        extras["city_demand"] = bench_demand(args)
     cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_steps, args.cpu_steps_mt)
     out = dict(metric=METRIC, value=round(value, 1), unit="vehicle-steps/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms / args.steps, 5),

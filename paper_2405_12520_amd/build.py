@@ -1,4 +1,5 @@
-"""Compiles libmoss.so for gfx950 with hipcc (in-tree, under _build/).
+"""Compiles libmoss.so for gfx950 with hipcc (in-tree, under _build/), and the
+scenario generator's host helper libscen.so with gcc.
 
 Flags: no FP contraction (the op order is part of the model's definition),
 correctly rounded FP32 divide/sqrt, denormals kept, and packed-FP32
@@ -21,7 +22,32 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
+SCEN_LIB = os.path.join(BUILD, "libscen.so")
+SCEN_SRC = os.path.join(HERE, "csrc", "scen_routes.c")
+
+
+def build_scen(verbose: bool = False) -> str:
+    """Host helper of the scenario generator (shortest-path routes; gcc,
+    OpenMP)."""
+    os.makedirs(BUILD, exist_ok=True)
+    tmp = SCEN_LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-Wall", "-o", tmp,
+           SCEN_SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SCEN_LIB)
+    return SCEN_LIB
+
+
+def ensure_scen() -> str:
+    if not os.path.exists(SCEN_LIB):
+        build_scen()
+    return SCEN_LIB
+
+
 def build(verbose: bool = False) -> str:
+    build_scen(verbose)
     os.makedirs(BUILD, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]

@@ -16,6 +16,8 @@ here is synthetic; the shapes follow the five workloads the project measures:
                     fixed-time signals with random offsets, shortest-path routes;
 * ``city_snapshot`` ~40k-node random planar graph, ~120k lanes, log-normal road
                     lengths (median 150 m), 2M vehicles pre-placed on long routes;
+* ``city_demand``   the same city with 2M gravity-model trips over 400 zones
+                    departing over one hour on shortest paths;
 * ``batch``         256 independent grids (4x4 .. 16x16, 1k..50k vehicles each)
                     joined into one disjoint-union network;
 * ``ring`` / ``toy``  small closed-form and brute-force test cases.
@@ -562,21 +564,11 @@ def _placed_speeds(rng, v0, vlim):
     return (np.minimum(v0, vlim) * rng.uniform(0.3, 1.0, size=v0.shape[0])).astype(np.float32)
 
 
-def city_snapshot(n_veh: int = 2_000_000, *, side: int = 200, target_undirected: int = 46_000,
-                  hops: int = 64, seed: int = NETWORK_SEED, demand_seed: int = DEMAND_SEED,
-                  param_seed: int = PARAM_SEED, params=None) -> Scenario:
-    """City-scale synthetic network with vehicles already on the road.
-
-    ``side`` x ``side`` jittered lattice (40k nodes at side 200); a random
-    spanning tree of the lattice plus random extra lattice links up to
-    ``target_undirected`` links keeps it connected and planar.  Each link is
-    two roads with 1-4 lanes per direction drawn with P = (.80, .12, .05, .03)
-    and a log-normal length (median 150 m, sigma 0.75, clipped to
-    [20, 2000] m).  Nodes of degree >= 3 carry fixed-time signals (60 s cycle,
-    30 s phases, random offsets).  ``n_veh`` vehicles are pre-placed over all
-    lanes in proportion to lane length, each on a ``hops``-road random-walk
-    route so that arrivals stay rare over a timed window.
-    """
+def _city_network(side: int, target_undirected: int, seed: int):
+    """Jittered side x side lattice, random spanning tree plus extra lattice
+    links up to target_undirected, two roads per link with 1-4 lanes per
+    direction (P = .80, .12, .05, .03), log-normal lengths (median 150 m,
+    sigma 0.75, clipped to [20, 2000] m), signals at nodes of degree >= 3."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import minimum_spanning_tree
 
@@ -616,6 +608,27 @@ def city_snapshot(n_veh: int = 2_000_000, *, side: int = 200, target_undirected:
     off = np.where(signalised, rng.integers(0, 60, size=nn), 0).astype(np.int32)
     grp = _heading_groups(node_x, node_y, rf, rt, signalised)
 
+    return node_x, node_y, rf, rt, rl, rn, rv, cyc, ph, off, grp
+
+
+def city_snapshot(n_veh: int = 2_000_000, *, side: int = 200, target_undirected: int = 46_000,
+                  hops: int = 64, seed: int = NETWORK_SEED, demand_seed: int = DEMAND_SEED,
+                  param_seed: int = PARAM_SEED, params=None) -> Scenario:
+    """City-scale synthetic network with vehicles already on the road.
+
+    ``side`` x ``side`` jittered lattice (40k nodes at side 200); a random
+    spanning tree of the lattice plus random extra lattice links up to
+    ``target_undirected`` links keeps it connected and planar.  Each link is
+    two roads with 1-4 lanes per direction drawn with P = (.80, .12, .05, .03)
+    and a log-normal length (median 150 m, sigma 0.75, clipped to
+    [20, 2000] m).  Nodes of degree >= 3 carry fixed-time signals (60 s cycle,
+    30 s phases, random offsets).  ``n_veh`` vehicles are pre-placed over all
+    lanes in proportion to lane length, each on a ``hops``-road random-walk
+    route so that arrivals stay rare over a timed window.
+    """
+    node_x, node_y, rf, rt, rl, rn, rv, cyc, ph, off, grp = _city_network(
+        side, target_undirected, seed)
+    nn = side * side
     lane0, n_lanes, lane_road = _lane_layout(rn)
     rng_d = np.random.default_rng(demand_seed)
     lane_len = rl[lane_road].astype(np.float64)
@@ -631,6 +644,109 @@ def city_snapshot(n_veh: int = 2_000_000, *, side: int = 200, target_undirected:
     return _make("city", node_x, node_y, rf, rt, rl, rn, rv, cyc, ph, off, grp, ids,
                  np.zeros(n, np.int32), v0, roff, rflat, placement, params,
                  meta=dict(seed=seed, demand_seed=demand_seed, side=side))
+
+
+_scen_lib = None
+
+
+def _scen():
+    """ctypes handle of the generator's host helper (shortest-path routes)."""
+    global _scen_lib
+    if _scen_lib is None:
+        import ctypes as C
+        from .build import ensure_scen
+        L = C.CDLL(ensure_scen())
+        vp = C.c_void_p
+        L.scen_next_roads.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp, vp,
+                                      C.c_int32]
+        L.scen_walk_routes.argtypes = [C.c_int32, vp, vp, C.c_int64, vp, vp, vp, C.c_int32, vp,
+                                       vp, vp, C.c_int32]
+        _scen_lib = L
+    return _scen_lib
+
+
+def _routes_to(n_nodes, road_from, road_to, road_length, orig, dest, max_hops, threads=None):
+    """Shortest-path routes (road lists, packed) from orig[i] to dest[i]: one
+    Dijkstra per distinct destination over the reversed road graph (host
+    helper, OpenMP)."""
+    import os
+    p = lambda a: a.ctypes.data_as(__import__("ctypes").c_void_p)   # noqa: E731
+    L = _scen()
+    thr = threads or int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    rf = np.ascontiguousarray(road_from, np.int32)
+    rt = np.ascontiguousarray(road_to, np.int32)
+    rl = np.ascontiguousarray(road_length, np.float32)
+    dests, dk = np.unique(np.asarray(dest, np.int32), return_inverse=True)
+    dests = dests.astype(np.int32)
+    dk = dk.astype(np.int32)
+    org = np.ascontiguousarray(orig, np.int32)
+    nxt = np.empty((dests.shape[0], n_nodes), np.int32)
+    L.scen_next_roads(n_nodes, rf.shape[0], p(rf), p(rt), p(rl), dests.shape[0], p(dests),
+                      p(nxt), thr)
+    n = org.shape[0]
+    ln = np.empty(n, np.int32)
+    if L.scen_walk_routes(n_nodes, p(rt), p(nxt), n, p(org), p(dests), p(dk), max_hops, p(ln),
+                          None, None, thr) != 0:
+        raise ValueError("a trip cannot reach its destination within max_hops roads")
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(ln)
+    flat = np.empty(int(off[-1]), np.int32)
+    L.scen_walk_routes(n_nodes, p(rt), p(nxt), n, p(org), p(dests), p(dk), max_hops, None,
+                       p(off), p(flat), thr)
+    return off, flat
+
+
+def city_demand(n_veh: int = 2_000_000, *, side: int = 200, target_undirected: int = 46_000,
+                horizon: int = 3600, zone_side: int = 20, deterrence: float = 3000.0,
+                dest_per_zone: int = 8, seed: int = NETWORK_SEED,
+                demand_seed: int = DEMAND_SEED, param_seed: int = PARAM_SEED,
+                params=None) -> Scenario:
+    """The city network of city_snapshot with its travel demand: n_veh trips
+    between zone_side x zone_side zones (square blocks of the lattice) drawn
+    from a gravity model -- P(o, d) proportional to m_o m_d exp(-d_od /
+    deterrence), zone mass m = node count, d_od the distance between zone
+    centroids -- departing at uniform steps in [0, horizon) and following
+    shortest paths by length.  A trip starts at a uniform node of its origin
+    zone and ends at one of dest_per_zone fixed nodes of its destination zone
+    (distinct from its start), which bounds the shortest-path work to one
+    tree per such node.  Vehicles wait at the start of their first road until
+    they can enter (no pre-placement)."""
+    node_x, node_y, rf, rt, rl, rn, rv, cyc, ph, off, grp = _city_network(
+        side, target_undirected, seed)
+    nn = side * side
+    rng = np.random.default_rng(demand_seed)
+    blk = side // zone_side
+    ii, jj = np.divmod(np.arange(nn), side)
+    zone = (np.minimum(ii // blk, zone_side - 1) * zone_side +
+            np.minimum(jj // blk, zone_side - 1))
+    nz = zone_side * zone_side
+    mass = np.bincount(zone, minlength=nz).astype(np.float64)
+    cx = np.bincount(zone, weights=node_x, minlength=nz) / mass
+    cy = np.bincount(zone, weights=node_y, minlength=nz) / mass
+    dist = np.hypot(cx[:, None] - cx[None, :], cy[:, None] - cy[None, :])
+    w = mass[:, None] * mass[None, :] * np.exp(-dist / deterrence)
+    pair = rng.choice(nz * nz, size=n_veh, p=(w / w.sum()).ravel())
+    oz, dz = np.divmod(pair, nz)
+    order = np.argsort(zone, kind="stable")
+    zstart = np.zeros(nz + 1, np.int64)
+    zstart[1:] = np.cumsum(np.bincount(zone, minlength=nz))
+    dnodes = np.stack([order[zstart[z] + rng.choice(zstart[z + 1] - zstart[z], dest_per_zone,
+                                                    replace=False)] for z in range(nz)])
+    dest = dnodes[dz, rng.integers(0, dest_per_zone, size=n_veh)].astype(np.int32)
+    orig = order[zstart[oz] + rng.integers(0, zstart[oz + 1] - zstart[oz])].astype(np.int32)
+    same = orig == dest
+    while same.any():
+        k = np.flatnonzero(same)
+        orig[k] = order[zstart[oz[k]] + rng.integers(0, zstart[oz[k] + 1] - zstart[oz[k]])]
+        same = orig == dest
+    depart = np.sort(rng.integers(0, horizon, size=n_veh)).astype(np.int32)
+    roff, rflat = _routes_to(nn, rf, rt, rl, orig, dest, 4 * side)
+    v0 = _desired_speeds(np.random.default_rng(param_seed), n_veh)
+    ids = np.arange(n_veh, dtype=np.uint32)
+    return _make("city_demand", node_x, node_y, rf, rt, rl, rn, rv, cyc, ph, off, grp, ids,
+                 depart, v0, roff, rflat, None, params,
+                 meta=dict(seed=seed, demand_seed=demand_seed, side=side, horizon=horizon,
+                           zones=nz, deterrence=deterrence))
 
 
 def grid_snapshot(n: int, n_veh: int, *, lanes: int = 3, hops: int = 64, seed: int = NETWORK_SEED,
