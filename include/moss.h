@@ -156,11 +156,16 @@ enum {
     MOSS_N_COUNTERS
 };
 
-/* Device bytes needed for these inputs (host-only work). */
+/* Device bytes a simulation of these inputs needs: the road network and the
+ * travel demand, the simulator's two inputs (Sec. III-A, last paragraphs),
+ * plus the per-step index and proposal arrays of the two-phase step.
+ * Validates like moss_create (host-only work, no device call). */
 int moss_query_workspace(const moss_network *net, const moss_signals *sig,
                          const moss_vehicles *veh, const moss_params *prm, size_t *bytes);
 
-/* Validates and copies the inputs into the workspace and returns a handle.
+/* Starts a simulation of a road network and its travel demand (Sec. III-A,
+ * last paragraphs: the inputs of the GPU simulator).  Validates and copies
+ * the inputs into the workspace and returns a handle.
  * Errors: MOSS_EINVAL (inconsistent network, route that is not a chain,
  * overlapping placed vehicles, non-finite or non-positive parameters),
  * MOSS_ENOMEM (ws_bytes too small), MOSS_EDEVICE. */
@@ -168,11 +173,17 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
                 const moss_params *prm, void *d_ws, size_t ws_bytes, void *hip_stream,
                 moss_sim **out);
 
-/* Enqueues n >= 0 steps.  Asynchronous.  MOSS_ESTATE if an earlier read
- * found the device error word set. */
+/* Enqueues n >= 0 steps.  Each step is the paper's iteration (Sec. III-A,
+ * second paragraph): the update phase (every vehicle reads the state the
+ * step started from, finds its leader, takes IDM and randomised-MOBIL
+ * decisions and moves by Newton's equations), then the prepare phase that
+ * orders every lane's vehicles by position for the next step.  Asynchronous.
+ * MOSS_ESTATE if an earlier read found the device error word set. */
 int moss_step(moss_sim *h, int32_t n);
 
-/* Synchronises the stream and copies the requested state rows.  The copies
+/* The per-vehicle output of the simulator after the last step: position and
+ * speed (Sec. III-A, last paragraph), with lane, previous acceleration and
+ * route index.  Synchronises the stream and copies the requested state rows.  The copies
  * run on the simulator's stream and are complete on return; with device
  * destinations the whole device is synchronised first, so that a destination
  * just released by work on another stream is not written early. */
@@ -332,7 +343,9 @@ int moss_read_positions(moss_sim *h, int32_t capacity, int32_t device, double *x
  * (host array double[n_scen]). */
 int moss_read_mlp_error(moss_sim *h, double *sum_sq);
 
-/* Frees host-side resources of the handle (the workspace stays the caller's). */
+/* Ends the simulation started by moss_create: frees host-side resources of
+ * the handle (captured step graphs, host copies of the lane records); the
+ * workspace stays the caller's and may be freed after this returns. */
 int moss_destroy(moss_sim *h);
 
 /* Message of the calling thread's last error ("" if none). */

@@ -268,6 +268,25 @@ int validate(const moss_network *net, const moss_signals *sig, const moss_vehicl
                 return fail(MOSS_EINVAL, "vehicle %d: bad position, speed or acceleration", i);
         }
     }
+    // placed vehicles of one lane must not overlap: a follower's front at
+    // most its leader's front less one vehicle length
+    if (veh->placed) {
+        std::vector<int32_t> pl;
+        for (int32_t i = 0; i < veh->n; ++i)
+            if (veh->placed[i])
+                pl.push_back(i);
+        std::sort(pl.begin(), pl.end(), [&](int32_t x, int32_t y) {
+            if (veh->lane[x] != veh->lane[y]) return veh->lane[x] < veh->lane[y];
+            if (veh->s[x] != veh->s[y]) return veh->s[x] < veh->s[y];
+            return veh->id[x] < veh->id[y];
+        });
+        for (size_t k = 1; k < pl.size(); ++k) {
+            const int32_t f = pl[k - 1], l = pl[k];
+            if (veh->lane[f] == veh->lane[l] && !(veh->s[f] <= veh->s[l] - p.length))
+                return fail(MOSS_EINVAL, "placed vehicles %u and %u overlap", veh->id[f],
+                            veh->id[l]);
+        }
+    }
     return MOSS_OK;
 }
 
@@ -606,8 +625,6 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
         hptr[k] = rstart[i] + (uint32_t)veh->cursor[i];
         hnext[k] = route[hptr[k] + 1];
         ls[veh->lane[i] + 1]++;
-        if (k > 0 && hlane[k - 1] == hlane[k] && !(hs[k - 1] <= hs[k] - p.length))
-            return fail(MOSS_EINVAL, "placed vehicles %u and %u overlap", hid[k - 1], hid[k]);
     }
     for (int32_t l = 0; l < NL; ++l)
         ls[l + 1] += ls[l];

@@ -56,6 +56,7 @@ _arr.keep = []
 
 
 @pytest.mark.parametrize("case", ["route_not_chain", "dup_id", "bad_dt", "p_lc", "overlap_ok",
+                                  "overlap",
                                   "lane_gap", "reserved_id", "empty_route", "nan_v0"])
 def test_validation_errors(case):
     sc = S.toy(3, n_placed=20, n_pending=5)
@@ -87,6 +88,19 @@ def test_validation_errors(case):
         v0 = sc.v0.copy()
         v0[3] = np.nan
         sc.v0 = v0
+    elif case == "overlap":
+        # placed vehicle b given a's route, lane and position, 1 m ahead of
+        # a: less than a vehicle length apart
+        pl = np.flatnonzero(sc.placed)
+        a, b = int(pl[0]), int(pl[1])
+        ra, rb = int(sc.route_off[a]), int(sc.route_off[b])
+        k = int(sc.route_off[a + 1]) - ra
+        assert int(sc.route_off[b + 1]) - rb == k
+        rr, lane, cur, pos = sc.route_roads.copy(), sc.lane.copy(), sc.cursor.copy(), sc.s.copy()
+        rr[rb:rb + k] = rr[ra:ra + k]
+        lane[b], cur[b], pos[b] = lane[a], cur[a], pos[a] + 1.0
+        assert pos[b] < sc.road_length[rr[ra + cur[a]]]
+        sc.route_roads, sc.lane, sc.cursor, sc.s = rr, lane, cur, pos
     elif case == "overlap_ok":
         assert _query(sc) > 0
         return
@@ -94,3 +108,18 @@ def test_validation_errors(case):
         _query(sc)
     assert ei.value.code == moss.MOSS_EINVAL
     assert moss.moss_last_error() != ""
+
+
+def test_create_refuses_a_small_workspace_before_touching_the_device():
+    """MOSS_ENOMEM when the workspace is smaller than moss_query_workspace
+    says; checked on the host, before the pointer is ever used."""
+    sc = S.toy(3, n_placed=20, n_pending=5)
+    net, sig, veh, prm, keep = moss.marshal(sc)
+    need = moss.moss_query_workspace(net, sig, veh, prm)
+    out = C.c_void_p()
+    rc = moss.load().moss_create(C.byref(net), C.byref(sig), C.byref(veh), C.byref(prm),
+                                 C.c_void_p(256), need - 1, None, C.byref(out))
+    assert rc == moss.MOSS_ENOMEM
+    assert "needed" in moss.moss_last_error()
+    assert not out.value
+
