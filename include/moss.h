@@ -288,6 +288,27 @@ int moss_mlp_grad(const float *feat, const float *label, const int32_t *idx, int
                   float out_hi, float *grad, float *loss, void *scratch, size_t scratch_bytes,
                   void *hip_stream);
 
+/* Largest batch moss_mlp_grad_static accepts. */
+#define MOSS_MLP_STATIC_MAX_SAMPLES 8192
+
+/* moss_mlp_grad without a scratch argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training loops, hosts
+ * that forbid hipMalloc): the same kernels and the same result, bit for bit,
+ * as moss_mlp_grad, on a scratch area the library holds as a static device
+ * array of moss_mlp_scratch_bytes(MOSS_MLP_STATIC_MAX_SAMPLES) bytes (about
+ * 9.3 MB), one copy per GPU, kept until the process ends.  It runs on the
+ * current device; the first call on a device looks up that device's copy.
+ * It allocates nothing.  Every call on one GPU shares that GPU's copy: calls
+ * that overlap in time on one GPU (different streams, or threads) race and
+ * must be serialised by the caller; calls in order on one stream are safe.
+ * Nothing needs to start at zero (each call writes every scratch value it
+ * reads).  MOSS_EINVAL for n > MOSS_MLP_STATIC_MAX_SAMPLES (use moss_mlp_grad
+ * with a workspace) and the argument errors of moss_mlp_grad; MOSS_EDEVICE if
+ * the device copy cannot be found. */
+int moss_mlp_grad_static(const float *feat, const float *label, const int32_t *idx, int32_t n,
+                         const float *theta, const float *norm, int32_t bf16, float out_lo,
+                         float out_hi, float *grad, float *loss, void *hip_stream);
+
 /* One Adam step (Kingma & Ba) on theta with moments m, v (all
  * float[MOSS_MLP_PARAMS]); step counts from 1. */
 int moss_mlp_adam(float *theta, float *m, float *v, const float *grad, int32_t step, float lr,

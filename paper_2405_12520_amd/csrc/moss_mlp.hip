@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "../../include/moss.h"
@@ -220,34 +221,27 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *feat, int n, c
 }
 
 
-}  // namespace
-
-extern "C" {
-
-size_t moss_mlp_scratch_bytes(int32_t n)
+// Argument checks shared by both gradient entry points.
+int check_grad_args(const char *who, const float *feat, const float *label, int32_t n,
+                    const float *theta, const float *norm, float out_lo, float out_hi,
+                    const float *grad)
 {
-    const size_t b = n > 0 ? (size_t)n : 1;
-    const size_t nslice = (b + kSlice - 1) / kSlice;
-    return 4 * (b * (kMlpIn + 4 * kMlpH + 2) + nslice * kMlpParams) + 1024;
+    if (n <= 0)
+        return set_error(MOSS_EINVAL, "%s: n = %d, needs at least one sample", who, n);
+    if (!feat || !label || !theta || !norm || !grad)
+        return set_error(MOSS_EINVAL, "%s: null buffer", who);
+    if (!(out_lo < out_hi))
+        return set_error(MOSS_EINVAL, "%s: out_lo %g not below out_hi %g", who, out_lo, out_hi);
+    return MOSS_OK;
 }
 
-int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_idx, int32_t n,
-                  const float *d_theta, const float *d_norm, int32_t bf16, float out_lo,
-                  float out_hi, float *d_grad, float *d_loss, void *d_scratch,
-                  size_t scratch_bytes, void *stream)
+// The gradient's three kernels on a scratch area of at least
+// moss_mlp_scratch_bytes(n) bytes.  Every scratch element the kernels read is
+// written earlier in the same call, so the area needs no clearing.
+int launch_grad(const float *d_feat, const float *d_label, const int32_t *d_idx, int32_t n,
+                const float *d_theta, const float *d_norm, int32_t bf16, float out_lo,
+                float out_hi, float *d_grad, float *d_loss, void *d_scratch, hipStream_t st)
 {
-    clear_error();
-    if (n <= 0)
-        return set_error(MOSS_EINVAL, "moss_mlp_grad: n = %d, needs at least one sample", n);
-    if (!d_feat || !d_label || !d_theta || !d_norm || !d_grad || !d_scratch)
-        return set_error(MOSS_EINVAL, "moss_mlp_grad: null buffer");
-    if (!(out_lo < out_hi))
-        return set_error(MOSS_EINVAL, "moss_mlp_grad: out_lo %g not below out_hi %g", out_lo,
-                         out_hi);
-    if (scratch_bytes < moss_mlp_scratch_bytes(n))
-        return set_error(MOSS_ENOMEM, "moss_mlp_grad: scratch of %zu bytes, needs %zu",
-                         scratch_bytes, moss_mlp_scratch_bytes(n));
-    hipStream_t st = (hipStream_t)stream;
     const size_t b = (size_t)n;
     const int nslice = (n + kSlice - 1) / kSlice;
     Scratch sc;
@@ -278,6 +272,99 @@ int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_id
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MOSS_OK
                            : set_error(MOSS_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+}
+
+}  // namespace
+
+// Scratch of moss_mlp_grad_static: room for MOSS_MLP_STATIC_MAX_SAMPLES
+// samples (about 9 MB), one copy per GPU, held until the process ends.
+constexpr size_t kStaticSlices = (MOSS_MLP_STATIC_MAX_SAMPLES + kSlice - 1) / kSlice;
+constexpr size_t kStaticScratchBytes =
+    4 * ((size_t)MOSS_MLP_STATIC_MAX_SAMPLES * (kMlpIn + 4 * kMlpH + 2) +
+         kStaticSlices * kMlpParams) + 1024;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// (with that device current).  In host code the array's name is not a device
+// address; only the pointer returned here may be passed to kernels.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return set_error(MOSS_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(MOSS_EDEVICE, "device %d beyond the %d the library tracks", dev,
+                         kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(MOSS_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MOSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t moss_mlp_scratch_bytes(int32_t n)
+{
+    const size_t b = n > 0 ? (size_t)n : 1;
+    const size_t nslice = (b + kSlice - 1) / kSlice;
+    return 4 * (b * (kMlpIn + 4 * kMlpH + 2) + nslice * kMlpParams) + 1024;
+}
+
+int moss_mlp_grad(const float *d_feat, const float *d_label, const int32_t *d_idx, int32_t n,
+                  const float *d_theta, const float *d_norm, int32_t bf16, float out_lo,
+                  float out_hi, float *d_grad, float *d_loss, void *d_scratch,
+                  size_t scratch_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_grad_args("moss_mlp_grad", d_feat, d_label, n, d_theta, d_norm, out_lo,
+                             out_hi, d_grad);
+    if (rc)
+        return rc;
+    if (!d_scratch)
+        return set_error(MOSS_EINVAL, "moss_mlp_grad: null buffer");
+    if (scratch_bytes < moss_mlp_scratch_bytes(n))
+        return set_error(MOSS_ENOMEM, "moss_mlp_grad: scratch of %zu bytes, needs %zu",
+                         scratch_bytes, moss_mlp_scratch_bytes(n));
+    return launch_grad(d_feat, d_label, d_idx, n, d_theta, d_norm, bf16, out_lo, out_hi, d_grad,
+                       d_loss, d_scratch, (hipStream_t)stream);
+}
+
+int moss_mlp_grad_static(const float *d_feat, const float *d_label, const int32_t *d_idx,
+                         int32_t n, const float *d_theta, const float *d_norm, int32_t bf16,
+                         float out_lo, float out_hi, float *d_grad, float *d_loss, void *stream)
+{
+    clear_error();
+    int rc = check_grad_args("moss_mlp_grad_static", d_feat, d_label, n, d_theta, d_norm,
+                             out_lo, out_hi, d_grad);
+    if (rc)
+        return rc;
+    if (n > MOSS_MLP_STATIC_MAX_SAMPLES)
+        return set_error(MOSS_EINVAL,
+                         "moss_mlp_grad_static: %d samples, at most %d (the size of the "
+                         "library's static scratch); use moss_mlp_grad with a workspace",
+                         n, MOSS_MLP_STATIC_MAX_SAMPLES);
+    void *ptr = nullptr;
+    rc = static_scratch(&ptr);
+    if (rc)
+        return rc;
+    return launch_grad(d_feat, d_label, d_idx, n, d_theta, d_norm, bf16, out_lo, out_hi, d_grad,
+                       d_loss, ptr, (hipStream_t)stream);
 }
 
 int moss_mlp_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int32_t step,

@@ -21,6 +21,7 @@ MOSS_FLAG_DEBUG = 1
 MOSS_FLAG_TRACE = 2
 MOSS_MODE_IDM, MOSS_MODE_MLP = 0, 1
 MLP_PARAMS, MLP_NORM = 4801, 32
+MLP_STATIC_MAX_SAMPLES = 8192       # MOSS_MLP_STATIC_MAX_SAMPLES
 COUNTER_NAMES = ("inserted", "insert_fail", "arrived", "trip_time", "clamps", "lane_changes",
                  "veh_steps", "mlp_eval", "mlp_fallback")
 NONE = 0xFFFFFFFF
@@ -70,7 +71,7 @@ LAUNCH_FIELDS = tuple(f for f, _ in moss_launch._fields_)
 EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state",
            "moss_read_counters", "moss_read_pending", "moss_read_debug", "moss_step_timed",
            "moss_kernel_name",
-           "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_adam", "moss_mlp_predict",
+           "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_grad_static", "moss_mlp_adam", "moss_mlp_predict",
            "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
            "moss_read_road_stats", "moss_read_positions", "moss_set_signal_phase",
            "moss_set_lane_vlim",
@@ -110,6 +111,8 @@ def load(path: str = LIB_PATH):
     L.moss_mlp_scratch_bytes.argtypes = [C.c_int32]
     L.moss_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, vp, C.c_int32, C.c_float, C.c_float,
                                 vp, vp, vp, C.c_size_t, vp]
+    L.moss_mlp_grad_static.argtypes = [vp, vp, vp, C.c_int32, vp, vp, C.c_int32, C.c_float,
+                                       C.c_float, vp, vp, vp]
     L.moss_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
                                 C.c_float, vp]
     L.moss_mlp_predict.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
@@ -263,6 +266,20 @@ def mlp_grad(feat, label, theta, norm, *, idx=None, bf16=True, out_lo=-1e30, out
     _check(load().moss_mlp_grad(_dp(feat), _dp(label), _dp(idx), n, _dp(theta), _dp(norm),
                                 1 if bf16 else 0, out_lo, out_hi, _dp(grad), _dp(loss),
                                 _dp(scratch), nb, vp(st)))
+    return loss, grad
+
+
+def mlp_grad_static(feat, label, theta, norm, grad, loss, *, idx=None, bf16=True,
+                    out_lo=-1e30, out_hi=1e30, stream=None):
+    """mlp_grad through the entry point that allocates nothing: the caller
+    passes the outputs grad (float32[MLP_PARAMS]) and loss (float32[1]); the
+    library's static scratch holds the intermediates."""
+    import torch
+    n = int(idx.shape[0]) if idx is not None else int(feat.shape[0])
+    st = (stream or torch.cuda.current_stream(feat.device)).cuda_stream
+    _check(load().moss_mlp_grad_static(_dp(feat), _dp(label), _dp(idx), n, _dp(theta),
+                                       _dp(norm), 1 if bf16 else 0, out_lo, out_hi, _dp(grad),
+                                       _dp(loss), vp(st)))
     return loss, grad
 
 

@@ -123,3 +123,13 @@ def test_create_refuses_a_small_workspace_before_touching_the_device():
     assert "needed" in moss.moss_last_error()
     assert not out.value
 
+
+def test_static_gradient_refuses_a_batch_beyond_its_scratch():
+    """moss_mlp_grad_static checks the batch size against its static scratch
+    on the host, before any device work."""
+    L = moss.load()
+    fake = C.c_void_p(256)
+    n = moss.MLP_STATIC_MAX_SAMPLES + 1
+    rc = L.moss_mlp_grad_static(fake, fake, None, n, fake, fake, 1, -9.0, 2.0, fake, None, None)
+    assert rc == moss.MOSS_EINVAL
+    assert "at most %d" % moss.MLP_STATIC_MAX_SAMPLES in moss.moss_last_error()
