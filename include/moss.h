@@ -337,9 +337,22 @@ int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, 
  * the last phase given.
  *
  * moss_set_lane_vlim: speed limits (m/s, finite, > 0) of n lanes; a lane
- * named twice takes the last value.  Host arrays for both. */
+ * named twice takes the last value.
+ *
+ * moss_set_lane_closed: lane restrictions (Sec. III-C-4): closed[i] != 0
+ * closes lane[i], 0 opens it (a lane named twice takes the last value).  A
+ * closed lane admits no vehicle: it is never a lane-change target, a vehicle
+ * entering its road (or looking ahead along its route) takes the open lane
+ * nearest to the lane index it would take, the lower of two equally near,
+ * and its departure queue waits (counted as insertion failures); vehicles
+ * already on it carry on and may leave it.  MOSS_EINVAL, changing nothing,
+ * for a lane out of range, a road of more than 32 lanes, or a batch that
+ * would leave a road without an open lane.
+ *
+ * Host arrays for all three. */
 int moss_set_signal_phase(moss_sim *h, const int32_t *node, const int32_t *phase, int32_t n);
 int moss_set_lane_vlim(moss_sim *h, const int32_t *lane, const float *vlim, int32_t n);
+int moss_set_lane_closed(moss_sim *h, const int32_t *lane, const int32_t *closed, int32_t n);
 
 /* Road measures of the current state (the simulator's road outputs, Sec.
  * III-A: average speed per road): count[r] vehicles on road r (all lanes) and
@@ -359,6 +372,21 @@ int moss_read_road_stats(moss_sim *h, int32_t device, int32_t *count, float *mea
  * device pointers per the device flag; *n receives the row count. */
 int moss_read_positions(moss_sim *h, int32_t capacity, int32_t device, double *x, double *y,
                         double *heading, int32_t *n);
+
+/* Travel time and distance of every vehicle (the paper's query APIs for
+ * traffic participants, Sec. III-C-4), in ascending id order: id, status (0
+ * waiting to depart, 1 on the network, 2 arrived), travel time in steps
+ * (arrival step - depart once arrived; the index of the next step - depart
+ * on the network; 0 while waiting) and distance in metres along the route
+ * since the vehicle entered the simulation (the whole route once arrived; the
+ * roads before its current one plus its position while on the network; for a
+ * vehicle placed at creation, less the route distance of its placement; 0
+ * while waiting), road lengths summed in FP64 in route order.  Arrays of
+ * capacity >= the number of vehicles given at creation (*n receives it;
+ * MOSS_ENOMEM if larger, nothing written), host or device pointers per the
+ * device flag; any array may be NULL.  Synchronises like moss_read_state. */
+int moss_read_trips(moss_sim *h, int32_t capacity, int32_t device, uint32_t *id,
+                    int32_t *status, int32_t *travel_time, double *distance, int32_t *n);
 
 /* Sum over the network's evaluations of (a_network - a_IDM)^2, per scenario
  * (host array double[n_scen]). */

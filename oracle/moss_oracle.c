@@ -328,6 +328,7 @@ void orc_mlp_candidates_batch(const float *theta, const float *norm, int32_t n, 
 typedef struct {
     float dt, a_max, b, s0, T, len, b_max, b_safe, p, a_thr, p_lc, d_look;
     float two_sqrt_ab;     /* fl32(2*sqrt(a_max*b)), formed in double */
+    float b_mand, tau_yield;
     int32_t h_look;
     uint32_t key0, key1;
 } params_t;
@@ -356,6 +357,10 @@ struct orc_sim {
     double *node_x, *node_y;          /* NULL without coordinates */
     int32_t *node_cycle, *node_phase, *node_offset;
     int32_t *node_manual;             /* phase held by control, -1: fixed-time plan */
+    uint8_t *lane_closed;             /* lane restriction by control: 1 closed */
+    /* junction internal lanes (NULL without) */
+    uint8_t *road_internal;
+    int32_t *succ_off, *succ, *conf_off, *conf, *conf_feed;
     int8_t *road_group;
     uint32_t *vid;
     int32_t *depart;
@@ -363,6 +368,12 @@ struct orc_sim {
     int64_t *route_off;
     int32_t *route_len;
     int32_t *routes;
+    /* trips: arrival step (-1 before arrival) and the route distance at which
+     * each vehicle entered the simulation (road lengths before its starting
+     * road plus its starting position; 0 for a vehicle inserted at a route
+     * start) */
+    int64_t *arr;
+    double *dist0;
     /* active state, lane order */
     int32_t n_act;
     int32_t *ls;       /* lane segment starts, n_lanes+1 */
@@ -415,7 +426,9 @@ static void free_sim(orc_sim *m)
                     m->route_off, m->route_len, m->routes, m->ls, m->sl, m->vi, m->s, m->v,
                     m->a, m->cur, m->q_start, m->q_end, m->q_head, m->q_list, m->cnt, m->sumv, m->mlp_sq,
                     m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin,
-                    m->node_x, m->node_y, m->node_manual, m->d_feat, m->d_use};
+                    m->node_x, m->node_y, m->node_manual, m->d_feat, m->d_use, m->arr,
+                    m->dist0, m->lane_closed, m->road_internal, m->succ_off, m->succ,
+                    m->conf_off, m->conf, m->conf_feed};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i)
         free(ptrs[i]);
     free(m);
@@ -445,6 +458,35 @@ static int cmp_pend(const void *x, const void *y)
     return p->id < q->id ? -1 : (p->id > q->id);
 }
 
+static int permits(const orc_sim *m, int32_t x, int32_t rd);
+
+/* Origin lane of a pending vehicle i (see the departure queues in orc_create). */
+static int32_t origin_lane(const orc_sim *m, int32_t i)
+{
+    const int32_t r0 = m->routes[m->route_off[i]], l0 = m->road_lane0[r0];
+    const int32_t n = m->road_nlanes[r0];
+    int32_t ok[256], cnt = 0;
+    if (m->route_len[i] > 1) {
+        const int32_t r1 = m->routes[m->route_off[i] + 1];
+        for (int32_t k = 0; k < n; ++k)
+            if (permits(m, l0 + k, r1))
+                ok[cnt++] = l0 + k;
+    }
+    if (cnt == 0)
+        return l0 + (int32_t)(m->vid[i] % (uint32_t)n);
+    return ok[m->vid[i] % (uint32_t)cnt];
+}
+
+/* Length of the first c roads of vehicle i's route, summed in FP64 in route
+ * order. */
+static double route_dist(const orc_sim *m, int32_t i, int32_t c)
+{
+    double d = 0.0;
+    for (int32_t k = 0; k < c; ++k)
+        d += (double)m->road_length[m->routes[m->route_off[i] + k]];
+    return d;
+}
+
 orc_sim *orc_create(const orc_input *in)
 {
     orc_sim *m = calloc(1, sizeof *m);
@@ -463,6 +505,15 @@ orc_sim *orc_create(const orc_input *in)
     if (in->node_x && in->node_y) {
         m->node_x = dup_arr(in->node_x, m->n_nodes, 8);
         m->node_y = dup_arr(in->node_y, m->n_nodes, 8);
+    }
+    m->lane_closed = calloc((size_t)Lc + 1, 1);
+    if (in->lane_succ_off) {
+        m->road_internal = dup_arr(in->road_internal, R, 1);
+        m->succ_off = dup_arr(in->lane_succ_off, (size_t)Lc + 1, 4);
+        m->succ = dup_arr(in->lane_succ, (size_t)m->succ_off[Lc], 4);
+        m->conf_off = dup_arr(in->lane_conf_off, (size_t)Lc + 1, 4);
+        m->conf = dup_arr(in->lane_conf, (size_t)m->conf_off[Lc], 4);
+        m->conf_feed = dup_arr(in->lane_conf_feed, (size_t)m->conf_off[Lc], 4);
     }
     m->node_manual = malloc(sizeof(int32_t) * ((size_t)m->n_nodes + 1));
     for (int32_t j = 0; j < m->n_nodes; ++j)
@@ -487,11 +538,16 @@ orc_sim *orc_create(const orc_input *in)
         }
     for (int32_t i = 0; i < N; ++i)
         m->route_len[i] = (int32_t)(m->route_off[i + 1] - m->route_off[i]);
+    m->arr = malloc(sizeof(int64_t) * (N ? N : 1));
+    m->dist0 = calloc(N ? N : 1, sizeof(double));
+    for (int32_t i = 0; i < N; ++i)
+        m->arr[i] = -1;
 
     params_t *P = &m->P;
     P->dt = in->dt; P->a_max = in->a_max; P->b = in->b; P->s0 = in->s0; P->T = in->T;
     P->len = in->length; P->b_max = in->b_max; P->b_safe = in->b_safe; P->p = in->politeness;
     P->a_thr = in->a_thr; P->p_lc = in->p_lc; P->d_look = in->d_look; P->h_look = in->h_look;
+    P->b_mand = in->b_mand; P->tau_yield = in->tau_yield;
     P->two_sqrt_ab = (float)(2.0 * sqrt((double)in->a_max * (double)in->b));
     P->key0 = (uint32_t)(in->seed & 0xFFFFFFFFu);
     P->key1 = (uint32_t)(in->seed >> 32);
@@ -532,17 +588,22 @@ orc_sim *orc_create(const orc_input *in)
     for (int32_t l = 0; l < Lc; ++l)
         m->ls[l + 1] += m->ls[l];
     m->n_act = n_pl;
+    for (int32_t k = 0; k < n_pl; ++k) {
+        int32_t i = m->vi[k];
+        m->dist0[i] = route_dist(m, i, m->cur[k]) + (double)m->s[k];
+    }
     free(pl);
 
-    /* pending vehicles queue on the origin lane of their first road, lane
-     * index id mod (lanes of that road) [reading], in (depart, id) order */
+    /* pending vehicles queue on an origin lane of their first road [reading]:
+     * among the lanes of that road that continue along the route (all of them
+     * without junction lanes, or for a one-road route), the one of index id
+     * mod their number; in (depart, id) order */
     int32_t n_pe = N - n_pl;
     pend_t *pe = malloc(sizeof(pend_t) * (n_pe ? n_pe : 1));
     j = 0;
     for (int32_t i = 0; i < N; ++i)
         if (!(in->placed && in->placed[i])) {
-            int32_t r0 = m->routes[m->route_off[i]];
-            pe[j].lane = m->road_lane0[r0] + (int32_t)(m->vid[i] % (uint32_t)m->road_nlanes[r0]);
+            pe[j].lane = origin_lane(m, i);
             pe[j].depart = m->depart[i]; pe[j].id = m->vid[i]; pe[j].veh = i; ++j;
         }
     qsort(pe, n_pe, sizeof(pend_t), cmp_pend);
@@ -595,18 +656,70 @@ static int red_for(const orc_sim *m, int32_t road, int64_t t)
     return ph != g;
 }
 
+/* Lane index taken on road rd by a vehicle coming from lane index k
+ * [reading]: min(k, lanes-1); when control has closed that lane, the open
+ * lane nearest to it, the lower one of two equally near (a road always keeps
+ * an open lane). */
+static int32_t pick_lane(const orc_sim *m, int32_t rd, int32_t k)
+{
+    const int32_t n = m->road_nlanes[rd], l0 = m->road_lane0[rd];
+    int32_t kk = k > n - 1 ? n - 1 : k;
+    if (!m->lane_closed[l0 + kk])
+        return kk;
+    for (int32_t dd = 1; dd < n; ++dd) {
+        if (kk - dd >= 0 && !m->lane_closed[l0 + kk - dd])
+            return kk - dd;
+        if (kk + dd < n && !m->lane_closed[l0 + kk + dd])
+            return kk + dd;
+    }
+    return kk;
+}
+
+/* Lane connectivity inside junctions [reading; junction internal lanes].
+ * succ_on: the successor of lane x on road rd in x's successor list, -1 if
+ * x has a list without an entry on rd or has no list. */
+static int32_t succ_on(const orc_sim *m, int32_t x, int32_t rd)
+{
+    if (!m->succ_off)
+        return -1;
+    for (int32_t q = m->succ_off[x]; q < m->succ_off[x + 1]; ++q)
+        if (m->lane_road[m->succ[q]] == rd)
+            return m->succ[q];
+    return -1;
+}
+
+/* Whether lane x lets a vehicle continue onto road rd: x has no successor
+ * list (every lane continues), or its list has a lane on rd. */
+static int permits(const orc_sim *m, int32_t x, int32_t rd)
+{
+    if (!m->succ_off || m->succ_off[x] == m->succ_off[x + 1])
+        return 1;
+    return succ_on(m, x, rd) >= 0;
+}
+
+/* The lane a vehicle takes on road rd after lane x: x's successor there
+ * (the open lane nearest to it if control closed it), else the lane of
+ * index pick_lane(k) with k the index of x in its road. */
+static int32_t step_lane(const orc_sim *m, int32_t x, int32_t rd)
+{
+    int32_t y = succ_on(m, x, rd);
+    if (y >= 0)
+        return m->lane_closed[y] ? m->road_lane0[rd] + pick_lane(m, rd, m->lane_k[y]) : y;
+    return m->road_lane0[rd] + pick_lane(m, rd, m->lane_k[x]);
+}
+
 typedef struct { int has; float v, gap; uint32_t id; } leader_t;
 
 /* Leader beyond the end of the vehicle's lane [reading]: follow the route for
  * at most h_look roads and while the distance already covered is within
- * d_look; on each next road take lane min(k, lanes-1) (k carried along) and
+ * d_look; on each next road take the lane step_lane gives after the previous one and
  * use its last vehicle (lowest position) as leader.  A vehicle never leads
  * itself (a ring road with one vehicle). */
 static leader_t lookahead(const orc_sim *m, int32_t lane, float s, int32_t veh, int32_t cur)
 {
     leader_t L = {0, 0.0f, 0.0f, ORC_NONE};
     float dist = road_len(m, lane) - s;
-    int32_t kk = m->lane_k[lane];
+    int32_t y = lane;
     int32_t c = cur;
     for (int32_t h = 0; h < m->P.h_look; ++h) {
         if (c + 1 >= m->route_len[veh])
@@ -615,9 +728,7 @@ static leader_t lookahead(const orc_sim *m, int32_t lane, float s, int32_t veh, 
             break;
         c += 1;
         int32_t rd = m->routes[m->route_off[veh] + c];
-        if (kk > m->road_nlanes[rd] - 1)
-            kk = m->road_nlanes[rd] - 1;
-        int32_t y = m->road_lane0[rd] + kk;
+        y = step_lane(m, y, rd);
         if (m->ls[y] < m->ls[y + 1]) {
             int32_t tail = m->ls[y];
             if (m->vi[tail] != veh) {
@@ -636,6 +747,30 @@ static leader_t lookahead(const orc_sim *m, int32_t lane, float s, int32_t veh, 
 static float idm_p(const params_t *P, float v, float v0e, int has, float vl, float gap)
 {
     return orc_idm(v, v0e, has, vl, gap, P->a_max, P->two_sqrt_ab, P->s0, P->T, P->b_max);
+}
+
+/* Yield rule at a junction [reading]: connector lane cl is busy when one of
+ * the conflicting connector lanes with priority over it holds a vehicle, or
+ * the lane feeding such a connector has a first vehicle that is headed into
+ * it, not held by a red light, and within tau_yield seconds of its stop line
+ * at its current speed (L - s <= v * tau_yield; a standing vehicle is not
+ * approaching).  Everything read is the state at the start of the step. */
+static int conflict_busy(const orc_sim *m, int32_t cl, int64_t t)
+{
+    for (int32_t q = m->conf_off[cl]; q < m->conf_off[cl + 1]; ++q) {
+        const int32_t c2 = m->conf[q], f = m->conf_feed[q];
+        if (m->ls[c2] < m->ls[c2 + 1])
+            return 1;
+        if (m->ls[f] < m->ls[f + 1]) {
+            const int32_t hd = m->ls[f + 1] - 1, hv = m->vi[hd], hc = m->cur[hd];
+            if (hc + 1 < m->route_len[hv] &&
+                m->routes[m->route_off[hv] + hc + 1] == m->lane_road[c2] &&
+                !red_for(m, m->lane_road[f], t) &&
+                road_len(m, f) - m->s[hd] <= m->v[hd] * m->P.tau_yield)
+                return 1;
+        }
+    }
+    return 0;
 }
 
 /* --------------------------------------------------------- update phase --- */
@@ -663,14 +798,7 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
     m->d_id[i] = id; m->d_leader[i] = ORC_NONE; m->d_tl[i] = ORC_NONE; m->d_tf[i] = ORC_NONE;
     m->d_flags[i] = 0; m->d_margin[i] = 0.0f;
 
-    /* red light obstacle at the stop line, applied only if the vehicle can
-     * still stop with the braking limit [reading] */
-    int red = 0;
-    if (has_next && red_for(m, r, t)) {
-        float stop_dist = (v * v) / (2.0f * P->b_max);
-        if (L - s >= stop_dist)
-            red = 1;
-    }
+    int32_t nr = has_next ? m->routes[m->route_off[veh] + c + 1] : -1;
 
     /* in-lane neighbours through the ordering */
     int32_t Lc = (i + 1 < hi) ? i + 1 : -1;
@@ -682,9 +810,11 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
      * accelerations from IDM without signal or lookahead. */
     int change = 0;
     int32_t lt = -1, Lt = -1, nb = -1;
-    if (s >= 0.0f) {
+    /* no lane changes inside a junction (internal roads) */
+    if (s >= 0.0f && !(m->road_internal && m->road_internal[r])) {
         int32_t kt = (t % 2 == 0) ? k - 1 : k + 1;
-        if (kt >= 0 && kt < nl) {
+        /* a lane closed by control is never a target */
+        if (kt >= 0 && kt < nl && !m->lane_closed[m->road_lane0[r] + kt]) {
             lt = m->road_lane0[r] + kt;
             /* brute force over the target lane: leader = lowest s_j >= s,
              * follower = highest s_j < s */
@@ -727,10 +857,22 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
                 if (!(gap_f > 0.0f)) safe = 0;
             }
             float inc = (at_c - a_c) + P->p * (d_n + d_o);
+            /* lanes that continue the route [reading]: a target lane that
+             * does, when the own lane does not, adds b_mand to the incentive
+             * (mandatory lane change); a target lane that does not, when the
+             * own lane does, is never taken */
+            int allowed = 1;
+            if (has_next && m->succ_off) {
+                const int pc = permits(m, l, nr), pt = permits(m, lt, nr);
+                if (pt && !pc)
+                    inc = inc + P->b_mand;
+                else if (pc && !pt)
+                    allowed = 0;
+            }
             uint32_t ctr[4] = {(uint32_t)t, id, 0u, 0u}, key[2] = {P->key0, P->key1}, rnd[4];
             orc_philox4x32_10(ctr, key, rnd);
             float u = (float)(rnd[0] >> 8) * (1.0f / 16777216.0f);
-            change = safe && inc > P->a_thr && u < P->p_lc;
+            change = safe && allowed && inc > P->a_thr && u < P->p_lc;
             m->d_margin[i] = inc - P->a_thr;
             m->d_flags[i] |= change ? 2 : 1;
             m->d_tl[i] = Lt >= 0 ? m->vid[m->vi[Lt]] : ORC_NONE;
@@ -750,6 +892,34 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
         if (ld.has) m->d_flags[i] |= 8;
     }
     m->d_leader[i] = ld.id;
+
+    /* stop line [reading]: the end of the final lane is an obstacle (a
+     * standing vehicle at the line) when the road's signal is red, or when
+     * the vehicle, first in its lane, would enter a connector lane whose
+     * conflicts with priority are busy; applied only if the vehicle can still
+     * stop with the braking limit.  The last road of a route never stops.  A
+     * vehicle still in a lane that does not continue its route (flag 32) is
+     * not held: it takes the route's connector on the lane step_lane gives. */
+    int red = 0;
+    if (has_next) {
+        int line = red_for(m, r, t);
+        if (m->succ_off) {
+            if (!permits(m, lf, nr))
+                m->d_flags[i] |= 32;
+            if (lead_slot < 0) {
+                const int32_t cl = step_lane(m, lf, nr);
+                if (conflict_busy(m, cl, t)) {
+                    line = 1;
+                    m->d_flags[i] |= 64;
+                }
+            }
+        }
+        if (line) {
+            float stop_dist = (v * v) / (2.0f * P->b_max);
+            if (L - s >= stop_dist)
+                red = 1;
+        }
+    }
     float v0e = fmin32(v0, m->lane_vlim[lf]);
     float acc = idm_p(P, v, v0e, ld.has, ld.v, ld.gap);
     if (red) {
@@ -811,14 +981,12 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
     float sp = s + dx;
 
     /* --- transfer along the route; arrival at the end of the last road --- */
-    int32_t x = lf, c2 = c, kk = m->lane_k[lf];
+    int32_t x = lf, c2 = c;
     while (sp >= road_len(m, x) && c2 + 1 < m->route_len[veh]) {
         sp = sp - road_len(m, x);
         c2 += 1;
         int32_t rd = m->routes[m->route_off[veh] + c2];
-        if (kk > m->road_nlanes[rd] - 1)
-            kk = m->road_nlanes[rd] - 1;
-        x = m->road_lane0[rd] + kk;
+        x = step_lane(m, x, rd);
     }
     int arrived = sp >= road_len(m, x);
     out->s = sp; out->v = vn; out->a = a; out->lane = x; out->cur = c2; out->veh = veh;
@@ -870,7 +1038,10 @@ static void one_step(orc_sim *m)
         float v0e = fmin32(m->v0[veh], m->lane_vlim[l]);
         int ok;
         float vins;
-        if (m->ls[l] == m->ls[l + 1]) {
+        if (m->lane_closed[l]) {
+            /* a closed lane holds its departure queue */
+            ok = 0; vins = 0.0f;
+        } else if (m->ls[l] == m->ls[l + 1]) {
             ok = 1; vins = v0e;
         } else {
             int32_t tail = m->ls[l];
@@ -914,6 +1085,7 @@ static void one_step(orc_sim *m)
             size_t sc = (size_t)m->lane_scen[pr[i].src_lane] * ORC_N_COUNTERS;
             m->cnt[sc + ORC_ARRIVED]++;
             m->cnt[sc + ORC_TRIP_TIME] += (t + 1) - m->depart[pr[i].veh];
+            m->arr[pr[i].veh] = t + 1;
         }
 
     /* --- joiners (lane changers, road transfers, insertions) by (lane, s, id) --- */
@@ -1050,6 +1222,30 @@ void orc_set_lane_vlim(orc_sim *m, int32_t lane, float vlim)
     m->lane_vlim[lane] = vlim;
 }
 
+int orc_set_lane_closed(orc_sim *m, int32_t n, const int32_t *lane, const int32_t *closed)
+{
+    for (int32_t q = 0; q < n; ++q)
+        if (lane[q] < 0 || lane[q] >= m->n_lanes)
+            return -1;
+    uint8_t *next = malloc((size_t)m->n_lanes + 1);
+    memcpy(next, m->lane_closed, (size_t)m->n_lanes);
+    for (int32_t q = 0; q < n; ++q)
+        next[lane[q]] = closed[q] ? 1 : 0;
+    for (int32_t q = 0; q < n; ++q) {
+        const int32_t r = m->lane_road[lane[q]], l0 = m->road_lane0[r];
+        int32_t open = 0;
+        for (int32_t k = 0; k < m->road_nlanes[r]; ++k)
+            open += !next[l0 + k];
+        if (open == 0) {             /* a road keeps an open lane */
+            free(next);
+            return -1;
+        }
+    }
+    memcpy(m->lane_closed, next, (size_t)m->n_lanes);
+    free(next);
+    return 0;
+}
+
 void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v)
 {
     double *sum = calloc((size_t)m->n_roads + 1, sizeof(double));
@@ -1110,6 +1306,57 @@ int32_t orc_read_mlp_inputs(const orc_sim *m, float *feat, int8_t *use)
 void orc_mlp_sq(const orc_sim *m, double *sum_sq)
 {
     memcpy(sum_sq, m->mlp_sq, sizeof(double) * (size_t)m->n_scen);
+}
+
+static int cmp_u32_idx(const void *x, const void *y)
+{
+    const uint64_t a = *(const uint64_t *)x, b = *(const uint64_t *)y;
+    return a < b ? -1 : (a > b);
+}
+
+/* Trips of all vehicles in ascending id order [reading of the paper's query
+ * APIs for travel time and distance, Sec. III-C-4]: status 0 while waiting
+ * to depart, 1 on the network, 2 arrived; travel time in steps (arrival step
+ * minus departure step once arrived, the current step index minus the
+ * departure step on the network, 0 while waiting); distance in metres along
+ * the route from where the vehicle entered the simulation (the whole route
+ * once arrived; the roads before its current one plus its position while on
+ * the network; 0 while waiting), in FP64 with road lengths summed in route
+ * order. */
+void orc_read_trips(const orc_sim *m, uint32_t *id, int32_t *status, int32_t *travel,
+                    double *dist)
+{
+    const int32_t N = m->n_veh;
+    uint64_t *ord = malloc(sizeof(uint64_t) * (N ? N : 1));
+    int32_t *row = malloc(sizeof(int32_t) * (N ? N : 1));
+    for (int32_t i = 0; i < N; ++i) {
+        ord[i] = ((uint64_t)m->vid[i] << 32) | (uint32_t)i;
+        row[i] = -1;
+    }
+    qsort(ord, N, sizeof(uint64_t), cmp_u32_idx);
+    for (int32_t q = 0; q < m->n_act; ++q)
+        row[m->vi[q]] = q;
+    for (int32_t k = 0; k < N; ++k) {
+        const int32_t i = (int32_t)(ord[k] & 0xFFFFFFFFu);
+        int32_t st = 0, tt = 0;
+        double d = 0.0;
+        if (m->arr[i] >= 0) {
+            st = 2;
+            tt = (int32_t)(m->arr[i] - m->depart[i]);
+            d = route_dist(m, i, m->route_len[i]) - m->dist0[i];
+        } else if (row[i] >= 0) {
+            const int32_t q = row[i];
+            st = 1;
+            tt = (int32_t)(m->t - m->depart[i]);
+            d = (route_dist(m, i, m->cur[q]) + (double)m->s[q]) - m->dist0[i];
+        }
+        if (id) id[k] = m->vid[i];
+        if (status) status[k] = st;
+        if (travel) travel[k] = tt;
+        if (dist) dist[k] = d;
+    }
+    free(ord);
+    free(row);
 }
 
 void orc_counters(const orc_sim *m, int64_t *cnt, double *sum_v)

@@ -56,6 +56,16 @@ typedef struct {
     int32_t mode;
     const float *mlp_theta;
     const float *mlp_norm;
+    /* junction internal lanes (all NULL without): internal-road flags,
+     * lane successors (CSR over lanes) and, per connector lane, the
+     * conflicting connector lanes with priority over it and the lane feeding
+     * each; b_mand (m/s^2) biases lane changes toward lanes that continue
+     * along the route; tau_yield (s) is the time within which an approaching
+     * vehicle with priority makes a vehicle yield */
+    const uint8_t *road_internal;
+    const int32_t *lane_succ_off, *lane_succ;
+    const int32_t *lane_conf_off, *lane_conf, *lane_conf_feed;
+    float b_mand, tau_yield;
 } orc_input;
 
 typedef struct orc_sim orc_sim;
@@ -121,6 +131,13 @@ int32_t orc_pending(const orc_sim *m);
 int orc_set_signal_phase(orc_sim *m, int32_t node, int32_t phase);
 /* Speed limit of a lane from the next step on. */
 void orc_set_lane_vlim(orc_sim *m, int32_t lane, float vlim);
+/* Lane restriction from the next step on: lane[q] is closed (closed[q] != 0)
+ * or opened, in order (a lane named twice takes the last value).  A closed
+ * lane is never a lane change target, vehicles entering its road take the
+ * nearest open lane (pick_lane), and its departure queue waits; vehicles on
+ * it carry on.  Returns -1, changing nothing, for a lane out of range or
+ * when a road would be left without an open lane. */
+int orc_set_lane_closed(orc_sim *m, int32_t n, const int32_t *lane, const int32_t *closed);
 /* Vehicles and mean speed (FP64 sum in state order, 0 if empty) per road. */
 void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v);
 /* Position and heading of each state row: on the segment from the road's
@@ -128,6 +145,14 @@ void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v);
  * (k + 1/2) * 3.5 m to the right of the direction of travel; heading
  * atan2(By - Ay, Bx - Ax).  Returns -1 without node coordinates. */
 int orc_positions(const orc_sim *m, double *x, double *y, double *heading);
+
+/* Trips of all n_veh vehicles in ascending id order: status (0 waiting to
+ * depart, 1 on the network, 2 arrived), travel time in steps (arrival -
+ * depart; current step index - depart on the network; 0 waiting) and the
+ * distance along the route since the vehicle entered the simulation (FP64,
+ * road lengths summed in route order). */
+void orc_read_trips(const orc_sim *m, uint32_t *id, int32_t *status, int32_t *travel,
+                    double *dist);
 
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -31,6 +31,9 @@ class OrcInput(C.Structure):
         ("d_look", C.c_float),
         ("h_look", C.c_int32), ("t0", C.c_int32), ("seed", C.c_uint64),
         ("mode", C.c_int32), ("mlp_theta", C.c_void_p), ("mlp_norm", C.c_void_p),
+        ("road_internal", C.c_void_p), ("lane_succ_off", C.c_void_p), ("lane_succ", C.c_void_p),
+        ("lane_conf_off", C.c_void_p), ("lane_conf", C.c_void_p), ("lane_conf_feed", C.c_void_p),
+        ("b_mand", C.c_float), ("tau_yield", C.c_float),
     ]
 
 
@@ -59,6 +62,9 @@ def lib():
         L.orc_set_signal_phase.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.orc_set_signal_phase.restype = C.c_int
         L.orc_set_lane_vlim.argtypes = [C.c_void_p, C.c_int32, C.c_float]
+        L.orc_set_lane_closed.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.orc_set_lane_closed.restype = C.c_int
+        L.orc_read_trips.argtypes = [C.c_void_p] + [C.c_void_p] * 4
         L.orc_positions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_positions.restype = C.c_int
         L.orc_mlp_sq.argtypes = [C.c_void_p, C.c_void_p]
@@ -134,6 +140,15 @@ class OracleSim:
         inp.h_look = int(p["h_look"])
         inp.t0 = int(p["t0"])
         inp.seed = int(p["seed"])
+        inp.b_mand = float(p.get("b_mand", 1.0))
+        inp.tau_yield = float(p.get("tau_yield", 3.0))
+        if sc.lane_succ_off is not None:
+            inp.road_internal = arr(sc.road_internal, np.uint8)
+            inp.lane_succ_off = arr(sc.lane_succ_off, np.int32)
+            inp.lane_succ = arr(sc.lane_succ, np.int32)
+            inp.lane_conf_off = arr(sc.lane_conf_off, np.int32)
+            inp.lane_conf = arr(sc.lane_conf, np.int32)
+            inp.lane_conf_feed = arr(sc.lane_conf_feed, np.int32)
         mlp_cfg = p.get("mlp")
         if mlp_cfg is not None:
             inp.mode = 1
@@ -145,6 +160,7 @@ class OracleSim:
         self._h = h
         self.n_scen = sc.n_scen
         self.n_roads = sc.n_roads
+        self.n_veh = sc.n_veh
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -205,12 +221,28 @@ class OracleSim:
         for l, v in zip(np.atleast_1d(lanes), np.atleast_1d(vlims)):
             lib().orc_set_lane_vlim(self._h, int(l), float(np.float32(v)))
 
+    def set_lane_closed(self, lanes, closed):
+        ln = np.ascontiguousarray(np.atleast_1d(lanes), np.int32)
+        cl = np.ascontiguousarray(np.atleast_1d(closed), np.int32)
+        if lib().orc_set_lane_closed(self._h, int(ln.shape[0]), _p(ln), _p(cl)) != 0:
+            raise ValueError("lane out of range, or a road would have no open lane")
+
     def road_stats(self):
         """(vehicles per road, mean speed per road)."""
         cnt = np.empty(self.n_roads, np.int32)
         mv = np.empty(self.n_roads, np.float32)
         lib().orc_road_stats(self._h, _p(cnt), _p(mv))
         return cnt, mv
+
+    def trips(self):
+        """Per vehicle in ascending id order: dict of id, status (0 waiting,
+        1 on the network, 2 arrived), travel time (steps) and distance (m)."""
+        n = self.n_veh
+        out = dict(id=np.empty(n, np.uint32), status=np.empty(n, np.int32),
+                   travel=np.empty(n, np.int32), distance=np.empty(n, np.float64))
+        lib().orc_read_trips(self._h, _p(out["id"]), _p(out["status"]), _p(out["travel"]),
+                             _p(out["distance"]))
+        return out
 
     def positions(self):
         """(x, y, heading) per state row."""

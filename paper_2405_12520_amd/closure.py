@@ -12,12 +12,14 @@
 2. Input description: per-input mean and standard deviation for the
    normalisation, and the [0.1, 99.9] percentile range as the envelope
    outside which the simulator keeps IDM.
-3. Training: Adam on mean squared error with batches drawn on the GPU,
-   forward/backward through the project's kernels (moss_mlp_grad), in
-   bfloat16 mode so that training sees the simulator's rounding.
+3. Training: Adam on mean squared error with random batches (indices drawn
+   on the host), forward/backward through the project's kernels
+   (moss_mlp_grad), in bfloat16 mode so that training sees the simulator's
+   rounding.
 
-All arithmetic runs in libmoss kernels; this module only sequences calls and
-keeps tensors.
+The network's arithmetic (traces, forward, backward, Adam, inference) runs
+in libmoss kernels; the input description and the error statistics are FP64
+numpy on host copies.  torch only holds the device tensors.
 """
 from __future__ import annotations
 
@@ -77,20 +79,19 @@ LOG_INPUTS = (0, 4, 6)      # distances enter the network as ln(max(x, 0.5 m))
 
 def describe(F) -> np.ndarray:
     """mean[8], inv_std[8] of the network inputs (distances log-transformed)
-    and lo[8], hi[8] of the raw inputs (the envelope)."""
-    import torch
-    f = F.double()
-    ft = f.clone()
+    and lo[8], hi[8] of the raw inputs (the envelope: 0.1 % and 99.9 %
+    quantiles, linear interpolation).  Computed in FP64 with numpy on a host
+    copy of the features."""
+    f = F.cpu().numpy().astype(np.float64) if hasattr(F, "cpu") else np.asarray(F, np.float64)
+    ft = f.copy()
     for q in LOG_INPUTS:
-        ft[:, q] = torch.log(ft[:, q].clamp_min(0.5))
+        ft[:, q] = np.log(np.maximum(ft[:, q], 0.5))
     mean = ft.mean(0)
-    std = ft.std(0).clamp_min(1e-3)
-    q = torch.tensor([0.001, 0.999], dtype=torch.float64, device=F.device)
-    # torch.quantile limits its input size; every k-th row of each input
+    std = np.maximum(ft.std(0, ddof=1), 1e-3)
+    # quantiles on every k-th row (at most about a million per input)
     step = max(1, f.shape[0] // 1_000_000)
-    lohi = torch.stack([torch.quantile(f[::step, c], q) for c in range(f.shape[1])], dim=1)
-    out = torch.cat([mean, 1.0 / std, lohi[0], lohi[1]]).float().cpu().numpy()
-    return out
+    lohi = np.quantile(f[::step], [0.001, 0.999], axis=0)
+    return np.concatenate([mean, 1.0 / std, lohi[0], lohi[1]]).astype(np.float32)
 
 
 def he_init(seed: int) -> np.ndarray:
@@ -115,11 +116,15 @@ def fit(F, Y, norm: np.ndarray, *, steps: int = 60000, batch: int = 4096, lr: fl
     th = torch.from_numpy(he_init(seed)).to(dev)
     m = torch.zeros_like(th)
     v = torch.zeros_like(th)
-    gen = torch.Generator(device=dev).manual_seed(seed)
+    rng = np.random.default_rng(seed)
     n = F.shape[0]
     t0 = time.time()
+    block = 256                 # steps whose batch indices are copied at once
     for s in range(1, steps + 1):
-        idx = torch.randint(0, n, (batch,), device=dev, generator=gen, dtype=torch.int32)
+        if (s - 1) % block == 0:
+            k = min(block, steps - s + 1)
+            idx_blk = torch.from_numpy(rng.integers(0, n, (k, batch), dtype=np.int32)).to(dev)
+        idx = idx_blk[(s - 1) % block]
         q = bf16 and s > (3 * steps) // 4
         loss, g = moss.mlp_grad(F, Y, th, N, idx=idx, bf16=q, out_lo=-S.DEFAULT_PARAMS["b_max"],
                                 out_hi=S.DEFAULT_PARAMS["a_max"])
@@ -132,18 +137,22 @@ def fit(F, Y, norm: np.ndarray, *, steps: int = 60000, batch: int = 4096, lr: fl
 
 
 def rms(F, Y, theta: np.ndarray, norm: np.ndarray, inside_only: bool = True) -> Dict[str, float]:
-    """RMS error of the network (simulator inference path) against the labels."""
+    """RMS error of the network (simulator inference path, the project's
+    kernel) against the labels, over the samples inside the envelope (or
+    all); the error arithmetic is FP64 numpy on host copies."""
     import torch
     dev = F.device
     pred = moss.mlp_predict(F, torch.from_numpy(theta).to(dev), torch.from_numpy(norm).to(dev))
-    lo = torch.from_numpy(norm[16:24]).to(dev)
-    hi = torch.from_numpy(norm[24:32]).to(dev)
-    inside = ((F >= lo) & (F <= hi)).all(1)
+    f = F.cpu().numpy()
+    y = Y.cpu().numpy().astype(np.float64)
+    p = pred.cpu().numpy().astype(np.float64)
+    inside = np.all((f >= norm[16:24]) & (f <= norm[24:32]), axis=1)
     amax, bmax = S.DEFAULT_PARAMS["a_max"], S.DEFAULT_PARAMS["b_max"]
-    p = pred.clamp(-bmax, amax)
-    e = (p - Y)[inside] if inside_only else (p - Y)
-    return dict(rms=float(torch.sqrt((e.double() ** 2).mean()).item()),
-                inside=float(inside.double().mean().item()), n=int(e.shape[0]))
+    e = np.clip(p, -bmax, amax) - y
+    if inside_only:
+        e = e[inside]
+    return dict(rms=float(np.sqrt(np.mean(e * e))) if e.size else 0.0,
+                inside=float(inside.mean()), n=int(e.shape[0]))
 
 
 def build_closure(path: str = DEFAULT_PATH, *, steps_trace: int = 3600,

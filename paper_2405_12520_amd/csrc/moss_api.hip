@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -69,8 +70,8 @@ struct Layout {
     size_t total;
     size_t S[8], Pr[8], J[8], ls[2], idv[2][2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_hdep, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
-        vt_rstart, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq, tr_feat,
-        tr_label, road_ab, out_buf, ctl_idx, ctl_rec;
+        vt_rstart, vt_dist0, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq,
+        tr_feat, tr_label, road_ab, out_buf, trip_buf, ctl_idx, ctl_rec, ctl_ridx, ctl_rrec;
 
     void plan()
     {
@@ -115,7 +116,7 @@ struct Layout {
         scal = take(64);
         lanes = take(sizeof(LaneInfo) * (size_t)n_lanes);
         roads = take(sizeof(RoadInfo) * (size_t)n_roads);
-        route = take(4 * ((size_t)n_route + 2 * (size_t)n_veh + 1));
+        route = take(4 * ((size_t)n_route + 3 * (size_t)n_veh + 1));
         qlanes = take(4 * (size_t)n_qlanes);
         q_hdep = take(4 * (size_t)n_qlanes);
         q_head = take(4 * (size_t)n_lanes);
@@ -128,6 +129,7 @@ struct Layout {
         vt_id = take(4 * (size_t)n_veh);
         vt_dep = take(4 * (size_t)n_veh);
         vt_rstart = take(4 * (size_t)n_veh);
+        vt_dist0 = take(8 * (size_t)n_veh);
         cnt = take(8 * (size_t)kStripes * stripe_elems((int64_t)n_scen * C_N));
         sumv = take(8 * (size_t)kStripes * stripe_elems(n_scen));
         for (auto &x : dbg) x = take(debug ? 4 * c : 4);
@@ -141,11 +143,33 @@ struct Layout {
         road_ab = take(xy ? 32 * (size_t)n_roads : 32);
         ctl_idx = take(4 * (size_t)n_lanes);
         ctl_rec = take(sizeof(LaneInfo) * (size_t)n_lanes);
+        ctl_ridx = take(4 * (size_t)n_roads);
+        ctl_rrec = take(sizeof(RoadInfo) * (size_t)n_roads);
         // staging of the read functions' results for host destinations
         out_buf = take(std::max(8 * (size_t)n_roads, xy ? 24 * c : (size_t)8));
+        // staging of moss_read_trips for host destinations: status, travel
+        // time and distance per vehicle
+        trip_buf = take(16 * (size_t)n_veh);
         total = off;
     }
 };
+
+// The kernels address every workspace array through 32-bit byte offsets from
+// the array's start, so no single array may reach 4 GiB: the route table
+// (4 bytes per route entry, plus 3 per vehicle) and the trace's features (32
+// bytes per vehicle) are the largest.
+int check_array_sizes(const Layout &L)
+{
+    const double lim = 4294967296.0;
+    if (4.0 * ((double)L.n_route + 3.0 * L.n_veh + 1.0) >= lim)
+        return fail(MOSS_EINVAL, "route table of %lld entries exceeds 4 GiB",
+                    (long long)L.n_route);
+    if (32.0 * (double)std::max(L.cap, 1) + 32.0 * L.n_qlanes >= lim)
+        return fail(MOSS_EINVAL, "%d vehicles exceed the per-array limit of 4 GiB", L.cap);
+    if ((double)L.n_lanes * 32.0 >= lim || (double)L.n_roads * 32.0 >= lim)
+        return fail(MOSS_EINVAL, "network tables exceed 4 GiB");
+    return MOSS_OK;
+}
 
 bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
 bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
@@ -313,6 +337,10 @@ struct moss_sim {
     std::vector<uint8_t> node_sig;
     std::vector<int32_t> patch_idx;
     std::vector<LaneInfo> patch_rec;
+    // host copy of the road records (closed-lane masks) and their staging
+    std::vector<RoadInfo> roads_h;
+    std::vector<int32_t> rpatch_idx;
+    std::vector<RoadInfo> rpatch_rec;
 };
 
 static Dev step_dev(const moss_sim *h, int parity);
@@ -445,6 +473,7 @@ static void fill_dev(moss_sim *h)
     d.vt_id = U(L.vt_id);
     d.vt_dep = I(L.vt_dep);
     d.vt_rstart = U(L.vt_rstart);
+    d.vt_dist0 = (const double *)(w + L.vt_dist0);
     d.cnt = (unsigned long long *)(w + L.cnt);
     d.sumv = (double *)(w + L.sumv);
     d.cnt_stride = stripe_elems((int64_t)h->n_scen * C_N);
@@ -519,6 +548,9 @@ int moss_query_workspace(const moss_network *net, const moss_signals *sig,
         return rc;
     Layout L;
     plan_layout(net, veh, prm, &L);
+    rc = check_array_sizes(L);
+    if (rc)
+        return rc;
     *bytes = L.total;
     return MOSS_OK;
 }
@@ -538,6 +570,9 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
         return fail(MOSS_EINVAL, "workspace is null");
     Layout L;
     plan_layout(net, veh, prm, &L);
+    rc = check_array_sizes(L);
+    if (rc)
+        return rc;
     if (ws_bytes < L.total)
         return fail(MOSS_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
     if (((uintptr_t)d_ws & 255) != 0)
@@ -583,10 +618,11 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     // phase_len differs from the road's group
     std::vector<uint8_t> red0(NL, 0);
     for (int32_t l = 0; l < NL; ++l)
-        red0[l] = lane_red_at(lanes[l], (uint32_t)p.t0) ? 1 : 0;
+        red0[l] = lane_flags_at(lanes[l], (uint32_t)p.t0);
 
-    // --- routes, each followed by -1 and the vehicle's departure step
-    std::vector<int32_t> route((size_t)L.n_route + 2 * (size_t)N + 1);
+    // --- routes, each followed by -1, the vehicle's departure step and its
+    // arrival step (-1 until it arrives)
+    std::vector<int32_t> route((size_t)L.n_route + 3 * (size_t)N + 1);
     std::vector<uint32_t> rstart(N);
     {
         size_t w = 0;
@@ -596,6 +632,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
                 route[w++] = veh->route_roads[k];
             route[w++] = -1;
             route[w++] = veh->depart[i];
+            route[w++] = -1;
         }
         route[w] = -1;
     }
@@ -672,10 +709,21 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     std::sort(byid.begin(), byid.end(), [&](int32_t x, int32_t y) { return veh->id[x] < veh->id[y]; });
     std::vector<uint32_t> vtid(N), vtr(N);
     std::vector<int32_t> vtdep(N);
+    std::vector<double> vtd0(N, 0.0);
     for (int32_t k = 0; k < N; ++k) {
-        vtid[k] = veh->id[byid[k]];
-        vtdep[k] = veh->depart[byid[k]];
-        vtr[k] = rstart[byid[k]];
+        const int32_t i = byid[k];
+        vtid[k] = veh->id[i];
+        vtdep[k] = veh->depart[i];
+        vtr[k] = rstart[i];
+        // route distance where the vehicle enters the simulation: the road
+        // lengths before its starting road (FP64, route order) plus its
+        // starting position; 0 at a route start
+        if (veh->placed && veh->placed[i]) {
+            double d0 = 0.0;
+            for (int32_t c = 0; c < veh->cursor[i]; ++c)
+                d0 += (double)net->road_length[veh->route_roads[veh->route_off[i] + c]];
+            vtd0[k] = d0 + (double)veh->s[i];
+        }
     }
 
     moss_sim *h = new moss_sim();
@@ -751,6 +799,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
             for (int32_t k = 0; k < net->road_nlanes[r]; ++k)
                 h->in_lanes[fill[net->road_to[r]]++] = net->road_lane0[r] + k;
         h->lanes_h = lanes;
+        h->roads_h = roads;
     }
     if (L.xy) {
         // each road's segment (upstream node, downstream node) for positions
@@ -781,6 +830,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     chk(up(L.vt_id, vtid.data(), 4 * (size_t)N));
     chk(up(L.vt_dep, vtdep.data(), 4 * (size_t)N));
     chk(up(L.vt_rstart, vtr.data(), 4 * (size_t)N));
+    chk(up(L.vt_dist0, vtd0.data(), 8 * (size_t)N));
     if (L.mlp) {
         chk(up(L.mlp_theta, p.mlp_theta, 4 * (size_t)MOSS_MLP_PARAMS));
         chk(up(L.mlp_norm, p.mlp_norm, 4 * (size_t)MOSS_MLP_NORM));
@@ -1185,6 +1235,75 @@ int moss_set_signal_phase(moss_sim *h, const int32_t *node, const int32_t *phase
     return stage_and_upload(h);
 }
 
+int moss_set_lane_closed(moss_sim *h, const int32_t *lane, const int32_t *closed, int32_t n)
+{
+    g_err.clear();
+    if (!h || (n > 0 && (!lane || !closed)) || n < 0)
+        return fail(MOSS_EINVAL, "null argument or negative count");
+    const int32_t NL = (int32_t)h->lanes_h.size();
+    for (int32_t i = 0; i < n; ++i)
+        if (lane[i] < 0 || lane[i] >= NL)
+            return fail(MOSS_EINVAL, "lane %d out of range", lane[i]);
+    // the masks after the whole batch, checked before anything changes
+    std::map<int32_t, uint32_t> mask;
+    for (int32_t i = 0; i < n; ++i) {
+        const LaneInfo &li = h->lanes_h[lane[i]];
+        if (!mask.count(li.road))
+            mask[li.road] = h->roads_h[li.road].closed;
+        if (li.nlanes > 32 && closed[i])
+            return fail(MOSS_EINVAL, "lane %d: roads of more than 32 lanes cannot close lanes",
+                        lane[i]);
+        const uint32_t bit = li.nlanes > 32 ? 0u : 1u << li.k;
+        mask[li.road] = closed[i] ? (mask[li.road] | bit) : (mask[li.road] & ~bit);
+    }
+    for (const auto &rm : mask) {
+        const int32_t nl = h->roads_h[rm.first].nlanes;
+        const uint32_t all = nl >= 32 ? 0xFFFFFFFFu : ((1u << nl) - 1u);
+        if ((rm.second & all) == all)
+            return fail(MOSS_EINVAL, "road %d would have no open lane", rm.first);
+    }
+    h->patch_idx.clear();
+    for (int32_t i = 0; i < n; ++i) {
+        h->lanes_h[lane[i]].closed = closed[i] ? 1 : 0;
+        h->patch_idx.push_back(lane[i]);
+    }
+    h->rpatch_idx.clear();
+    h->rpatch_rec.clear();
+    for (const auto &rm : mask) {
+        h->roads_h[rm.first].closed = rm.second;
+        h->rpatch_idx.push_back(rm.first);
+        h->rpatch_rec.push_back(h->roads_h[rm.first]);
+    }
+    const int32_t nr = (int32_t)h->rpatch_idx.size();
+    if (nr > 0) {
+        HIP_TRY(hipSetDevice(h->device));
+        int32_t *di = (int32_t *)(h->ws + h->lay.ctl_ridx);
+        RoadInfo *dr = (RoadInfo *)(h->ws + h->lay.ctl_rrec);
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(hipMemcpyAsync(di, h->rpatch_idx.data(), 4 * (size_t)nr, hipMemcpyHostToDevice,
+                               h->stream));
+        HIP_TRY(hipMemcpyAsync(dr, h->rpatch_rec.data(), sizeof(RoadInfo) * (size_t)nr,
+                               hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(launch_road_patch(step_dev(h, h->parity), di, dr, nr, h->stream));
+    }
+    int32_t any = 0;
+    for (const RoadInfo &rd : h->roads_h)
+        any |= rd.closed != 0u;
+    const int rc = stage_and_upload(h);
+    if (rc)
+        return rc;
+    if (any != h->dev.closures) {
+        // the step's update kernel changes: graphs captured with the other
+        // one are redone
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        drop_graphs(h);
+        h->dev.closures = any;
+        h->graphs_ok = true;
+        prepare_graphs(h);
+    }
+    return MOSS_OK;
+}
+
 int moss_set_lane_vlim(moss_sim *h, const int32_t *lane, const float *vlim, int32_t n)
 {
     g_err.clear();
@@ -1267,6 +1386,44 @@ int moss_read_positions(moss_sim *h, int32_t capacity, int32_t device, double *x
             HIP_TRY(rc_.finish());
         }
     }
+    if (h->err_seen)
+        return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
+    return MOSS_OK;
+}
+
+int moss_read_trips(moss_sim *h, int32_t capacity, int32_t device, uint32_t *id,
+                    int32_t *status, int32_t *travel_time, double *distance, int32_t *n)
+{
+    g_err.clear();
+    if (!h || !n)
+        return fail(MOSS_EINVAL, "null argument");
+    const int32_t N = h->lay.n_veh;
+    *n = N;
+    if (capacity < N)
+        return fail(MOSS_ENOMEM, "%d vehicles, capacity %d", N, capacity);
+    int rc = sync_and_check(h);
+    if (rc)
+        return rc;
+    if (N == 0)
+        return MOSS_OK;
+    int32_t n_act = 0;
+    HIP_TRY(hipMemcpy(&n_act, h->dev.n_cur, 4, hipMemcpyDeviceToHost));
+    const Dev dc = step_dev(h, h->parity);
+    // device destinations are written in place; host ones are staged
+    char *tb = h->ws + h->lay.trip_buf;
+    int32_t *d_st = device && status ? status : (int32_t *)tb;
+    int32_t *d_tt = device && travel_time ? travel_time : (int32_t *)(tb + 4 * (size_t)N);
+    double *d_ds = device && distance ? distance : (double *)(tb + 8 * (size_t)N);
+    ReadCopies rc_(h, device != 0);
+    if (rc_.e == hipSuccess)
+        rc_.e = launch_trips(dc, n_act, d_st, d_tt, d_ds, h->stream);
+    rc_.copy(id, dc.vt_id, 4 * (size_t)N);
+    if (!device) {
+        rc_.copy(status, d_st, 4 * (size_t)N);
+        rc_.copy(travel_time, d_tt, 4 * (size_t)N);
+        rc_.copy(distance, d_ds, 8 * (size_t)N);
+    }
+    HIP_TRY(rc_.finish());
     if (h->err_seen)
         return fail(MOSS_ESTATE, "device error word 0x%x", h->err_seen);
     return MOSS_OK;

@@ -27,7 +27,7 @@ struct LaneInfo {
     uint8_t k;          // index in the road
     uint8_t nlanes;
     int8_t group;       // signal group of the road at its downstream node, -1 none
-    uint8_t pad0;
+    uint8_t closed;     // lane restriction by control: 1 closed to entering vehicles
     uint16_t cycle, phase, offset;         // plan of the downstream node (offset < cycle)
     int16_t manual;     // phase held by signal control, -1: the fixed-time plan
     int32_t road;
@@ -51,8 +51,38 @@ struct RoadInfo {
     int32_t lane0;
     int32_t nlanes;
     float L;
-    int32_t pad;
+    uint32_t closed;    // bit k: lane k closed by control (roads of at most 32 lanes)
 };
+
+// Lane index taken on a road of n lanes (closed-lane mask `closed`) by a
+// vehicle coming from lane index k: min(k, n - 1), or when control has
+// closed that lane, the open lane nearest to it, the lower of two equally
+// near.  A road always keeps an open lane, and only roads of at most 32
+// lanes close lanes.  Branch-free: the nearest open lanes below and above
+// come from the highest and lowest set bits of the open-lane mask.
+__host__ __device__ inline int pick_lane(int k, int n, uint32_t closed)
+{
+    const int kk = k < n - 1 ? k : n - 1;
+    const uint32_t nmask = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+    const uint32_t open = ~closed & nmask;
+    const uint32_t bit = 1u << (kk & 31);
+    const uint32_t lo = open & (bit - 1u);
+    const uint32_t hi = open & ~(bit | (bit - 1u));
+    const int l = lo ? 31 - __builtin_clz(lo) : -64;
+    const int h = hi ? __builtin_ctz(hi) : 64;
+    const int near = (kk - l <= h - kk) ? l : h;
+    return (closed == 0u || (open & bit)) ? kk : near;
+}
+
+// Per-lane flags of the current step (lane_red): bit 0 the lane's road
+// waits at a red light, bit 1 the lane is closed.
+constexpr uint8_t kRedBit = 1u, kClosedBit = 2u;
+
+// Flags byte of a lane at step t (kRedBit, kClosedBit).
+__host__ __device__ inline uint8_t lane_flags_at(const LaneInfo &li, uint32_t t)
+{
+    return (uint8_t)((lane_red_at(li, t) ? kRedBit : 0u) | (li.closed ? kClosedBit : 0u));
+}
 
 // Last vehicle (lowest position) of each lane; id == kNone when empty.
 struct Tail {
@@ -86,7 +116,9 @@ struct Dev {
     int32_t n_lanes, n_scen, cap, n_qlanes;
     const LaneInfo *lanes;
     const RoadInfo *roads;
-    const int32_t *route;         // routes, each followed by -1
+    // routes, each followed by -1, the departure step and the arrival step
+    // (-1 until the vehicle arrives; written by the update at arrival)
+    int32_t *route;
     SoA S;                        // state at the start of a step
     SoA Pr;                       // proposals, indexed by row at step start (+ insertions)
     // id and v0 never change in a step: they alternate between two buffers
@@ -117,7 +149,7 @@ struct Dev {
     // jslane), copied by k_jscatter so that the merge reads them coalesced
     SoA J;
     int32_t *jcnt, *jcur;
-    uint8_t *lane_red;            // red light for the lane's road at the current step
+    uint8_t *lane_red;            // lane flags of the current step (kRedBit, kClosedBit)
     int32_t *n_cur, *n_next, *n_dbg;
     uint32_t *n_ins;
     int64_t *t;
@@ -136,6 +168,7 @@ struct Dev {
     const uint32_t *vt_id;
     const int32_t *vt_dep;
     const uint32_t *vt_rstart;
+    const double *vt_dist0;       // route distance at which the vehicle entered
     // observables, each in kStripes copies (stripe k at k * cnt_stride /
     // sv_stride elements) so that concurrent waves add to different lines;
     // readers sum the copies
@@ -146,6 +179,9 @@ struct Dev {
     // launch shape (results do not depend on it): update and scatter grid
     // sizes (0 = default) and XCD-contiguous tile order
     int32_t upd_blocks, jsc_blocks, xcd_remap;
+    // some lane is closed by control: the update variant that applies
+    // closures is launched (set between steps; captured graphs are redone)
+    int32_t closures;
     // learned closure (mode 1) and its training trace
     int32_t mode;
     const float *mlp_theta, *mlp_norm;
@@ -193,6 +229,9 @@ hipError_t launch_tails(const Dev &d, hipStream_t st);
 // their red flags for the step about to run.
 hipError_t launch_lane_patch(const Dev &d, const int32_t *idx, const LaneInfo *rec, int32_t n,
                              hipStream_t st);
+// Overwrites n road records (lane closures).
+hipError_t launch_road_patch(const Dev &d, const int32_t *idx, const RoadInfo *rec, int32_t n,
+                             hipStream_t st);
 // Road measures and positions of the current state (read functions).
 hipError_t launch_road_stats(const Dev &d, int32_t n_roads, int32_t *count, float *mean_v,
                              hipStream_t st);
@@ -201,6 +240,10 @@ hipError_t launch_positions(const Dev &d, int32_t n, const double *road_ab, doub
 // Builds the packed network image from mlp_theta / mlp_norm (once per simulator).
 hipError_t launch_mlp_pack(const Dev &d, hipStream_t st);
 size_t mlp_pack_bytes();
+// Trips of every vehicle in id order (status, travel time, distance; see
+// moss_read_trips) from the current state of n_act rows.
+hipError_t launch_trips(const Dev &d, int32_t n_act, int32_t *status, int32_t *travel,
+                        double *dist, hipStream_t st);
 hipError_t launch_cursor(const Dev &d, const uint32_t *ids, const uint32_t *ptrs, int32_t *out,
                          int32_t n, hipStream_t st);
 

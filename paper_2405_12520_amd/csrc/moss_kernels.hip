@@ -17,6 +17,22 @@
 
 namespace moss {
 
+// Element idx of a device array, addressed as the array's base plus a 32-bit
+// byte offset: the access then uses the scalar base register with one 32-bit
+// vector offset instead of 64-bit address arithmetic per array.  Every array
+// of the workspace is below 4 GiB (checked at creation).
+template <class T>
+__device__ __forceinline__ T &at(T *base, uint32_t idx)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T &at(const T *base, uint32_t idx)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                        idx * (uint32_t)sizeof(T));
+}
+
 __device__ __forceinline__ float fmin32(float x, float y) { return x < y ? x : y; }
 __device__ __forceinline__ float fmax32(float x, float y) { return x > y ? x : y; }
 
@@ -146,7 +162,7 @@ struct Lead {
 // rd0 is the record of the next road nxt (already loaded by the caller);
 // with pre, tl0 is the tail the first road gives (loaded by the caller too).
 __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id, uint32_t ptr,
-                          int32_t nxt, RoadInfo rd0, bool pre, Tail tl0)
+                          int32_t nxt, RoadInfo rd0, bool pre, Tail tl0, bool closures)
 {
     Lead r = {false, 0.0f, 0.0f, kNone};
     float dist = li.L - s;
@@ -160,14 +176,13 @@ __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id
         if (dist > d.P.d_look)
             break;
         if (h > 0)
-            rd = d.roads[nr];
-        if (kk > rd.nlanes - 1)
-            kk = rd.nlanes - 1;
+            rd = at(d.roads, nr);
+        kk = closures ? pick_lane(kk, rd.nlanes, rd.closed) : min(kk, rd.nlanes - 1);
         Tail tl;
         if (h == 0 && pre)
             tl = tl0;
         else
-            tl = d.tails[rd.lane0 + kk];
+            tl = at(d.tails, rd.lane0 + kk);
         if (tl.id != kNone) {
             if (tl.id != id) {
                 r.has = true;
@@ -179,7 +194,7 @@ __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id
         }
         dist = dist + rd.L;
         p += 1;
-        nr = d.route[p + 1];
+        nr = at(d.route, p + 1);
     }
     return r;
 }
@@ -263,20 +278,22 @@ __global__ void k_insert(Dev d)
     float vins = 0.0f;
     // the head's departure step is kept per queue, so that lanes with nothing
     // due leave after one coalesced load
-    if (q < d.n_qlanes && (int64_t)d.q_hdep[q] <= *d.t) {
-        l = d.qlanes[q];
-        h = d.q_head[l];
+    if (q < d.n_qlanes && (int64_t)at(d.q_hdep, q) <= *d.t) {
+        l = at(d.qlanes, q);
+        h = at(d.q_head, l);
         {
-            const LaneInfo li = d.lanes[l];
-            const float v0e = fmin32(d.q_v0[h], li.vlim);
-            const int lo = d.ls_old[l], hi = d.ls_old[l + 1];
+            const LaneInfo li = at(d.lanes, l);
+            const float v0e = fmin32(at(d.q_v0, h), li.vlim);
+            const int lo = at(d.ls_old, l), hi = at(d.ls_old, l + 1);
             bool ok;
-            if (lo == hi) {
+            if (li.closed) {
+                ok = false;     // a closed lane holds its departure queue
+            } else if (lo == hi) {
                 ok = true;
                 vins = v0e;
             } else {
-                vins = fmin32(v0e, d.S.v[lo]);
-                ok = (d.S.s[lo] - P.len) >= (P.s0 + vins * P.T);
+                vins = fmin32(v0e, at(d.S.v, lo));
+                ok = (at(d.S.s, lo) - P.len) >= (P.s0 + vins * P.T);
             }
             scen = li.scen;
             ins = ok;
@@ -290,20 +307,20 @@ __global__ void k_insert(Dev d)
     // are marked kNone.
     if (q < d.n_qlanes) {
         const uint32_t slot = (uint32_t)(*d.n_cur) + (uint32_t)q;
-        d.jins_list[q] = slot;
-        d.jins_lane[q] = ins ? (uint32_t)l : kNone;
+        at(d.jins_list, q) = slot;
+        at(d.jins_lane, q) = ins ? (uint32_t)l : kNone;
         if (ins) {
-            d.Pr.s[slot] = 0.0f;
-            d.Pr.v[slot] = vins;
-            d.Pr.a[slot] = 0.0f;
-            d.Pr.id[slot] = d.q_id[h];
-            d.Pr.lane[slot] = (uint32_t)l | kJoinBit;
-            d.Pr.ptr[slot] = d.q_ptr[h];
-            d.Pr.next[slot] = d.q_next[h];
-            d.Pr.v0[slot] = d.q_v0[h];
-            atomicAdd(d.jcount + l, 1);
-            d.q_head[l] = h + 1;
-            d.q_hdep[q] = h + 1 < d.q_end[l] ? d.q_dep[h + 1] : INT32_MAX;
+            at(d.Pr.s, slot) = 0.0f;
+            at(d.Pr.v, slot) = vins;
+            at(d.Pr.a, slot) = 0.0f;
+            at(d.Pr.id, slot) = at(d.q_id, h);
+            at(d.Pr.lane, slot) = (uint32_t)l | kJoinBit;
+            at(d.Pr.ptr, slot) = at(d.q_ptr, h);
+            at(d.Pr.next, slot) = at(d.q_next, h);
+            at(d.Pr.v0, slot) = at(d.q_v0, h);
+            atomicAdd(&at(d.jcount, l), 1);
+            at(d.q_head, l) = h + 1;
+            at(d.q_hdep, q) = h + 1 < at(d.q_end, l) ? at(d.q_dep, h + 1) : INT32_MAX;
         }
     }
     if (q == 0)
@@ -358,7 +375,7 @@ __device__ __forceinline__ int xcd_tile(int remap, int ntiles)
 // Joiners are listed in the tile's own region of jlist, so no atomic result
 // is waited for.  MODE 1 evaluates the learned closure for the wave's 64
 // vehicles on the matrix cores between the acceleration and the integration.
-template <int MODE, bool AUX>
+template <int MODE, bool AUX, bool CLOSED>
 __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
@@ -367,6 +384,9 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 
     const int n = *d.n_cur;
     const int64_t t = *d.t;
+    // lane closures by control change the lane taken on the next road (the
+    // variant without them is launched while no lane is closed)
+    constexpr bool closures = CLOSED;
     const Params &P = d.P;
     const uint32_t tt = (uint32_t)t;
     const int tid = threadIdx.x;
@@ -395,10 +415,10 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         int32_t nxt = -1;
         float a_prev = 0.0f;
         if (act) {
-            ptr = d.S.ptr[i];
-            nxt = d.S.next[i];
+            ptr = at(d.S.ptr, i);
+            nxt = at(d.S.next, i);
             if (want_feat)
-                a_prev = d.S.a[i];
+                a_prev = at(d.S.a, i);
         }
         __syncthreads();
         if (tid == 0)
@@ -409,10 +429,10 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         {
             const int r0 = ws + tid, r1 = ws + tid + kUT;
             const int q0 = min(r0, we - 1), q1 = min(r1, we - 1);
-            const float s0 = d.S.s[q0], v0a = d.S.v[q0], v00 = d.S.v0[q0];
-            const uint32_t id0 = d.S.id[q0], ln0 = d.S.lane[q0];
-            const float s1 = d.S.s[q1], v1a = d.S.v[q1], v01 = d.S.v0[q1];
-            const uint32_t id1 = d.S.id[q1], ln1 = d.S.lane[q1];
+            const float s0 = at(d.S.s, q0), v0a = at(d.S.v, q0), v00 = at(d.S.v0, q0);
+            const uint32_t id0 = at(d.S.id, q0), ln0 = at(d.S.lane, q0);
+            const float s1 = at(d.S.s, q1), v1a = at(d.S.v, q1), v01 = at(d.S.v0, q1);
+            const uint32_t id1 = at(d.S.id, q1), ln1 = at(d.S.lane, q1);
             if (r0 < we) {
                 w_s[r0 - ws] = s0;
                 w_v[r0 - ws] = v0a;
@@ -440,12 +460,15 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         const bool side_ok = act && ls_side >= 0 && ls_side < d.n_lanes;
         const int ls_c = side_ok ? ls_side : (int)l;
         const bool head_next = act && !hasLc && nxt >= 0;
-        const LaneInfo li = d.lanes[l];
-        const uint8_t red_raw = d.lane_red[l];
-        const float vlim_c_side = d.lanes[ls_c].vlim;
-        const int r0_c = d.ls_old[ls_c], r1_c = d.ls_old[ls_c + 1];
-        const RoadInfo rd_c = d.roads[head_next ? nxt : 0];
-        const bool red_now = act && red_raw != 0;
+        const LaneInfo li = at(d.lanes, l);
+        const uint8_t red_raw = at(d.lane_red, l);
+        const float vlim_c_side = at(d.lanes, ls_c).vlim;
+        const uint8_t side_flags = CLOSED ? at(d.lane_red, ls_c) : (uint8_t)0;
+        const int r0_c = at(d.ls_old, ls_c), r1_c = at(d.ls_old, ls_c + 1);
+        const RoadInfo rd_c = at(d.roads, head_next ? nxt : 0);
+        const bool red_now = act && (red_raw & kRedBit) != 0;
+        // a lane closed by control is never a lane-change target
+        const bool side_open = (side_flags & kClosedBit) == 0;
         const float vlim_side = side_ok ? vlim_c_side : 0.0f;
         // rows of the side lane (the MOBIL target when it is on the same road)
         const int side_r0 = side_ok ? r0_c : 0;
@@ -461,11 +484,13 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         // 0 for the other vehicles)
         Tail tl_own, tl_side;
         {
-            const int nl1 = rd_c.nlanes - 1;
-            const int k_own = min((int)li.k, nl1);
-            const int k_side = min(max((int)li.k + side, 0), nl1);
-            tl_own = d.tails[head_next ? rd_c.lane0 + k_own : 0];
-            tl_side = d.tails[head_next ? rd_c.lane0 + k_side : 0];
+            const int k_own = closures ? pick_lane((int)li.k, rd_c.nlanes, rd_c.closed)
+                                       : min((int)li.k, rd_c.nlanes - 1);
+            const int k_side = closures ? pick_lane(max((int)li.k + side, 0), rd_c.nlanes,
+                                                    rd_c.closed)
+                                        : min(max((int)li.k + side, 0), rd_c.nlanes - 1);
+            tl_own = at(d.tails, head_next ? rd_c.lane0 + k_own : 0);
+            tl_side = at(d.tails, head_next ? rd_c.lane0 + k_side : 0);
         }
         const int scen0 = __builtin_amdgcn_readlane(li.scen, 0);
         const bool uni_scen = __all(!act || li.scen == scen0);
@@ -519,7 +544,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             uint32_t idLt = kNone;
             if (s >= 0.0f) {
                 const int kt = (int)li.k + side;
-                if (kt >= 0 && kt < (int)li.nlanes) {
+                if (kt >= 0 && kt < (int)li.nlanes && side_open) {
                     mobil = true;
                     lt = ls_side;
                     float sN = 0.0f, vN = 0.0f, v0N = 0.0f;
@@ -541,17 +566,17 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                         int lo2 = g0, hi2 = g1;
                         while (lo2 < hi2) {
                             int mid = (lo2 + hi2) >> 1;
-                            if (d.S.s[mid] >= s)
+                            if (at(d.S.s, mid) >= s)
                                 hi2 = mid;
                             else
                                 lo2 = mid + 1;
                         }
                         if (lo2 < g1) {
-                            hasLt = true; sLt = d.S.s[lo2]; vLt = d.S.v[lo2]; idLt = d.S.id[lo2];
+                            hasLt = true; sLt = at(d.S.s, lo2); vLt = at(d.S.v, lo2); idLt = at(d.S.id, lo2);
                         }
                         if (lo2 - 1 >= g0) {
-                            hasN = true; sN = d.S.s[lo2 - 1]; vN = d.S.v[lo2 - 1];
-                            v0N = d.S.v0[lo2 - 1]; idN = d.S.id[lo2 - 1];
+                            hasN = true; sN = at(d.S.s, lo2 - 1); vN = at(d.S.v, lo2 - 1);
+                            v0N = at(d.S.v0, lo2 - 1); idN = at(d.S.id, lo2 - 1);
                         }
                     }
                     const float vlim_c = li.vlim, vlim_t = vlim_side;
@@ -615,11 +640,11 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 lead_id = change ? idLt : w_id[x_i + 1];
             } else {
                 if (!rd_ok && nxt >= 0) {
-                    rd_next = d.roads[nxt];
+                    rd_next = at(d.roads, nxt);
                     rd_ok = true;
                 }
                 const Lead ld = lookahead(d, lif, s, id, ptr, nxt, rd_next, head_next,
-                                          change ? tl_side : tl_own);
+                                          change ? tl_side : tl_own, closures);
                 if (ld.has) flags |= 8;
                 has_lead = ld.has;
                 lead_v = ld.v;
@@ -654,15 +679,15 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             if (act && trc) {
 #pragma unroll
                 for (int q = 0; q < kMlpIn; ++q)
-                    d.tr_feat[(size_t)i * kMlpIn + q] = feat[q];
-                d.tr_label[i] = a_idm;
+                    at(d.tr_feat, (size_t)i * kMlpIn + q) = feat[q];
+                at(d.tr_label, i) = a_idm;
             }
             if (act && dbg) {
-                d.d_id[i] = id;
-                d.d_leader[i] = lead_id;
-                d.d_margin[i] = margin;
-                d.d_tl[i] = tl_id;
-                d.d_tf[i] = tf_id;
+                at(d.d_id, i) = id;
+                at(d.d_leader, i) = lead_id;
+                at(d.d_margin, i) = margin;
+                at(d.d_tl, i) = tl_id;
+                at(d.d_tf, i) = tf_id;
             }
             // learned closure for the whole wave; inside the envelope it
             // replaces the IDM acceleration, limited to [-b_max, a_max]
@@ -699,11 +724,11 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 v = w_v[x_i];
                 id = w_id[x_i];
                 v0 = w_v0[x_i];
-                ptr0 = d.S.ptr[i];
+                ptr0 = at(d.S.ptr, i);
                 p = ptr0;
-                nr = d.S.next[i];
+                nr = at(d.S.next, i);
                 rd_ok = false;
-                const LaneInfo lr = d.lanes[l];
+                const LaneInfo lr = at(d.lanes, l);
                 lif.L = lr.L;
                 lif.k = (uint8_t)((int)lr.k + (change ? side : 0));
             }
@@ -729,13 +754,12 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             while (sp >= Lx && nr >= 0) {
                 sp = sp - Lx;
                 p += 1;
-                const RoadInfo rd = (first && rd_ok) ? rd_next : d.roads[nr];
+                const RoadInfo rd = (first && rd_ok) ? rd_next : at(d.roads, nr);
                 first = false;
-                if (kk > rd.nlanes - 1)
-                    kk = rd.nlanes - 1;
+                kk = closures ? pick_lane(kk, rd.nlanes, rd.closed) : min(kk, rd.nlanes - 1);
                 x = rd.lane0 + kk;
                 Lx = rd.L;
-                nr = d.route[p + 1];
+                nr = at(d.route, p + 1);
             }
             arrived = sp >= Lx;
             joins = !arrived && !(x == (int)l && p == ptr0);
@@ -744,20 +768,20 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             if (arrived)
                 flags |= 16;
             if (dbg) {
-                d.d_flags[i] = flags;
+                at(d.d_flags, i) = flags;
                 if constexpr (MODE == 0) {
-                    d.d_id[i] = id;
-                    d.d_leader[i] = lead_id;
-                    d.d_margin[i] = margin;
-                    d.d_tl[i] = tl_id;
-                    d.d_tf[i] = tf_id;
+                    at(d.d_id, i) = id;
+                    at(d.d_leader, i) = lead_id;
+                    at(d.d_margin, i) = margin;
+                    at(d.d_tl, i) = tl_id;
+                    at(d.d_tf, i) = tf_id;
                 }
             }
             if (MODE == 0 && trc) {
 #pragma unroll
                 for (int q = 0; q < kMlpIn; ++q)
-                    d.tr_feat[(size_t)i * kMlpIn + q] = feat[q];
-                d.tr_label[i] = a_idm;
+                    at(d.tr_feat, (size_t)i * kMlpIn + q) = feat[q];
+                at(d.tr_label, i) = a_idm;
             }
         }
 
@@ -773,34 +797,35 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         }
         if (act) {
             if (arrived || joins)
-                atomicAdd(d.leave + l, 1);
+                atomicAdd(&at(d.leave, l), 1);
             if (arrived) {
                 // the route array stores the departure step after the -1 that
                 // ends the route
-                const int32_t dep = d.route[p + 2];
+                const int32_t dep = at(d.route, p + 2);
+                at(d.route, p + 3) = (int32_t)(t + 1);      // arrival step
                 atomicAdd(cnt_at(d, li.scen, C_TRIP_TIME),
                           (unsigned long long)((t + 1) - (int64_t)dep));
             } else if (joins) {
                 const int lane_id = __lane_id();
                 const unsigned long long below = lane_id ? (~0ull >> (64 - lane_id)) : 0ull;
                 const uint32_t slot = (uint32_t)base + jbase + (uint32_t)__popcll(jm & below);
-                d.jlist[slot] = (uint32_t)i;
-                d.jlane[slot] = (uint32_t)x;
-                atomicAdd(d.jcount + x, 1);
+                at(d.jlist, slot) = (uint32_t)i;
+                at(d.jlane, slot) = (uint32_t)x;
+                atomicAdd(&at(d.jcount, x), 1);
             }
             // (id and v0 of the row are already in Pr: the step's id/v0 buffer)
-            d.Pr.s[i] = sp;
-            d.Pr.v[i] = vn;
-            d.Pr.a[i] = a;
-            d.Pr.lane[i] = l | ((arrived || joins) ? kJoinBit : 0u);
-            d.Pr.ptr[i] = p;
-            d.Pr.next[i] = nr;
+            at(d.Pr.s, i) = sp;
+            at(d.Pr.v, i) = vn;
+            at(d.Pr.a, i) = a;
+            at(d.Pr.lane, i) = l | ((arrived || joins) ? kJoinBit : 0u);
+            at(d.Pr.ptr, i) = p;
+            at(d.Pr.next, i) = nr;
         }
         wave_count(d, C_ARRIVED, arrived, li.scen, scen0, uni_scen);
         wave_count(d, C_LANE_CHANGES, change, li.scen, scen0, uni_scen);
         __syncthreads();
         if (tid == 0)
-            d.jcnt[base / kUT] = (int32_t)s_jn;
+            at(d.jcnt, base / kUT) = (int32_t)s_jn;
     }
 }
 
@@ -832,8 +857,8 @@ __device__ __forceinline__ void block_scan2(int &x, int &y, int *sh)
 // new lane size = old size - vehicles leaving + vehicles joining
 __device__ __forceinline__ int new_count(const Dev &d, int l, int &j)
 {
-    j = d.jcount[l];
-    return (d.ls_old[l + 1] - d.ls_old[l]) - d.leave[l] + j;
+    j = at(d.jcount, l);
+    return (at(d.ls_old, l + 1) - at(d.ls_old, l)) - at(d.leave, l) + j;
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Dev d)
@@ -851,8 +876,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Dev d)
     }
     block_scan2(tot, tj, sh);
     if (threadIdx.x == kScanThreads - 1) {
-        d.blk[2 * blockIdx.x] = tot;
-        d.blk[2 * blockIdx.x + 1] = tj;
+        at(d.blk, 2 * blockIdx.x) = tot;
+        at(d.blk, 2 * blockIdx.x + 1) = tj;
     }
 }
 
@@ -862,8 +887,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
     const int b = blockIdx.x;
     int off = 0, offj = 0;
     for (int q = threadIdx.x; q < b; q += kScanThreads) {
-        off += d.blk[2 * q];
-        offj += d.blk[2 * q + 1];
+        off += at(d.blk, 2 * q);
+        offj += at(d.blk, 2 * q + 1);
     }
     block_scan2(off, offj, sh);
     __shared__ int base_tot, base_j;
@@ -892,30 +917,30 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(Dev d)
     for (int q = 0; q < kScanPer; ++q) {
         int l = base + q;
         if (l < d.n_lanes) {
-            d.ls_new[l] = run;
-            d.joff[l] = runj;
-            d.jcur[l] = runj;
-            d.leave[l] = 0;
-            d.jcount[l] = 0;
+            at(d.ls_new, l) = run;
+            at(d.joff, l) = runj;
+            at(d.jcur, l) = runj;
+            at(d.leave, l) = 0;
+            at(d.jcount, l) = 0;
             // red light of the lane's road at the next step
-            d.lane_red[l] = lane_red_at(d.lanes[l], tnext) ? 1 : 0;
+            at(d.lane_red, l) = lane_flags_at(at(d.lanes, l), tnext);
             // chunks past lane l's and up to lane l+1's begin at lane l+1:
             // record its lane, new start, old start and joiner offset
             for (int w = chunk_of(l, run) + 1; w <= chunk_of(l + 1, run + cnt[q]); ++w)
-                d.chunk[w] = make_int4(l + 1, run + cnt[q], d.ls_old[l + 1], runj + jc[q]);
+                at(d.chunk, w) = make_int4(l + 1, run + cnt[q], at(d.ls_old, l + 1), runj + jc[q]);
         }
         run += cnt[q];
         runj += jc[q];
     }
     if (b == 0 && threadIdx.x == 0)
-        d.chunk[0] = make_int4(0, 0, 0, 0);
+        at(d.chunk, 0) = make_int4(0, 0, 0, 0);
     if (b == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
-        d.ls_new[d.n_lanes] = run;
-        d.joff[d.n_lanes] = runj;
+        at(d.ls_new, d.n_lanes) = run;
+        at(d.joff, d.n_lanes) = runj;
         *d.n_next = run;
         // upper bound of the last chunk (merge blocks past it read nothing)
-        d.chunk[chunk_of(d.n_lanes, run) + 1] =
-            make_int4(d.n_lanes, run, d.ls_old[d.n_lanes], runj);
+        at(d.chunk, chunk_of(d.n_lanes, run) + 1) =
+            make_int4(d.n_lanes, run, at(d.ls_old, d.n_lanes), runj);
     }
 }
 
@@ -937,7 +962,7 @@ __global__ void __launch_bounds__(256) k_jscatter(Dev d)
          tile += waves) {
         const bool ins = tile >= ntiles;
         const int k0 = ins ? (tile - ntiles) * kUpdateRows : 0;
-        const int cnt = ins ? min(kUpdateRows, nins - k0) : d.jcnt[tile];
+        const int cnt = ins ? min(kUpdateRows, nins - k0) : at(d.jcnt, tile);
         const uint32_t *lst = ins ? d.jins_list + k0 : d.jlist + (size_t)tile * kUpdateRows;
         const uint32_t *lan = ins ? d.jins_lane + k0 : d.jlane + (size_t)tile * kUpdateRows;
         for (int k = lane; k < cnt; k += 64) {
@@ -945,19 +970,19 @@ __global__ void __launch_bounds__(256) k_jscatter(Dev d)
             if (x == kNone)
                 continue;       // a queue lane that inserted nothing
             // the record's loads do not wait for the slot
-            const float s = d.Pr.s[src], v = d.Pr.v[src], a = d.Pr.a[src], v0 = d.Pr.v0[src];
-            const uint32_t id = d.Pr.id[src], ptr = d.Pr.ptr[src];
-            const int32_t next = d.Pr.next[src];
-            const int pos = atomicAdd(d.jcur + x, 1);
-            d.jidx[pos] = src;
-            d.J.lane[pos] = x;
-            d.J.s[pos] = s;
-            d.J.v[pos] = v;
-            d.J.a[pos] = a;
-            d.J.id[pos] = id;
-            d.J.ptr[pos] = ptr;
-            d.J.next[pos] = next;
-            d.J.v0[pos] = v0;
+            const float s = at(d.Pr.s, src), v = at(d.Pr.v, src), a = at(d.Pr.a, src), v0 = at(d.Pr.v0, src);
+            const uint32_t id = at(d.Pr.id, src), ptr = at(d.Pr.ptr, src);
+            const int32_t next = at(d.Pr.next, src);
+            const int pos = atomicAdd(&at(d.jcur, x), 1);
+            at(d.jidx, pos) = src;
+            at(d.J.lane, pos) = x;
+            at(d.J.s, pos) = s;
+            at(d.J.v, pos) = v;
+            at(d.J.a, pos) = a;
+            at(d.J.id, pos) = id;
+            at(d.J.ptr, pos) = ptr;
+            at(d.J.next, pos) = next;
+            at(d.J.v0, pos) = v0;
         }
     }
 }
@@ -976,10 +1001,10 @@ __global__ void __launch_bounds__(256) k_jscatter(Dev d)
 
 __device__ __forceinline__ bool key_less(const Dev &d, uint32_t a, uint32_t b)
 {
-    float sa = d.Pr.s[a], sb = d.Pr.s[b];
+    float sa = at(d.Pr.s, a), sb = at(d.Pr.s, b);
     if (sa != sb)
         return sa < sb;
-    return d.Pr.id[a] < d.Pr.id[b];
+    return at(d.Pr.id, a) < at(d.Pr.id, b);
 }
 
 // (s, id) as one unsigned key with the order of the float comparison followed
@@ -994,14 +1019,14 @@ __device__ __forceinline__ uint64_t okey(float s, uint32_t id)
 __device__ __forceinline__ void write_row(const Dev &d, int w, uint32_t src, uint32_t lane, float s,
                                           float v)
 {
-    d.S.s[w] = s;
-    d.S.v[w] = v;
-    d.S.a[w] = d.Pr.a[src];
-    d.id_next[w] = d.Pr.id[src];
-    d.S.lane[w] = lane;
-    d.S.ptr[w] = d.Pr.ptr[src];
-    d.S.next[w] = d.Pr.next[src];
-    d.v0_next[w] = d.Pr.v0[src];
+    at(d.S.s, w) = s;
+    at(d.S.v, w) = v;
+    at(d.S.a, w) = at(d.Pr.a, src);
+    at(d.id_next, w) = at(d.Pr.id, src);
+    at(d.S.lane, w) = lane;
+    at(d.S.ptr, w) = at(d.Pr.ptr, src);
+    at(d.S.next, w) = at(d.Pr.next, src);
+    at(d.v0_next, w) = at(d.Pr.v0, src);
 }
 
 __device__ __forceinline__ void write_tail(const Dev &d, int l, bool any, float s, float v,
@@ -1012,7 +1037,7 @@ __device__ __forceinline__ void write_tail(const Dev &d, int l, bool any, float 
     tl.s = any ? s : 0.0f;
     tl.v = any ? v : 0.0f;
     tl.id = any ? id : kNone;
-    d.tails[l] = tl;
+    at(d.tails, l) = tl;
 }
 
 // Merge of one lane straight from global memory, walking both lists (used for
@@ -1021,21 +1046,21 @@ __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned lo
 {
     vsum = 0.0;
     clamps = 0;
-    const int o0 = d.ls_old[l], o1 = d.ls_old[l + 1];
-    const int j0 = d.joff[l], j1 = d.joff[l + 1];
-    const int w0 = d.ls_new[l], w1 = d.ls_new[l + 1];
+    const int o0 = at(d.ls_old, l), o1 = at(d.ls_old, l + 1);
+    const int j0 = at(d.joff, l), j1 = at(d.joff, l + 1);
+    const int w0 = at(d.ls_new, l), w1 = at(d.ls_new, l + 1);
     for (int a = j0 + 1; a < j1; ++a) {
-        uint32_t xk = d.jidx[a];
+        uint32_t xk = at(d.jidx, a);
         int b = a - 1;
-        while (b >= j0 && key_less(d, xk, d.jidx[b])) {
-            d.jidx[b + 1] = d.jidx[b];
+        while (b >= j0 && key_less(d, xk, at(d.jidx, b))) {
+            at(d.jidx, b + 1) = at(d.jidx, b);
             --b;
         }
-        d.jidx[b + 1] = xk;
+        at(d.jidx, b + 1) = xk;
     }
     int ip = o0, jp = j0, w = w0;
     for (;;) {
-        while (ip < o1 && (d.Pr.lane[ip] & kJoinBit))
+        while (ip < o1 && (at(d.Pr.lane, ip) & kJoinBit))
             ++ip;
         const bool hs = ip < o1, hj = jp < j1;
         if (!hs && !hj)
@@ -1045,26 +1070,26 @@ __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned lo
             break;
         }
         uint32_t src;
-        if (hs && (!hj || key_less(d, (uint32_t)ip, d.jidx[jp])))
+        if (hs && (!hj || key_less(d, (uint32_t)ip, at(d.jidx, jp))))
             src = (uint32_t)ip++;
         else
-            src = d.jidx[jp++];
-        write_row(d, w, src, (uint32_t)l, d.Pr.s[src], d.Pr.v[src]);
+            src = at(d.jidx, jp++);
+        write_row(d, w, src, (uint32_t)l, at(d.Pr.s, src), at(d.Pr.v, src));
         ++w;
     }
     if (w != w1)
         atomicOr(d.err, 1u);
     for (int f = w1 - 2; f >= w0; --f) {
-        float lim = d.S.s[f + 1] - d.P.len;
-        if (d.S.s[f] > lim) {
-            d.S.s[f] = lim;
-            d.S.v[f] = fmin32(d.S.v[f], d.S.v[f + 1]);
+        float lim = at(d.S.s, f + 1) - d.P.len;
+        if (at(d.S.s, f) > lim) {
+            at(d.S.s, f) = lim;
+            at(d.S.v, f) = fmin32(at(d.S.v, f), at(d.S.v, f + 1));
             ++clamps;
         }
     }
-    write_tail(d, l, w1 > w0, d.S.s[w0], d.S.v[w0], d.id_next[w0]);
+    write_tail(d, l, w1 > w0, at(d.S.s, w0), at(d.S.v, w0), at(d.id_next, w0));
     for (int f = w0; f < w1; ++f)
-        vsum += (double)d.S.v[f];
+        vsum += (double)at(d.S.v, f);
 }
 
 constexpr int kMT = 256;          // threads per merge block (4 waves)
@@ -1170,36 +1195,36 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
     const bool lt_ok = lb - la <= kLaneCap;
     static_assert(kLaneCap + 1 <= kMT, "one lane-table entry per thread");
     const int qc = la + min(tid, lb - la);
-    const int lt_o = d.ls_old[qc], lt_n = d.ls_new[qc], lt_j = d.joff[qc];
+    const int lt_o = at(d.ls_old, qc), lt_n = at(d.ls_new, qc), lt_j = at(d.joff, qc);
     float rs[3], rv[3], ra[3], rv0[3];
     uint32_t rl[3], rid[3], rptr[3];
     int32_t rnext[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int r = no > 0 ? o0 + min(tid + k * kMT, no - 1) : 0;
-        rs[k] = d.Pr.s[r];
-        rv[k] = d.Pr.v[r];
-        rl[k] = d.Pr.lane[r];
-        rid[k] = d.Pr.id[r];
-        ra[k] = d.Pr.a[r];
-        rptr[k] = d.Pr.ptr[r];
-        rnext[k] = d.Pr.next[r];
-        rv0[k] = d.Pr.v0[r];
+        rs[k] = at(d.Pr.s, r);
+        rv[k] = at(d.Pr.v, r);
+        rl[k] = at(d.Pr.lane, r);
+        rid[k] = at(d.Pr.id, r);
+        ra[k] = at(d.Pr.a, r);
+        rptr[k] = at(d.Pr.ptr, r);
+        rnext[k] = at(d.Pr.next, r);
+        rv0[k] = at(d.Pr.v0, r);
     }
     const int qj = nj > 0 ? j0 + min(tid, nj - 1) : 0;
-    const float js = d.J.s[qj], jv = d.J.v[qj];
-    const uint32_t jid = d.J.id[qj], jl = d.J.lane[qj];
-    const float ja = d.J.a[qj], jv0 = d.J.v0[qj];
-    const uint32_t jptr = d.J.ptr[qj];
-    const int32_t jnext = d.J.next[qj];
+    const float js = at(d.J.s, qj), jv = at(d.J.v, qj);
+    const uint32_t jid = at(d.J.id, qj), jl = at(d.J.lane, qj);
+    const float ja = at(d.J.a, qj), jv0 = at(d.J.v0, qj);
+    const uint32_t jptr = at(d.J.ptr, qj);
+    const int32_t jnext = at(d.J.next, qj);
     if (lt_ok && tid <= lb - la) {
         lt_old[tid] = lt_o;
         lt_new[tid] = lt_n;
         lt_jo[tid] = lt_j;
     }
-    auto LO = [&](int l) { return lt_ok ? lt_old[l - la] : d.ls_old[l]; };
-    auto LN = [&](int l) { return lt_ok ? lt_new[l - la] : d.ls_new[l]; };
-    auto JO = [&](int l) { return lt_ok ? lt_jo[l - la] : d.joff[l]; };
+    auto LO = [&](int l) { return lt_ok ? lt_old[l - la] : at(d.ls_old, l); };
+    auto LN = [&](int l) { return lt_ok ? lt_new[l - la] : at(d.ls_new, l); };
+    auto JO = [&](int l) { return lt_ok ? lt_jo[l - la] : at(d.joff, l); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int r = tid + k * kMT;
@@ -1304,12 +1329,12 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
         if (pos >= 0 && pos < nw) {
             w_src[pos] = (uint16_t)(kTagJ | e);
             const int g = n0 + pos;
-            d.S.a[g] = ja;
-            d.id_next[g] = j_id[e];
-            d.S.lane[g] = l;
-            d.S.ptr[g] = jptr;
-            d.S.next[g] = jnext;
-            d.v0_next[g] = jv0;
+            at(d.S.a, g) = ja;
+            at(d.id_next, g) = j_id[e];
+            at(d.S.lane, g) = l;
+            at(d.S.ptr, g) = jptr;
+            at(d.S.next, g) = jnext;
+            at(d.v0_next, g) = jv0;
         } else {
             atomicOr(d.err, 1u);
         }
@@ -1340,12 +1365,12 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
         if (pos >= 0 && pos < nw) {
             w_src[pos] = (uint16_t)r;
             const int g = n0 + pos;
-            d.S.a[g] = ra[k];
-            d.id_next[g] = o_id[r];
-            d.S.lane[g] = ln;
-            d.S.ptr[g] = rptr[k];
-            d.S.next[g] = rnext[k];
-            d.v0_next[g] = rv0[k];
+            at(d.S.a, g) = ra[k];
+            at(d.id_next, g) = o_id[r];
+            at(d.S.lane, g) = ln;
+            at(d.S.ptr, g) = rptr[k];
+            at(d.S.next, g) = rnext[k];
+            at(d.v0_next, g) = rv0[k];
         } else {
             atomicOr(d.err, 1u);
         }
@@ -1405,7 +1430,7 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
                 else { o_s[kf] = sf; o_v[kf] = vf; }
                 ++clamps;
                 if (!one_scen)
-                    atomicAdd(cnt_at(d, d.lanes[lane_of(w_src[k])].scen, C_CLAMPS), 1ull);
+                    atomicAdd(cnt_at(d, at(d.lanes, lane_of(w_src[k])).scen, C_CLAMPS), 1ull);
             } else if (f < bot) {
                 break;
             }
@@ -1440,12 +1465,12 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
             const uint32_t e = x & ~kTagJ;
             const float s = jx ? j_s[e] : o_s[e];
             v = jx ? j_v[e] : o_v[e];
-            d.S.s[n0 + k] = s;
-            d.S.v[n0 + k] = v;
+            at(d.S.s, n0 + k) = s;
+            at(d.S.v, n0 + k) = v;
             if (one_scen)
                 vsum += (double)v;
             else
-                sc = d.lanes[lane_of(x)].scen;
+                sc = at(d.lanes, lane_of(x)).scen;
         }
         if (!one_scen) {
             wave_count_scen(d, C_VEH_STEPS, ok, sc);
@@ -1463,15 +1488,15 @@ __device__ void merge_lanes_global(const Dev &d, const int la, const int lb, con
         double ls;
         unsigned long long lc;
         merge_lane_global(d, l, ls, lc);
-        const int cnt = d.ls_new[l + 1] - d.ls_new[l];
+        const int cnt = at(d.ls_new, l + 1) - at(d.ls_new, l);
         if (one_scen) {
             vsum += ls;
             clamps += lc;
         } else {
-            unsigned long long *c = cnt_at(d, d.lanes[l].scen, 0);
+            unsigned long long *c = cnt_at(d, at(d.lanes, l).scen, 0);
             if (cnt) {
                 atomicAdd(c + C_VEH_STEPS, (unsigned long long)cnt);
-                atomicAdd(sv_at(d, d.sumv, d.lanes[l].scen), ls);
+                atomicAdd(sv_at(d, d.sumv, at(d.lanes, l).scen), ls);
             }
             if (lc) atomicAdd(c + C_CLAMPS, lc);
         }
@@ -1502,20 +1527,20 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     // guess is wrong; w is uniform, every thread reads the same records.
     const int wg = min(xcd_tile(d.xcd_remap, (int)gridDim.x),
                        d.cap / kMC + d.n_lanes / kMergeLanes + 1);
-    int4 ca = d.chunk[wg], cb = d.chunk[wg + 1];
+    int4 ca = at(d.chunk, wg), cb = at(d.chunk, wg + 1);
     const int n_next = *d.n_next;
     const int nch = chunk_of(d.n_lanes, n_next);     // the last chunk
     const int w = xcd_tile(d.xcd_remap, nch + 1);
     if (w > nch)
         return;
     if (w != wg) {
-        ca = d.chunk[w];
-        cb = d.chunk[w + 1];
+        ca = at(d.chunk, w);
+        cb = at(d.chunk, w + 1);
     }
     const int la = ca.x, lb = cb.x;
     const int n0 = ca.y, n1 = cb.y, o0 = ca.z, o1 = cb.z, j0 = ca.w, j1 = cb.w;
     const int nw = n1 - n0;
-    const bool one_scen = (lb <= la) || d.lanes[la].scen == d.lanes[lb - 1].scen;
+    const bool one_scen = (lb <= la) || at(d.lanes, la).scen == at(d.lanes, lb - 1).scen;
     double vsum = 0.0;
     unsigned long long clamps = 0;
 
@@ -1526,7 +1551,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             int lo = ga, hi = lb;      // [ga, lo) fits, [ga, hi) does not
             while (hi - lo > 1) {
                 const int mid = lo + ((hi - lo) >> 1);
-                if (group_fits(d.ls_new[mid] - g_n0, d.ls_old[mid] - g_o0, d.joff[mid] - g_j0,
+                if (group_fits(at(d.ls_new, mid) - g_n0, at(d.ls_old, mid) - g_o0, at(d.joff, mid) - g_j0,
                                mid - ga))
                     lo = mid;
                 else
@@ -1546,23 +1571,23 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     int ga = la;
     int gb = group_fits(nw, o1 - o0, j1 - j0, lb - la) ? lb : longest_fit(la, n0, o0, j0);
     if (gb > ga) {
-        const int g_n1 = gb == lb ? n1 : __builtin_amdgcn_readfirstlane(d.ls_new[gb]);
-        const int g_o1 = gb == lb ? o1 : __builtin_amdgcn_readfirstlane(d.ls_old[gb]);
-        const int g_j1 = gb == lb ? j1 : __builtin_amdgcn_readfirstlane(d.joff[gb]);
+        const int g_n1 = gb == lb ? n1 : __builtin_amdgcn_readfirstlane(at(d.ls_new, gb));
+        const int g_o1 = gb == lb ? o1 : __builtin_amdgcn_readfirstlane(at(d.ls_old, gb));
+        const int g_j1 = gb == lb ? j1 : __builtin_amdgcn_readfirstlane(at(d.joff, gb));
         merge_group(d, ga, gb, n0, g_n1, o0, g_o1, j0, g_j1, one_scen, vsum, clamps);
         ga = gb;
     }
     if (ga < lb) {
         __syncthreads();               // the LDS tile is reused
-        const int g_n0 = __builtin_amdgcn_readfirstlane(d.ls_new[ga]);
-        const int g_o0 = __builtin_amdgcn_readfirstlane(d.ls_old[ga]);
-        const int g_j0 = __builtin_amdgcn_readfirstlane(d.joff[ga]);
+        const int g_n0 = __builtin_amdgcn_readfirstlane(at(d.ls_new, ga));
+        const int g_o0 = __builtin_amdgcn_readfirstlane(at(d.ls_old, ga));
+        const int g_j0 = __builtin_amdgcn_readfirstlane(at(d.joff, ga));
         gb = group_fits(n1 - g_n0, o1 - g_o0, j1 - g_j0, lb - ga) ? lb
                                                                   : longest_fit(ga, g_n0, g_o0, g_j0);
         if (gb > ga) {
-            const int g_n1 = __builtin_amdgcn_readfirstlane(d.ls_new[gb]);
-            const int g_o1 = __builtin_amdgcn_readfirstlane(d.ls_old[gb]);
-            const int g_j1 = __builtin_amdgcn_readfirstlane(d.joff[gb]);
+            const int g_n1 = __builtin_amdgcn_readfirstlane(at(d.ls_new, gb));
+            const int g_o1 = __builtin_amdgcn_readfirstlane(at(d.ls_old, gb));
+            const int g_j1 = __builtin_amdgcn_readfirstlane(at(d.joff, gb));
             merge_group(d, ga, gb, g_n0, g_n1, g_o0, g_o1, g_j0, g_j1, one_scen, vsum, clamps);
             ga = gb;
         }
@@ -1585,7 +1610,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
                 sv += red_d[q];
                 ck += red_k[q];
             }
-            const int sc = d.lanes[la].scen;
+            const int sc = at(d.lanes, la).scen;
             unsigned long long *c = cnt_at(d, sc, 0);
             if (nw) atomicAdd(c + C_VEH_STEPS, (unsigned long long)nw);
             if (ck) atomicAdd(c + C_CLAMPS, ck);
@@ -1607,10 +1632,10 @@ __global__ void k_tails(Dev d)
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= d.n_lanes)
         return;
-    const int w0 = d.ls_old[l], w1 = d.ls_old[l + 1];
+    const int w0 = at(d.ls_old, l), w1 = at(d.ls_old, l + 1);
     const bool any = w1 > w0;
-    write_tail(d, l, any, any ? d.S.s[w0] : 0.0f, any ? d.S.v[w0] : 0.0f,
-               any ? d.S.id[w0] : kNone);
+    write_tail(d, l, any, any ? at(d.S.s, w0) : 0.0f, any ? at(d.S.v, w0) : 0.0f,
+               any ? at(d.S.id, w0) : kNone);
 }
 
 __device__ __forceinline__ int find_vehicle(const Dev &d, uint32_t id)
@@ -1618,7 +1643,7 @@ __device__ __forceinline__ int find_vehicle(const Dev &d, uint32_t id)
     int lo = 0, hi = d.n_veh;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (d.vt_id[mid] < id)
+        if (at(d.vt_id, mid) < id)
             lo = mid + 1;
         else
             hi = mid;
@@ -1632,7 +1657,49 @@ __global__ void k_cursor(Dev d, const uint32_t *ids, const uint32_t *ptrs, int32
     if (i >= n)
         return;
     int vi = find_vehicle(d, ids[i]);
-    out[i] = (int32_t)(ptrs[i] - d.vt_rstart[vi]);
+    out[i] = (int32_t)(ptrs[i] - at(d.vt_rstart, vi));
+}
+
+// Trips, first pass, one thread per vehicle in id order: a vehicle whose
+// arrival step is recorded after its route has arrived (status 2; trip time;
+// its whole route's length, summed in FP64 in route order, less the route
+// distance where it entered).  Every other vehicle is set to waiting (status
+// 0), and the second pass overwrites those on the network.
+__global__ void k_trips_all(Dev d, int32_t *status, int32_t *travel, double *dist)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n_veh)
+        return;
+    uint32_t p = at(d.vt_rstart, k);
+    double acc = 0.0;
+    for (int32_t r = at(d.route, p); r >= 0; r = at(d.route, p)) {
+        acc += (double)at(d.roads, r).L;
+        ++p;
+    }
+    const int32_t dep = at(d.route, p + 1), arr = at(d.route, p + 2);
+    const bool done = arr >= 0;
+    at(status, k) = done ? 2 : 0;
+    at(travel, k) = done ? arr - dep : 0;
+    at(dist, k) = done ? acc - at(d.vt_dist0, k) : 0.0;
+}
+
+// Trips, second pass, one thread per state row: the vehicle is on the network
+// (status 1); travel time = current step index - departure step; distance =
+// lengths of the roads before its current one (FP64, route order) plus its
+// position, less the route distance where it entered.
+__global__ void k_trips_active(Dev d, int32_t n, int32_t *status, int32_t *travel, double *dist)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int k = find_vehicle(d, at(d.S.id, i));
+    const uint32_t r0 = at(d.vt_rstart, k), ptr = at(d.S.ptr, i);
+    double acc = 0.0;
+    for (uint32_t p = r0; p < ptr; ++p)
+        acc += (double)at(d.roads, at(d.route, p)).L;
+    at(status, k) = 1;
+    at(travel, k) = (int32_t)(*d.t - (int64_t)at(d.vt_dep, k));
+    at(dist, k) = (acc + (double)at(d.S.s, i)) - at(d.vt_dist0, k);
 }
 
 static inline unsigned blocks_for(long long n, int per)
@@ -1666,8 +1733,13 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     if (d.upd_blocks > 0) gu = (unsigned)d.upd_blocks;
     if (d.xcd_remap) gu = (gu + 7u) & ~7u;     // workgroups past the last tile find no work
     const bool aux = d.P.debug || d.P.trace;
-    void (*ku)(Dev) = d.mode == 1 ? (aux ? k_update<1, true> : k_update<1, false>)
-                                  : (aux ? k_update<0, true> : k_update<0, false>);
+    void (*ku)(Dev);
+    if (d.closures)
+        ku = d.mode == 1 ? (aux ? k_update<1, true, true> : k_update<1, false, true>)
+                         : (aux ? k_update<0, true, true> : k_update<0, false, true>);
+    else
+        ku = d.mode == 1 ? (aux ? k_update<1, true, false> : k_update<1, false, false>)
+                         : (aux ? k_update<0, true, false> : k_update<0, false, false>);
     hipLaunchKernelGGL(ku, dim3(gu), dim3(kUT), 0, st, d);
     mark(2);
     const unsigned gs = blocks_for(d.n_lanes, kScanLanes);
@@ -1701,7 +1773,23 @@ __global__ void k_lane_patch(Dev d, const int32_t *idx, const LaneInfo *rec, int
         return;
     const int l = idx[i];
     const_cast<LaneInfo *>(d.lanes)[l] = rec[i];
-    d.lane_red[l] = lane_red_at(rec[i], (uint32_t)*d.t) ? 1 : 0;
+    at(d.lane_red, l) = lane_flags_at(rec[i], (uint32_t)*d.t);
+}
+
+__global__ void k_road_patch(Dev d, const int32_t *idx, const RoadInfo *rec, int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        const_cast<RoadInfo *>(d.roads)[idx[i]] = rec[i];
+}
+
+hipError_t launch_road_patch(const Dev &d, const int32_t *idx, const RoadInfo *rec, int32_t n,
+                             hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_road_patch, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, idx, rec,
+                           n);
+    return hipGetLastError();
 }
 
 hipError_t launch_lane_patch(const Dev &d, const int32_t *idx, const LaneInfo *rec, int32_t n,
@@ -1721,11 +1809,11 @@ __global__ void k_road_stats(Dev d, int32_t n_roads, int32_t *count, float *mean
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_roads)
         return;
-    const RoadInfo rd = d.roads[r];
-    const int a = d.ls_old[rd.lane0], b = d.ls_old[rd.lane0 + rd.nlanes];
+    const RoadInfo rd = at(d.roads, r);
+    const int a = at(d.ls_old, rd.lane0), b = at(d.ls_old, rd.lane0 + rd.nlanes);
     double sum = 0.0;
     for (int i = a; i < b; ++i)
-        sum += (double)d.S.v[i];
+        sum += (double)at(d.S.v, i);
     if (count)
         count[r] = b - a;
     if (mean_v)
@@ -1742,12 +1830,12 @@ __global__ void k_positions(Dev d, int32_t n, const double4 *road_ab, double *x,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    const LaneInfo li = d.lanes[d.S.lane[i]];
+    const LaneInfo li = at(d.lanes, d.S.lane[i]);
     const double4 ab = road_ab[li.road];
     const double dx = ab.z - ab.x, dy = ab.w - ab.y;
     const double len = sqrt(dx * dx + dy * dy);
     const double ux = len > 0.0 ? dx / len : 1.0, uy = len > 0.0 ? dy / len : 0.0;
-    const double f = (double)d.S.s[i] / (double)li.L;
+    const double f = (double)at(d.S.s, i) / (double)li.L;
     const double off = ((double)li.k + 0.5) * 3.5;
     x[i] = ab.x + dx * f + uy * off;
     y[i] = ab.y + dy * f - ux * off;
@@ -1781,6 +1869,18 @@ hipError_t launch_mlp_pack(const Dev &d, hipStream_t st)
 hipError_t launch_tails(const Dev &d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_tails, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_trips(const Dev &d, int32_t n_act, int32_t *status, int32_t *travel,
+                        double *dist, hipStream_t st)
+{
+    if (d.n_veh > 0)
+        hipLaunchKernelGGL(k_trips_all, dim3(blocks_for(d.n_veh, 256)), dim3(256), 0, st, d,
+                           status, travel, dist);
+    if (n_act > 0)
+        hipLaunchKernelGGL(k_trips_active, dim3(blocks_for(n_act, 256)), dim3(256), 0, st, d,
+                           n_act, status, travel, dist);
     return hipGetLastError();
 }
 

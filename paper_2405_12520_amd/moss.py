@@ -73,8 +73,9 @@ EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state"
            "moss_kernel_name",
            "moss_mlp_scratch_bytes", "moss_mlp_grad", "moss_mlp_grad_static", "moss_mlp_adam", "moss_mlp_predict",
            "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
-           "moss_read_road_stats", "moss_read_positions", "moss_set_signal_phase",
-           "moss_set_lane_vlim",
+           "moss_read_road_stats", "moss_read_positions", "moss_read_trips",
+           "moss_set_signal_phase",
+           "moss_set_lane_vlim", "moss_set_lane_closed",
            "moss_destroy", "moss_last_error")
 
 _lib = None
@@ -122,8 +123,11 @@ def load(path: str = LIB_PATH):
     L.moss_read_road_stats.argtypes = [vp, C.c_int32, vp, vp]
     L.moss_set_signal_phase.argtypes = [vp, vp, vp, C.c_int32]
     L.moss_set_lane_vlim.argtypes = [vp, vp, vp, C.c_int32]
+    L.moss_set_lane_closed.argtypes = [vp, vp, vp, C.c_int32]
     L.moss_read_positions.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.POINTER(C.c_int32)]
     L.moss_get_launch.argtypes = [vp, C.POINTER(moss_launch)]
+    L.moss_read_trips.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp,
+                                  C.POINTER(C.c_int32)]
     for f in EXPORTS:
         getattr(L, f).restype = C.c_char_p if f in ("moss_last_error", "moss_kernel_name") \
             else C.c_int
@@ -412,6 +416,14 @@ class Simulator:
             raise ValueError("lanes and limits differ in length")
         _check(load().moss_set_lane_vlim(vp(self.h), _ptr(l), _ptr(v), int(l.shape[0])))
 
+    def set_lane_closed(self, lanes, closed):
+        """Closes (1) or opens (0) lanes from the next step on."""
+        l = np.ascontiguousarray(np.atleast_1d(lanes), np.int32)
+        c = np.ascontiguousarray(np.atleast_1d(closed), np.int32)
+        if l.shape != c.shape:
+            raise ValueError("lanes and flags differ in length")
+        _check(load().moss_set_lane_closed(vp(self.h), _ptr(l), _ptr(c), int(l.shape[0])))
+
     def road_stats(self):
         """(vehicles per road [n_roads] int32, mean speed per road [n_roads] float32)."""
         cnt = np.empty(self.sc_n_roads, np.int32)
@@ -427,6 +439,18 @@ class Simulator:
         _check(load().moss_read_positions(vp(self.h), c, 0, _ptr(x), _ptr(y), _ptr(hd),
                                           C.byref(n)))
         return x[:n.value], y[:n.value], hd[:n.value]
+
+    def trips(self):
+        """Per vehicle in ascending id order (host arrays): id, status (0
+        waiting, 1 on the network, 2 arrived), travel time (steps) and
+        distance (m) since it entered the simulation."""
+        c = self.cap
+        out = dict(id=np.empty(c, np.uint32), status=np.empty(c, np.int32),
+                   travel=np.empty(c, np.int32), distance=np.empty(c, np.float64))
+        n = C.c_int32(0)
+        _check(load().moss_read_trips(vp(self.h), c, 0, _ptr(out["id"]), _ptr(out["status"]),
+                                      _ptr(out["travel"]), _ptr(out["distance"]), C.byref(n)))
+        return {k: v[:n.value] for k, v in out.items()}
 
     def set_launch(self, **cfg):
         """Changes the launch shape (fields of moss_launch; omitted ones keep

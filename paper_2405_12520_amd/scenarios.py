@@ -60,6 +60,8 @@ DEFAULT_PARAMS: Dict[str, float] = dict(
     p_lc=0.5,          # probability of executing a beneficial, safe change
     d_look=300.0,      # m, lookahead distance across junctions
     h_look=3,          # max roads scanned ahead for a leader
+    b_mand=1.0,        # m/s^2, lane-change bias toward lanes that continue the route
+    tau_yield=3.0,     # s, approach time within which a vehicle with priority is yielded to
     seed=4,            # RNG key for the lane-change draws
     t0=0,              # first step index
 )
@@ -101,6 +103,16 @@ class Scenario:
     params: Dict[str, float]
     n_scen: int = 1
     meta: Dict[str, object] = dataclasses.field(default_factory=dict)
+    # junction internal lanes (junctions.with_junction_lanes), None without:
+    # internal-road flags, lane successors (CSR over lanes) and, per connector
+    # lane, the conflicting connector lanes with priority over it and the
+    # in-lane feeding each
+    road_internal: Optional[np.ndarray] = None
+    lane_succ_off: Optional[np.ndarray] = None
+    lane_succ: Optional[np.ndarray] = None
+    lane_conf_off: Optional[np.ndarray] = None
+    lane_conf: Optional[np.ndarray] = None
+    lane_conf_feed: Optional[np.ndarray] = None
 
     @property
     def n_nodes(self) -> int:

@@ -101,6 +101,63 @@ def stayer_joiner_tie(id_stayer: int, id_joiner: int) -> S.Scenario:
     return S.with_vehicles("stay_join_tie", net, vs, params=dict(h_look=0))
 
 
+def two_lane_insertion() -> S.Scenario:
+    """A vehicle (id 1) due at step 0 on an empty two-lane road: it queues on
+    lane 1 mod 2 = 1."""
+    net = S.corridor([500.0, 100.0], 2)
+    return S.with_vehicles("ins_two", net, [dict(id=1, route=[0, 1], depart=0, v0=14.0)])
+
+
+def transfer_into(k: int) -> S.Scenario:
+    """A vehicle on lane k of a 100 m three-lane road at s = 95, v = v0 = 25,
+    no lookahead: free at its desired speed, it moves exactly 25 m and enters
+    the next (three-lane, 200 m) road at s = 20, on lane index min(k, 2)
+    unless control has closed that lane."""
+    net = S.corridor([100.0, 200.0], 3, vlim=30.0)
+    return S.with_vehicles("transfer", net,
+                           [dict(id=1, route=[0, 1], lane=k, s=95.0, v=25.0, v0=25.0)],
+                           params=dict(h_look=0))
+
+
+def slow_leader_change() -> S.Scenario:
+    """Even step on a two-lane road: vehicle 1 (lane 1, s = 200, v = 10)
+    behind a standing vehicle 20 m ahead, target lane 0 empty; p_lc = 1.  The
+    change is safe and worth it (IDM at a standing leader 15 m away brakes
+    hard; the empty lane gives free acceleration)."""
+    net = S.corridor([1000.0, 100.0], 2)
+    vs = [dict(id=1, route=[0, 1], lane=1, s=200.0, v=10.0),
+          dict(id=2, route=[0, 1], lane=1, s=220.0, v=0.0, v0=0.5)]
+    return S.with_vehicles("slow_leader", net, vs, params=dict(t0=0, p_lc=1.0))
+
+
+def lookahead_into(closed_k1: bool) -> S.Scenario:
+    """Vehicle 1 on lane 1 of a two-lane 100 m road at s = 90 (v = 10); the
+    next two-lane road holds one vehicle, vehicle 2, on lane 0 at s = 30.  The
+    lookahead takes lane min(1, 1) = 1, which is empty (no leader), unless
+    lane 1 is closed: then lane 0, whose last vehicle 2 leads at gap
+    (100 - 90) + 30 - 5 = 35 m."""
+    net = S.corridor([100.0, 300.0], 2, vlim=16.67)
+    vs = [dict(id=1, route=[0, 1], lane=1, s=90.0, v=10.0),
+          dict(id=2, route=[1], lane=2, s=30.0, v=5.0)]
+    return S.with_vehicles("lookahead_closed" if closed_k1 else "lookahead_open", net, vs)
+
+
+# lane restriction cases as (name, scenario, lanes closed before the first
+# step, steps) for the GPU parity test
+def closure_cases():
+    return [
+        ("transfer_open", transfer_into(2), [], 2),
+        ("transfer_closed_2", transfer_into(2), [5], 2),
+        ("transfer_closed_12", transfer_into(2), [4, 5], 2),
+        ("transfer_tie", transfer_into(1), [4], 2),
+        ("change_open", slow_leader_change(), [], 2),
+        ("change_closed", slow_leader_change(), [0], 2),
+        ("lookahead_open", lookahead_into(False), [], 2),
+        ("lookahead_closed", lookahead_into(True), [3], 2),
+        ("queue_closed", two_lane_insertion(), [1], 3),
+    ]
+
+
 # every case above as (name, scenario, steps) for the GPU parity test
 def all_cases():
     f32 = np.float32

@@ -1,8 +1,10 @@
-"""Road measures and vehicle positions on the GPU vs the oracle.
+"""Road measures, vehicle positions and trips on the GPU vs the oracle.
 
 Counts per road must be identical; mean speeds too (both sides add the
 road's speeds in FP64 in state row order); positions agree to 1e-9 m and
 headings to 1e-12 rad (FP64 throughout, atan2 from different libraries).
+Trips (status, travel time, distance) are identical bit for bit: both sides
+add the same road lengths in FP64 in route order.
 """
 import sys
 
@@ -39,6 +41,14 @@ def _compare(g, o, where):
     np.testing.assert_allclose(xg, xo, rtol=0, atol=1e-9, err_msg=where)
     np.testing.assert_allclose(yg, yo, rtol=0, atol=1e-9, err_msg=where)
     np.testing.assert_allclose(hg, ho, rtol=0, atol=1e-12, err_msg=where)
+    _compare_trips(g, o, where)
+
+
+def _compare_trips(g, o, where):
+    tg, to = g.trips(), o.trips()
+    for f in ("id", "status", "travel"):
+        assert np.array_equal(tg[f], to[f]), (where, f)
+    assert np.array_equal(tg["distance"].view(np.uint64), to["distance"].view(np.uint64)), where
 
 
 def test_grid_outputs_over_a_run(sim_cls):
@@ -63,6 +73,25 @@ def test_city_outputs_full_size(sim_cls):
     g.step(2)
     o.step(2)
     _compare(g, o, "city t=2")
+    g.close()
+
+
+def test_trips_with_placed_and_departing_vehicles(sim_cls):
+    """Placed vehicles measure distance from their placement; departing ones
+    from their route start; arrivals are recorded as they happen."""
+    from oracle import OracleSim
+    sc = S.toy(11, n_placed=40, n_pending=30, horizon=60)
+    _say("trips toy")
+    g = sim_cls(sc)
+    o = OracleSim(sc)
+    _compare_trips(g, o, "toy t=0")
+    seen = np.zeros(3, bool)
+    for k in range(10):
+        g.step(12)
+        o.step(12)
+        _compare_trips(g, o, f"toy t={12 * (k + 1)}")
+        seen |= np.bincount(g.trips()["status"], minlength=3) > 0
+    assert seen.all()
     g.close()
 
 

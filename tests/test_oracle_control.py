@@ -1,6 +1,7 @@
 """Pins of the oracle's runtime control (CPU): a held signal phase stops the
 other group's approaches until released; a lowered speed limit brings free
-traffic down to it."""
+traffic down to it; a closed lane admits no vehicle (hand-built toy states
+from tests/rule_cases.py with hand-computed outcomes)."""
 import numpy as np
 import pytest
 
@@ -66,3 +67,76 @@ def test_lowered_speed_limit_is_reached_from_above():
     o.step(40)
     v = o.state()["v"]
     assert v.max() <= 8.0 + 1e-3 and v.min() > 7.9
+
+
+# ------------------------------------------------------ lane restriction --
+
+def _lane_after(sc, closed, steps):
+    from oracle import OracleSim
+    o = OracleSim(sc)
+    if closed:
+        o.set_lane_closed(closed, [1] * len(closed))
+    o.step(steps)
+    st = o.state()
+    return o, st
+
+
+@pytest.mark.parametrize("k, closed, lane", [(2, [], 5), (2, [5], 4), (2, [4, 5], 3),
+                                             (1, [4], 3), (0, [3], 4)])
+def test_transfer_takes_the_nearest_open_lane(k, closed, lane):
+    """Road 1 has lanes 3, 4, 5.  From lane index k the vehicle enters
+    min(k, 2); if that lane is closed, the nearest open one, the lower of two
+    equally near."""
+    import rule_cases as RC
+    _, st = _lane_after(RC.transfer_into(k), closed, 1)
+    assert st["lane"].tolist() == [lane]
+    assert st["s"].tolist() == [20.0]
+
+
+def test_no_lane_change_into_a_closed_lane():
+    import rule_cases as RC
+    o, st = _lane_after(RC.slow_leader_change(), [], 1)
+    assert dict(zip(st["id"].tolist(), st["lane"].tolist()))[1] == 0
+    o, st = _lane_after(RC.slow_leader_change(), [0], 1)
+    assert dict(zip(st["id"].tolist(), st["lane"].tolist()))[1] == 1
+    assert (o.debug()["flags"] & 3).tolist() == [0, 0]      # not even evaluated
+
+
+def test_lookahead_follows_the_open_lane():
+    import rule_cases as RC
+    from oracle import OracleSim
+    for closed, leader in (([], 0xFFFFFFFF), ([3], 2)):
+        o = OracleSim(RC.lookahead_into(bool(closed)))
+        if closed:
+            o.set_lane_closed(closed, [1])
+        o.step(1)
+        d = o.debug()
+        lead = dict(zip(d["id"].tolist(), d["leader"].tolist()))
+        assert lead[1] == leader
+
+
+def test_closed_lane_holds_its_departure_queue():
+    import rule_cases as RC
+    from oracle import OracleSim
+    o = OracleSim(RC.two_lane_insertion())
+    o.set_lane_closed([1], [1])
+    o.step(3)
+    c, _ = o.counters()
+    assert o.n_active == 0 and c[0, 0] == 0 and c[0, 1] == 3
+    o.set_lane_closed([1], [0])
+    o.step(1)
+    assert o.n_active == 1 and o.counters()[0][0, 0] == 1
+
+
+def test_closing_the_last_open_lane_is_refused():
+    import rule_cases as RC
+    from oracle import OracleSim
+    o = OracleSim(RC.slow_leader_change())
+    o.set_lane_closed([0], [1])
+    with pytest.raises(ValueError):
+        o.set_lane_closed([1], [1])                          # road 0 would have none
+    with pytest.raises(ValueError):
+        o.set_lane_closed([0, 1], [1, 1])
+    o.set_lane_closed([1, 0], [1, 0])                        # judged as a whole: one open
+    with pytest.raises(ValueError):
+        o.set_lane_closed([99], [1])

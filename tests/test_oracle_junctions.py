@@ -1,0 +1,279 @@
+"""Pins of junction internal lanes (CPU): the map builder's connectors,
+turn-permitted lanes and conflict table on a 4-way junction, checked against
+what the geometry of the junction fixes by hand; then the oracle's rules on
+hand-built states at that junction (yielding to an approaching vehicle with
+priority or to an occupied connector, the stop line of a vehicle in the
+wrong lane, the lane-change bias toward the lanes that continue the route,
+the way through a connector), and invariants over whole runs.
+
+Junction: arms N, E, S, W (roads 0/1, 2/3, 4/5, 6/7 are each arm's in- and
+out-road, 500 m, two lanes); lane 0 of a road is its left lane.  The N/S
+approaches have the first 30 s of the 60 s cycle.
+"""
+import numpy as np
+import pytest
+
+from paper_2405_12520_amd import junctions as J
+from paper_2405_12520_amd import scenarios as S
+
+N_IN, N_OUT, E_IN, E_OUT, S_IN, S_OUT, W_IN, W_OUT = range(8)
+
+
+def _net():
+    return J.with_junction_lanes(S.intersection())
+
+
+def _conn(jl, r, r2):
+    return jl.meta["junction_lanes"]["movements"][(r, r2)]
+
+
+def _succ(jl, lane):
+    return jl.lane_succ[jl.lane_succ_off[lane]:jl.lane_succ_off[lane + 1]].tolist()
+
+
+def _conf(jl, lane):
+    a, b = jl.lane_conf_off[lane], jl.lane_conf_off[lane + 1]
+    return jl.lane_conf[a:b].tolist(), jl.lane_conf_feed[a:b].tolist()
+
+
+def _lane(jl, road, k):
+    return int(jl.road_lane0[road]) + k
+
+
+def test_turns_of_the_four_way_junction():
+    """From the north arm (heading south) the east exit is a left turn, the
+    south exit straight on, the west exit a right turn."""
+    jl = _net()
+    t = jl.meta["junction_lanes"]["turns"]
+    assert t[_conn(jl, N_IN, E_OUT)] == "L"
+    assert t[_conn(jl, N_IN, S_OUT)] == "S"
+    assert t[_conn(jl, N_IN, W_OUT)] == "R"
+    assert t[_conn(jl, E_IN, S_OUT)] == "L" and t[_conn(jl, E_IN, N_OUT)] == "R"
+
+
+def test_connector_lanes_and_successors():
+    """Two-lane approach: the left lane turns left or goes straight, the
+    right lane goes straight or turns right.  The straight connector has two
+    lanes ending on out-lanes 0 and 1, the left turn ends on the out-road's
+    left lane, the right turn on its right lane."""
+    jl = _net()
+    left, straight, right = (_conn(jl, N_IN, x) for x in (E_OUT, S_OUT, W_OUT))
+    assert jl.road_nlanes[left] == 1 and jl.road_nlanes[straight] == 2
+    assert jl.road_nlanes[right] == 1
+    assert jl.road_internal[left] == 1 and jl.road_internal[N_IN] == 0
+    l0, l1 = _lane(jl, N_IN, 0), _lane(jl, N_IN, 1)
+    assert sorted(_succ(jl, l0)) == sorted([_lane(jl, left, 0), _lane(jl, straight, 0)])
+    assert sorted(_succ(jl, l1)) == sorted([_lane(jl, straight, 1), _lane(jl, right, 0)])
+    assert _succ(jl, _lane(jl, left, 0)) == [_lane(jl, E_OUT, 0)]
+    assert _succ(jl, _lane(jl, straight, 0)) == [_lane(jl, S_OUT, 0)]
+    assert _succ(jl, _lane(jl, straight, 1)) == [_lane(jl, S_OUT, 1)]
+    assert _succ(jl, _lane(jl, right, 0)) == [_lane(jl, W_OUT, 1)]
+    assert _succ(jl, _lane(jl, N_OUT, 0)) == []          # out-roads lead nowhere here
+    assert jl.road_group[left] == -1 and jl.road_length[left] == 20.0
+
+
+def test_conflicts_and_priorities():
+    """The north left turn crosses the south straight paths and yields to
+    them; the straight paths do not yield to it; two straight paths in
+    parallel (N and S) do not conflict; the north right turn merges with the
+    east straight lane ending on the same out-lane and yields to it."""
+    jl = _net()
+    nl = _lane(jl, _conn(jl, N_IN, E_OUT), 0)
+    ss0, ss1 = (_lane(jl, _conn(jl, S_IN, N_OUT), k) for k in (0, 1))
+    ns0 = _lane(jl, _conn(jl, N_IN, S_OUT), 0)
+    conf, feed = _conf(jl, nl)
+    assert ss0 in conf and ss1 in conf
+    assert feed[conf.index(ss0)] == _lane(jl, S_IN, 0)
+    assert nl not in _conf(jl, ss0)[0]
+    assert ss0 not in _conf(jl, ns0)[0] and ns0 not in _conf(jl, ss0)[0]
+    nr = _lane(jl, _conn(jl, N_IN, W_OUT), 0)
+    es1 = _lane(jl, _conn(jl, E_IN, W_OUT), 1)
+    assert _succ(jl, nr) == _succ(jl, es1)
+    assert es1 in _conf(jl, nr)[0] and nr not in _conf(jl, es1)[0]
+
+
+# ------------------------------------------------------------- dynamics --
+
+def _state(vehicles, params=None):
+    """The junction with the given vehicles (routes over regular roads, the
+    connectors inserted by the builder), t0 = 0 (N/S green)."""
+    base = S.intersection(n_veh=1)
+    net = dict(node_x=base.node_x, node_y=base.node_y, road_from=base.road_from,
+               road_to=base.road_to, road_length=base.road_length,
+               road_nlanes=base.road_nlanes, road_vlim=np.full(8, 16.67, np.float32),
+               node_cycle=base.node_cycle, node_phase=base.node_phase,
+               node_offset=base.node_offset, road_group=base.road_group)
+    sc = S.with_vehicles("junction", net, vehicles, params=dict(t0=0, **(params or {})))
+    return J.with_junction_lanes(sc)
+
+
+def _run(sc, steps=1):
+    from oracle import OracleSim
+    o = OracleSim(sc)
+    o.step(steps)
+    d = o.debug()
+    return o, dict(zip(d["id"].tolist(), d["flags"].tolist())), o.state()
+
+
+def _left_turner(extra=(), **kw):
+    return _state([dict(id=1, route=[N_IN, E_OUT], lane=0, s=480.0, v=5.0)] + list(extra), **kw)
+
+
+def test_left_turn_yields_to_an_approaching_straight_vehicle():
+    """Opposing vehicle 2 on the south approach, 30 m from its line at
+    10 m/s, headed straight: within 3 s, so vehicle 1 (first in its lane,
+    20 m before the line) yields: the line is its obstacle (flags 64 | 4)."""
+    opp = dict(id=2, route=[S_IN, N_OUT], lane=_lane(_left_turner(), S_IN, 0), s=470.0, v=10.0)
+    _, f, _ = _run(_left_turner([opp]))
+    assert f[1] & 64 and f[1] & 4
+    assert not (f[2] & 64)                      # the straight vehicle has priority
+
+
+@pytest.mark.parametrize("s_opp, v_opp, route", [
+    (400.0, 10.0, [S_IN, N_OUT]),               # 100 m away: more than 3 s
+    (495.0, 0.0, [S_IN, N_OUT]),                # standing: not approaching
+    (470.0, 10.0, [S_IN, W_OUT]),               # turning left itself: no crossing
+])
+def test_left_turn_does_not_yield(s_opp, v_opp, route):
+    sc0 = _left_turner()
+    opp = dict(id=2, route=route, lane=_lane(sc0, S_IN, 0), s=s_opp, v=v_opp)
+    _, f, _ = _run(_left_turner([opp]))
+    assert not (f[1] & 64) and not (f[1] & 4)
+
+
+def test_left_turn_yields_to_an_occupied_connector():
+    """A vehicle inside the south straight connector (placed on its lane)
+    makes the left turner wait even with nobody approaching."""
+    sc0 = _left_turner()
+    cs = _conn(sc0, S_IN, N_OUT)
+    # the placed vehicle's route starts on the connector (cursor 0 there)
+    sc = _state([dict(id=1, route=[N_IN, E_OUT], lane=0, s=480.0, v=5.0)])
+    import dataclasses
+    n = sc.n_veh
+    route = list(sc.route_roads) + [cs, N_OUT]
+    off = np.concatenate([sc.route_off, [sc.route_off[-1] + 2]])
+    sc = dataclasses.replace(
+        sc, veh_id=np.append(sc.veh_id, 2).astype(np.uint32), depart=np.append(sc.depart, 0),
+        v0=np.append(sc.v0, 14.0).astype(np.float32), route_off=off.astype(np.int64),
+        route_roads=np.asarray(route, np.int32), placed=np.append(sc.placed, 1).astype(np.uint8),
+        lane=np.append(sc.lane, _lane(sc, cs, 0)).astype(np.int32),
+        s=np.append(sc.s, 5.0).astype(np.float32), v=np.append(sc.v, 0.0).astype(np.float32),
+        a=np.append(sc.a, 0.0).astype(np.float32), cursor=np.append(sc.cursor, 0).astype(np.int32))
+    assert sc.n_veh == n + 1
+    _, f, _ = _run(sc)
+    assert f[1] & 64 and f[1] & 4
+
+
+def test_wrong_lane_changes_toward_the_route():
+    """Vehicle 1 in the right lane (k = 1) wants to turn left, which only the
+    left lane does.  On the even step it looks at lane k - 1 = 0, empty: the
+    change is safe, the incentive carries the bias b_mand, and with p_lc = 1
+    it changes; its final lane continues the route (no flag 32).  With p_lc
+    = 0 it stays and is flagged."""
+    o, f, st = _run(_state([dict(id=1, route=[N_IN, E_OUT], lane=1, s=300.0, v=10.0)],
+                           params=dict(p_lc=1.0)))
+    assert f[1] & 2 and not (f[1] & 32)
+    assert st["lane"].tolist() == [0]
+    o, f, st = _run(_state([dict(id=1, route=[N_IN, E_OUT], lane=1, s=300.0, v=10.0)],
+                           params=dict(p_lc=0.0)))
+    assert (f[1] & 3) == 1 and f[1] & 32
+    assert st["lane"].tolist() == [1]
+
+
+def test_wrong_lane_at_the_line_is_not_held():
+    """A vehicle that reaches the junction still in a lane that does not
+    continue its route is not stopped (no flag 4 on green, no conflict): it
+    enters the route's connector on the lane nearest its index, the single
+    lane of the left-turn connector."""
+    sc = _state([dict(id=1, route=[N_IN, E_OUT], lane=1, s=495.0, v=10.0)],
+                params=dict(p_lc=0.0))
+    o, f, st = _run(sc)
+    assert f[1] & 32 and not (f[1] & 4)
+    assert st["lane"].tolist() == [_lane(sc, _conn(sc, N_IN, E_OUT), 0)]
+
+
+def test_bias_enters_the_incentive_and_wrong_lanes_are_never_taken():
+    """The same lane-change evaluation with and without junction lanes: a
+    vehicle in a lane that does not continue its route, looking at one that
+    does, has an incentive larger by b_mand; a vehicle in a lane that
+    continues its route never moves into one that does not, whatever the
+    incentive; both lanes continuing: nothing changes."""
+    # lane 1 turning left on the even step looks at lane 0 (turns left)
+    m_plain0, _ = _margin_at(1, [N_IN, E_OUT], jl=False, t0=0)
+    m_jl0, _ = _margin_at(1, [N_IN, E_OUT], jl=True, t0=0)
+    assert abs(m_jl0 - (m_plain0 + 1.0)) < 1e-5
+    # lane 0 turning left on the odd step looks at lane 1 (no left turn): the
+    # slow leader makes the change worth it without junction lanes only
+    m_plain1, f_plain1 = _margin_at(0, [N_IN, E_OUT], jl=False, t0=1, p_lc=1.0)
+    m_jl1, f_jl1 = _margin_at(0, [N_IN, E_OUT], jl=True, t0=1, p_lc=1.0)
+    assert m_plain1 > 0.0 and (f_plain1 & 3) == 2
+    assert m_jl1 == m_plain1 and (f_jl1 & 3) == 1
+    # straight on: both lanes continue
+    assert _margin_at(0, [N_IN, S_OUT], jl=True, t0=1) == _margin_at(0, [N_IN, S_OUT], jl=False,
+                                                                      t0=1)
+
+
+def _state_plain(vehicles, t0=0, p_lc=0.5):
+    base = S.intersection(n_veh=1)
+    net = dict(node_x=base.node_x, node_y=base.node_y, road_from=base.road_from,
+               road_to=base.road_to, road_length=base.road_length,
+               road_nlanes=base.road_nlanes, road_vlim=np.full(8, 16.67, np.float32),
+               node_cycle=base.node_cycle, node_phase=base.node_phase,
+               node_offset=base.node_offset, road_group=base.road_group)
+    return S.with_vehicles("junction_plain", net, vehicles, params=dict(t0=t0, p_lc=p_lc))
+
+
+def _margin_at(lane, route, jl, t0, p_lc=0.5):
+    """(MOBIL margin, flags) of vehicle 1 behind a slower vehicle 2 in the
+    same lane, one step from t0."""
+    from oracle import OracleSim
+    vs = [dict(id=1, route=route, lane=lane, s=300.0, v=10.0),
+          dict(id=2, route=route, lane=lane, s=330.0, v=4.0)]
+    sc = _state_plain(vs, t0=t0, p_lc=p_lc)
+    if jl:
+        sc = J.with_junction_lanes(sc)
+    o = OracleSim(sc)
+    o.step(1)
+    d = o.debug()
+    k = d["id"].tolist().index(1)
+    assert d["flags"][k] & 3                      # the change was evaluated
+    return float(d["margin"][k]), int(d["flags"][k])
+
+
+def test_the_way_through_a_connector():
+    """A left turner crosses: from lane 0 of the north approach onto the
+    left-turn connector, then onto the east out-road's left lane."""
+    from oracle import OracleSim
+    sc = _state([dict(id=1, route=[N_IN, E_OUT], lane=0, s=470.0, v=12.0)])
+    o = OracleSim(sc)
+    conn = _lane(sc, _conn(sc, N_IN, E_OUT), 0)
+    seen = []
+    for _ in range(12):
+        o.step(1)
+        st = o.state()
+        if st["lane"].size:
+            seen.append(int(st["lane"][0]))
+    assert conn in seen
+    assert seen[-1] == _lane(sc, E_OUT, 0)
+    i = seen.index(conn)
+    assert all(x == _lane(sc, N_IN, 0) for x in seen[:i])
+
+
+@pytest.mark.parametrize("name", ["intersection", "grid"])
+def test_runs_with_junction_lanes_keep_the_invariants(name):
+    """Whole runs: no overlap within a lane, vehicles are conserved, and the
+    junction intersection empties (every vehicle arrives)."""
+    from oracle import OracleSim
+    sc = S.intersection() if name == "intersection" else S.grid(6, 2000, horizon=300)
+    sc = J.with_junction_lanes(sc)
+    o = OracleSim(sc)
+    steps = 1800 if name == "intersection" else 600
+    for _ in range(steps // 100):
+        o.step(100)
+        st = o.state()
+        same = st["lane"][1:] == st["lane"][:-1]
+        assert np.all(st["s"][1:][same] - st["s"][:-1][same] >= 5.0 - 1e-4)
+        c, _ = o.counters()
+        assert c[0, 0] == o.n_active + c[0, 2]
+    if name == "intersection":
+        assert o.counters()[0][0, 2] == sc.n_veh

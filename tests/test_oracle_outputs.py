@@ -89,3 +89,96 @@ def test_position_invariants_on_grid():
     same = st["lane"][1:] == st["lane"][:-1]
     proj = along
     assert np.all(proj[1:][same] >= proj[:-1][same])
+
+
+# ---------------------------------------------------------------- trips --
+
+def _trip_run():
+    """A 6x6 grid with 2500 trips departing over 300 s, run past many
+    arrivals, with the per-step states kept for the distance pins."""
+    from oracle import OracleSim
+    sc = S.grid(6, 2500, horizon=300)
+    o = OracleSim(sc)
+    return sc, o
+
+
+def _route_lengths(sc):
+    """Cumulative road lengths along each vehicle's route (FP64), by vehicle
+    index: cum[i][c] = length of the first c roads."""
+    cum = []
+    for i in range(sc.n_veh):
+        r = sc.route_roads[sc.route_off[i]:sc.route_off[i + 1]]
+        cum.append(np.concatenate([[0.0], np.cumsum(sc.road_length[r].astype(np.float64))]))
+    return cum
+
+
+def test_trips_agree_with_counters_and_state():
+    """Arrived vehicles and their travel times add up to the arrival and trip
+    time counters; vehicles on the network are the state's rows; the rest
+    are the waiting vehicles; travel times count from the departure step."""
+    sc, o = _trip_run()
+    o.step(700)
+    tr = o.trips()
+    c, _ = o.counters()
+    st = o.state()
+    assert np.all(np.diff(tr["id"].astype(np.int64)) > 0)
+    arrived = tr["status"] == 2
+    assert arrived.sum() == c[0, 2] > 500
+    assert tr["travel"][arrived].sum() == c[0, 3]
+    on = tr["status"] == 1
+    assert set(tr["id"][on]) == set(st["id"].tolist())
+    assert (tr["status"] == 0).sum() == o.pending
+    idx = {int(v): k for k, v in enumerate(sc.veh_id)}
+    dep = np.array([sc.depart[idx[int(v)]] for v in tr["id"]])
+    np.testing.assert_array_equal(tr["travel"][on], 700 - dep[on])
+    assert np.all(tr["travel"][tr["status"] == 0] == 0)
+    assert np.all(tr["distance"][tr["status"] == 0] == 0.0)
+
+
+def test_trip_distance_is_the_path_driven():
+    """Distance along the route, followed step by step: for a vehicle on the
+    network it is the length of the roads it has left plus its position (it
+    entered at the start of its first road); once arrived it is its whole
+    route; and it never decreases from step to step by more than the
+    overlap correction can move a vehicle back (one vehicle length)."""
+    sc, o = _trip_run()
+    cum = _route_lengths(sc)
+    idx = {int(v): k for k, v in enumerate(sc.veh_id)}
+    prev = None
+    for t in range(0, 600, 50):
+        o.step(50)
+        tr = o.trips()
+        st = o.state()
+        d_by_id = dict(zip(tr["id"].tolist(), tr["distance"].tolist()))
+        for vid, cur, s in zip(st["id"], st["cursor"], st["s"]):
+            i = idx[int(vid)]
+            assert d_by_id[int(vid)] == cum[i][cur] + float(s)
+        for k in np.flatnonzero(tr["status"] == 2):
+            i = idx[int(tr["id"][k])]
+            assert tr["distance"][k] == cum[i][-1]
+        if prev is not None:
+            both = (prev["status"] >= 1) & (tr["status"] >= 1)
+            assert np.all(tr["distance"][both] >= prev["distance"][both] - 5.0)
+        prev = tr
+
+
+def test_trip_distance_of_placed_vehicles_starts_at_zero():
+    """A vehicle placed at creation has travelled nothing yet; after a step
+    its distance is what it moved, route roads crossed included."""
+    from oracle import OracleSim
+    sc = S.toy(5, n_placed=30, n_pending=0)
+    o = OracleSim(sc)
+    tr0 = o.trips()
+    assert np.all(tr0["status"] == 1)
+    assert np.all(tr0["distance"] == 0.0)
+    st0 = o.state()
+    o.step(1)
+    tr1 = o.trips()
+    st1 = o.state()
+    cum = _route_lengths(sc)
+    idx = {int(v): k for k, v in enumerate(sc.veh_id)}
+    pos0 = {int(v): cum[idx[int(v)]][c] + float(s) for v, c, s in zip(st0["id"], st0["cursor"], st0["s"])}
+    pos1 = {int(v): cum[idx[int(v)]][c] + float(s) for v, c, s in zip(st1["id"], st1["cursor"], st1["s"])}
+    for vid, d in zip(tr1["id"], tr1["distance"]):
+        if int(vid) in pos1:
+            assert abs(d - (pos1[int(vid)] - pos0[int(vid)])) < 1e-9
