@@ -240,6 +240,42 @@ def bench_batch(args):
                 launch=rec["launch"], launch_tuned_ms_per_step=rec["ms_per_step"])
 
 
+def bench_small(args):
+    """The two small workloads over their full hour (3600 steps): the single
+    signalised intersection (200 vehicles departing over 600 s) and the
+    10 x 10 grid (20,000 vehicles departing over the hour), on the GPU and
+    with the oracle on all the host threads OpenMP is given.  Both are
+    latency-bound on the GPU (a few thousand vehicles at most): steps per
+    second is the figure that matters there."""
+    import torch
+    from paper_2405_12520_amd import scenarios as S
+    from paper_2405_12520_amd.moss import Simulator
+    out = {}
+    for name, sc in (("c1_intersection", S.intersection()), ("c2_grid", S.grid(10, 20000))):
+        sim = Simulator(sc)
+        ms, dc = timed_steps(sim, 3600)
+        vs = int(dc[:, 6].sum())
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        r = dict(steps=3600, vehicles=int(sc.n_veh), vehicle_steps=vs,
+                 gpu=dict(ms=round(ms, 2), steps_per_s=round(3600 / (ms / 1e3), 1),
+                          vehicle_steps_per_s=round(vs / (ms / 1e3), 1)))
+        if not args.no_cpu:
+            from oracle import OracleSim, max_threads
+            o = OracleSim(sc)
+            o.set_threads(max_threads())
+            t0 = time.perf_counter()
+            o.step(3600)
+            dt = time.perf_counter() - t0
+            r["cpu_oracle"] = dict(s=round(dt, 3), steps_per_s=round(3600 / dt, 1),
+                                   vehicle_steps_per_s=round(vs / dt, 1),
+                                   threads=int(max_threads()))
+        say(f"[bench] {name}: {r}")
+        out[name] = r
+    return out
+
+
 def bench_demand(args):
     """The city with its travel demand (2M gravity-model trips over 400 zones,
     departures over one hour, shortest-path routes), the whole hour (3600
@@ -314,6 +350,8 @@ def main():
     ap.add_argument("--no-demand", action="store_true",
                     help="skip the city's hour with its travel demand (IDM and closure)")
     ap.add_argument("--demand-steps", type=int, default=3600)
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the intersection and 10x10 grid hours")
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 8M-vehicle city (beyond the Infinity Cache)")
     ap.add_argument("--batch-scenarios", type=int, default=256)
@@ -440,6 +478,8 @@ def main():
         extras["city8M"] = bench_big(args)
     if not args.no_demand:
         extras["city_demand"] = bench_demand(args)
+    if not args.no_small:
+        extras.update(bench_small(args))
     cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_steps, args.cpu_steps_mt)
     out = dict(metric=METRIC, value=round(value, 1), unit="vehicle-steps/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms / args.steps, 5),

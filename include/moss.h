@@ -69,6 +69,22 @@ typedef struct {
     const int32_t *lane_scen;    /* [n_lanes] or NULL (all 0) */
     const double *node_x;        /* [n_nodes] m, or NULL (then moss_read_positions fails) */
     const double *node_y;        /* [n_nodes] m, or NULL */
+    /* Junction internal lanes (the map builder's lane connectivity inside
+     * intersections, Sec. III-C-1), all NULL without them.  road_internal[r]
+     * = 1 marks a connector road inside a junction (no lane changes on it).
+     * lane_succ[lane_succ_off[l] .. lane_succ_off[l+1]-1] are the lanes a
+     * vehicle on lane l may continue on, at most one per road; a vehicle whose
+     * next route road is r takes l's successor on r, and a lane without a
+     * list takes lane min(k, n-1) of r as without junction lanes.
+     * lane_conf[lane_conf_off[c] .. ] are the connector lanes whose paths
+     * conflict with connector lane c and that have priority over it, and
+     * lane_conf_feed[] the lane feeding each of them. */
+    const uint8_t *road_internal;       /* [n_roads] */
+    const int32_t *lane_succ_off;       /* [n_lanes+1] */
+    const int32_t *lane_succ;           /* [lane_succ_off[n_lanes]] */
+    const int32_t *lane_conf_off;       /* [n_lanes+1] */
+    const int32_t *lane_conf;           /* [lane_conf_off[n_lanes]] */
+    const int32_t *lane_conf_feed;      /* [lane_conf_off[n_lanes]] */
 } moss_network;
 
 /* Fixed-time signal plans.  Node j with node_cycle[j] > 0 shows phase
@@ -122,6 +138,10 @@ typedef struct {
     int32_t mode;      /* MOSS_MODE_* */
     const float *mlp_theta;  /* host float[MOSS_MLP_PARAMS], used when mode = MLP */
     const float *mlp_norm;   /* host float[MOSS_MLP_NORM] */
+    /* junction internal lanes: lane-change bias toward lanes that continue
+     * the route (m/s^2, >= 0) and the approach time within which a vehicle
+     * with priority makes a vehicle yield (s, >= 0) */
+    float b_mand, tau_yield;
 } moss_params;
 
 typedef struct moss_sim moss_sim;
@@ -353,6 +373,20 @@ int moss_read_trace(moss_sim *h, int32_t capacity, int32_t device, float *feat, 
 int moss_set_signal_phase(moss_sim *h, const int32_t *node, const int32_t *phase, int32_t n);
 int moss_set_lane_vlim(moss_sim *h, const int32_t *lane, const float *vlim, int32_t n);
 int moss_set_lane_closed(moss_sim *h, const int32_t *lane, const int32_t *closed, int32_t n);
+
+/* Dynamic lanes (Sec. III-C-4), with junction internal lanes: from the next
+ * step on, lane[i] lets vehicles continue onto road[i] (allowed[i] != 0) or
+ * no longer does, by taking its successor on that road in or out of use; the
+ * movements of a lane are those its successor list holds (the map builder's
+ * connectors).  Lane changes, the lane-change bias and the lanes vehicles
+ * take follow the change; a lane none of whose successors is in use
+ * continues nowhere (its vehicles change lanes, or go through on the nearest
+ * connector lane).  Departure lanes stay those chosen at creation.
+ * Synchronises the stream.  MOSS_EINVAL, changing nothing, without junction
+ * lanes, for a lane out of range or a lane without a successor on the road.
+ * Host arrays. */
+int moss_set_lane_turns(moss_sim *h, const int32_t *lane, const int32_t *road,
+                        const int32_t *allowed, int32_t n);
 
 /* Road measures of the current state (the simulator's road outputs, Sec.
  * III-A: average speed per road): count[r] vehicles on road r (all lanes) and

@@ -361,6 +361,7 @@ struct orc_sim {
     /* junction internal lanes (NULL without) */
     uint8_t *road_internal;
     int32_t *succ_off, *succ, *conf_off, *conf, *conf_feed;
+    uint8_t *succ_en;                 /* successor entry in use (dynamic lanes) */
     int8_t *road_group;
     uint32_t *vid;
     int32_t *depart;
@@ -428,7 +429,7 @@ static void free_sim(orc_sim *m)
                     m->d_id, m->d_leader, m->d_tl, m->d_tf, m->d_flags, m->d_margin,
                     m->node_x, m->node_y, m->node_manual, m->d_feat, m->d_use, m->arr,
                     m->dist0, m->lane_closed, m->road_internal, m->succ_off, m->succ,
-                    m->conf_off, m->conf, m->conf_feed};
+                    m->conf_off, m->conf, m->conf_feed, m->succ_en};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i)
         free(ptrs[i]);
     free(m);
@@ -514,6 +515,8 @@ orc_sim *orc_create(const orc_input *in)
         m->conf_off = dup_arr(in->lane_conf_off, (size_t)Lc + 1, 4);
         m->conf = dup_arr(in->lane_conf, (size_t)m->conf_off[Lc], 4);
         m->conf_feed = dup_arr(in->lane_conf_feed, (size_t)m->conf_off[Lc], 4);
+        m->succ_en = malloc((size_t)m->succ_off[Lc] + 1);
+        memset(m->succ_en, 1, (size_t)m->succ_off[Lc] + 1);
     }
     m->node_manual = malloc(sizeof(int32_t) * ((size_t)m->n_nodes + 1));
     for (int32_t j = 0; j < m->n_nodes; ++j)
@@ -677,13 +680,14 @@ static int32_t pick_lane(const orc_sim *m, int32_t rd, int32_t k)
 
 /* Lane connectivity inside junctions [reading; junction internal lanes].
  * succ_on: the successor of lane x on road rd in x's successor list, -1 if
- * x has a list without an entry on rd or has no list. */
+ * x has a list without an entry in use on rd or has no list (control may
+ * take entries out of use: dynamic lanes). */
 static int32_t succ_on(const orc_sim *m, int32_t x, int32_t rd)
 {
     if (!m->succ_off)
         return -1;
     for (int32_t q = m->succ_off[x]; q < m->succ_off[x + 1]; ++q)
-        if (m->lane_road[m->succ[q]] == rd)
+        if (m->succ_en[q] && m->lane_road[m->succ[q]] == rd)
             return m->succ[q];
     return -1;
 }
@@ -1220,6 +1224,32 @@ int orc_set_signal_phase(orc_sim *m, int32_t node, int32_t phase)
 void orc_set_lane_vlim(orc_sim *m, int32_t lane, float vlim)
 {
     m->lane_vlim[lane] = vlim;
+}
+
+int orc_set_lane_turns(orc_sim *m, int32_t n, const int32_t *lane, const int32_t *road,
+                       const int32_t *allowed)
+{
+    if (!m->succ_off)
+        return -1;
+    int32_t *at = malloc(sizeof(int32_t) * (n > 0 ? (size_t)n : 1));
+    for (int32_t q = 0; q < n; ++q) {
+        at[q] = -1;
+        if (lane[q] < 0 || lane[q] >= m->n_lanes) {
+            free(at);
+            return -1;
+        }
+        for (int32_t e = m->succ_off[lane[q]]; e < m->succ_off[lane[q] + 1]; ++e)
+            if (m->lane_road[m->succ[e]] == road[q])
+                at[q] = e;
+        if (at[q] < 0) {
+            free(at);
+            return -1;
+        }
+    }
+    for (int32_t q = 0; q < n; ++q)
+        m->succ_en[at[q]] = allowed[q] ? 1 : 0;
+    free(at);
+    return 0;
 }
 
 int orc_set_lane_closed(orc_sim *m, int32_t n, const int32_t *lane, const int32_t *closed)

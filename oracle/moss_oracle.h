@@ -138,6 +138,13 @@ void orc_set_lane_vlim(orc_sim *m, int32_t lane, float vlim);
  * it carry on.  Returns -1, changing nothing, for a lane out of range or
  * when a road would be left without an open lane. */
 int orc_set_lane_closed(orc_sim *m, int32_t n, const int32_t *lane, const int32_t *closed);
+/* Dynamic lanes (junction internal lanes): from the next step on, lane[q]
+ * lets vehicles continue onto road[q] (allowed[q] != 0) or not, by taking
+ * its successor entry on that road in or out of use.  A lane with entries
+ * none of which are in use continues nowhere.  Returns -1, changing nothing,
+ * without junction lanes or when a lane has no successor on the road. */
+int orc_set_lane_turns(orc_sim *m, int32_t n, const int32_t *lane, const int32_t *road,
+                       const int32_t *allowed);
 /* Vehicles and mean speed (FP64 sum in state order, 0 if empty) per road. */
 void orc_road_stats(const orc_sim *m, int32_t *count, float *mean_v);
 /* Position and heading of each state row: on the segment from the road's

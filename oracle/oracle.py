@@ -64,6 +64,9 @@ def lib():
         L.orc_set_lane_vlim.argtypes = [C.c_void_p, C.c_int32, C.c_float]
         L.orc_set_lane_closed.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.orc_set_lane_closed.restype = C.c_int
+        L.orc_set_lane_turns.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]
+        L.orc_set_lane_turns.restype = C.c_int
         L.orc_read_trips.argtypes = [C.c_void_p] + [C.c_void_p] * 4
         L.orc_positions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_positions.restype = C.c_int
@@ -226,6 +229,13 @@ class OracleSim:
         cl = np.ascontiguousarray(np.atleast_1d(closed), np.int32)
         if lib().orc_set_lane_closed(self._h, int(ln.shape[0]), _p(ln), _p(cl)) != 0:
             raise ValueError("lane out of range, or a road would have no open lane")
+
+    def set_lane_turns(self, lanes, roads, allowed):
+        ln = np.ascontiguousarray(np.atleast_1d(lanes), np.int32)
+        rd = np.ascontiguousarray(np.atleast_1d(roads), np.int32)
+        al = np.ascontiguousarray(np.atleast_1d(allowed), np.int32)
+        if lib().orc_set_lane_turns(self._h, int(ln.shape[0]), _p(ln), _p(rd), _p(al)) != 0:
+            raise ValueError("no junction lanes, or a lane without a successor on the road")
 
     def road_stats(self):
         """(vehicles per road, mean speed per road)."""

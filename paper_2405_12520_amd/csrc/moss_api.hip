@@ -71,7 +71,9 @@ struct Layout {
     size_t S[8], Pr[8], J[8], ls[2], idv[2][2], tails, chunk, leave, jcount, joff, blk, jlist, jlane, jidx, jslane, jins_list, jins_lane, jcnt, jcur, lane_red, scal, lanes,
         roads, route, qlanes, q_hdep, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, vt_dist0, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq,
-        tr_feat, tr_label, road_ab, out_buf, trip_buf, ctl_idx, ctl_rec, ctl_ridx, ctl_rrec;
+        tr_feat, tr_label, road_ab, out_buf, trip_buf, ctl_idx, ctl_rec, ctl_ridx, ctl_rrec,
+        succ_off, succ, conf_off, conf, conf_feed, heads;
+    int64_t n_succ = 0, n_conf = 0;
 
     void plan()
     {
@@ -145,6 +147,14 @@ struct Layout {
         ctl_rec = take(sizeof(LaneInfo) * (size_t)n_lanes);
         ctl_ridx = take(4 * (size_t)n_roads);
         ctl_rrec = take(sizeof(RoadInfo) * (size_t)n_roads);
+        // junction internal lanes (tiny placeholders without them)
+        const bool jl = n_succ > 0 || n_conf > 0;
+        succ_off = take(jl ? 4 * ((size_t)n_lanes + 1) : 4);
+        succ = take(sizeof(Succ) * (size_t)std::max<int64_t>(n_succ, 1));
+        conf_off = take(jl ? 4 * ((size_t)n_lanes + 1) : 4);
+        conf = take(sizeof(Succ) * (size_t)std::max<int64_t>(n_conf, 1));
+        conf_feed = take(4 * (size_t)std::max<int64_t>(n_conf, 1));
+        heads = take(jl ? sizeof(Head) * (size_t)n_lanes : sizeof(Head));
         // staging of the read functions' results for host destinations
         out_buf = take(std::max(8 * (size_t)n_roads, xy ? 24 * c : (size_t)8));
         // staging of moss_read_trips for host destinations: status, travel
@@ -209,6 +219,47 @@ int validate(const moss_network *net, const moss_signals *sig, const moss_vehicl
     }
     if (lanes != net->n_lanes)
         return fail(MOSS_EINVAL, "lane count %lld != n_lanes %d", (long long)lanes, net->n_lanes);
+    {
+        // junction internal lanes: all tables or none, lanes in range, at
+        // most one successor per road
+        const bool any = net->road_internal || net->lane_succ_off || net->lane_succ ||
+                         net->lane_conf_off || net->lane_conf || net->lane_conf_feed;
+        const bool all = net->road_internal && net->lane_succ_off && net->lane_conf_off &&
+                         (net->lane_succ || net->lane_succ_off[net->n_lanes] == 0) &&
+                         ((net->lane_conf && net->lane_conf_feed) ||
+                          net->lane_conf_off[net->n_lanes] == 0);
+        if (any && !all)
+            return fail(MOSS_EINVAL, "junction lane tables must be given together");
+        if (all) {
+            std::vector<int32_t> road_of(net->n_lanes);
+            for (int32_t r = 0; r < net->n_roads; ++r)
+                for (int32_t k = 0; k < net->road_nlanes[r]; ++k)
+                    road_of[net->road_lane0[r] + k] = r;
+            const int32_t *so = net->lane_succ_off, *co = net->lane_conf_off;
+            if (so[0] != 0 || co[0] != 0)
+                return fail(MOSS_EINVAL, "junction lane offsets must start at 0");
+            for (int32_t l = 0; l < net->n_lanes; ++l) {
+                if (so[l + 1] < so[l] || co[l + 1] < co[l])
+                    return fail(MOSS_EINVAL, "lane %d: junction lane offsets decrease", l);
+                for (int32_t q = so[l]; q < so[l + 1]; ++q) {
+                    const int32_t y = net->lane_succ[q];
+                    if (y < 0 || y >= net->n_lanes)
+                        return fail(MOSS_EINVAL, "lane %d: successor out of range", l);
+                    if (net->road_from[road_of[y]] != net->road_to[road_of[l]])
+                        return fail(MOSS_EINVAL, "lane %d: successor %d does not start where it "
+                                                 "ends", l, y);
+                    for (int32_t q2 = so[l]; q2 < q; ++q2)
+                        if (road_of[net->lane_succ[q2]] == road_of[y])
+                            return fail(MOSS_EINVAL, "lane %d: two successors on road %d", l,
+                                        road_of[y]);
+                }
+                for (int32_t q = co[l]; q < co[l + 1]; ++q)
+                    if (net->lane_conf[q] < 0 || net->lane_conf[q] >= net->n_lanes ||
+                        net->lane_conf_feed[q] < 0 || net->lane_conf_feed[q] >= net->n_lanes)
+                        return fail(MOSS_EINVAL, "lane %d: conflict entry out of range", l);
+            }
+        }
+    }
     if ((net->node_x == nullptr) != (net->node_y == nullptr))
         return fail(MOSS_EINVAL, "node_x and node_y must be given together");
     if (net->node_x)
@@ -234,10 +285,12 @@ int validate(const moss_network *net, const moss_signals *sig, const moss_vehicl
     for (float x : pos)
         if (!finite_pos(x))
             return fail(MOSS_EINVAL, "dt, a_max, b, length and b_max must be finite and > 0");
-    const float nonneg[] = {p.s0, p.T, p.b_safe, p.politeness, p.d_look};
+    const float nonneg[] = {p.s0, p.T, p.b_safe, p.politeness, p.d_look, p.b_mand,
+                            p.tau_yield};
     for (float x : nonneg)
         if (!finite_nonneg(x))
-            return fail(MOSS_EINVAL, "s0, T, b_safe, politeness and d_look must be finite, >= 0");
+            return fail(MOSS_EINVAL, "s0, T, b_safe, politeness, d_look, b_mand and tau_yield "
+                                     "must be finite, >= 0");
     if (!std::isfinite(p.a_thr) || !std::isfinite(p.p_lc) || p.p_lc < 0.0f || p.p_lc > 1.0f)
         return fail(MOSS_EINVAL, "a_thr must be finite and p_lc in [0, 1]");
     if (p.h_look < 0 || p.t0 < 0)
@@ -339,6 +392,10 @@ struct moss_sim {
     std::vector<LaneInfo> patch_rec;
     // host copy of the road records (closed-lane masks) and their staging
     std::vector<RoadInfo> roads_h;
+    // junction internal lanes: host copy of the successor table (an entry
+    // out of use by control carries road -1 - road) and its offsets
+    std::vector<Succ> succ_h;
+    std::vector<int32_t> succ_off_h;
     std::vector<int32_t> rpatch_idx;
     std::vector<RoadInfo> rpatch_rec;
 };
@@ -474,6 +531,12 @@ static void fill_dev(moss_sim *h)
     d.vt_dep = I(L.vt_dep);
     d.vt_rstart = U(L.vt_rstart);
     d.vt_dist0 = (const double *)(w + L.vt_dist0);
+    d.succ_off = I(L.succ_off);
+    d.succ = (const Succ *)(w + L.succ);
+    d.conf_off = I(L.conf_off);
+    d.conf = (const Succ *)(w + L.conf);
+    d.conf_feed = I(L.conf_feed);
+    d.heads = (Head *)(w + L.heads);
     d.cnt = (unsigned long long *)(w + L.cnt);
     d.sumv = (double *)(w + L.sumv);
     d.cnt_stride = stripe_elems((int64_t)h->n_scen * C_N);
@@ -504,6 +567,37 @@ static Dev step_dev(const moss_sim *h, int parity)
     return d;
 }
 
+// Whether lane l lets a vehicle continue onto road rd: no successor list, or
+// a successor on rd (junction internal lanes).
+static bool lane_permits(const moss_network *net, int32_t l, int32_t rd)
+{
+    if (!net->lane_succ_off || net->lane_succ_off[l] == net->lane_succ_off[l + 1])
+        return true;
+    for (int32_t q = net->lane_succ_off[l]; q < net->lane_succ_off[l + 1]; ++q) {
+        const int32_t y = net->lane_succ[q];
+        if (y >= net->road_lane0[rd] && y < net->road_lane0[rd] + net->road_nlanes[rd])
+            return true;
+    }
+    return false;
+}
+
+// Origin lane of pending vehicle i: among the lanes of its first road that
+// continue along its route (all of them without junction lanes, or for a
+// one-road route), the one of index id mod their number.
+static int32_t origin_lane(const moss_network *net, const moss_vehicles *veh, int32_t i)
+{
+    const int64_t a = veh->route_off[i];
+    const int32_t r0 = veh->route_roads[a], l0 = net->road_lane0[r0], n = net->road_nlanes[r0];
+    int32_t ok[256], cnt = 0;
+    if (veh->route_off[i + 1] - a > 1)
+        for (int32_t k = 0; k < n; ++k)
+            if (lane_permits(net, l0 + k, veh->route_roads[a + 1]))
+                ok[cnt++] = l0 + k;
+    if (cnt == 0)
+        return l0 + (int32_t)(veh->id[i] % (uint32_t)n);
+    return ok[veh->id[i] % (uint32_t)cnt];
+}
+
 static void plan_layout(const moss_network *net, const moss_vehicles *veh, const moss_params *prm,
                         Layout *L)
 {
@@ -516,13 +610,13 @@ static void plan_layout(const moss_network *net, const moss_vehicles *veh, const
     int32_t n_pl = 0;
     std::vector<char> is_q(net->n_lanes, 0);
     for (int32_t i = 0; i < veh->n; ++i) {
-        if (veh->placed && veh->placed[i]) {
+        if (veh->placed && veh->placed[i])
             ++n_pl;
-        } else {
-            int32_t r0 = veh->route_roads[veh->route_off[i]];
-            is_q[net->road_lane0[r0] + (int32_t)(veh->id[i] % (uint32_t)net->road_nlanes[r0])] = 1;
-        }
+        else
+            is_q[origin_lane(net, veh, i)] = 1;
     }
+    L->n_succ = net->lane_succ_off ? net->lane_succ_off[net->n_lanes] : 0;
+    L->n_conf = net->lane_conf_off ? net->lane_conf_off[net->n_lanes] : 0;
     L->n_pend = veh->n - n_pl;
     L->n_qlanes = (int32_t)std::count(is_q.begin(), is_q.end(), 1);
     L->nblk = (net->n_lanes + kScanBlockLanes - 1) / kScanBlockLanes;
@@ -611,6 +705,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
             li.offset = (uint16_t)(signalised ? sig->node_offset[j] % sig->node_cycle[j] : 0);
             li.manual = -1;
             li.road = r;
+            li.lflags = (net->road_internal && net->road_internal[r]) ? kLaneInternal : 0;
         }
     }
 
@@ -667,10 +762,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
         ls[l + 1] += ls[l];
 
     // --- departure queues: origin lane, then (depart, id)
-    auto origin = [&](int32_t i) {
-        int32_t r0 = veh->route_roads[veh->route_off[i]];
-        return net->road_lane0[r0] + (int32_t)(veh->id[i] % (uint32_t)net->road_nlanes[r0]);
-    };
+    auto origin = [&](int32_t i) { return origin_lane(net, veh, i); };
     std::vector<int32_t> olane(N, -1);
     for (int32_t i : pend)
         olane[i] = origin(i);
@@ -750,11 +842,14 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     P.d_look = p.d_look;
     P.two_sqrt_ab = (float)(2.0 * std::sqrt((double)p.a_max * (double)p.b));
     P.h_look = p.h_look;
+    P.b_mand = p.b_mand;
+    P.tau_yield = p.tau_yield;
     P.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
     P.key1 = (uint32_t)(p.seed >> 32);
     P.debug = L.debug ? 1u : 0u;
     P.trace = L.trace ? 1u : 0u;
     h->dev.mode = L.mlp ? 1 : 0;
+    h->dev.junctions = net->lane_succ_off ? 1 : 0;
 
     hipStream_t st = h->stream;
     char *w = h->ws;
@@ -812,6 +907,28 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
         }
         chk(up(L.road_ab, ab.data(), 8 * ab.size()));
     }
+    std::vector<Succ> succ_keep;
+    std::vector<int32_t> succ_off_keep;
+    if (net->lane_succ_off) {
+        // junction internal lanes: successors as (lane, road) pairs
+        std::vector<int32_t> road_of(NL);
+        for (int32_t r = 0; r < NR; ++r)
+            for (int32_t k = 0; k < net->road_nlanes[r]; ++k)
+                road_of[net->road_lane0[r] + k] = r;
+        std::vector<Succ> sv((size_t)L.n_succ);
+        for (int64_t q = 0; q < L.n_succ; ++q)
+            sv[q] = Succ{net->lane_succ[q], road_of[net->lane_succ[q]]};
+        std::vector<Succ> cv((size_t)L.n_conf);
+        for (int64_t q = 0; q < L.n_conf; ++q)
+            cv[q] = Succ{net->lane_conf[q], road_of[net->lane_conf[q]]};
+        chk(up(L.succ_off, net->lane_succ_off, 4 * ((size_t)NL + 1)));
+        chk(up(L.succ, sv.data(), sizeof(Succ) * sv.size()));
+        succ_keep = sv;
+        succ_off_keep.assign(net->lane_succ_off, net->lane_succ_off + NL + 1);
+        chk(up(L.conf_off, net->lane_conf_off, 4 * ((size_t)NL + 1)));
+        chk(up(L.conf, cv.data(), sizeof(Succ) * cv.size()));
+        chk(up(L.conf_feed, net->lane_conf_feed, 4 * (size_t)L.n_conf));
+    }
     chk(up(L.route, route.data(), 4 * route.size()));
     chk(up(L.qlanes, qlanes.data(), 4 * qlanes.size()));
     {
@@ -837,10 +954,14 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     }
     if (e == hipSuccess)
         e = launch_tails(step_dev(h, 0), st);
+    if (e == hipSuccess && h->dev.junctions)
+        e = launch_heads(step_dev(h, 0), st);
     if (e == hipSuccess && L.mlp)
         e = launch_mlp_pack(step_dev(h, 0), st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
+    h->succ_h.swap(succ_keep);
+    h->succ_off_h.swap(succ_off_keep);
     if (e != hipSuccess) {
         delete h;
         return fail(MOSS_EDEVICE, "device setup failed: %s", hipGetErrorString(e));
@@ -1235,6 +1356,40 @@ int moss_set_signal_phase(moss_sim *h, const int32_t *node, const int32_t *phase
     return stage_and_upload(h);
 }
 
+int moss_set_lane_turns(moss_sim *h, const int32_t *lane, const int32_t *road,
+                        const int32_t *allowed, int32_t n)
+{
+    g_err.clear();
+    if (!h || (n > 0 && (!lane || !road || !allowed)) || n < 0)
+        return fail(MOSS_EINVAL, "null argument or negative count");
+    if (h->succ_off_h.empty())
+        return fail(MOSS_EINVAL, "the network has no junction lanes");
+    const int32_t NL = (int32_t)h->succ_off_h.size() - 1;
+    std::vector<int32_t> entry(n);
+    for (int32_t i = 0; i < n; ++i) {
+        if (lane[i] < 0 || lane[i] >= NL)
+            return fail(MOSS_EINVAL, "lane %d out of range", lane[i]);
+        entry[i] = -1;
+        for (int32_t q = h->succ_off_h[lane[i]]; q < h->succ_off_h[lane[i] + 1]; ++q) {
+            const int32_t r = h->succ_h[q].road;
+            if ((r >= 0 ? r : -1 - r) == road[i])
+                entry[i] = q;
+        }
+        if (entry[i] < 0)
+            return fail(MOSS_EINVAL, "lane %d has no successor on road %d", lane[i], road[i]);
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        Succ &sx = h->succ_h[entry[i]];
+        const int32_t r = sx.road >= 0 ? sx.road : -1 - sx.road;
+        sx.road = allowed[i] ? r : -1 - r;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(h->ws + h->lay.succ, h->succ_h.data(), sizeof(Succ) * h->succ_h.size(),
+                      hipMemcpyHostToDevice));
+    return MOSS_OK;
+}
+
 int moss_set_lane_closed(moss_sim *h, const int32_t *lane, const int32_t *closed, int32_t n)
 {
     g_err.clear();
@@ -1264,7 +1419,8 @@ int moss_set_lane_closed(moss_sim *h, const int32_t *lane, const int32_t *closed
     }
     h->patch_idx.clear();
     for (int32_t i = 0; i < n; ++i) {
-        h->lanes_h[lane[i]].closed = closed[i] ? 1 : 0;
+        uint8_t &lf = h->lanes_h[lane[i]].lflags;
+        lf = (uint8_t)(closed[i] ? (lf | kLaneClosed) : (lf & ~kLaneClosed));
         h->patch_idx.push_back(lane[i]);
     }
     h->rpatch_idx.clear();

@@ -27,11 +27,13 @@ struct LaneInfo {
     uint8_t k;          // index in the road
     uint8_t nlanes;
     int8_t group;       // signal group of the road at its downstream node, -1 none
-    uint8_t closed;     // lane restriction by control: 1 closed to entering vehicles
+    uint8_t lflags;     // kLaneClosed (control: closed to entering vehicles), kLaneInternal
     uint16_t cycle, phase, offset;         // plan of the downstream node (offset < cycle)
     int16_t manual;     // phase held by signal control, -1: the fixed-time plan
     int32_t road;
 };
+
+constexpr uint8_t kLaneClosed = 1u, kLaneInternal = 2u;
 
 // Red light for the lanes of a road at step t: the road waits unless the
 // phase its downstream junction shows (held by control, else of the
@@ -74,15 +76,30 @@ __host__ __device__ inline int pick_lane(int k, int n, uint32_t closed)
     return (closed == 0u || (open & bit)) ? kk : near;
 }
 
-// Per-lane flags of the current step (lane_red): bit 0 the lane's road
-// waits at a red light, bit 1 the lane is closed.
-constexpr uint8_t kRedBit = 1u, kClosedBit = 2u;
+// Per-lane flags of the current step (lane_red): the lane's road waits at a
+// red light, the lane is closed, the lane lies inside a junction.
+constexpr uint8_t kRedBit = 1u, kClosedBit = 2u, kInternalBit = 4u;
 
 // Flags byte of a lane at step t (kRedBit, kClosedBit).
 __host__ __device__ inline uint8_t lane_flags_at(const LaneInfo &li, uint32_t t)
 {
-    return (uint8_t)((lane_red_at(li, t) ? kRedBit : 0u) | (li.closed ? kClosedBit : 0u));
+    return (uint8_t)((lane_red_at(li, t) ? kRedBit : 0u) |
+                     ((li.lflags & kLaneClosed) ? kClosedBit : 0u) |
+                     ((li.lflags & kLaneInternal) ? kInternalBit : 0u));
 }
+
+// First vehicle (highest position) of each lane with its next route road
+// (-1 on the last road or when the lane is empty), for the yield rule.
+struct Head {
+    float s, v;
+    int32_t next;
+    int32_t pad;
+};
+
+// A lane's successor on another road (junction internal lanes).
+struct Succ {
+    int32_t lane, road;
+};
 
 // Last vehicle (lowest position) of each lane; id == kNone when empty.
 struct Tail {
@@ -104,6 +121,7 @@ struct SoA {
 struct Params {
     float dt, a_max, s0, T, len, b_max, b_safe, pol, a_thr, p_lc, d_look;
     float two_sqrt_ab;  // fl32(2 sqrt(a_max b)) formed in double on the host
+    float b_mand, tau_yield;
     int32_t h_look;
     uint32_t key0, key1;
     uint32_t debug;
@@ -182,6 +200,13 @@ struct Dev {
     // some lane is closed by control: the update variant that applies
     // closures is launched (set between steps; captured graphs are redone)
     int32_t closures;
+    // junction internal lanes: successor lists (CSR over lanes), per
+    // connector lane the conflicting lanes with priority and their feeders,
+    // and the lane heads written after every step
+    int32_t junctions;
+    const int32_t *succ_off, *conf_off, *conf_feed;
+    const Succ *succ, *conf;
+    Head *heads;
     // learned closure (mode 1) and its training trace
     int32_t mode;
     const float *mlp_theta, *mlp_norm;
@@ -225,6 +250,8 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);
 int step_kernel_count();
 const char *step_kernel_name(int i);
 hipError_t launch_tails(const Dev &d, hipStream_t st);
+// Lane heads of the current state (junction internal lanes).
+hipError_t launch_heads(const Dev &d, hipStream_t st);
 // Overwrites n lane records (signal control, speed limits) and recomputes
 // their red flags for the step about to run.
 hipError_t launch_lane_patch(const Dev &d, const int32_t *idx, const LaneInfo *rec, int32_t n,

@@ -156,17 +156,79 @@ struct Lead {
     uint32_t id;
 };
 
+// Lane taken on road rd (record rdi, next road of the route) by a vehicle
+// leaving lane y (index kk in its road).  EXT handles control's lane
+// closures and junction internal lanes: y's successor on rd when y has a
+// successor list (the nearest open lane if it is closed), else lane index
+// min(kk, n-1), or with closures the open lane nearest to it.  Without EXT
+// the lane index is min(kk, n-1).
+template <bool EXT>
+__device__ __forceinline__ int next_lane(const Dev &d, int y, int kk, int rd, const RoadInfo &rdi)
+{
+    if constexpr (EXT) {
+        if (d.junctions) {
+            const int a = at(d.succ_off, y), b = at(d.succ_off, y + 1);
+            for (int q = a; q < b; ++q) {
+                const Succ sx = at(d.succ, q);
+                if (sx.road == rd) {
+                    const int k2 = sx.lane - rdi.lane0;
+                    return rdi.lane0 + (d.closures ? pick_lane(k2, rdi.nlanes, rdi.closed) : k2);
+                }
+            }
+        }
+        return rdi.lane0 +
+               (d.closures ? pick_lane(kk, rdi.nlanes, rdi.closed) : min(kk, rdi.nlanes - 1));
+    } else {
+        return rdi.lane0 + min(kk, rdi.nlanes - 1);
+    }
+}
+
+// Whether lane y lets a vehicle continue onto road rd (junction internal
+// lanes): y has no successor list, or a successor on rd.
+__device__ __forceinline__ bool lane_permits(const Dev &d, int y, int rd)
+{
+    const int a = at(d.succ_off, y), b = at(d.succ_off, y + 1);
+    bool ok = a == b;
+    for (int q = a; q < b; ++q)
+        ok = ok || at(d.succ, q).road == rd;
+    return ok;
+}
+
+// Yield rule at a junction: connector lane cl is busy when one of the
+// conflicting connector lanes with priority over it holds a vehicle (its
+// tail at the start of the step), or the lane feeding such a connector has a
+// first vehicle headed into it, not held by a red light, and within
+// tau_yield seconds of its stop line at its speed (L - s <= v tau_yield).
+__device__ bool conflict_busy(const Dev &d, int cl)
+{
+    const int a = at(d.conf_off, cl), b = at(d.conf_off, cl + 1);
+    for (int q = a; q < b; ++q) {
+        const Succ c2 = at(d.conf, q);
+        if (at(d.tails, c2.lane).id != kNone)
+            return true;
+        const int f = at(d.conf_feed, q);
+        const Head hd = at(d.heads, f);
+        if (hd.next == c2.road && !(at(d.lane_red, f) & kRedBit) &&
+            at(d.lanes, f).L - hd.s <= hd.v * d.P.tau_yield)
+            return true;
+    }
+    return false;
+}
+
 // Leader beyond the lane end: follow the route for at most h_look roads while
-// the distance covered is within d_look; on each road take lane min(k, n-1)
-// and use its last vehicle (lane tail).  A vehicle never leads itself.
-// rd0 is the record of the next road nxt (already loaded by the caller);
-// with pre, tl0 is the tail the first road gives (loaded by the caller too).
-__device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id, uint32_t ptr,
-                          int32_t nxt, RoadInfo rd0, bool pre, Tail tl0, bool closures)
+// the distance covered is within d_look; on each road take the lane
+// next_lane gives and use its last vehicle (lane tail).  A vehicle never
+// leads itself.  lf is the vehicle's (final) lane, li its record; rd0 is the
+// record of the next road nxt (already loaded by the caller); with pre, tl0
+// is the tail the first road gives (loaded by the caller too).
+template <bool EXT>
+__device__ Lead lookahead(const Dev &d, int lf, const LaneInfo &li, float s, uint32_t id,
+                          uint32_t ptr, int32_t nxt, RoadInfo rd0, bool pre, Tail tl0)
 {
     Lead r = {false, 0.0f, 0.0f, kNone};
     float dist = li.L - s;
     int kk = li.k;
+    int y = lf;
     uint32_t p = ptr;
     int32_t nr = nxt;
     RoadInfo rd = rd0;
@@ -177,12 +239,13 @@ __device__ Lead lookahead(const Dev &d, const LaneInfo &li, float s, uint32_t id
             break;
         if (h > 0)
             rd = at(d.roads, nr);
-        kk = closures ? pick_lane(kk, rd.nlanes, rd.closed) : min(kk, rd.nlanes - 1);
+        y = next_lane<EXT>(d, y, kk, nr, rd);
+        kk = y - rd.lane0;
         Tail tl;
         if (h == 0 && pre)
             tl = tl0;
         else
-            tl = at(d.tails, rd.lane0 + kk);
+            tl = at(d.tails, y);
         if (tl.id != kNone) {
             if (tl.id != id) {
                 r.has = true;
@@ -286,7 +349,7 @@ __global__ void k_insert(Dev d)
             const float v0e = fmin32(at(d.q_v0, h), li.vlim);
             const int lo = at(d.ls_old, l), hi = at(d.ls_old, l + 1);
             bool ok;
-            if (li.closed) {
+            if (li.lflags & kLaneClosed) {
                 ok = false;     // a closed lane holds its departure queue
             } else if (lo == hi) {
                 ok = true;
@@ -375,7 +438,7 @@ __device__ __forceinline__ int xcd_tile(int remap, int ntiles)
 // Joiners are listed in the tile's own region of jlist, so no atomic result
 // is waited for.  MODE 1 evaluates the learned closure for the wave's 64
 // vehicles on the matrix cores between the acceleration and the integration.
-template <int MODE, bool AUX, bool CLOSED>
+template <int MODE, bool AUX, bool EXT>
 __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
@@ -384,9 +447,10 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 
     const int n = *d.n_cur;
     const int64_t t = *d.t;
-    // lane closures by control change the lane taken on the next road (the
-    // variant without them is launched while no lane is closed)
-    constexpr bool closures = CLOSED;
+    // lane closures by control and junction internal lanes change the lane
+    // taken on the next road, the lane-change rule and the stop line; the
+    // variant without them (EXT false) is launched when neither is present
+    const bool junctions = EXT && d.junctions;
     const Params &P = d.P;
     const uint32_t tt = (uint32_t)t;
     const int tid = threadIdx.x;
@@ -463,7 +527,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         const LaneInfo li = at(d.lanes, l);
         const uint8_t red_raw = at(d.lane_red, l);
         const float vlim_c_side = at(d.lanes, ls_c).vlim;
-        const uint8_t side_flags = CLOSED ? at(d.lane_red, ls_c) : (uint8_t)0;
+        const uint8_t side_flags = EXT ? at(d.lane_red, ls_c) : (uint8_t)0;
         const int r0_c = at(d.ls_old, ls_c), r1_c = at(d.ls_old, ls_c + 1);
         const RoadInfo rd_c = at(d.roads, head_next ? nxt : 0);
         const bool red_now = act && (red_raw & kRedBit) != 0;
@@ -484,13 +548,14 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         // 0 for the other vehicles)
         Tail tl_own, tl_side;
         {
-            const int k_own = closures ? pick_lane((int)li.k, rd_c.nlanes, rd_c.closed)
-                                       : min((int)li.k, rd_c.nlanes - 1);
-            const int k_side = closures ? pick_lane(max((int)li.k + side, 0), rd_c.nlanes,
-                                                    rd_c.closed)
-                                        : min(max((int)li.k + side, 0), rd_c.nlanes - 1);
-            tl_own = at(d.tails, head_next ? rd_c.lane0 + k_own : 0);
-            tl_side = at(d.tails, head_next ? rd_c.lane0 + k_side : 0);
+            int ln_own = 0, ln_side = 0;
+            if (head_next) {
+                ln_own = next_lane<EXT>(d, (int)l, (int)li.k, nxt, rd_c);
+                ln_side = next_lane<EXT>(d, side_ok ? ls_side : (int)l,
+                                         max((int)li.k + side, 0), nxt, rd_c);
+            }
+            tl_own = at(d.tails, ln_own);
+            tl_side = at(d.tails, ln_side);
         }
         const int scen0 = __builtin_amdgcn_readlane(li.scen, 0);
         const bool uni_scen = __all(!act || li.scen == scen0);
@@ -542,7 +607,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             bool hasLt = false, hasN = false;
             float sLt = 0.0f, vLt = 0.0f;
             uint32_t idLt = kNone;
-            if (s >= 0.0f) {
+            // no lane changes inside a junction
+            if (s >= 0.0f && (!EXT || !(red_raw & kInternalBit))) {
                 const int kt = (int)li.k + side;
                 if (kt >= 0 && kt < (int)li.nlanes && side_open) {
                     mobil = true;
@@ -607,7 +673,19 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                         if (!(gap_f > 0.0f)) safe = false;
                     }
                     float inc = (acc_t - acc_c) + P.pol * (d_n + d_o);
-                    const bool cand = safe && inc > P.a_thr;
+                    // lanes that continue the route: a target lane that does,
+                    // when the own lane does not, adds b_mand to the incentive;
+                    // one that does not, when the own lane does, is never taken
+                    bool allowed = true;
+                    if (junctions && nxt >= 0) {
+                        const bool pc = lane_permits(d, (int)l, nxt);
+                        const bool pt = lane_permits(d, lt, nxt);
+                        if (pt && !pc)
+                            inc = inc + P.b_mand;
+                        else if (pc && !pt)
+                            allowed = false;
+                    }
+                    const bool cand = safe && allowed && inc > P.a_thr;
                     if (cand) {       // the random draw only matters for candidates
                         uint32_t x0 = philox_x0(tt, id, 0u, 0u, P.key0, P.key1);
                         float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
@@ -628,6 +706,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             }
             const float free_f = change ? free_t : free_c;
             const bool inlane = change ? hasLt : hasLc;
+            if (junctions && nxt >= 0 && !lane_permits(d, lf, nxt))
+                flags |= 32;        // final lane does not continue the route
             float acc;
             bool has_lead;
             float lead_v, lead_gap;
@@ -643,8 +723,22 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                     rd_next = at(d.roads, nxt);
                     rd_ok = true;
                 }
-                const Lead ld = lookahead(d, lif, s, id, ptr, nxt, rd_next, head_next,
-                                          change ? tl_side : tl_own, closures);
+                const Lead ld = lookahead<EXT>(d, lf, lif, s, id, ptr, nxt, rd_next, head_next,
+                                               change ? tl_side : tl_own);
+                // yield at a junction: the first vehicle of its lane stops at
+                // the line when the connector lane it would take has busy
+                // conflicts with priority (applied if it can still stop)
+                if (junctions && nxt >= 0) {
+                    const int cl = next_lane<EXT>(d, lf, (int)lif.k, nxt, rd_next);
+                    if (conflict_busy(d, cl)) {
+                        flags |= 64;
+                        if (!red) {
+                            float stop_dist = (v * v) / (2.0f * P.b_max);
+                            if (L - s >= stop_dist)
+                                red = true;
+                        }
+                    }
+                }
                 if (ld.has) flags |= 8;
                 has_lead = ld.has;
                 lead_v = ld.v;
@@ -756,8 +850,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 p += 1;
                 const RoadInfo rd = (first && rd_ok) ? rd_next : at(d.roads, nr);
                 first = false;
-                kk = closures ? pick_lane(kk, rd.nlanes, rd.closed) : min(kk, rd.nlanes - 1);
-                x = rd.lane0 + kk;
+                x = next_lane<EXT>(d, x, kk, nr, rd);
+                kk = x - rd.lane0;
                 Lx = rd.L;
                 nr = at(d.route, p + 1);
             }
@@ -1638,6 +1732,23 @@ __global__ void k_tails(Dev d)
                any ? at(d.S.id, w0) : kNone);
 }
 
+// First vehicle (highest position) of every lane with its next route road,
+// from the lane starts ls of the state held in S (the new starts after a
+// step's merge, the current ones at creation).
+__global__ void k_heads(Dev d, const int32_t *ls)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= d.n_lanes)
+        return;
+    const int w0 = at(ls, l), w1 = at(ls, l + 1);
+    Head hd;
+    hd.pad = 0;
+    hd.s = w1 > w0 ? at(d.S.s, w1 - 1) : 0.0f;
+    hd.v = w1 > w0 ? at(d.S.v, w1 - 1) : 0.0f;
+    hd.next = w1 > w0 ? at(d.S.next, w1 - 1) : -1;
+    at(d.heads, l) = hd;
+}
+
 __device__ __forceinline__ int find_vehicle(const Dev &d, uint32_t id)
 {
     int lo = 0, hi = d.n_veh;
@@ -1709,7 +1820,7 @@ static inline unsigned blocks_for(long long n, int per)
 }
 
 static const char *const kStepKernels[] = {"k_insert", "k_update", "k_scan_reduce",
-                                            "k_scan_apply", "k_jscatter", "k_merge"};
+                                            "k_scan_apply", "k_jscatter", "k_merge", "k_heads"};
 
 int step_kernel_count() { return (int)(sizeof kStepKernels / sizeof kStepKernels[0]); }
 const char *step_kernel_name(int i)
@@ -1734,7 +1845,7 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     if (d.xcd_remap) gu = (gu + 7u) & ~7u;     // workgroups past the last tile find no work
     const bool aux = d.P.debug || d.P.trace;
     void (*ku)(Dev);
-    if (d.closures)
+    if (d.closures || d.junctions)
         ku = d.mode == 1 ? (aux ? k_update<1, true, true> : k_update<1, false, true>)
                          : (aux ? k_update<0, true, true> : k_update<0, false, true>);
     else
@@ -1756,6 +1867,10 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     if (d.xcd_remap) gm = (gm + 7u) & ~7u;     // chunks past the last one return at once
     hipLaunchKernelGGL(k_merge, dim3(gm), dim3(kMT), 0, st, d);
     mark(6);
+    if (d.junctions)
+        hipLaunchKernelGGL(k_heads, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d,
+                           (const int32_t *)d.ls_new);
+    mark(7);
     return hipGetLastError();
 }
 
@@ -1863,6 +1978,12 @@ hipError_t launch_positions(const Dev &d, int32_t n, const double *road_ab, doub
 hipError_t launch_mlp_pack(const Dev &d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_heads(const Dev &d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_heads, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d, d.ls_old);
     return hipGetLastError();
 }
 

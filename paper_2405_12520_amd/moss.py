@@ -33,7 +33,9 @@ class moss_network(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_roads", C.c_int32), ("n_lanes", C.c_int32),
                 ("n_scen", C.c_int32), ("road_from", vp), ("road_to", vp), ("road_nlanes", vp),
                 ("road_lane0", vp), ("road_length", vp), ("lane_vlim", vp), ("lane_scen", vp),
-                ("node_x", vp), ("node_y", vp)]
+                ("node_x", vp), ("node_y", vp), ("road_internal", vp), ("lane_succ_off", vp),
+                ("lane_succ", vp), ("lane_conf_off", vp), ("lane_conf", vp),
+                ("lane_conf_feed", vp)]
 
 
 class moss_signals(C.Structure):
@@ -52,7 +54,8 @@ class moss_params(C.Structure):
                 ("b_safe", C.c_float), ("politeness", C.c_float), ("a_thr", C.c_float),
                 ("p_lc", C.c_float), ("d_look", C.c_float), ("h_look", C.c_int32),
                 ("t0", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32),
-                ("mode", C.c_int32), ("mlp_theta", vp), ("mlp_norm", vp)]
+                ("mode", C.c_int32), ("mlp_theta", vp), ("mlp_norm", vp),
+                ("b_mand", C.c_float), ("tau_yield", C.c_float)]
 
 
 class moss_state_out(C.Structure):
@@ -75,7 +78,7 @@ EXPORTS = ("moss_query_workspace", "moss_create", "moss_step", "moss_read_state"
            "moss_read_trace", "moss_read_mlp_error", "moss_set_launch", "moss_get_launch",
            "moss_read_road_stats", "moss_read_positions", "moss_read_trips",
            "moss_set_signal_phase",
-           "moss_set_lane_vlim", "moss_set_lane_closed",
+           "moss_set_lane_vlim", "moss_set_lane_closed", "moss_set_lane_turns",
            "moss_destroy", "moss_last_error")
 
 _lib = None
@@ -124,6 +127,7 @@ def load(path: str = LIB_PATH):
     L.moss_set_signal_phase.argtypes = [vp, vp, vp, C.c_int32]
     L.moss_set_lane_vlim.argtypes = [vp, vp, vp, C.c_int32]
     L.moss_set_lane_closed.argtypes = [vp, vp, vp, C.c_int32]
+    L.moss_set_lane_turns.argtypes = [vp, vp, vp, vp, C.c_int32]
     L.moss_read_positions.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.POINTER(C.c_int32)]
     L.moss_get_launch.argtypes = [vp, C.POINTER(moss_launch)]
     L.moss_read_trips.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp,
@@ -166,6 +170,13 @@ def marshal(sc, debug: bool = False, trace: bool = False):
                        arr(sc.road_length, np.float32), arr(sc.lane_vlim, np.float32),
                        arr(sc.lane_scen, np.int32), arr(sc.node_x, np.float64),
                        arr(sc.node_y, np.float64))
+    if sc.lane_succ_off is not None:
+        net.road_internal = arr(sc.road_internal, np.uint8)
+        net.lane_succ_off = arr(sc.lane_succ_off, np.int32)
+        net.lane_succ = arr(sc.lane_succ, np.int32)
+        net.lane_conf_off = arr(sc.lane_conf_off, np.int32)
+        net.lane_conf = arr(sc.lane_conf, np.int32)
+        net.lane_conf_feed = arr(sc.lane_conf_feed, np.int32)
     sig = moss_signals(arr(sc.node_cycle, np.int32), arr(sc.node_phase, np.int32),
                        arr(sc.node_offset, np.int32), arr(sc.road_group, np.int8))
     veh = moss_vehicles(sc.n_veh, arr(sc.veh_id, np.uint32), arr(sc.depart, np.int32),
@@ -181,7 +192,8 @@ def marshal(sc, debug: bool = False, trace: bool = False):
                       int(p["h_look"]), int(p["t0"]), int(p["seed"]), flags,
                       MOSS_MODE_MLP if mlp_cfg is not None else MOSS_MODE_IDM,
                       arr(mlp_cfg["theta"], np.float32) if mlp_cfg is not None else None,
-                      arr(mlp_cfg["norm"], np.float32) if mlp_cfg is not None else None)
+                      arr(mlp_cfg["norm"], np.float32) if mlp_cfg is not None else None,
+                      float(p.get("b_mand", 1.0)), float(p.get("tau_yield", 3.0)))
     return net, sig, veh, prm, keep
 
 
@@ -423,6 +435,17 @@ class Simulator:
         if l.shape != c.shape:
             raise ValueError("lanes and flags differ in length")
         _check(load().moss_set_lane_closed(vp(self.h), _ptr(l), _ptr(c), int(l.shape[0])))
+
+    def set_lane_turns(self, lanes, roads, allowed):
+        """Lets lanes continue onto roads (1) or not (0) from the next step on
+        (junction internal lanes)."""
+        l = np.ascontiguousarray(np.atleast_1d(lanes), np.int32)
+        r = np.ascontiguousarray(np.atleast_1d(roads), np.int32)
+        a = np.ascontiguousarray(np.atleast_1d(allowed), np.int32)
+        if not (l.shape == r.shape == a.shape):
+            raise ValueError("lanes, roads and flags differ in length")
+        _check(load().moss_set_lane_turns(vp(self.h), _ptr(l), _ptr(r), _ptr(a),
+                                          int(l.shape[0])))
 
     def road_stats(self):
         """(vehicles per road [n_roads] int32, mean speed per road [n_roads] float32)."""

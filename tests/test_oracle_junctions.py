@@ -277,3 +277,51 @@ def test_runs_with_junction_lanes_keep_the_invariants(name):
         assert c[0, 0] == o.n_active + c[0, 2]
     if name == "intersection":
         assert o.counters()[0][0, 2] == sc.n_veh
+
+
+# -------------------------------------------------------- dynamic lanes --
+
+def dynamic_lane_case():
+    """Vehicle 1 in the right lane of the north approach going straight on
+    (the right lane does), 200 m from the line; p_lc = 1, even first step."""
+    return _state([dict(id=1, route=[N_IN, S_OUT], lane=1, s=300.0, v=10.0)],
+                  params=dict(p_lc=1.0))
+
+
+def test_dynamic_lane_takes_a_movement_away():
+    """Taking the straight movement away from the right lane: the vehicle's
+    lane no longer continues its route (flag 32), the left lane does, so the
+    bias moves it there; given back, the right lane continues again."""
+    from oracle import OracleSim
+    sc = dynamic_lane_case()
+    straight = _conn(sc, N_IN, S_OUT)
+    l1 = _lane(sc, N_IN, 1)
+    o = OracleSim(sc)
+    o.step(1)
+    assert not (o.debug()["flags"][0] & 32)
+    o = OracleSim(sc)
+    o.set_lane_turns([l1], [straight], [0])
+    o.step(1)
+    assert o.debug()["flags"][0] & 2                          # changed to lane 0
+    assert o.state()["lane"].tolist() == [_lane(sc, N_IN, 0)]
+    o = OracleSim(dataclasses_replace_p_lc(sc, 0.0))
+    o.set_lane_turns([l1], [straight], [0])
+    o.step(1)
+    assert o.debug()["flags"][0] & 32
+    o.set_lane_turns([l1], [straight], [1])
+    o.step(1)
+    assert not (o.debug()["flags"][0] & 32)
+
+
+def dataclasses_replace_p_lc(sc, p_lc):
+    return sc.with_params(p_lc=p_lc)
+
+
+def test_dynamic_lane_rejects_unknown_movements():
+    from oracle import OracleSim
+    sc = dynamic_lane_case()
+    o = OracleSim(sc)
+    with pytest.raises(ValueError):                           # lane 1 does not turn left
+        o.set_lane_turns([_lane(sc, N_IN, 1)], [_conn(sc, N_IN, E_OUT)], [1])
+    with pytest.raises(ValueError):
+        OracleSim(S.intersection()).set_lane_turns([0], [1], [0])
