@@ -197,7 +197,7 @@ def bench_big(args):
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    per = {k: v / 20 for k, v in kms.items()}
+    per = {k: v / 20 for k, v in kms.items() if v > 0}
     frac = {k: round(ALGO_BYTES[k] * n_act / (per[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             for k in ALGO_BYTES}
     say(f"[bench] 8M city: {veh_steps / (ms / 1e3):.4g} vehicle-steps/s, per-kernel ms "
@@ -230,14 +230,29 @@ def bench_batch(args):
     sim.step(600)
     ms, dc = timed_steps(sim, args.steps)
     veh_steps = int(dc[:, 6].sum())
+    # per-kernel durations over the next 20 steps (HIP events on the
+    # simulator's stream) and the roofline of the dominant per-vehicle kernel
+    n0 = sim.n_active
+    kms = sim.step_timed(20)
+    n_act = 0.5 * (n0 + sim.n_active)
     sim.close()
     torch.cuda.empty_cache()
-    say(f"[bench] batch: {veh_steps / (ms / 1e3):.4g} vehicle-steps/s")
+    per = {k: v / 20 for k, v in kms.items() if v > 0}
+    dom = max(ALGO_BYTES, key=lambda k: per[k])
+    achieved = ALGO_BYTES[dom] * n_act / (per[dom] * 1e-3) / 1e9
+    say(f"[bench] batch: {veh_steps / (ms / 1e3):.4g} vehicle-steps/s, per-kernel ms "
+        f"{ {k: round(v, 4) for k, v in per.items()} }")
     return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
                 ms_per_step=round(ms / args.steps, 5), scenarios=int(sc.n_scen),
                 vehicles_total=int(sc.n_veh), active_mean=round(veh_steps / args.steps, 1),
                 window="steps 600..600+K of 1800", lanes=int(sc.n_lanes),
-                launch=rec["launch"], launch_tuned_ms_per_step=rec["ms_per_step"])
+                launch=rec["launch"], launch_tuned_ms_per_step=rec["ms_per_step"],
+                kernel_ms={k: round(v, 5) for k, v in per.items()},
+                roofline=dict(bound="hbm", kernel=dom, achieved=round(achieved, 1),
+                              peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(achieved / HBM_PEAK_GBS, 4),
+                              algo_bytes_per_vehicle=ALGO_BYTES[dom],
+                              active_vehicles=round(n_act, 1)))
 
 
 def bench_small(args):
@@ -447,7 +462,7 @@ def main():
     # per-kernel durations with HIP events on the simulator's stream
     kms = sim.step_timed(args.steps)
     n_act = sim.n_active
-    per_launch = {k: v / args.steps for k, v in kms.items()}
+    per_launch = {k: v / args.steps for k, v in kms.items() if v > 0}
     dom = max(ALGO_BYTES, key=lambda k: per_launch[k])
     algo = ALGO_BYTES[dom] * n_act
     achieved = algo / (per_launch[dom] / 1e3) / 1e9

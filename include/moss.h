@@ -242,9 +242,10 @@ int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leade
  * duration of each of its kernels, measured with HIP events on the
  * simulator's stream, to kernel_ms[k] (milliseconds; array of capacity
  * entries, zeroed first).  *n_kernels receives the number of kernels per
- * step; moss_kernel_name(k) names kernel k (NULL if out of range).  Meant
- * for measurement: the per-step synchronisation makes it slower than
- * moss_step. */
+ * step; moss_kernel_name(k) names kernel k (NULL if out of range); a kernel
+ * the workload does not launch (insertion without departures, lane heads
+ * without junction lanes) reports 0.  Meant for measurement: the per-step
+ * synchronisation makes it slower than moss_step. */
 int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
                     int32_t *n_kernels);
 const char *moss_kernel_name(int32_t i);

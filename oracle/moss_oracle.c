@@ -71,11 +71,13 @@ static float fmax32(float x, float y) { return x > y ? x : y; }
 
 /* IDM acceleration (Treiber, Hennecke, Helbing 2000) with exponent 4:
  *   a_max * (1 - (v/v0)^4 - (s*(v, dv) / gap)^2),
- *   s* = s0 + max(0, v*T + v*dv / (2*sqrt(a_max*b))).
+ *   s* = s0 + max(0, v*T + v*dv / (2*sqrt(a_max*b))),
+ * the last term evaluated as v*dv times the FP32 reciprocal of 2*sqrt(a_max*b)
+ * formed in double [reading: the paper prints no formula].
  * Without a leader only the free-road term remains.  A non-positive gap
  * returns the braking limit [reading: guards the division]. */
 float orc_idm(float v, float v0e, int has_leader, float v_lead, float gap, float a_max,
-              float two_sqrt_ab, float s0, float T, float b_max)
+              float inv_tsab, float s0, float T, float b_max)
 {
     float r = v / v0e;
     float r2 = r * r;
@@ -87,7 +89,7 @@ float orc_idm(float v, float v0e, int has_leader, float v_lead, float gap, float
         return -b_max;
     float dv = v - v_lead;
     float t1 = v * T;
-    float t2 = (v * dv) / two_sqrt_ab;
+    float t2 = (v * dv) * inv_tsab;
     float tt = t1 + t2;
     float ss = s0 + (tt > 0.0f ? tt : 0.0f);
     float q = ss / gap;
@@ -327,7 +329,8 @@ void orc_mlp_candidates_batch(const float *theta, const float *norm, int32_t n, 
 
 typedef struct {
     float dt, a_max, b, s0, T, len, b_max, b_safe, p, a_thr, p_lc, d_look;
-    float two_sqrt_ab;     /* fl32(2*sqrt(a_max*b)), formed in double */
+    float inv_tsab;        /* fl32(1/(2*sqrt(a_max*b))), formed in double */
+    float inv_2bmax;       /* fl32(1/(2*b_max)), formed in double */
     float b_mand, tau_yield;
     int32_t h_look;
     uint32_t key0, key1;
@@ -551,7 +554,8 @@ orc_sim *orc_create(const orc_input *in)
     P->len = in->length; P->b_max = in->b_max; P->b_safe = in->b_safe; P->p = in->politeness;
     P->a_thr = in->a_thr; P->p_lc = in->p_lc; P->d_look = in->d_look; P->h_look = in->h_look;
     P->b_mand = in->b_mand; P->tau_yield = in->tau_yield;
-    P->two_sqrt_ab = (float)(2.0 * sqrt((double)in->a_max * (double)in->b));
+    P->inv_tsab = (float)(1.0 / (2.0 * sqrt((double)in->a_max * (double)in->b)));
+    P->inv_2bmax = (float)(1.0 / (2.0 * (double)in->b_max));
     P->key0 = (uint32_t)(in->seed & 0xFFFFFFFFu);
     P->key1 = (uint32_t)(in->seed >> 32);
     m->t = in->t0;
@@ -750,7 +754,7 @@ static leader_t lookahead(const orc_sim *m, int32_t lane, float s, int32_t veh, 
 
 static float idm_p(const params_t *P, float v, float v0e, int has, float vl, float gap)
 {
-    return orc_idm(v, v0e, has, vl, gap, P->a_max, P->two_sqrt_ab, P->s0, P->T, P->b_max);
+    return orc_idm(v, v0e, has, vl, gap, P->a_max, P->inv_tsab, P->s0, P->T, P->b_max);
 }
 
 /* Yield rule at a junction [reading]: connector lane cl is busy when one of
@@ -919,7 +923,7 @@ static void update_vehicle(orc_sim *m, int32_t i, prop_t *out)
             }
         }
         if (line) {
-            float stop_dist = (v * v) / (2.0f * P->b_max);
+            float stop_dist = (v * v) * P->inv_2bmax;
             if (L - s >= stop_dist)
                 red = 1;
         }

@@ -163,9 +163,10 @@ void orc_read_trips(const orc_sim *m, uint32_t *id, int32_t *status, int32_t *tr
 
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-/* IDM acceleration in FP32 (has_leader = 0: free road). */
+/* IDM acceleration in FP32 (has_leader = 0: free road); inv_tsab is the
+ * FP32 reciprocal of 2 sqrt(a_max b), formed in double. */
 float orc_idm(float v, float v0e, int has_leader, float v_lead, float gap, float a_max,
-              float two_sqrt_ab, float s0, float T, float b_max);
+              float inv_tsab, float s0, float T, float b_max);
 
 #ifdef __cplusplus
 }

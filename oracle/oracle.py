@@ -310,11 +310,11 @@ def mlp_candidates(theta, norm, feat, lo, hi, cap=64, threads=None):
     return out, cnt, info
 
 
-def idm(v, v0e, has_leader, v_lead, gap, a_max=2.0, two_sqrt_ab=None, s0=2.0, T=1.5, b=4.5,
-        b_max=9.0):
-    if two_sqrt_ab is None:
-        two_sqrt_ab = float(np.float32(2.0 * np.sqrt(a_max * b)))
-    return float(lib().orc_idm(v, v0e, int(has_leader), v_lead, gap, a_max, two_sqrt_ab, s0, T,
+def idm(v, v0e, has_leader, v_lead, gap, a_max=2.0, s0=2.0, T=1.5, b=4.5, b_max=9.0):
+    """The oracle's FP32 IDM acceleration (reciprocal of 2 sqrt(a_max b)
+    formed in double, as in the simulation)."""
+    inv_tsab = float(np.float32(1.0 / (2.0 * np.sqrt(a_max * b))))
+    return float(lib().orc_idm(v, v0e, int(has_leader), v_lead, gap, a_max, inv_tsab, s0, T,
                                b_max))
 
 

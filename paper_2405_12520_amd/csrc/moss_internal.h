@@ -120,7 +120,8 @@ struct SoA {
 
 struct Params {
     float dt, a_max, s0, T, len, b_max, b_safe, pol, a_thr, p_lc, d_look;
-    float two_sqrt_ab;  // fl32(2 sqrt(a_max b)) formed in double on the host
+    float inv_tsab;     // fl32(1 / (2 sqrt(a_max b))) formed in double on the host
+    float inv_2bmax;    // fl32(1 / (2 b_max)) formed in double on the host
     float b_mand, tau_yield;
     int32_t h_look;
     uint32_t key0, key1;

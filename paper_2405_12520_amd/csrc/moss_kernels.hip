@@ -37,7 +37,9 @@ __device__ __forceinline__ float fmin32(float x, float y) { return x < y ? x : y
 __device__ __forceinline__ float fmax32(float x, float y) { return x > y ? x : y; }
 
 // IDM acceleration (Treiber, Hennecke, Helbing 2000), exponent 4:
-//   a_max (1 - (v/v0)^4 - (s*/gap)^2),  s* = s0 + max(0, v T + v dv / (2 sqrt(a b))).
+//   a_max (1 - (v/v0)^4 - (s*/gap)^2),  s* = s0 + max(0, v T + v dv / (2 sqrt(a b))),
+// the last term as v dv times the FP32 reciprocal of 2 sqrt(a b) formed in
+// double on the host (no division per evaluation).
 // idm_free gives the free-road factor 1 - (v/v0)^4, idm_lead the acceleration
 // behind a leader from that factor (a non-positive gap returns the braking
 // limit); without a leader the acceleration is a_max times the factor.  The
@@ -58,7 +60,7 @@ __device__ __forceinline__ float idm_lead(const Params &P, float free_term, floa
         return -P.b_max;
     float dv = v - vl;
     float t1 = v * P.T;
-    float t2 = (v * dv) / P.two_sqrt_ab;
+    float t2 = (v * dv) * P.inv_tsab;
     float tt = t1 + t2;
     float ss = P.s0 + (tt > 0.0f ? tt : 0.0f);
     float q = ss / gap;
@@ -585,7 +587,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             // red light at the stop line, applied if the vehicle can still stop
             bool red = false;
             if (nxt >= 0 && red_now) {
-                float stop_dist = (v * v) / (2.0f * P.b_max);
+                float stop_dist = (v * v) * P.inv_2bmax;
                 if (L - s >= stop_dist)
                     red = true;
             }
@@ -733,7 +735,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                     if (conflict_busy(d, cl)) {
                         flags |= 64;
                         if (!red) {
-                            float stop_dist = (v * v) / (2.0f * P.b_max);
+                            float stop_dist = (v * v) * P.inv_2bmax;
                             if (L - s >= stop_dist)
                                 red = true;
                         }

@@ -15,12 +15,13 @@ from paper_2405_12520_amd import scenarios as S
 pytestmark = pytest.mark.gpu
 
 SHAPES = [
-    dict(graph_steps=16, update_blocks=0, scatter_blocks=0, xcd_remap=0),     # default
-    dict(graph_steps=0, update_blocks=0, scatter_blocks=0, xcd_remap=0),      # no graphs
+    dict(graph_steps=16, update_blocks=0, scatter_blocks=0, xcd_remap=0),  # default
+    dict(graph_steps=0, update_blocks=0, scatter_blocks=0, xcd_remap=0),   # no graphs
     dict(graph_steps=2, update_blocks=3, scatter_blocks=1, xcd_remap=0),
     dict(graph_steps=32, update_blocks=16, scatter_blocks=5, xcd_remap=1),
     dict(graph_steps=64, update_blocks=0, scatter_blocks=0, xcd_remap=1),
     dict(graph_steps=8, update_blocks=1000, scatter_blocks=4096, xcd_remap=1),
+    dict(graph_steps=0, update_blocks=0, scatter_blocks=0, xcd_remap=1),   # serial, direct
 ]
 
 

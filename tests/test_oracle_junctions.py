@@ -325,3 +325,73 @@ def test_dynamic_lane_rejects_unknown_movements():
         o.set_lane_turns([_lane(sc, N_IN, 1)], [_conn(sc, N_IN, E_OUT)], [1])
     with pytest.raises(ValueError):
         OracleSim(S.intersection()).set_lane_turns([0], [1], [0])
+
+
+# ------------------------------------------- rules each pin singles out --
+
+def test_no_yield_to_a_vehicle_held_by_red():
+    """At t = 0 the east approach is red; an east vehicle 30 m from its line
+    at 10 m/s, headed straight across the north left turn's path, does not
+    make the left turner yield (it is held by its own signal)."""
+    sc0 = _left_turner()
+    east = dict(id=2, route=[E_IN, W_OUT], lane=_lane(sc0, E_IN, 0), s=470.0, v=10.0)
+    _, f, _ = _run(_left_turner([east]))
+    assert not (f[1] & 64)
+
+
+def test_right_turn_ends_on_the_out_road_right_lane():
+    """From the right lane, through the one-lane right-turn connector, onto
+    the west out-road's right lane (its successor), not lane min(k, n-1) = 0
+    of the out-road."""
+    from oracle import OracleSim
+    sc = _state([dict(id=1, route=[N_IN, W_OUT], lane=1, s=480.0, v=10.0)])
+    o = OracleSim(sc)
+    o.step(4)
+    assert o.state()["lane"].tolist() == [_lane(sc, W_OUT, 1)]
+
+
+def test_no_lane_change_on_a_connector():
+    """A vehicle on lane 0 of the two-lane straight connector behind a
+    standing one, lane 1 free, p_lc = 1, odd step (looking at lane k + 1 =
+    1): no lane change is evaluated."""
+    import dataclasses
+    sc = _state([dict(id=1, route=[N_IN, S_OUT], lane=0, s=10.0, v=5.0)],
+                params=dict(p_lc=1.0)).with_params(t0=1)
+    cs = _conn(sc, N_IN, S_OUT)
+    sc = dataclasses.replace(
+        sc, lane=np.array([_lane(sc, cs, 0)], np.int32), s=np.array([2.0], np.float32),
+        cursor=np.array([1], np.int32))
+    sc = dataclasses.replace(
+        sc, veh_id=np.append(sc.veh_id, 2).astype(np.uint32), depart=np.append(sc.depart, 0),
+        v0=np.append(sc.v0, 0.5).astype(np.float32),
+        route_off=np.append(sc.route_off, sc.route_off[-1] + 3).astype(np.int64),
+        route_roads=np.concatenate([sc.route_roads, sc.route_roads[:3]]).astype(np.int32),
+        placed=np.append(sc.placed, 1).astype(np.uint8),
+        lane=np.append(sc.lane, _lane(sc, cs, 0)).astype(np.int32),
+        s=np.append(sc.s, 12.0).astype(np.float32), v=np.append(sc.v, 0.0).astype(np.float32),
+        a=np.append(sc.a, 0.0).astype(np.float32), cursor=np.append(sc.cursor, 1).astype(np.int32))
+    _, f, st = _run(sc)
+    assert (f[1] & 3) == 0
+    assert st["lane"].tolist() == [_lane(sc, cs, 0)] * 2
+
+
+def test_departure_lane_continues_the_route():
+    """Vehicle 2 (even id) departing on the north approach to turn right:
+    the only lane that turns right is lane 1, so it queues there (id mod 2
+    would give lane 0)."""
+    from oracle import OracleSim
+    sc = _state([dict(id=2, route=[N_IN, W_OUT], depart=0)])
+    o = OracleSim(sc)
+    o.step(1)
+    assert o.state()["lane"].tolist() == [_lane(sc, N_IN, 1)]
+
+
+def test_closed_successor_takes_the_nearest_open_lane():
+    """The left-turn connector's successor is the east out-road's lane 0;
+    with that lane closed the vehicle enters lane 1."""
+    from oracle import OracleSim
+    sc = _state([dict(id=1, route=[N_IN, E_OUT], lane=0, s=470.0, v=12.0)])
+    o = OracleSim(sc)
+    o.set_lane_closed([_lane(sc, E_OUT, 0)], [1])
+    o.step(12)
+    assert o.state()["lane"].tolist() == [_lane(sc, E_OUT, 1)]
