@@ -210,9 +210,13 @@ int moss_step(moss_sim *h, int32_t n);
 int moss_read_state(moss_sim *h, moss_state_out *out);
 
 /* Synchronises and copies host arrays counters[n_scen][MOSS_N_COUNTERS] and
- * sum_v[n_scen] (sum over steps and active vehicles of speed) and the device
- * error word (0 = healthy; bit 0 lane capacity exceeded, bit 1 non-finite
- * state).  Any pointer may be NULL. */
+ * sum_v[n_scen] and the device error word (0 = healthy; bit 0 lane capacity
+ * exceeded, bit 1 non-finite state).  Any pointer may be NULL.  sum_v is the
+ * sum over steps and active vehicles of speed, from which the mean speed is
+ * formed (Sec. III-A, last paragraph; Sec. IV-A): each vehicle adds its
+ * speed in whole units of 2^-20 m/s (truncated; 0 for speeds <= 0, 2^32 - 1
+ * from 4096 m/s on) to a 64-bit integer, exact and independent of the order
+ * of the additions, and sum_v is that integer / 2^20 rounded to double. */
 int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *error_word);
 
 /* Ids of the vehicles that have not entered the network yet (host buffer of

@@ -64,6 +64,19 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* A speed in fixed point for the summed-speed observable (Sec. III-A: the
+ * simulator reports speeds, from which the mean speed is formed): the whole
+ * number of 2^-20 m/s units in v, 0 for v <= 0 (speeds are never negative)
+ * and saturated at 2^32 - 1 from 4096 m/s on.
+ * Scaling by a power of two is exact and the conversion truncates, so each
+ * vehicle adds an exact integer and the sum is the same in any order. */
+static uint64_t speed_fx(float v)
+{
+    if (v >= 4096.0f)
+        return 0xFFFFFFFFull;
+    return v > 0.0f ? (uint64_t)(uint32_t)(v * 1048576.0f) : 0u;
+}
+
 /* ---------------------------------------------------------------- IDM --- */
 
 static float fmin32(float x, float y) { return x < y ? x : y; }
@@ -389,7 +402,7 @@ struct orc_sim {
     int32_t *q_start, *q_end, *q_head, *q_list;
     int64_t t;
     int64_t *cnt;      /* [n_scen][ORC_N_COUNTERS] */
-    double *sumv;
+    uint64_t *sumv;    /* [n_scen] sum of speed_fx over steps and vehicles */
     double *mlp_sq;    /* [n_scen] */
     int32_t mode;
     int32_t threads;   /* OpenMP threads of the update and merge loops */
@@ -1171,7 +1184,7 @@ static void one_step(orc_sim *m)
     for (int32_t q = 0; q < w; ++q) {
         size_t sc = (size_t)m->lane_scen[m->sl[q]];
         m->cnt[sc * ORC_N_COUNTERS + ORC_VEH_STEPS]++;
-        m->sumv[sc] += (double)m->v[q];
+        m->sumv[sc] += speed_fx(m->v[q]);
     }
     free(lanebuf); free(jn); free(pr); free(ins);
 }
@@ -1396,5 +1409,6 @@ void orc_read_trips(const orc_sim *m, uint32_t *id, int32_t *status, int32_t *tr
 void orc_counters(const orc_sim *m, int64_t *cnt, double *sum_v)
 {
     memcpy(cnt, m->cnt, sizeof(int64_t) * (size_t)m->n_scen * ORC_N_COUNTERS);
-    memcpy(sum_v, m->sumv, sizeof(double) * (size_t)m->n_scen);
+    for (int32_t q = 0; q < m->n_scen; ++q)
+        sum_v[q] = (double)m->sumv[q] / 1048576.0;
 }

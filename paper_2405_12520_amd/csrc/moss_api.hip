@@ -538,7 +538,7 @@ static void fill_dev(moss_sim *h)
     d.conf_feed = I(L.conf_feed);
     d.heads = (Head *)(w + L.heads);
     d.cnt = (unsigned long long *)(w + L.cnt);
-    d.sumv = (double *)(w + L.sumv);
+    d.sumv = (unsigned long long *)(w + L.sumv);
     d.cnt_stride = stripe_elems((int64_t)h->n_scen * C_N);
     d.sv_stride = stripe_elems(h->n_scen);
     d.mlp_theta = F(L.mlp_theta);
@@ -1211,8 +1211,18 @@ int moss_read_counters(moss_sim *h, int64_t *counters, double *sum_v, uint32_t *
             counters[q] = (int64_t)s;
         }
     }
-    if (sum_v)
-        HIP_TRY(sum_stripes(h, h->dev.sumv, sum_v));
+    if (sum_v) {
+        // integer stripes: exact in any order; the total in m/s rounded once
+        const size_t st = (size_t)h->dev.sv_stride;
+        std::vector<unsigned long long> all(kStripes * st);
+        HIP_TRY(hipMemcpy(all.data(), h->dev.sumv, 8 * all.size(), hipMemcpyDeviceToHost));
+        for (int32_t q = 0; q < h->n_scen; ++q) {
+            unsigned long long s = 0;
+            for (int k = 0; k < kStripes; ++k)
+                s += all[k * st + q];
+            sum_v[q] = (double)s / 1048576.0;
+        }
+    }
     if (error_word)
         *error_word = h->err_seen;
     return MOSS_OK;

@@ -192,7 +192,7 @@ struct Dev {
     // sv_stride elements) so that concurrent waves add to different lines;
     // readers sum the copies
     unsigned long long *cnt;      // [kStripes][n_scen][C_N]
-    double *sumv;                 // [kStripes][n_scen]
+    unsigned long long *sumv;     // [kStripes][n_scen] speeds in 2^-20 m/s units
     int32_t cnt_stride, sv_stride;
     uint32_t *err;
     // launch shape (results do not depend on it): update and scatter grid

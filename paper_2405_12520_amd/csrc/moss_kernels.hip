@@ -139,6 +139,32 @@ __device__ __forceinline__ double wave_sum_f64_l63(double x)
     return x;
 }
 
+// The same for 64-bit integers.
+__device__ __forceinline__ uint64_t wave_sum_u64_l63(uint64_t x)
+{
+    auto step = [&](auto mv) {
+        const uint32_t lo = mv((uint32_t)x), hi = mv((uint32_t)(x >> 32));
+        x += ((uint64_t)hi << 32) | lo;
+    };
+    step([](uint32_t u) { return dpp_move<kDppShr1, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr2, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr4, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppShr8, 0xF>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppBcast15, 0xA>(0u, u); });
+    step([](uint32_t u) { return dpp_move<kDppBcast31, 0xC>(0u, u); });
+    return x;
+}
+
+// A vehicle's term of the summed speed (Sec. III-A: speeds are the output
+// the mean speed is formed from), in whole units of 2^-20 m/s: v * 2^20 is
+// exact and the conversion truncates, 0 for v <= 0, 2^32 - 1 from 4096 m/s
+// on.  Integer terms make the sum independent of the order of the atomics.
+__device__ __forceinline__ uint64_t speed_fx(float v)
+{
+    const uint32_t q = v > 0.0f ? (uint32_t)(v * 1048576.0f) : 0u;
+    return v >= 4096.0f ? 0xFFFFFFFFull : (uint64_t)q;
+}
+
 // Inclusive scan over the wave: lane i gets the sum of lanes 0..i (lane 63
 // the wave's sum).
 __device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x)
@@ -277,6 +303,10 @@ __device__ __forceinline__ double *sv_at(const Dev &d, double *base, int scen)
 {
     return base + (size_t)wave_stripe() * d.sv_stride + scen;
 }
+__device__ __forceinline__ unsigned long long *sumv_at(const Dev &d, int scen)
+{
+    return d.sumv + (size_t)wave_stripe() * d.sv_stride + scen;
+}
 
 // Adds the wave's count of pred to counter c (one atomic per wave when the
 // wave's vehicles are all of one scenario).
@@ -296,10 +326,9 @@ __device__ __forceinline__ void wave_count_scen(const Dev &d, int c, bool pred, 
     }
 }
 
-// The same for a sum of doubles kept per scenario at base (one wave sum per
-// scenario present).  Wave-uniform call.
-__device__ __forceinline__ void wave_sum_scen(const Dev &d, double *base, bool pred, int scen,
-                                              double x)
+// The same for the summed speed of each scenario (one wave sum per scenario
+// present).  Wave-uniform call.
+__device__ __forceinline__ void wave_sumv_scen(const Dev &d, bool pred, int scen, uint64_t x)
 {
     unsigned long long todo = __ballot(pred);
     while (todo) {
@@ -307,9 +336,9 @@ __device__ __forceinline__ void wave_sum_scen(const Dev &d, double *base, bool p
         const int s0 = __builtin_amdgcn_readlane(scen, leader);
         const bool mine = pred && scen == s0;
         const unsigned long long mm = __ballot(mine);
-        const double sum = wave_sum_f64_l63(mine ? x : 0.0);
+        const uint64_t sum = wave_sum_u64_l63(mine ? x : 0ull);
         if (__lane_id() == 63)
-            atomicAdd(sv_at(d, base, s0), sum);
+            atomicAdd(sumv_at(d, s0), (unsigned long long)sum);
         todo &= ~mm;
     }
 }
@@ -1138,9 +1167,9 @@ __device__ __forceinline__ void write_tail(const Dev &d, int l, bool any, float 
 
 // Merge of one lane straight from global memory, walking both lists (used for
 // chunks too large for the LDS tile).
-__device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned long long &clamps)
+__device__ void merge_lane_global(const Dev &d, int l, uint64_t &vsum, unsigned long long &clamps)
 {
-    vsum = 0.0;
+    vsum = 0;
     clamps = 0;
     const int o0 = at(d.ls_old, l), o1 = at(d.ls_old, l + 1);
     const int j0 = at(d.joff, l), j1 = at(d.joff, l + 1);
@@ -1185,7 +1214,7 @@ __device__ void merge_lane_global(const Dev &d, int l, double &vsum, unsigned lo
     }
     write_tail(d, l, w1 > w0, at(d.S.s, w0), at(d.S.v, w0), at(d.id_next, w0));
     for (int f = w0; f < w1; ++f)
-        vsum += (double)at(d.S.v, f);
+        vsum += speed_fx(at(d.S.v, f));
 }
 
 constexpr int kMT = 256;          // threads per merge block (4 waves)
@@ -1258,7 +1287,7 @@ __device__ __forceinline__ void wave_seg_scan(bool valid, bool head, bool st, ui
 __device__ __forceinline__ void merge_group(const Dev &d, const int la, const int lb, const int n0,
                                             const int n1, const int o0, const int o1,
                                             const int j0, const int j1, const bool one_scen,
-                                            double &vsum, unsigned long long &clamps)
+                                            uint64_t &vsum, unsigned long long &clamps)
 {
     __shared__ float o_s[kOldCap], o_v[kOldCap];
     __shared__ uint32_t o_id[kOldCap];
@@ -1564,24 +1593,24 @@ __device__ __forceinline__ void merge_group(const Dev &d, const int la, const in
             at(d.S.s, n0 + k) = s;
             at(d.S.v, n0 + k) = v;
             if (one_scen)
-                vsum += (double)v;
+                vsum += speed_fx(v);
             else
                 sc = at(d.lanes, lane_of(x)).scen;
         }
         if (!one_scen) {
             wave_count_scen(d, C_VEH_STEPS, ok, sc);
-            wave_sum_scen(d, d.sumv, ok, sc, (double)v);
+            wave_sumv_scen(d, ok, sc, speed_fx(v));
         }
     }
 }
 
 // Lanes [la, lb) one per thread, straight from global memory.
 __device__ void merge_lanes_global(const Dev &d, const int la, const int lb, const bool one_scen,
-                                   double &vsum, unsigned long long &clamps)
+                                   uint64_t &vsum, unsigned long long &clamps)
 {
     const int tid = threadIdx.x;
     for (int l = la + tid; l < lb; l += kMT) {
-        double ls;
+        uint64_t ls;
         unsigned long long lc;
         merge_lane_global(d, l, ls, lc);
         const int cnt = at(d.ls_new, l + 1) - at(d.ls_new, l);
@@ -1592,7 +1621,7 @@ __device__ void merge_lanes_global(const Dev &d, const int la, const int lb, con
             unsigned long long *c = cnt_at(d, at(d.lanes, l).scen, 0);
             if (cnt) {
                 atomicAdd(c + C_VEH_STEPS, (unsigned long long)cnt);
-                atomicAdd(sv_at(d, d.sumv, at(d.lanes, l).scen), ls);
+                atomicAdd(sumv_at(d, at(d.lanes, l).scen), (unsigned long long)ls);
             }
             if (lc) atomicAdd(c + C_CLAMPS, lc);
         }
@@ -1611,7 +1640,7 @@ __device__ __forceinline__ bool group_fits(int new_rows, int old_rows, int joine
 // the tile on, or beyond the two groups, take merge_lanes_global.
 __global__ void __launch_bounds__(kMT) k_merge(Dev d)
 {
-    __shared__ double red_d[kMT / 64];
+    __shared__ uint64_t red_d[kMT / 64];
     __shared__ unsigned long long red_k[kMT / 64];
     __shared__ int s_gb;
 
@@ -1637,7 +1666,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     const int n0 = ca.y, n1 = cb.y, o0 = ca.z, o1 = cb.z, j0 = ca.w, j1 = cb.w;
     const int nw = n1 - n0;
     const bool one_scen = (lb <= la) || at(d.lanes, la).scen == at(d.lanes, lb - 1).scen;
-    double vsum = 0.0;
+    uint64_t vsum = 0;
     unsigned long long clamps = 0;
 
     // the longest run of whole lanes from ga that fits the tile (ga itself
@@ -1692,7 +1721,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     }
 
     if (one_scen) {
-        vsum = wave_sum_f64_l63(vsum);
+        vsum = wave_sum_u64_l63(vsum);
         const uint32_t ck32 = wave_scan_u32((uint32_t)clamps);
         if (lane == 63) {
             red_d[wv] = vsum;
@@ -1700,7 +1729,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
         }
         __syncthreads();
         if (tid == 0 && lb > la) {
-            double sv = 0.0;
+            uint64_t sv = 0;
             unsigned long long ck = 0;
             for (int q = 0; q < kMT / 64; ++q) {
                 sv += red_d[q];
@@ -1710,7 +1739,7 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
             unsigned long long *c = cnt_at(d, sc, 0);
             if (nw) atomicAdd(c + C_VEH_STEPS, (unsigned long long)nw);
             if (ck) atomicAdd(c + C_CLAMPS, ck);
-            if (nw) atomicAdd(sv_at(d, d.sumv, sc), sv);
+            if (nw) atomicAdd(sumv_at(d, sc), (unsigned long long)sv);
         }
     }
     if (w == 0 && tid == 0) {

@@ -58,7 +58,7 @@ def test_city_demand_hour(sim_cls):  # noqa: F811
         co, svo = o.counters()
         assert err == 0
         assert np.array_equal(cg, co), (where, cg, co)
-        np.testing.assert_allclose(svg, svo, rtol=1e-9)
+        np.testing.assert_array_equal(svg, svo)
         assert len(g.pending()) == o.pending, where
         _say(f"{where}: {o.n_active} active, {int(co[0, 2])} arrived, "
              f"{int(co[0, 1])} insert failures")

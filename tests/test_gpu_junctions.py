@@ -89,7 +89,7 @@ def _run_pair(sim_cls, sc, stops, name, launch=None):
         co, svo = o.counters()
         assert err == 0
         assert np.array_equal(cg, co), (where, cg, co)
-        np.testing.assert_allclose(svg, svo, rtol=1e-9)
+        np.testing.assert_array_equal(svg, svo)
         _say(f"{where}: {o.n_active} active, {int(co[0, 2])} arrived")
     g.close()
     return co

@@ -86,7 +86,7 @@ def run_pair(sim_cls, sc, steps, every=1, debug=True):
     co, svo = o.counters()
     assert err == 0
     assert np.array_equal(cg, co), (cg, co)
-    np.testing.assert_allclose(svg, svo, rtol=1e-9)
+    np.testing.assert_array_equal(svg, svo)
     g.close()
     return nbits
 
@@ -199,7 +199,7 @@ def test_city_snapshot_long_run_bench_launch(sim_cls):
     cg, svg, err = g.counters()
     co, svo = o.counters()
     assert err == 0 and np.array_equal(cg, co)
-    np.testing.assert_allclose(svg, svo, rtol=1e-9)
+    np.testing.assert_array_equal(svg, svo)
     g.close()
 
 
@@ -222,7 +222,7 @@ def test_city_8M_bench_launch(sim_cls):
     cg, svg, err = g.counters()
     co, svo = o.counters()
     assert err == 0 and np.array_equal(cg, co)
-    np.testing.assert_allclose(svg, svo, rtol=1e-9)
+    np.testing.assert_array_equal(svg, svo)
     g.close()
 
 
@@ -311,7 +311,7 @@ def test_batch_full_size_long_run(sim_cls):
     cg, svg, err = g.counters()
     co, svo = o.counters()
     assert err == 0 and np.array_equal(cg, co)
-    np.testing.assert_allclose(svg, svo, rtol=1e-9)
+    np.testing.assert_array_equal(svg, svo)
     g.close()
 
 

@@ -40,4 +40,5 @@ def test_rule_case(sim_cls, name, sc, steps):  # noqa: F811
     co, svo = o.counters()
     assert err == 0
     assert np.array_equal(cg, co), (name, cg, co)
+    np.testing.assert_array_equal(svg, svo)
     g.close()

@@ -551,6 +551,40 @@ def test_grid_conservation_and_trips():
     assert 0 < sv[0] / c[0, 6] < 16.67
 
 
+def test_summed_speed_is_a_truncated_fixed_point_sum():
+    """The summed speed adds each active vehicle's speed once per step, in
+    whole units of 2^-20 m/s: after each step it lies at most n_active units
+    below the exact sum of the state's speeds (never above it), and it is a
+    whole number of units."""
+    import math
+    sc = S.toy(3, n=4, max_lanes=3, n_placed=200, n_pending=60, horizon=40)
+    o = OracleSim(sc)
+    exact = 0.0
+    bound = 0
+    prev = 0.0
+    for _ in range(30):
+        o.step(1)
+        v = o.state()["v"].astype(np.float64)
+        exact = math.fsum([exact, *v.tolist()])
+        bound += v.shape[0]
+        _, sv = o.counters()
+        assert sv[0] * 2 ** 20 == math.floor(sv[0] * 2 ** 20)
+        assert exact - bound * 2.0 ** -20 <= sv[0] <= exact
+        assert sv[0] >= prev
+        prev = sv[0]
+    assert bound > 0 and exact > 1.0
+    # one vehicle at a speed that is not a multiple of 2^-20: the term is
+    # truncated, not rounded
+    net = S.corridor([2000.0], 1)
+    o = OracleSim(S.with_vehicles("one", net, [dict(id=0, route=[0], lane=0, s=0.0, v=0.6,
+                                                   v0=13.9)]))
+    o.step(1)
+    v1 = float(o.state()["v"][0])
+    assert v1 * 2 ** 20 != math.floor(v1 * 2 ** 20)     # the case is not a whole unit
+    _, sv = o.counters()
+    assert sv[0] == math.floor(v1 * 2 ** 20) / 2 ** 20
+
+
 def test_insertion_order_and_gap():
     """Queue heads enter in (depart, id) order per origin lane, never before
     their departure step, at most one per lane per step."""
@@ -600,7 +634,7 @@ def test_trip_time_counts_from_departure():
 def test_threads_give_identical_results(make):
     """The OpenMP mode (vehicles and lanes on several threads, sums taken in
     a fixed order afterwards) reproduces the single-thread run bit for bit:
-    state, counters and the FP64 speed sums."""
+    state, counters and the summed speeds."""
     sc = make()
     a, b = OracleSim(sc), OracleSim(sc)
     b.set_threads(4)
