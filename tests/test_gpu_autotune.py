@@ -77,6 +77,25 @@ def test_every_launch_shape_gives_identical_state(torch_dev, name):
             _same(ref, out)
 
 
+def test_step_calls_of_any_length_give_identical_state(torch_dev):
+    """A run split into calls of odd and uneven lengths (each call's part
+    below the graph length launched step by step, starting from either
+    lane-start parity) equals the same run in one call."""
+    from paper_2405_12520_amd.moss import Simulator
+    sc = S.batch(12, horizon=400)
+    splits = [1, 3, 14, 17, 30, 5, 7, 31, 33, 9, 2, 48]
+    ref = _run(sc, dict(graph_steps=16, update_blocks=0, scatter_blocks=0, xcd_remap=1),
+               sum(splits))
+    g = Simulator(sc)
+    g.set_launch(xcd_remap=1)
+    for n in splits:
+        g.step(n)
+    out = (g.state(), *g.counters())
+    g.close()
+    assert ref[0]["id"].shape[0] > 0
+    _same(ref, out)
+
+
 def test_set_launch_rejects_bad_shapes(torch_dev):
     from paper_2405_12520_amd.moss import MossError, Simulator
     g = Simulator(S.toy(3))
