@@ -560,7 +560,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         const float vlim_c_side = at(d.lanes, ls_c).vlim;
         const uint8_t side_flags = EXT ? at(d.lane_red, ls_c) : (uint8_t)0;
         const int r0_c = at(d.ls_old, ls_c), r1_c = at(d.ls_old, ls_c + 1);
-        const RoadInfo rd_c = at(d.roads, head_next ? nxt : 0);
+        const RoadInfo rd_c = at(d.roads, (act && nxt >= 0) ? nxt : 0);
         const bool red_now = act && (red_raw & kRedBit) != 0;
         // a lane closed by control is never a lane-change target
         const bool side_open = (side_flags & kClosedBit) == 0;
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         const int side_r1 = side_ok ? r1_c : 0;
         RoadInfo rd_next = {0, 1, 0.0f, 0};
         bool rd_ok = false;       // rd_next holds roads[nxt]
-        if (head_next) {
+        if (act && nxt >= 0) {
             rd_next = rd_c;
             rd_ok = true;
         }
@@ -587,6 +587,17 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
             }
             tl_own = at(d.tails, ln_own);
             tl_side = at(d.tails, ln_side);
+        }
+        // a vehicle that may pass its lane's end this step: the route entry
+        // after its next road, loaded now so that the transfer does not wait
+        // for it (s + v dt + a_max dt^2 / 2 bounds the new position, the
+        // metre covers rounding; the others load entry 0)
+        bool pre = false;
+        int32_t nr_pre = -1;
+        if constexpr (MODE == 0) {
+            if (act && nxt >= 0)
+                pre = w_s[x_i] + w_v[x_i] * P.dt + 0.5f * P.a_max * (P.dt * P.dt) + 1.0f >= li.L;
+            nr_pre = at(d.route, pre ? ptr + 2u : 0u);
         }
         const int scen0 = __builtin_amdgcn_readlane(li.scen, 0);
         const bool uni_scen = __all(!act || li.scen == scen0);
@@ -880,11 +891,11 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 sp = sp - Lx;
                 p += 1;
                 const RoadInfo rd = (first && rd_ok) ? rd_next : at(d.roads, nr);
-                first = false;
                 x = next_lane<EXT>(d, x, kk, nr, rd);
                 kk = x - rd.lane0;
                 Lx = rd.L;
-                nr = at(d.route, p + 1);
+                nr = (first && pre) ? nr_pre : at(d.route, p + 1);
+                first = false;
             }
             arrived = sp >= Lx;
             joins = !arrived && !(x == (int)l && p == ptr0);
