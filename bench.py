@@ -135,7 +135,21 @@ def bench_mlp(sc, args):
         say("[bench] training the closure on the grid workload")
         theta, norm, _ = closure.build_closure(path, log=say)
         src = "trained in this run"
-    sim = Simulator(sc.with_params(mlp=dict(theta=theta, norm=norm)))
+    msc = sc.with_params(mlp=dict(theta=theta, norm=norm))
+    rec = None
+    if not args.no_tune:
+        # network mode has its own launch shape (its update block holds the
+        # weights in LDS, so persistent blocks copy them fewer times)
+        from paper_2405_12520_amd import autotune
+        t0 = time.time()
+        rec = autotune.tune(lambda: Simulator(msc), msc, args.warmup, log=say)
+        torch.cuda.empty_cache()
+        say(f"[bench] network-mode launch shape {rec['launch']} "
+            f"({'cached' if rec['cached'] else 'searched'} in {time.time() - t0:.1f} s)")
+    sim = Simulator(msc)
+    if rec:
+        autotune.apply(sim, rec)
+    launch = sim.launch()
     sim.step(args.warmup)
     sq0 = sim.mlp_error().sum()
     ms, dc = timed_steps(sim, args.steps)
@@ -154,7 +168,7 @@ def bench_mlp(sc, args):
         f"fallback {n_fb / max(veh_steps, 1):.4f}")
     return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
                 ms_per_step=round(ms / args.steps, 5), rms_accel_error_vs_idm=round(rms, 5),
-                fallback_rate=round(n_fb / max(veh_steps, 1), 5), weights=src,
+                fallback_rate=round(n_fb / max(veh_steps, 1), 5), weights=src, launch=launch,
                 roofline=dict(bound="mfma", kernel="k_update<mlp>", dtype="bf16",
                               achieved=round(tflops, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
                               frac=round(tflops / BF16_PEAK_TFLOPS, 5),
