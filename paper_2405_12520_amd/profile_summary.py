@@ -84,6 +84,11 @@ def main():
                                  "SQ_BUSY_CYCLES, SQ_WAIT_INST_ANY, SQ_INSTS_VALU, "
                                  "SQ_INSTS_LDS, SQ_INSTS_SALU, SQ_ACTIVE_INST_VALU")
     ap.add_argument("--sq-command", default="")
+    ap.add_argument("--waits", help="counter CSV of a pass over SQ_WAVES, SQ_WAIT_ANY, "
+                                    "SQ_ACTIVE_INST_ANY, SQ_INSTS_VMEM_RD, SQ_INSTS_VMEM_WR "
+                                    "(needs --sq for the wave cycles)")
+    ap.add_argument("--waits-command", default="")
+    ap.add_argument("--note", default="", help="closing paragraph")
     ap.add_argument("--no-traffic-json", action="store_true",
                     help="keep traffic.json as it is (a workload other than the benchmark's)")
     args = ap.parse_args()
@@ -149,6 +154,32 @@ def main():
             lines.append(f"| {k} | {per['SQ_WAVES'][k]:.0f} | {g('SQ_INSTS_VALU'):.0f} | "
                          f"{g('SQ_INSTS_SALU'):.0f} | {g('SQ_INSTS_LDS'):.0f} | "
                          f"{g('SQ_WAVE_CYCLES'):.0f} | {g('SQ_WAIT_INST_ANY'):.0f} |")
+    if args.waits and args.sq:
+        names = ("SQ_WAVES", "SQ_WAIT_ANY", "SQ_ACTIVE_INST_ANY", "SQ_INSTS_VMEM_RD",
+                 "SQ_INSTS_VMEM_WR")
+        per = {n: counter_means(args.waits, n) for n in names}
+        cyc = counter_means(args.sq, "SQ_WAVE_CYCLES")
+        waves = counter_means(args.sq, "SQ_WAVES")
+        lines += ["", "## Where the waves' time goes (second counter pass)", ""]
+        if args.waits_command:
+            lines += ["```", args.waits_command, "```", ""]
+        lines += ["Per wave, in the units of the wave cycles above (their ratios are what "
+                  "matter): cycles waiting on anything (memory, barriers, dependencies), cycles "
+                  "issuing any instruction, and vector memory instructions.", "",
+                  "| kernel | wave cycles | waiting | issuing | waiting share | issuing share "
+                  "| VMEM reads | VMEM writes |", "|---|---|---|---|---|---|---|---|"]
+        for k in sorted(per["SQ_WAVES"]):
+            if not k.startswith("k_") or not waves.get(k):
+                continue
+            w = per["SQ_WAVES"][k] or 1.0
+            wc = cyc.get(k, 0.0) / waves[k]
+            g = lambda n: per[n].get(k, 0.0) / w
+            wa, ac = g("SQ_WAIT_ANY"), g("SQ_ACTIVE_INST_ANY")
+            lines.append(f"| {k} | {wc:.0f} | {wa:.0f} | {ac:.0f} | {wa / wc:.2f} | "
+                         f"{ac / wc:.2f} | {g('SQ_INSTS_VMEM_RD'):.1f} | "
+                         f"{g('SQ_INSTS_VMEM_WR'):.1f} |")
+    if args.note:
+        lines += ["", args.note]
     with open(args.out + ".md", "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
