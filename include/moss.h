@@ -242,14 +242,16 @@ int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leade
                     int32_t *flags, float *margin, uint32_t *t_leader, uint32_t *t_follower,
                     int32_t *n);
 
-/* Runs n steps like moss_step but synchronises after each one and adds the
- * duration of each of its kernels, measured with HIP events on the
- * simulator's stream, to kernel_ms[k] (milliseconds; array of capacity
- * entries, zeroed first).  *n_kernels receives the number of kernels per
- * step; moss_kernel_name(k) names kernel k (NULL if out of range); a kernel
- * the workload does not launch (insertion without departures, lane heads
- * without junction lanes) reports 0.  Meant for measurement: the per-step
- * synchronisation makes it slower than moss_step. */
+/* Runs n steps like moss_step, each kernel launched directly between two HIP
+ * events on the simulator's stream, and adds each kernel's duration to
+ * kernel_ms[k] (milliseconds; array of capacity entries, zeroed first).
+ * Steps are enqueued back to back and synchronised every 64 steps.
+ * *n_kernels receives the number of kernels per step; moss_kernel_name(k)
+ * names kernel k (NULL if out of range); a kernel the workload does not
+ * launch (lane heads without junction lanes) reports 0.  Departures are
+ * inserted by workgroups of the update's launch, so their time is part of
+ * k_update's.  Meant for measurement: the events and direct launches make it
+ * slower than moss_step. */
 int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
                     int32_t *n_kernels);
 const char *moss_kernel_name(int32_t i);

@@ -1063,35 +1063,50 @@ int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
     if (h->t + n >= (int64_t)1 << 31)
         return fail(MOSS_EINVAL, "step index would exceed 2^31");
     HIP_TRY(hipSetDevice(h->device));
-    std::vector<hipEvent_t> ev(K + 1);
+    // steps are enqueued back to back in groups of kChunk with their events
+    // (K + 1 per step) and synchronised once per group, so that a step's
+    // first kernel does not include the host's submission after a sync
+    constexpr int kChunk = 64;
+    std::vector<hipEvent_t> ev((size_t)(K + 1) * kChunk, nullptr);
+    int rc = MOSS_OK;
     for (auto &e : ev)
-        HIP_TRY(hipEventCreate(&e));
+        if (hipEventCreate(&e) != hipSuccess) {
+            rc = fail(MOSS_EDEVICE, "event creation failed");
+            break;
+        }
     for (int k = 0; k < K; ++k)
         kernel_ms[k] = 0.0;
-    int rc = MOSS_OK;
-    for (int32_t s = 0; s < n && rc == MOSS_OK; ++s) {
-        hipError_t e = launch_step(step_dev(h, h->parity), h->stream, ev.data());
+    for (int32_t s0 = 0; s0 < n && rc == MOSS_OK; s0 += kChunk) {
+        const int m = std::min<int32_t>(kChunk, n - s0);
+        hipError_t e = hipSuccess;
+        int j = 0;
+        for (; j < m && e == hipSuccess; ++j) {
+            e = launch_step(step_dev(h, h->parity), h->stream, &ev[(size_t)j * (K + 1)]);
+            h->parity ^= 1;
+            h->t += 1;
+        }
         if (e == hipSuccess)
-            e = hipEventSynchronize(ev[K]);
+            e = hipEventSynchronize(ev[(size_t)(m - 1) * (K + 1) + K]);
         if (e != hipSuccess) {
             rc = fail(MOSS_EDEVICE, "timed step failed: %s", hipGetErrorString(e));
             break;
         }
-        h->parity ^= 1;
-        h->t += 1;
-        for (int k = 0; k < K; ++k) {
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-            kernel_ms[k] += ms;
-        }
+        for (j = 0; j < m; ++j)
+            for (int k = 0; k < K; ++k) {
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, ev[(size_t)j * (K + 1) + k],
+                                          ev[(size_t)j * (K + 1) + k + 1]);
+                kernel_ms[k] += ms;
+            }
     }
     for (auto &e : ev)
-        (void)hipEventDestroy(e);
+        if (e)
+            (void)hipEventDestroy(e);
     // kernels this workload does not launch: the gap between their two
     // events is event overhead, not work
     for (int k = 0; k < K; ++k) {
         const std::string name = step_kernel_name(k);
-        if ((name == "k_insert" && h->dev.n_qlanes == 0) || (name == "k_heads" && !h->dev.junctions))
+        if (name == "k_heads" && !h->dev.junctions)
             kernel_ms[k] = 0.0;
     }
     return rc;

@@ -1,9 +1,10 @@
 // Kernels of one simulation step on gfx950.
 //
 // A step is the paper's two-phase iteration (Sec. III-A):
-//   update  - k_insert, k_update: every vehicle reads only the state S the
-//             step started from (the read-only copy) and writes a proposal
-//             (new position, speed, lane, route index) to its own row of Pr;
+//   update  - k_update: every vehicle reads only the state S the step
+//             started from (the read-only copy) and writes a proposal (new
+//             position, speed, lane, route index) to its own row of Pr;
+//             workgroups after the update's own insert departures;
 //   prepare - k_scan_*, k_jscatter, k_merge: the proposals are re-ordered per
 //             lane into the next state S (the spatial index of the next step).
 // No kernel writes what another thread of the same kernel reads, so the
@@ -362,10 +363,12 @@ __device__ __forceinline__ void wave_count(const Dev &d, int c, bool pred, int s
 // Head of each origin-lane queue enters when due, if the lane is empty or the
 // gap behind its last vehicle is at least s0 + v T for the entry speed
 // v = min(v0, limit, speed of that vehicle); it joins the lane at s = 0 at
-// the end of the step.
-__global__ void k_insert(Dev d)
+// the end of the step.  Queue lane q; run by whole workgroups of the update
+// launch (insertion reads only the start-of-step state, writes proposal rows
+// from n_cur on and its own joiner list, and only adds to the lane counts,
+// so it runs beside the update).
+__device__ __forceinline__ void insert_lane(const Dev &d, const int q)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const Params &P = d.P;
     bool ins = false, fail = false;
     int l = 0, h = 0, scen = 0;
@@ -447,11 +450,11 @@ __device__ __forceinline__ int lds_lower_bound_f32(const float *a, int lo, int h
 // workgroups split those tiles into 8 contiguous ranges, one per XCD, so that
 // neighbouring tiles' shared rows meet in the same L2.  Workgroups from g on
 // keep their own index, which is past the last tile (g >= ntiles there).  A
-// bijection of [0, gridDim.x) either way; with a persistent loop (grid below
-// ntiles) each round adds gridDim.x.
-__device__ __forceinline__ int xcd_tile(int remap, int ntiles)
+// bijection of [0, grid) either way; with a persistent loop (grid below
+// ntiles) each round adds grid.
+__device__ __forceinline__ int xcd_tile(int remap, int ntiles, int grid)
 {
-    const int b = blockIdx.x, grid = gridDim.x;
+    const int b = blockIdx.x;
     if (!remap || (grid & 7))
         return b;
     const int g = min(grid, ((ntiles + 7) >> 3) << 3);
@@ -469,13 +472,23 @@ __device__ __forceinline__ int xcd_tile(int remap, int ntiles)
 // Joiners are listed in the tile's own region of jlist, so no atomic result
 // is waited for.  MODE 1 evaluates the learned closure for the wave's 64
 // vehicles on the matrix cores between the acceleration and the integration.
-template <int MODE, bool AUX, bool EXT>
+template <int MODE, bool AUX, bool EXT, bool INS>
 __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
 {
     __shared__ float w_s[kUW], w_v[kUW], w_v0[kUW];
     __shared__ uint32_t w_id[kUW], w_ln[kUW];
     __shared__ uint32_t s_jn;
 
+    // the workgroups after the update's own insert departures (INS: the
+    // variant for networks with departure queues; without them the code is
+    // left out, which keeps scalar registers free)
+    const int gu = INS ? (int)gridDim.x - (d.n_qlanes + kUT - 1) / kUT : (int)gridDim.x;
+    if constexpr (INS) {
+        if ((int)blockIdx.x >= gu) {
+            insert_lane(d, ((int)blockIdx.x - gu) * kUT + (int)threadIdx.x);
+            return;
+        }
+    }
     const int n = *d.n_cur;
     const int64_t t = *d.t;
     // lane closures by control and junction internal lanes change the lane
@@ -501,8 +514,8 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
         mz = s_z + (tid >> 6) * kMlpStage;
     }
 
-    for (int base = xcd_tile(d.xcd_remap, (n + kUT - 1) / kUT) * kUT; base < n;
-         base += gridDim.x * kUT) {
+    for (int base = xcd_tile(d.xcd_remap, (n + kUT - 1) / kUT, gu) * kUT; base < n;
+         base += gu * kUT) {
         const int ws = max(base - kUH, 0), we = min(base + kUT + kUH, n);
         const int i = base + tid;
         const bool act = i < n;
@@ -1661,12 +1674,12 @@ __global__ void __launch_bounds__(kMT) k_merge(Dev d)
     // The chunk of this block when the rows fill the grid (the usual case)
     // is loaded together with the row count, and loaded again only when that
     // guess is wrong; w is uniform, every thread reads the same records.
-    const int wg = min(xcd_tile(d.xcd_remap, (int)gridDim.x),
+    const int wg = min(xcd_tile(d.xcd_remap, (int)gridDim.x, (int)gridDim.x),
                        d.cap / kMC + d.n_lanes / kMergeLanes + 1);
     int4 ca = at(d.chunk, wg), cb = at(d.chunk, wg + 1);
     const int n_next = *d.n_next;
     const int nch = chunk_of(d.n_lanes, n_next);     // the last chunk
-    const int w = xcd_tile(d.xcd_remap, nch + 1);
+    const int w = xcd_tile(d.xcd_remap, nch + 1, (int)gridDim.x);
     if (w > nch)
         return;
     if (w != wg) {
@@ -1861,13 +1874,20 @@ static inline unsigned blocks_for(long long n, int per)
     return (unsigned)(b < 1 ? 1 : b);
 }
 
-static const char *const kStepKernels[] = {"k_insert", "k_update", "k_scan_reduce",
-                                            "k_scan_apply", "k_jscatter", "k_merge", "k_heads"};
+static const char *const kStepKernels[] = {"k_update", "k_scan_reduce", "k_scan_apply",
+                                            "k_jscatter", "k_merge", "k_heads"};
 
 int step_kernel_count() { return (int)(sizeof kStepKernels / sizeof kStepKernels[0]); }
 const char *step_kernel_name(int i)
 {
     return (i >= 0 && i < step_kernel_count()) ? kStepKernels[i] : nullptr;
+}
+
+// The update kernel with or without the insertion workgroups.
+template <int MODE, bool AUX, bool EXT>
+static void (*update_variant(bool ins))(Dev)
+{
+    return ins ? k_update<MODE, AUX, EXT, true> : k_update<MODE, AUX, EXT, false>;
 }
 
 // Enqueues one step.  With ev != nullptr, ev[0] is recorded before the first
@@ -1878,41 +1898,41 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
-    if (d.n_qlanes > 0)
-        hipLaunchKernelGGL(k_insert, dim3(blocks_for(d.n_qlanes, 256)), dim3(256), 0, st, d);
-    mark(1);
     unsigned gu = blocks_for(d.cap, kUT);
     if (gu > 16384) gu = 16384;
     if (d.upd_blocks > 0) gu = (unsigned)d.upd_blocks;
     if (d.xcd_remap) gu = (gu + 7u) & ~7u;     // workgroups past the last tile find no work
     const bool aux = d.P.debug || d.P.trace;
+    const bool ins = d.n_qlanes > 0;
     void (*ku)(Dev);
     if (d.closures || d.junctions)
-        ku = d.mode == 1 ? (aux ? k_update<1, true, true> : k_update<1, false, true>)
-                         : (aux ? k_update<0, true, true> : k_update<0, false, true>);
+        ku = d.mode == 1 ? (aux ? update_variant<1, true, true>(ins) : update_variant<1, false, true>(ins))
+                         : (aux ? update_variant<0, true, true>(ins) : update_variant<0, false, true>(ins));
     else
-        ku = d.mode == 1 ? (aux ? k_update<1, true, false> : k_update<1, false, false>)
-                         : (aux ? k_update<0, true, false> : k_update<0, false, false>);
-    hipLaunchKernelGGL(ku, dim3(gu), dim3(kUT), 0, st, d);
-    mark(2);
+        ku = d.mode == 1 ? (aux ? update_variant<1, true, false>(ins) : update_variant<1, false, false>(ins))
+                         : (aux ? update_variant<0, true, false>(ins) : update_variant<0, false, false>(ins));
+    // insertion: one more workgroup per kUT queue lanes
+    const unsigned gi = ins ? (unsigned)((d.n_qlanes + kUT - 1) / kUT) : 0u;
+    hipLaunchKernelGGL(ku, dim3(gu + gi), dim3(kUT), 0, st, d);
+    mark(1);
     const unsigned gs = blocks_for(d.n_lanes, kScanLanes);
     hipLaunchKernelGGL(k_scan_reduce, dim3(gs), dim3(kScanThreads), 0, st, d);
-    mark(3);
+    mark(2);
     hipLaunchKernelGGL(k_scan_apply, dim3(gs), dim3(kScanThreads), 0, st, d);
-    mark(4);
+    mark(3);
     unsigned gj = blocks_for((long long)d.cap / kUpdateRows + 1, 4);
     if (gj > 2048) gj = 2048;
     if (d.jsc_blocks > 0) gj = (unsigned)d.jsc_blocks;
     hipLaunchKernelGGL(k_jscatter, dim3(gj), dim3(256), 0, st, d);
-    mark(5);
+    mark(4);
     unsigned gm = (unsigned)(d.cap / kMC + d.n_lanes / kMergeLanes + 1);
     if (d.xcd_remap) gm = (gm + 7u) & ~7u;     // chunks past the last one return at once
     hipLaunchKernelGGL(k_merge, dim3(gm), dim3(kMT), 0, st, d);
-    mark(6);
+    mark(5);
     if (d.junctions)
         hipLaunchKernelGGL(k_heads, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d,
                            (const int32_t *)d.ls_new);
-    mark(7);
+    mark(6);
     return hipGetLastError();
 }
 
