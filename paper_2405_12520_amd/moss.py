@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from typing import Dict, Optional
+from typing import Dict, List, Optional
 
 import numpy as np
 
@@ -252,6 +252,17 @@ def moss_step_timed(h: int, n: int):
     k = C.c_int32(0)
     _check(load().moss_step_timed(vp(h), int(n), _ptr(ms), 32, C.byref(k)))
     return {load().moss_kernel_name(i).decode(): float(ms[i]) for i in range(k.value)}
+
+
+def kernel_names() -> List[str]:
+    """Names of the step kernels in moss_step_timed's order."""
+    L = load()
+    out = []
+    while True:
+        n = L.moss_kernel_name(len(out))
+        if n is None:
+            return out
+        out.append(n.decode())
 
 
 def moss_set_launch(h: int, cfg: Dict[str, int]):

@@ -133,3 +133,14 @@ def test_static_gradient_refuses_a_batch_beyond_its_scratch():
     rc = L.moss_mlp_grad_static(fake, fake, None, n, fake, fake, 1, -9.0, 2.0, fake, None, None)
     assert rc == moss.MOSS_EINVAL
     assert "at most %d" % moss.MLP_STATIC_MAX_SAMPLES in moss.moss_last_error()
+
+
+def test_step_kernel_names():
+    """The step kernels in timing order, read through moss_kernel_name (a
+    host table; no GPU needed); out-of-range indices give NULL."""
+    from paper_2405_12520_amd import moss
+    names = moss.kernel_names()
+    assert names == ["k_update", "k_scan_reduce", "k_scan_apply", "k_jscatter", "k_merge",
+                     "k_heads"]
+    assert moss.load().moss_kernel_name(-1) is None
+    assert moss.load().moss_kernel_name(len(names)) is None

@@ -333,6 +333,36 @@ def test_graph_replay_matches_direct_steps(sim_cls):
     b.close()
 
 
+def test_timed_steps_match_graph_steps(sim_cls):
+    """moss_step_timed (direct launches between events, 64 steps per
+    synchronisation) computes the same steps as moss_step, reports every step
+    kernel with a non-negative time, and 0 for the lane-head kernel of a
+    network without junction lanes; the grid has departures, so the update's
+    launch carries the insertion workgroups."""
+    from paper_2405_12520_amd.moss import kernel_names
+    sc = S.grid(10, 6000, horizon=600)
+    _say("timed vs graph steps")
+    a = sim_cls(sc)
+    b = sim_cls(sc)
+    a.step(150)
+    kms = b.step_timed(150)
+    assert list(kms) == kernel_names()
+    assert all(v >= 0.0 for v in kms.values()), kms
+    assert kms["k_update"] > 0.0 and kms["k_merge"] > 0.0
+    assert kms["k_heads"] == 0.0
+    sa, sb = a.state(), b.state()
+    assert a.t == b.t == 150
+    for f in sa:
+        assert np.array_equal(sa[f], sb[f]), f
+    ca, va, ea = a.counters()
+    cb, vb, eb = b.counters()
+    assert ea == 0 and eb == 0
+    assert np.array_equal(ca, cb)
+    np.testing.assert_array_equal(va, vb)
+    a.close()
+    b.close()
+
+
 def test_device_reads_are_ordered_before_later_steps(sim_cls):
     """Device-pointer reads of the state and of the trace are complete when
     they return, so a step enqueued right after them cannot change what they
