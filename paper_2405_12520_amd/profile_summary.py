@@ -94,18 +94,34 @@ def main():
     args = ap.parse_args()
 
     rows = list(csv.DictReader(open(args.trace)))
+    # the same durations without each step kernel's first two dispatches (the
+    # steps right after creation), from the per-dispatch trace beside the stats
+    steady = {}
+    trace_csv = os.path.join(os.path.dirname(args.trace),
+                             os.path.basename(args.trace).replace("kernel_stats", "kernel_trace"))
+    if trace_csv != args.trace and os.path.exists(trace_csv):
+        per = collections.defaultdict(list)
+        for r in csv.DictReader(open(trace_csv)):
+            per[short(r["Kernel_Name"])].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0)
+        steady = {k: sum(v[2:]) / len(v[2:]) for k, v in per.items()
+                  if k.startswith("k_") and len(v) > 2}
     lines = [f"# rocprofv3 summary: {args.title}", ""]
     if args.command:
         lines += ["Commands (from the repository root):", "", "```", args.command, "```", ""]
     lines += ["## Kernel durations (rocprofv3 --kernel-trace --stats)", "",
-              "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+              "The last column leaves out each step kernel's first two dispatches (the steps "
+              "right after creation), as the byte and instruction counters below do.", "",
+              "| kernel | calls | avg us | min us | max us | share | avg us after 2 |",
+              "|---|---|---|---|---|---|---|"]
     dur = {}
     for r in rows:
         k = short(r["Name"])
         dur[k] = float(r["AverageNs"]) / 1000.0
+        st = f"{steady[k]:.2f}" if k in steady else "-"
         lines.append(f"| {k} | {r['Calls']} | {float(r['AverageNs'])/1e3:.2f} | "
                      f"{float(r['MinNs'])/1e3:.2f} | {float(r['MaxNs'])/1e3:.2f} | "
-                     f"{float(r['Percentage']):.1f}% |")
+                     f"{float(r['Percentage']):.1f}% | {st} |")
     traffic = {}
     if args.fetch and args.write:
         f = counter_means(args.fetch, "FETCH_SIZE")
@@ -119,7 +135,7 @@ def main():
                   f"Calibration: a device copy of {args.copy_bytes} bytes reads "
                   f"FETCH_SIZE = {pf:.0f} KiB and WRITE_SIZE = {pw:.0f} KiB; scale factors "
                   f"{sf:.3f} (fetch) and {sw:.3f} (write) are applied below.", "",
-                  "| kernel | fetch MB | write MB | total MB | B per vehicle | GB/s at avg duration |",
+                  "| kernel | fetch MB | write MB | total MB | B per vehicle | GB/s at the steady duration |",
                   "|---|---|---|---|---|---|"]
         for k in sorted(set(f) & set(w)):
             if not k.startswith("k_"):
@@ -128,7 +144,8 @@ def main():
             wb = w[k] * 1024 * sw
             tot = fb + wb
             traffic[k] = dict(bytes_per_launch=tot, fetch=fb, write=wb)
-            gbs = tot / (dur.get(k, 0) * 1e-6) / 1e9 if dur.get(k) else 0.0
+            dk = steady.get(k, dur.get(k, 0.0))
+            gbs = tot / (dk * 1e-6) / 1e9 if dk else 0.0
             lines.append(f"| {k} | {fb/1e6:.1f} | {wb/1e6:.1f} | {tot/1e6:.1f} | "
                          f"{tot/args.vehicles:.1f} | {gbs:.0f} |")
         rec = dict(source_sha=kernel_sources_sha(), vehicles=args.vehicles,
