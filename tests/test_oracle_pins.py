@@ -648,3 +648,81 @@ def test_threads_give_identical_results(make):
     cb, svb = b.counters()
     assert np.array_equal(ca, cb)
     assert np.array_equal(sva.view(np.uint64), svb.view(np.uint64))
+
+
+# ------------------------------------------- lookahead reach, self, clip --
+
+def _accel_of(sc, vid, steps=1):
+    o = OracleSim(sc)
+    o.step(steps)
+    st = o.state()
+    return float(st["a"][np.flatnonzero(st["id"] == vid)[0]])
+
+
+def test_lookahead_stops_beyond_its_reach():
+    """A leader on the next road is seen only while the distance to the lane
+    end is within d_look (300 m): from 500 m away the vehicle accelerates
+    exactly as on an empty road, from 250 m away it does not."""
+    net = S.corridor([500.0, 200.0], 1)
+    lead = dict(id=2, route=[1], lane=1, s=10.0, v=0.0, v0=0.5)
+    for s0, sees in ((0.0, False), (250.0, True)):
+        a = dict(id=1, route=[0, 1], lane=0, s=s0, v=10.0, v0=13.9)
+        with_lead = _accel_of(S.with_vehicles("reach", net, [a, lead]), 1)
+        alone = _accel_of(S.with_vehicles("reach", net, [a]), 1)
+        assert (with_lead != alone) == sees, (s0, with_lead, alone)
+        if sees:
+            assert with_lead < alone
+
+
+def test_vehicle_never_leads_itself_on_a_ring():
+    """One vehicle on a 200 m ring finds its own lane behind it within the
+    lookahead; it has no leader and accelerates exactly like a lone vehicle
+    on a long straight road."""
+    ring = S.ring(1, 200.0, 10.0, v0=14.0)
+    o = OracleSim(ring)
+    o.step(1)
+    assert int(o.debug()["leader"][0]) == 0xFFFFFFFF
+    a_ring = float(o.state()["a"][0])
+    net = S.corridor([5000.0], 1, vlim=30.0)
+    a_free = _accel_of(S.with_vehicles("free", net, [dict(id=0, route=[0], lane=0, s=0.0,
+                                                          v=10.0, v0=14.0)]), 0)
+    assert a_ring == a_free
+    assert a_free > 0.0
+
+
+def test_idm_dynamic_gap_term_is_clipped_at_zero():
+    """When the leader pulls away fast enough that v T + v dv / (2 sqrt(a b))
+    is negative, the desired gap is s0 alone (the textbook model's max(0, .)):
+    the acceleration no longer depends on the leader's speed and equals
+    a (1 - (v/v0)^4 - (s0/gap)^2)."""
+    from oracle import idm
+    v, v0, gap = 2.0, 14.0, 10.0
+    closed = 2.0 * (1.0 - (v / v0) ** 4 - (2.0 / gap) ** 2)
+    a20 = idm(v, v0, True, 20.0, gap)
+    a30 = idm(v, v0, True, 30.0, gap)
+    assert a20 == a30
+    assert abs(a20 - closed) <= 1e-6 * abs(closed)
+    # a slower leader makes the term positive and the gap demand larger
+    assert idm(v, v0, True, 1.0, gap) < a20
+
+
+def test_lane_change_counter_counts_the_change():
+    """The hand-built slow-leader state (two vehicles in lane 1 of a two-lane
+    road, the leader standing): every step some lane changes happen (MOBIL
+    looks at lane 0 on even steps and lane 1 on odd ones, and politeness 0.2
+    also moves the standing leader that blocks its follower).  On this long
+    road no vehicle changes road, so the counter's increment in each step
+    equals the number of vehicles whose lane differs from the step before."""
+    from rule_cases import slow_leader_change
+    o = OracleSim(slow_leader_change())
+    lanes = {int(i): int(l) for i, l in zip(o.state()["id"], o.state()["lane"])}
+    total = 0
+    for _ in range(4):
+        o.step(1)
+        st = o.state()
+        now = {int(i): int(l) for i, l in zip(st["id"], st["lane"])}
+        moved = sum(now[i] != lanes[i] for i in now)
+        c, _ = o.counters()
+        assert int(c[0, 5]) - total == moved
+        total, lanes = int(c[0, 5]), now
+    assert total > 0
