@@ -92,6 +92,71 @@ def test_conflicts_and_priorities():
     assert es1 in _conf(jl, nr)[0] and nr not in _conf(jl, es1)[0]
 
 
+def test_connector_lengths_by_turn():
+    """Connector road lengths are fixed per turn: 16 m straight, 9 m right,
+    20 m left, 12 m for a U-turn."""
+    jl = _net()
+    assert jl.road_length[_conn(jl, N_IN, S_OUT)] == 16.0
+    assert jl.road_length[_conn(jl, N_IN, W_OUT)] == 9.0
+    assert jl.road_length[_conn(jl, N_IN, E_OUT)] == 20.0
+    mv = jl.meta["junction_lanes"]["movements"]
+    if (N_IN, N_OUT) in mv:
+        assert jl.road_length[mv[(N_IN, N_OUT)]] == 12.0
+
+
+def test_turn_classification_at_45_degrees():
+    """The turn is the signed angle between the in-road's and the out-road's
+    headings: beyond 45 degrees anticlockwise a left turn, beyond 45 degrees
+    clockwise a right turn, straight in between (checked at 40 and 50
+    degrees either way) and a U-turn onto the reverse road."""
+    import math
+    from types import SimpleNamespace
+
+    def turn(deg):
+        a = math.radians(deg)
+        sc = SimpleNamespace(node_x=[0.0, 100.0, 100.0 + 100.0 * math.cos(a)],
+                             node_y=[0.0, 0.0, 100.0 * math.sin(a)],
+                             road_from=[0, 1, 1], road_to=[1, 2, 0])
+        return J.turn_of(sc, 0, 1)
+
+    assert [turn(d) for d in (40.0, 50.0, -40.0, -50.0, 0.0)] == ["S", "L", "S", "R", "S"]
+    sc = SimpleNamespace(node_x=[0.0, 100.0], node_y=[0.0, 0.0], road_from=[0, 1], road_to=[1, 0])
+    assert J.turn_of(sc, 0, 1) == "U"
+
+
+def test_three_lane_approach_turn_lanes():
+    """Three-lane approach: the left lane turns left (or makes the U-turn),
+    the middle lane only goes straight, the right lane goes straight or turns
+    right."""
+    jl = J.with_junction_lanes(S.intersection(lanes=3))
+    t = jl.meta["junction_lanes"]["turns"]
+    lane_road = np.repeat(np.arange(jl.n_roads), jl.road_nlanes)
+
+    def turns(k):
+        return {t[int(lane_road[y])] for y in _succ(jl, _lane(jl, N_IN, k))}
+
+    assert turns(0) <= {"L", "U"} and "L" in turns(0)
+    assert turns(1) == {"S"}
+    assert turns(2) == {"S", "R"}
+
+
+def test_equal_priority_conflict_goes_to_the_lower_lane():
+    """Two straight paths from perpendicular approaches (north to south, east
+    to west) cross and have equal rank: the tie goes to the lower lane id,
+    which the other lists among the lanes it yields to."""
+    jl = _net()
+    ns = [_lane(jl, _conn(jl, N_IN, S_OUT), k) for k in (0, 1)]
+    ew = [_lane(jl, _conn(jl, E_IN, W_OUT), k) for k in (0, 1)]
+    pairs = 0
+    for a in ns:
+        for b in ew:
+            lo, hi = min(a, b), max(a, b)
+            if lo in _conf(jl, hi)[0] or hi in _conf(jl, lo)[0]:
+                pairs += 1
+                assert lo in _conf(jl, hi)[0] and hi not in _conf(jl, lo)[0]
+    assert pairs > 0
+
+
 # ------------------------------------------------------------- dynamics --
 
 def _state(vehicles, params=None):

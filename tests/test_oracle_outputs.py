@@ -117,22 +117,28 @@ def test_trips_agree_with_counters_and_state():
     time counters; vehicles on the network are the state's rows; the rest
     are the waiting vehicles; travel times count from the departure step."""
     sc, o = _trip_run()
-    o.step(700)
-    tr = o.trips()
-    c, _ = o.counters()
-    st = o.state()
-    assert np.all(np.diff(tr["id"].astype(np.int64)) > 0)
-    arrived = tr["status"] == 2
-    assert arrived.sum() == c[0, 2] > 500
-    assert tr["travel"][arrived].sum() == c[0, 3]
-    on = tr["status"] == 1
-    assert set(tr["id"][on]) == set(st["id"].tolist())
-    assert (tr["status"] == 0).sum() == o.pending
     idx = {int(v): k for k, v in enumerate(sc.veh_id)}
-    dep = np.array([sc.depart[idx[int(v)]] for v in tr["id"]])
-    np.testing.assert_array_equal(tr["travel"][on], 700 - dep[on])
-    assert np.all(tr["travel"][tr["status"] == 0] == 0)
-    assert np.all(tr["distance"][tr["status"] == 0] == 0.0)
+    t = 0
+    for stop in (200, 700):         # mid-run (many on the network), then late
+        o.step(stop - t)
+        t = stop
+        tr = o.trips()
+        c, _ = o.counters()
+        st = o.state()
+        assert np.all(np.diff(tr["id"].astype(np.int64)) > 0)
+        arrived = tr["status"] == 2
+        assert arrived.sum() == c[0, 2] > 0
+        assert tr["travel"][arrived].sum() == c[0, 3]
+        on = tr["status"] == 1
+        assert set(tr["id"][on]) == set(st["id"].tolist())
+        assert (tr["status"] == 0).sum() == o.pending
+        dep = np.array([sc.depart[idx[int(v)]] for v in tr["id"]])
+        np.testing.assert_array_equal(tr["travel"][on], t - dep[on])
+        assert np.all(tr["travel"][tr["status"] == 0] == 0)
+        assert np.all(tr["distance"][tr["status"] == 0] == 0.0)
+        if t == 200:
+            assert on.sum() > 100 and (tr["status"] == 0).sum() > 0
+    assert arrived.sum() > 500
 
 
 def test_trip_distance_is_the_path_driven():
@@ -182,3 +188,27 @@ def test_trip_distance_of_placed_vehicles_starts_at_zero():
     for vid, d in zip(tr1["id"], tr1["distance"]):
         if int(vid) in pos1:
             assert abs(d - (pos1[int(vid)] - pos0[int(vid)])) < 1e-9
+
+
+def test_trip_of_a_placed_vehicle_to_its_arrival():
+    """A vehicle placed 100 m into the first road of a 500 m + 200 m route
+    (no other traffic) arrives with a distance of exactly 600 m, the route
+    less its starting position, and with a travel time equal to the steps it
+    took; the step before arriving it is on the network with a travel time
+    of the steps so far."""
+    from oracle import OracleSim
+    net = S.corridor([500.0, 200.0], 1)
+    sc = S.with_vehicles("placed_trip", net, [dict(id=7, route=[0, 1], lane=0, s=100.0,
+                                                   v=15.0, v0=15.0)])
+    o = OracleSim(sc)
+    t = 0
+    while True:
+        tr = o.trips()
+        if tr["status"][0] == 2:
+            break
+        assert tr["status"][0] == 1 and tr["travel"][0] == t
+        o.step(1)
+        t += 1
+        assert t < 100
+    assert tr["distance"][0] == 600.0
+    assert tr["travel"][0] == t
