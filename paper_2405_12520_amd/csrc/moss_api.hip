@@ -1106,7 +1106,8 @@ int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
     // events is event overhead, not work
     for (int k = 0; k < K; ++k) {
         const std::string name = step_kernel_name(k);
-        if (name == "k_heads" && !h->dev.junctions)
+        if ((name == "k_heads" && !h->dev.junctions) ||
+            (name == "k_scan_reduce" && h->dev.n_lanes <= step_scan_block_lanes()))
             kernel_ms[k] = 0.0;
     }
     return rc;

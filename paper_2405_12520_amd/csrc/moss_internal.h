@@ -249,6 +249,7 @@ void clear_error();
 // Kernel launchers (moss_kernels.hip).
 hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev = nullptr);
 int step_kernel_count();
+int step_scan_block_lanes();     // lanes per lane-count scan block
 const char *step_kernel_name(int i);
 hipError_t launch_tails(const Dev &d, hipStream_t st);
 // Lane heads of the current state (junction internal lanes).

@@ -1878,6 +1878,7 @@ static const char *const kStepKernels[] = {"k_update", "k_scan_reduce", "k_scan_
                                             "k_jscatter", "k_merge", "k_heads"};
 
 int step_kernel_count() { return (int)(sizeof kStepKernels / sizeof kStepKernels[0]); }
+int step_scan_block_lanes() { return kScanLanes; }
 const char *step_kernel_name(int i)
 {
     return (i >= 0 && i < step_kernel_count()) ? kStepKernels[i] : nullptr;
@@ -1915,8 +1916,11 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     const unsigned gi = ins ? (unsigned)((d.n_qlanes + kUT - 1) / kUT) : 0u;
     hipLaunchKernelGGL(ku, dim3(gu + gi), dim3(kUT), 0, st, d);
     mark(1);
+    // with one scan block the apply kernel needs no block sums (its prefix
+    // over earlier blocks is empty), so the reduction is not launched
     const unsigned gs = blocks_for(d.n_lanes, kScanLanes);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(gs), dim3(kScanThreads), 0, st, d);
+    if (gs > 1)
+        hipLaunchKernelGGL(k_scan_reduce, dim3(gs), dim3(kScanThreads), 0, st, d);
     mark(2);
     hipLaunchKernelGGL(k_scan_apply, dim3(gs), dim3(kScanThreads), 0, st, d);
     mark(3);

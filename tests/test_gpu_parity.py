@@ -333,15 +333,17 @@ def test_graph_replay_matches_direct_steps(sim_cls):
     b.close()
 
 
-def test_timed_steps_match_graph_steps(sim_cls):
+@pytest.mark.parametrize("name", ["grid", "intersection"])
+def test_timed_steps_match_graph_steps(sim_cls, name):
     """moss_step_timed (direct launches between events, 64 steps per
-    synchronisation) computes the same steps as moss_step, reports every step
-    kernel with a non-negative time, and 0 for the lane-head kernel of a
-    network without junction lanes; the grid has departures, so the update's
-    launch carries the insertion workgroups."""
+    synchronisation) computes the same steps as moss_step and reports every
+    step kernel with a non-negative time: 0 for the lane-head kernel of a
+    network without junction lanes, and 0 for the lane-count block reduction
+    of a network of one scan block (the intersection's 16 lanes).  Both have
+    departures, so the update's launch carries the insertion workgroups."""
     from paper_2405_12520_amd.moss import kernel_names
-    sc = S.grid(10, 6000, horizon=600)
-    _say("timed vs graph steps")
+    sc = S.grid(10, 6000, horizon=600) if name == "grid" else S.intersection()
+    _say(f"timed vs graph steps: {name}")
     a = sim_cls(sc)
     b = sim_cls(sc)
     a.step(150)
@@ -350,6 +352,7 @@ def test_timed_steps_match_graph_steps(sim_cls):
     assert all(v >= 0.0 for v in kms.values()), kms
     assert kms["k_update"] > 0.0 and kms["k_merge"] > 0.0
     assert kms["k_heads"] == 0.0
+    assert (kms["k_scan_reduce"] == 0.0) == (name == "intersection")
     sa, sb = a.state(), b.state()
     assert a.t == b.t == 150
     for f in sa:
