@@ -309,6 +309,36 @@ def test_mlp_mode_step_parity(torch_dev):
         prev_ev, prev_fb = co[0, 7], co[0, 8]
 
 
+def test_mlp_mode_step_parity_with_departures(torch_dev):
+    """Network mode on a network with departure queues, so that the update's
+    launch carries the insertion workgroups: from the oracle's state, queues
+    and step (a resumed scenario), one GPU step against the oracle's, every
+    vehicle checked element by element, insertions and failures equal."""
+    from paper_2405_12520_amd.moss import Simulator
+    from oracle import OracleSim
+    cfg = _mlp_cfg()
+    sc = S.grid(10, 6000, horizon=300).with_params(mlp=cfg)
+    o = OracleSim(sc)
+    o.step(60)
+    _say("mlp mode parity with departures")
+    for k in range(3):
+        tr = o.trips()
+        ck = dict(state=o.state(), pending=tr["id"][tr["status"] == 0], t=o.t)
+        assert len(ck["pending"]) > 0 and len(ck["state"]["id"]) > 0
+        g = Simulator(S.resume(sc, ck))
+        g.step(1)
+        gs = g.state()
+        cg, _, err = g.counters()
+        g.close()
+        co0, _ = o.counters()
+        o.step(1)
+        co, _ = o.counters()
+        assert err == 0
+        assert cg[0, 0] == co[0, 0] - co0[0, 0] and cg[0, 1] == co[0, 1] - co0[0, 1]
+        assert cg[0, 0] > 0
+        check_network_step(gs, o, sc, cfg["theta"], cfg["norm"], f"grid with departures step {k}")
+
+
 def test_mlp_mode_city_full_size(torch_dev):
     """The network-mode workload the benchmark reports (2M-vehicle city, the
     trained closure weights, the benchmark's launch shape), one step from
