@@ -309,18 +309,26 @@ def test_mlp_mode_step_parity(torch_dev):
         prev_ev, prev_fb = co[0, 7], co[0, 8]
 
 
-def test_mlp_mode_step_parity_with_departures(torch_dev):
-    """Network mode on a network with departure queues, so that the update's
-    launch carries the insertion workgroups: from the oracle's state, queues
-    and step (a resumed scenario), one GPU step against the oracle's, every
-    vehicle checked element by element, insertions and failures equal."""
+@pytest.mark.parametrize("name", ["departures", "junction_lanes"])
+def test_mlp_mode_step_parity_with_departures(torch_dev, name):
+    """Network mode on networks with departure queues, so that the update's
+    launch carries the insertion workgroups, on a 10 x 10 grid and on a 6 x 6
+    grid built with junction internal lanes (the update variant with lane
+    successors, the turn bias and the yield rule): from the oracle's state,
+    queues and step (a resumed scenario), one GPU step against the oracle's,
+    every vehicle checked element by element, insertions and failures
+    equal."""
+    from paper_2405_12520_amd import junctions as J
     from paper_2405_12520_amd.moss import Simulator
     from oracle import OracleSim
     cfg = _mlp_cfg()
-    sc = S.grid(10, 6000, horizon=300).with_params(mlp=cfg)
+    if name == "departures":
+        sc = S.grid(10, 6000, horizon=300).with_params(mlp=cfg)
+    else:
+        sc = J.with_junction_lanes(S.grid(6, 3000, horizon=300)).with_params(mlp=cfg)
     o = OracleSim(sc)
     o.step(60)
-    _say("mlp mode parity with departures")
+    _say(f"mlp mode parity: {name}")
     for k in range(3):
         tr = o.trips()
         ck = dict(state=o.state(), pending=tr["id"][tr["status"] == 0], t=o.t)
@@ -336,7 +344,7 @@ def test_mlp_mode_step_parity_with_departures(torch_dev):
         assert err == 0
         assert cg[0, 0] == co[0, 0] - co0[0, 0] and cg[0, 1] == co[0, 1] - co0[0, 1]
         assert cg[0, 0] > 0
-        check_network_step(gs, o, sc, cfg["theta"], cfg["norm"], f"grid with departures step {k}")
+        check_network_step(gs, o, sc, cfg["theta"], cfg["norm"], f"{name} step {k}")
 
 
 def test_mlp_mode_city_full_size(torch_dev):
