@@ -389,8 +389,8 @@ def main():
                          "byte counters of a profiler run against a known transfer)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "partition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the simulator "
+              "partitions no network across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
