@@ -158,6 +158,52 @@ def closure_cases():
     ]
 
 
+def _two_lane(vs, vlim_lane0, vlim_lane1, **params):
+    net = S.corridor([1000.0, 100.0], 2)
+    sc = S.with_vehicles("two_lane", net, vs, params=dict(t0=0, **params))
+    vl = sc.lane_vlim.copy()
+    vl[0], vl[1] = vlim_lane0, vlim_lane1
+    return dataclasses.replace(sc, lane_vlim=vl.astype(np.float32))
+
+
+def level_in_target() -> S.Scenario:
+    """Even step: vehicle 1 (lane 1, s = 200) and vehicle 3 level with it in
+    the target lane 0 (s = 200); p_lc = 1."""
+    return _two_lane([dict(id=1, route=[0, 1], lane=1, s=200.0, v=10.0, v0=14.0),
+                      dict(id=3, route=[0, 1], lane=0, s=200.0, v=10.0, v0=14.0)],
+                     16.67, 16.67, p_lc=1.0)
+
+
+def old_follower_limits(vlim_target: float, with_follower: bool = True) -> S.Scenario:
+    """Even step: vehicle 1 (lane 1, s = 200, v = 8, desired 8) with an old
+    follower 2 (lane 1, s = 150, v = 9, desired 15); own lane limit 10 m/s,
+    target lane 0 limit vlim_target."""
+    vs = [dict(id=1, route=[0, 1], lane=1, s=200.0, v=8.0, v0=8.0)]
+    if with_follower:
+        vs.append(dict(id=2, route=[0, 1], lane=1, s=150.0, v=9.0, v0=15.0))
+    return _two_lane(vs, vlim_target, 10.0)
+
+
+def new_follower_limits(vlim_own: float, with_follower: bool = True) -> S.Scenario:
+    """Even step: vehicle 1 (lane 1, s = 200, v = 8, desired 8) with a new
+    follower 3 in the target lane 0 (s = 150, v = 9, desired 15); target lane
+    limit 10 m/s, own lane limit vlim_own."""
+    vs = [dict(id=1, route=[0, 1], lane=1, s=200.0, v=8.0, v0=8.0)]
+    if with_follower:
+        vs.append(dict(id=3, route=[0, 1], lane=0, s=150.0, v=9.0, v0=15.0))
+    return _two_lane(vs, 10.0, vlim_own)
+
+
+def entry_behind_two() -> S.Scenario:
+    """A one-lane 500 m road holding vehicles at 6 m (v = 4) and 300 m
+    (v = 10), and a vehicle due to enter it at step 0."""
+    net = S.corridor([500.0, 100.0], 1)
+    vs = [dict(id=1, route=[0, 1], lane=0, s=6.0, v=4.0, v0=14.0),
+          dict(id=2, route=[0, 1], lane=0, s=300.0, v=10.0, v0=14.0),
+          dict(id=3, route=[0, 1], depart=0, v0=14.0)]
+    return S.with_vehicles("entry", net, vs)
+
+
 # every case above as (name, scenario, steps) for the GPU parity test
 def all_cases():
     f32 = np.float32
@@ -181,4 +227,10 @@ def all_cases():
         ("join_tie_21", joiners_tie(2, 1), 2),
         ("stay_join_tie_12", stayer_joiner_tie(1, 2), 2),
         ("stay_join_tie_21", stayer_joiner_tie(2, 1), 2),
+        ("level_in_target", level_in_target(), 2),
+        ("old_follower_lim12", old_follower_limits(12.0), 2),
+        ("old_follower_lim14", old_follower_limits(14.0), 2),
+        ("new_follower_lim12", new_follower_limits(12.0), 2),
+        ("new_follower_lim14", new_follower_limits(14.0), 2),
+        ("entry_behind_two", entry_behind_two(), 3),
     ]

@@ -726,3 +726,36 @@ def test_lane_change_counter_counts_the_change():
         assert int(c[0, 5]) - total == moved
         total, lanes = int(c[0, 5]), now
     assert total > 0
+
+
+# ------------------------------- MOBIL neighbours' limits and ties, entry --
+
+def _debug_of(sc, vid):
+    o = OracleSim(sc)
+    o.step(1)
+    d = o.debug()
+    k = int(np.flatnonzero(d["id"] == vid)[0])
+    return {f: d[f][k] for f in d}
+
+
+def test_target_lane_leader_includes_an_equal_position():
+    """In the target lane the leader is the lowest position at or ahead of
+    the vehicle's own: a vehicle level with it is its leader (the change is
+    then unsafe: no gap ahead), and there is no follower."""
+    from rule_cases import level_in_target
+    d = _debug_of(level_in_target(), 1)
+    assert int(d["t_leader"]) == 3
+    assert int(d["t_follower"]) == 0xFFFFFFFF
+    assert int(d["flags"]) & 3 == 1          # evaluated, not changed
+
+
+def test_entry_gap_is_to_the_lowest_vehicle_of_the_lane():
+    """A departure is checked against the lane's last vehicle (lowest
+    position): with one vehicle 6 m into the lane and another at 300 m the
+    entry is refused (6 - 5 < 2 + 4 * 1.5)."""
+    from rule_cases import entry_behind_two
+    o = OracleSim(entry_behind_two())
+    o.step(1)
+    c, _ = o.counters()
+    assert int(c[0, 0]) == 0 and int(c[0, 1]) == 1
+    assert o.pending == 1
