@@ -42,6 +42,9 @@ def _cases():
                                                v=10.0)], params=dict(p_lc=0.0)), 4
     yield "through_connector", TJ._state([dict(id=1, route=[TJ.N_IN, TJ.E_OUT], lane=0, s=470.0,
                                                v=12.0)]), 12
+    # a right turn: the one-lane connector ends on the out-road's right lane
+    yield "right_turn_exit", TJ._state([dict(id=1, route=[TJ.N_IN, TJ.W_OUT], lane=1, s=470.0,
+                                             v=10.0)]), 10
     for t0 in (0, 1):
         vs = [dict(id=1, route=[TJ.N_IN, TJ.E_OUT], lane=lane, s=300.0, v=10.0)
               for lane in (0,)] + [dict(id=2, route=[TJ.N_IN, TJ.E_OUT], lane=0, s=330.0, v=4.0)]
