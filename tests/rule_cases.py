@@ -204,6 +204,19 @@ def entry_behind_two() -> S.Scenario:
     return S.with_vehicles("entry", net, vs)
 
 
+def clamp_two_chains() -> S.Scenario:
+    """One lane with two fast followers (v = 20) each 10 m behind a standing
+    vehicle, 200 m apart: both followers overrun their leader in one step
+    (braking at most b_max), so the lane has two overlapping pairs with a
+    clean pair between them."""
+    net = S.corridor([1000.0, 100.0], 1)
+    vs = [dict(id=1, route=[0, 1], lane=0, s=85.0, v=20.0, v0=20.0),
+          dict(id=2, route=[0, 1], lane=0, s=100.0, v=0.0, v0=0.5),
+          dict(id=3, route=[0, 1], lane=0, s=285.0, v=20.0, v0=20.0),
+          dict(id=4, route=[0, 1], lane=0, s=300.0, v=0.0, v0=0.5)]
+    return S.with_vehicles("clamp_two", net, vs)
+
+
 # every case above as (name, scenario, steps) for the GPU parity test
 def all_cases():
     f32 = np.float32
@@ -233,4 +246,5 @@ def all_cases():
         ("new_follower_lim12", new_follower_limits(12.0), 2),
         ("new_follower_lim14", new_follower_limits(14.0), 2),
         ("entry_behind_two", entry_behind_two(), 3),
+        ("clamp_two_chains", clamp_two_chains(), 3),
     ]

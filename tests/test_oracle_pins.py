@@ -759,3 +759,20 @@ def test_entry_gap_is_to_the_lowest_vehicle_of_the_lane():
     c, _ = o.counters()
     assert int(c[0, 0]) == 0 and int(c[0, 1]) == 1
     assert o.pending == 1
+
+
+def test_clamp_removes_every_overlap_of_a_lane():
+    """Two followers overrun their standing leaders in the same step, 200 m
+    apart in one lane: each ends exactly one vehicle length behind its
+    leader, with its leader's speed, and the step counts two clamps (the
+    clean pair between the two chains does not stop the removal)."""
+    from rule_cases import clamp_two_chains
+    o = OracleSim(clamp_two_chains())
+    o.step(1)
+    st = o.state()
+    s = dict(zip(st["id"].tolist(), st["s"].tolist()))
+    v = dict(zip(st["id"].tolist(), st["v"].tolist()))
+    assert s[1] == np.float32(np.float32(s[2]) - np.float32(5.0)) and v[1] == v[2]
+    assert s[3] == np.float32(np.float32(s[4]) - np.float32(5.0)) and v[3] == v[4]
+    c, _ = o.counters()
+    assert int(c[0, 4]) == 2
