@@ -61,8 +61,11 @@ def test_predict_matches_oracle_forward(torch_dev):
     rng = np.random.default_rng(0)
     f = _features(rng, 1000)
     nrm = _norm_for(f)
-    th = M.init_params(7)
-    th[M.N_PARAMS - 1] = 0.3
+    p = {k: np.array(v, np.float64) for k, v in M.unpack(M.init_params(7)).items()}
+    p["b1"] = rng.uniform(-0.3, 0.3, M.N_H)
+    p["b2"] = rng.uniform(-0.3, 0.3, M.N_H)
+    p["b3"] = np.array([0.3])
+    th = M.pack(p).astype(np.float32)
     _say("mlp predict")
     out = moss.mlp_predict(torch.from_numpy(f).cuda(), torch.from_numpy(th).cuda(),
                            torch.from_numpy(nrm).cuda()).cpu().numpy()
@@ -167,8 +170,18 @@ def _snapshot_from(sc, st, t):
 
 
 def _mlp_cfg():
-    th = M.init_params(21)
-    th[M.N_PARAMS - 1] = -0.2
+    """Closure weights for the network-mode parity cases: seeded He-style
+    layers with non-zero hidden biases (a dropped bias term shows) and an
+    output layer scaled by 12 with bias 1.0, so that on the 10 x 10 grid
+    about 4% of the evaluated outputs fall above a_max and 0.5% below
+    -b_max and the output limits bind."""
+    p = {k: np.array(v, np.float64) for k, v in M.unpack(M.init_params(21)).items()}
+    rng = np.random.default_rng(22)
+    p["b1"] = rng.uniform(-0.3, 0.3, M.N_H)
+    p["b2"] = rng.uniform(-0.3, 0.3, M.N_H)
+    p["w3"] = 12.0 * p["w3"]
+    p["b3"] = np.array([1.0])
+    th = M.pack(p).astype(np.float32)
     mean = np.array([3.5, 8, 8, 13, 5.0, 0, 4.5, 14], np.float32)
     inv = 1.0 / np.array([1.5, 5, 5, 2, 1.0, 2, 1.2, 2], np.float32)
     lo = np.array([-10, 0, 0, 0, 0, -10, 0, 0], np.float32)
@@ -302,6 +315,11 @@ def test_mlp_mode_step_parity(torch_dev):
         co, _ = o.counters()
         assert err == 0
         check_network_step(gs, o, sc, cfg["theta"], cfg["norm"], f"grid step {k}")
+        if k == 0:
+            # the step exercises both output limits
+            f, use = o.mlp_inputs()
+            y, _ = M.forward(cfg["theta"], M.normalise(f[use == 1], cfg["norm"]))
+            assert (y > sc.params["a_max"]).sum() > 0 and (y < -sc.params["b_max"]).sum() > 0
         st = o.state()
         # evaluations and fallbacks of this step
         ev_o = co[0, 7] - (0 if k == 0 else prev_ev)
