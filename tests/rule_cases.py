@@ -233,6 +233,7 @@ def all_cases():
         ("red_last_road", red_approach(200.0, v=10.0, route=(0,)), 20),
         ("cut_in_gap0", cut_in_behind(195.0), 2),
         ("cut_in_gap1", cut_in_behind(194.0), 2),
+        ("cut_in_at_b_safe", cut_in_behind(194.0, b_safe=6.0), 2),
         ("limit_low_target", limits_differ(8.0, 16.67), 2),
         ("limit_low_own", limits_differ(16.67, 8.0), 2),
         ("clamp", clamp_fast_follower(), 3),

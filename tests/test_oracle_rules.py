@@ -148,6 +148,17 @@ def test_cut_in_refused_by_follower_braking():
     assert _dbg(o, 1)["flags"] & 3 == 1
 
 
+def test_cut_in_at_the_braking_limit():
+    """Same rear gap of 1 m with b_safe = 6: the new follower's acceleration
+    after the change, 2 (1 - (2/1)^2) = -6, is exact in FP32 and equals
+    -b_safe.  MOBIL's safety criterion admits a~_n >= -b_safe, so the change
+    is made (a strict comparison would refuse it)."""
+    o = OracleSim(RC.cut_in_behind(194.0, b_safe=6.0))
+    o.step(1)
+    d = _dbg(o, 1)
+    assert d["flags"] & 3 == 2 and d["t_follower"] == 3
+
+
 def _idm64(v, v0e, vl=None, gap=None, a=2.0, b=4.5, s0=2.0, T=1.5):
     free = 1.0 - (v / v0e) ** 4
     if vl is None:
