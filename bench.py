@@ -245,6 +245,54 @@ def bench_big(args):
                 hbm_frac=frac, launch=used)
 
 
+def junction_city(sc):
+    """The city snapshot rebuilt with junction internal lanes: a connector
+    lane per movement through every junction, routes through the
+    connectors, the turn-lane bias and the yield rule at conflicting
+    movements."""
+    from paper_2405_12520_amd import junctions as J
+    t0 = time.time()
+    jsc = J.with_junction_lanes(sc)
+    jl = jsc.meta["junction_lanes"]
+    say(f"[bench] junction lanes built in {time.time() - t0:.1f} s: {jsc.summary()}, "
+        f"{jl['connectors']} connectors, {jl['connector_lanes']} connector lanes")
+    return jsc
+
+
+def bench_junctions(sc, launch, args):
+    """The 2M city with junction internal lanes (the update variant with lane
+    successors, the turn bias and the yield rule, plus the yield-flag kernel),
+    in the launch shape tuned for the snapshot."""
+    import torch
+    from paper_2405_12520_amd.moss import Simulator
+    jsc = junction_city(sc)
+    sim = Simulator(jsc)
+    sim.set_launch(**{k: v for k, v in launch.items() if k != "graph_steps"})
+    used = fit_graphs(sim, args.steps)
+    sim.step(args.warmup)
+    ms, dc = timed_steps(sim, args.steps)
+    veh_steps = int(dc[:, 6].sum())
+    kms = sim.step_timed(20)
+    n_act = sim.n_active
+    _, _, err = sim.counters()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if err:
+        raise RuntimeError(f"junction-lane city: device error word {err}")
+    per = {k: v / 20 for k, v in kms.items() if v > 0}
+    frac = {k: round(ALGO_BYTES[k] * n_act / (per[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            for k in ALGO_BYTES}
+    jl = jsc.meta["junction_lanes"]
+    say(f"[bench] junction-lane city: {veh_steps / (ms / 1e3):.4g} vehicle-steps/s, "
+        f"per-kernel ms { {k: round(v, 4) for k, v in per.items()} }")
+    return dict(value=round(veh_steps / (ms / 1e3), 1), unit="vehicle-steps/s",
+                ms_per_step=round(ms / args.steps, 5), vehicles=int(jsc.n_veh),
+                active_vehicles=int(n_act), lanes=int(jsc.n_lanes),
+                connector_lanes=int(jl["connector_lanes"]),
+                kernel_ms={k: round(v, 5) for k, v in per.items()}, hbm_frac=frac, launch=used)
+
+
 def bench_batch(args):
     """Disjoint union of independent grid scenarios (4x4 .. 16x16, 1k..50k
     vehicles each, departures over 1800 s) stepped as one network through the
@@ -407,6 +455,11 @@ def main():
                     help="skip the intersection and 10x10 grid hours")
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 8M-vehicle city (beyond the Infinity Cache)")
+    ap.add_argument("--junctions", action="store_true",
+                    help="with --profile-only: step the 2M city built with junction internal "
+                         "lanes instead of the snapshot")
+    ap.add_argument("--no-junctions", action="store_true",
+                    help="skip the 2M city built with junction internal lanes")
     ap.add_argument("--batch-scenarios", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also copy a device buffer of this size once (calibrates the HBM "
@@ -455,6 +508,8 @@ def main():
     t0 = time.time()
     sc = S.city_snapshot(args.vehicles)
     say(f"[bench] generated in {time.time() - t0:.1f} s: {sc.summary()}")
+    if args.profile_only and args.junctions:
+        sc = junction_city(sc)
     if args.mlp:
         from paper_2405_12520_amd import closure
         theta, norm = closure.load(closure.DEFAULT_PATH)
@@ -530,6 +585,8 @@ def main():
         extras["batch"] = bench_batch(args)
     if not args.no_big:
         extras["city8M"] = bench_big(args)
+    if not args.no_junctions:
+        extras["city_junction_lanes"] = bench_junctions(sc, used, args)
     if not args.no_demand:
         extras["city_demand"] = bench_demand(args)
     if not args.no_small:

@@ -248,7 +248,7 @@ int moss_read_debug(moss_sim *h, int32_t capacity, uint32_t *id, uint32_t *leade
  * Steps are enqueued back to back and synchronised every 64 steps.
  * *n_kernels receives the number of kernels per step; moss_kernel_name(k)
  * names kernel k (NULL if out of range); a kernel the workload does not
- * launch (lane heads without junction lanes, the lane-count block reduction
+ * launch (yield flags without junction lanes, the lane-count block reduction
  * on networks of at most 256 lanes) reports 0.  Departures are
  * inserted by workgroups of the update's launch, so their time is part of
  * k_update's.  Meant for measurement: the events and direct launches make it

@@ -72,7 +72,7 @@ struct Layout {
         roads, route, qlanes, q_hdep, q_head, q_end, q_id, q_dep, q_v0, q_ptr, q_next, vt_id, vt_dep,
         vt_rstart, vt_dist0, cnt, sumv, dbg[6], cursor, mlp_theta, mlp_norm, mlp_pack, mlp_sq,
         tr_feat, tr_label, road_ab, out_buf, trip_buf, ctl_idx, ctl_rec, ctl_ridx, ctl_rrec,
-        succ_off, succ, conf_off, conf, conf_feed, heads;
+        succ_off, succ, conf_off, conf, conf_feed, busy;
     int64_t n_succ = 0, n_conf = 0;
 
     void plan()
@@ -154,7 +154,7 @@ struct Layout {
         conf_off = take(jl ? 4 * ((size_t)n_lanes + 1) : 4);
         conf = take(sizeof(Succ) * (size_t)std::max<int64_t>(n_conf, 1));
         conf_feed = take(4 * (size_t)std::max<int64_t>(n_conf, 1));
-        heads = take(jl ? sizeof(Head) * (size_t)n_lanes : sizeof(Head));
+        busy = take(jl ? (size_t)n_lanes : 1);
         // staging of the read functions' results for host destinations
         out_buf = take(std::max(8 * (size_t)n_roads, xy ? 24 * c : (size_t)8));
         // staging of moss_read_trips for host destinations: status, travel
@@ -536,7 +536,7 @@ static void fill_dev(moss_sim *h)
     d.conf_off = I(L.conf_off);
     d.conf = (const Succ *)(w + L.conf);
     d.conf_feed = I(L.conf_feed);
-    d.heads = (Head *)(w + L.heads);
+    d.busy = (uint8_t *)(w + L.busy);
     d.cnt = (unsigned long long *)(w + L.cnt);
     d.sumv = (unsigned long long *)(w + L.sumv);
     d.cnt_stride = stripe_elems((int64_t)h->n_scen * C_N);
@@ -956,7 +956,7 @@ int moss_create(const moss_network *net, const moss_signals *sig, const moss_veh
     if (e == hipSuccess)
         e = launch_tails(step_dev(h, 0), st);
     if (e == hipSuccess && h->dev.junctions)
-        e = launch_heads(step_dev(h, 0), st);
+        e = launch_yield(step_dev(h, 0), st);
     if (e == hipSuccess && L.mlp)
         e = launch_mlp_pack(step_dev(h, 0), st);
     if (e == hipSuccess)
@@ -1106,7 +1106,7 @@ int moss_step_timed(moss_sim *h, int32_t n, double *kernel_ms, int32_t capacity,
     // events is event overhead, not work
     for (int k = 0; k < K; ++k) {
         const std::string name = step_kernel_name(k);
-        if ((name == "k_heads" && !h->dev.junctions) ||
+        if ((name == "k_yield" && !h->dev.junctions) ||
             (name == "k_scan_reduce" && h->dev.n_lanes <= step_scan_block_lanes()))
             kernel_ms[k] = 0.0;
     }
@@ -1348,6 +1348,9 @@ static int upload_patch(moss_sim *h)
     HIP_TRY(hipMemcpyAsync(dr, h->patch_rec.data(), sizeof(LaneInfo) * (size_t)n,
                            hipMemcpyHostToDevice, h->stream));
     HIP_TRY(launch_lane_patch(step_dev(h, h->parity), di, dr, n, h->stream));
+    // the yield flags depend on the red flags just rewritten
+    if (h->dev.junctions)
+        HIP_TRY(launch_yield(step_dev(h, h->parity), h->stream));
     // the host staging vectors are reused by the next call
     HIP_TRY(hipStreamSynchronize(h->stream));
     return MOSS_OK;

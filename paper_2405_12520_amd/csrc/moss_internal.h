@@ -88,14 +88,6 @@ __host__ __device__ inline uint8_t lane_flags_at(const LaneInfo &li, uint32_t t)
                      ((li.lflags & kLaneInternal) ? kInternalBit : 0u));
 }
 
-// First vehicle (highest position) of each lane with its next route road
-// (-1 on the last road or when the lane is empty), for the yield rule.
-struct Head {
-    float s, v;
-    int32_t next;
-    int32_t pad;
-};
-
 // A lane's successor on another road (junction internal lanes).
 struct Succ {
     int32_t lane, road;
@@ -203,11 +195,11 @@ struct Dev {
     int32_t closures;
     // junction internal lanes: successor lists (CSR over lanes), per
     // connector lane the conflicting lanes with priority and their feeders,
-    // and the lane heads written after every step
+    // and the lanes' yield flags written after every step (k_yield)
     int32_t junctions;
     const int32_t *succ_off, *conf_off, *conf_feed;
     const Succ *succ, *conf;
-    Head *heads;
+    uint8_t *busy;
     // learned closure (mode 1) and its training trace
     int32_t mode;
     const float *mlp_theta, *mlp_norm;
@@ -252,8 +244,9 @@ int step_kernel_count();
 int step_scan_block_lanes();     // lanes per lane-count scan block
 const char *step_kernel_name(int i);
 hipError_t launch_tails(const Dev &d, hipStream_t st);
-// Lane heads of the current state (junction internal lanes).
-hipError_t launch_heads(const Dev &d, hipStream_t st);
+// Yield flags of the current state for the step about to run (junction
+// internal lanes; after creation and after a change of the red flags).
+hipError_t launch_yield(const Dev &d, hipStream_t st);
 // Overwrites n lane records (signal control, speed limits) and recomputes
 // their red flags for the step about to run.
 hipError_t launch_lane_patch(const Dev &d, const int32_t *idx, const LaneInfo *rec, int32_t n,

@@ -223,27 +223,6 @@ __device__ __forceinline__ bool lane_permits(const Dev &d, int y, int rd)
     return ok;
 }
 
-// Yield rule at a junction: connector lane cl is busy when one of the
-// conflicting connector lanes with priority over it holds a vehicle (its
-// tail at the start of the step), or the lane feeding such a connector has a
-// first vehicle headed into it, not held by a red light, and within
-// tau_yield seconds of its stop line at its speed (L - s <= v tau_yield).
-__device__ bool conflict_busy(const Dev &d, int cl)
-{
-    const int a = at(d.conf_off, cl), b = at(d.conf_off, cl + 1);
-    for (int q = a; q < b; ++q) {
-        const Succ c2 = at(d.conf, q);
-        if (at(d.tails, c2.lane).id != kNone)
-            return true;
-        const int f = at(d.conf_feed, q);
-        const Head hd = at(d.heads, f);
-        if (hd.next == c2.road && !(at(d.lane_red, f) & kRedBit) &&
-            at(d.lanes, f).L - hd.s <= hd.v * d.P.tau_yield)
-            return true;
-    }
-    return false;
-}
-
 // Leader beyond the lane end: follow the route for at most h_look roads while
 // the distance covered is within d_look; on each road take the lane
 // next_lane gives and use its last vehicle (lane tail).  A vehicle never
@@ -785,7 +764,7 @@ __global__ void __launch_bounds__(kUT, 4) k_update(Dev d)
                 // conflicts with priority (applied if it can still stop)
                 if (junctions && nxt >= 0) {
                     const int cl = next_lane<EXT>(d, lf, (int)lif.k, nxt, rd_next);
-                    if (conflict_busy(d, cl)) {
+                    if (at(d.busy, cl)) {
                         flags |= 64;
                         if (!red) {
                             float stop_dist = (v * v) * P.inv_2bmax;
@@ -1787,21 +1766,35 @@ __global__ void k_tails(Dev d)
                any ? at(d.S.id, w0) : kNone);
 }
 
-// First vehicle (highest position) of every lane with its next route road,
-// from the lane starts ls of the state held in S (the new starts after a
-// step's merge, the current ones at creation).
-__global__ void k_heads(Dev d, const int32_t *ls)
+// Yield flags of the step about to run (junction internal lanes), one per
+// lane: connector lane cl is busy when a conflicting connector lane with
+// priority over it holds a vehicle (its tail), or the lane feeding such a
+// connector has a first vehicle (highest position) headed into it, not held
+// by a red light, and within tau_yield seconds of its stop line at its speed
+// (L - s <= v tau_yield); lanes without conflicts are never busy.  Computed
+// once per step from the state with lane starts ls, its tails and the red
+// flags of the step, so that a lane head reads one flag instead of walking
+// the conflict list.
+__global__ void k_yield(Dev d, const int32_t *ls)
 {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= d.n_lanes)
+    const int cl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= d.n_lanes)
         return;
-    const int w0 = at(ls, l), w1 = at(ls, l + 1);
-    Head hd;
-    hd.pad = 0;
-    hd.s = w1 > w0 ? at(d.S.s, w1 - 1) : 0.0f;
-    hd.v = w1 > w0 ? at(d.S.v, w1 - 1) : 0.0f;
-    hd.next = w1 > w0 ? at(d.S.next, w1 - 1) : -1;
-    at(d.heads, l) = hd;
+    const int a = at(d.conf_off, cl), b = at(d.conf_off, cl + 1);
+    uint8_t busy = 0;
+    for (int q = a; q < b && !busy; ++q) {
+        const Succ c2 = at(d.conf, q);
+        if (at(d.tails, c2.lane).id != kNone) {
+            busy = 1;
+            break;
+        }
+        const int f = at(d.conf_feed, q);
+        const int w0 = at(ls, f), w1 = at(ls, f + 1);
+        if (w1 > w0 && at(d.S.next, w1 - 1) == c2.road && !(at(d.lane_red, f) & kRedBit) &&
+            at(d.lanes, f).L - at(d.S.s, w1 - 1) <= at(d.S.v, w1 - 1) * d.P.tau_yield)
+            busy = 1;
+    }
+    at(d.busy, cl) = busy;
 }
 
 __device__ __forceinline__ int find_vehicle(const Dev &d, uint32_t id)
@@ -1875,7 +1868,7 @@ static inline unsigned blocks_for(long long n, int per)
 }
 
 static const char *const kStepKernels[] = {"k_update", "k_scan_reduce", "k_scan_apply",
-                                            "k_jscatter", "k_merge", "k_heads"};
+                                            "k_jscatter", "k_merge", "k_yield"};
 
 int step_kernel_count() { return (int)(sizeof kStepKernels / sizeof kStepKernels[0]); }
 int step_scan_block_lanes() { return kScanLanes; }
@@ -1934,7 +1927,7 @@ hipError_t launch_step(const Dev &d, hipStream_t st, hipEvent_t *ev)
     hipLaunchKernelGGL(k_merge, dim3(gm), dim3(kMT), 0, st, d);
     mark(5);
     if (d.junctions)
-        hipLaunchKernelGGL(k_heads, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d,
+        hipLaunchKernelGGL(k_yield, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d,
                            (const int32_t *)d.ls_new);
     mark(6);
     return hipGetLastError();
@@ -2047,9 +2040,9 @@ hipError_t launch_mlp_pack(const Dev &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_heads(const Dev &d, hipStream_t st)
+hipError_t launch_yield(const Dev &d, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_heads, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d, d.ls_old);
+    hipLaunchKernelGGL(k_yield, dim3(blocks_for(d.n_lanes, 256)), dim3(256), 0, st, d, d.ls_old);
     return hipGetLastError();
 }
 

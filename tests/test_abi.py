@@ -141,6 +141,6 @@ def test_step_kernel_names():
     from paper_2405_12520_amd import moss
     names = moss.kernel_names()
     assert names == ["k_update", "k_scan_reduce", "k_scan_apply", "k_jscatter", "k_merge",
-                     "k_heads"]
+                     "k_yield"]
     assert moss.load().moss_kernel_name(-1) is None
     assert moss.load().moss_kernel_name(len(names)) is None

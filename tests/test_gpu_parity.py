@@ -337,7 +337,7 @@ def test_graph_replay_matches_direct_steps(sim_cls):
 def test_timed_steps_match_graph_steps(sim_cls, name):
     """moss_step_timed (direct launches between events, 64 steps per
     synchronisation) computes the same steps as moss_step and reports every
-    step kernel with a non-negative time: 0 for the lane-head kernel of a
+    step kernel with a non-negative time: 0 for the yield-flag kernel of a
     network without junction lanes, and 0 for the lane-count block reduction
     of a network of one scan block (the intersection's 16 lanes).  Both have
     departures, so the update's launch carries the insertion workgroups."""
@@ -351,7 +351,7 @@ def test_timed_steps_match_graph_steps(sim_cls, name):
     assert list(kms) == kernel_names()
     assert all(v >= 0.0 for v in kms.values()), kms
     assert kms["k_update"] > 0.0 and kms["k_merge"] > 0.0
-    assert kms["k_heads"] == 0.0
+    assert kms["k_yield"] == 0.0
     assert (kms["k_scan_reduce"] == 0.0) == (name == "intersection")
     sa, sb = a.state(), b.state()
     assert a.t == b.t == 150
